@@ -1,0 +1,182 @@
+/*
+ * gs2d.h - C ABI of the MI355X (gfx950) 2D-Gaussian frame fitter.
+ *
+ * The library fits N 2D Gaussians to one RGB frame, the per-frame encoding
+ * loop of "Neural Video Compression using 2D Gaussian Splatting"
+ * (Sec. 3.1-3.2): each Gaussian has a mean mu (2 floats), a Cholesky vector
+ * l = (l1, l2, l3) with Sigma = L L^T, L = [[l1, 0], [l2, l3]] (Eq. 1), and a
+ * colour c' (3 floats).  A frame is rendered by the accumulated sum of
+ * Eq. 2, C(p) = sum_n c'_n exp(-q/2), q = d^T Sigma^-1 d, d = (x+1/2, y+1/2)
+ * - mu, over the Gaussians with q <= 9 (3-sigma cutoff, inclusive); the
+ * loop minimises the mean squared error to the target with Adam.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - All array arguments are DEVICE pointers to contiguous buffers owned by
+ *    the caller; the library never allocates device memory for them and keeps
+ *    no pointer after a call returns.  Scratch space is one caller-provided
+ *    workspace of gs2d_workspace_bytes() bytes (256-byte aligned).
+ *  - Parameter layout (structure of arrays, FP32): xy [N][2] (x, y in pixel
+ *    units, origin at the top-left corner of the frame), chol [N][3]
+ *    (l1, l2, l3), rgb [N][3].  Images are planar FP32 [3][H][W].
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default
+ *    stream.  Every call except gs2d_fit_frame only enqueues work and
+ *    returns; results are ready when the stream reaches them.
+ *  - Every call returns a gs2d_status and never aborts.  Invalid arguments
+ *    return GS2D_EINVAL before anything is enqueued.  Conditions found on the
+ *    device are reported in the workspace status word (gs2d_bins.status):
+ *    bit 0 = tile-pair capacity overflow (lists truncated, no out-of-bounds
+ *    write), bit 1 = at least one Gaussian culled (non-finite mean or
+ *    Cholesky vector, or |l1| or |l3| < 2^-14).
+ *  - Limits: 1 <= W, H; 1 <= N <= 65536; tile in {8, 16, 32};
+ *    ceil(W/tile) * ceil(H/tile) <= 65536; 1 <= max_pairs <= 2^30.
+ */
+#ifndef GS2D_H
+#define GS2D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GS2D_OK = 0,
+  GS2D_EINVAL = -1,    /* bad shape, NULL pointer, unsupported tile size   */
+  GS2D_ENOSPACE = -2,  /* workspace smaller than gs2d_workspace_bytes()    */
+  GS2D_EOVERFLOW = -3, /* tile pairs exceeded max_pairs (fit loop only)    */
+  GS2D_EHIP = -4       /* a HIP runtime call failed                        */
+} gs2d_status;
+
+/* One frame's problem size.  max_pairs is the capacity of the tile-pair
+ * list (pairs of (tile, Gaussian) whose 3-sigma box meets the tile). */
+typedef struct {
+  int32_t W, H, N, tile, max_pairs;
+} gs2d_shape;
+
+/* Device views into a workspace after gs2d_project_bin (read-only for the
+ * caller).  Sorted pair keys are (tile << 16) | gaussian_index, ascending;
+ * tile = ty * ceil(W/tile) + tx.  tile_start[t] is the first pair whose tile
+ * is >= t (n_tiles + 1 entries).  n_pairs is min(total pairs, max_pairs). */
+typedef struct {
+  const float *geom;          /* [N][8] per-Gaussian derived geometry      */
+  const int32_t *counts;      /* [N] tiles touched by each Gaussian        */
+  const int32_t *offsets;     /* [N+1] exclusive prefix sum of counts      */
+  const uint32_t *keys;       /* [max_pairs] sorted (tile, index) keys     */
+  const int32_t *tile_start;  /* [n_tiles + 1]                             */
+  const int32_t *n_pairs;     /* scalar                                    */
+  const uint32_t *status;     /* scalar status word (bits above)           */
+  const int32_t *n_culled;    /* scalar count of culled Gaussians          */
+  int32_t n_tiles, tiles_x, tiles_y;
+} gs2d_bins;
+
+/* Adam hyper-parameters; lr per parameter group (0 = mean, 1 = Cholesky
+ * vector, 2 = colour). */
+typedef struct {
+  float lr[3];
+  float beta1, beta2, eps;
+} gs2d_adam_cfg;
+
+typedef struct {
+  int32_t iters;        /* maximum iterations                               */
+  int32_t check_every;  /* iterations per launched chunk / PSNR check (>=1) */
+  float psnr_target;    /* stop at the first check with PSNR >= target; <=0 off */
+  int32_t use_graph;    /* 1: capture each chunk in a hipGraph and replay    */
+  gs2d_adam_cfg adam;
+} gs2d_fit_opts;
+
+typedef struct {
+  int32_t iters_run;        /* iterations executed                          */
+  int32_t iter_hit_target;  /* first iteration whose loss met the target, -1 */
+  float final_loss;         /* MSE of the last evaluated iteration          */
+  float final_psnr;
+  double seconds;           /* host wall time of the call                   */
+  uint32_t status;          /* workspace status word at return              */
+  int32_t n_culled;
+} gs2d_fit_stats;
+
+/* Human-readable name of a status code (static string). */
+const char *gs2d_status_str(int status);
+
+/* Bytes of workspace needed for `shape`; 0 if the shape is invalid. */
+size_t gs2d_workspace_bytes(const gs2d_shape *shape);
+
+/* Fill `out` with device views into workspace `ws`.  Host-only. */
+int gs2d_bins_view(const gs2d_shape *shape, void *ws, size_t ws_bytes, gs2d_bins *out);
+
+/* Projection and tile binning (the setup a tile-based rasteriser needs,
+ * Sec. 3.1, rendering of Eq. 2): per Gaussian the culling test, inverse
+ * diagonal of L, the 3-sigma box (half-widths 3|l1| and 3 sqrt(l2^2+l3^2)),
+ * the tile rectangle it meets and its tile count; an exclusive scan of the
+ * counts; one key (tile << 16 | index) per (Gaussian, tile); a stable device
+ * radix sort of the keys by tile; and the per-tile ranges.  The result is
+ * bit-identical for identical inputs.  Box and rectangle are evaluated in
+ * FP32 without contraction, in the order
+ *   r = sqrt(l2*l2 + l3*l3); ry = 3*r; rx = 3*|l1|; xlo = mx - rx; ...
+ *   tx0 = max(floor(xlo/tile), 0); tx1 = min(floor(xhi/tile), TX-1) ...
+ * xy, chol: device [N][2], [N][3].  ws: workspace. */
+int gs2d_project_bin(const gs2d_shape *shape, const float *xy, const float *chol,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* Forward render of Eq. 2 over the tile lists built by gs2d_project_bin
+ * (which must have run on the same workspace with the same xy/chol).
+ *   rgb     [N][3] colours c'.
+ *   target  [3][H][W] or NULL.  With a target the call also computes the
+ *           residual r = C - target, dl_dimg = 2 r / (3HW) and the MSE.
+ *   img     [3][H][W] output or NULL (not written).
+ *   dl_dimg [3][H][W] output or NULL; requires target.
+ *   loss    device float scalar output (MSE) or NULL; requires target.
+ * Pixels with no Gaussian in range render exactly 0. */
+int gs2d_render_fwd(const gs2d_shape *shape, void *ws, size_t ws_bytes, const float *rgb,
+                    const float *target, float *img, float *dl_dimg, float *loss,
+                    void *stream);
+
+/* Backward render: given g = dLoss/dC ([3][H][W]), the gradients of the loss
+ * w.r.t. every parameter, by the chain rule through Eq. 2 and Eq. 1 with the
+ * cutoff indicator held fixed:
+ *   dL/dc'_k = sum_p g_k w;  with s = (g . c') w, u = L^-1 d, v = L^-T u:
+ *   dL/dmu = s v;  dL/dl1 = s v1 u1;  dL/dl2 = s v2 u1;  dL/dl3 = s v2 u2.
+ * g_xy [N][2], g_chol [N][3], g_rgb [N][3] are overwritten.  Per-tile partial
+ * sums are reduced across the wavefront first and then added with atomics,
+ * so the summation order (and the last bits) may vary between runs. */
+int gs2d_render_bwd(const gs2d_shape *shape, void *ws, size_t ws_bytes, const float *rgb,
+                    const float *dl_dimg, float *g_xy, float *g_chol, float *g_rgb,
+                    void *stream);
+
+/* One Adam step (Kingma & Ba, bias-corrected, eps added to sqrt(v_hat)) on
+ * all 8N parameters, the optimiser of the fitting loop (Sec. 3.2, encoding
+ * optimisation steps).  m, v: [8N] moments laid out as [xy 2N | chol 3N |
+ * rgb 3N].  step: device int32[2]; step[0] is the number of steps taken so
+ * far (read, and incremented by one by this call), step[1] is scratch that
+ * must be 0 between calls.  active: [N] uint8 or NULL; a Gaussian with
+ * active[n] == 0 keeps its parameters and moments bit-for-bit.
+ * zero_grads != 0 clears g_* after reading them. */
+int gs2d_adam_step(int32_t N, float *xy, float *chol, float *rgb, float *g_xy, float *g_chol,
+                   float *g_rgb, float *m, float *v, int32_t *step, const gs2d_adam_cfg *cfg,
+                   const uint8_t *active, int32_t zero_grads, void *stream);
+
+/* The whole fitting loop for one frame: repeat {project+bin, forward render
+ * with fused loss and backward render in one pass per tile, Adam} for
+ * opts->iters iterations or until the PSNR of an evaluated iteration reaches
+ * opts->psnr_target (checked every opts->check_every iterations).
+ *   target [3][H][W]; xy/chol/rgb updated in place; m, v [8N] and step[2] as
+ *   for gs2d_adam_step (continue from their contents: zero them for a cold
+ *   start);
+ *   loss_trace [trace_len] device floats: loss_trace[k] = MSE at the
+ *   parameters before update k, k = step[0] at that iteration (entries the
+ *   call does not reach are left untouched); trace_len must exceed
+ *   step[0] + opts->iters.
+ * Synchronises with `stream` on entry, runs on an internal stream, and
+ * returns after the work is complete.  Returns GS2D_EOVERFLOW if the
+ * tile-pair capacity was exceeded. */
+int gs2d_fit_frame(const gs2d_shape *shape, const float *target, float *xy, float *chol,
+                   float *rgb, float *m, float *v, int32_t *step, float *loss_trace,
+                   int32_t trace_len, void *ws, size_t ws_bytes, const gs2d_fit_opts *opts,
+                   gs2d_fit_stats *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS2D_H */

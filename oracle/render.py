@@ -124,3 +124,28 @@ def count_pairs_in_cutoff(xy, chol, H: int, W: int) -> int:
             continue
         total += int(np.count_nonzero(t[3] <= CUTOFF_Q))
     return total
+
+
+def render_pixels(xy, chol, rgb, px, py):
+    """Eq. 2 at selected pixels only: for pixel (px[i], py[i]) the sum over
+    every non-culled Gaussian (brute force, vectorised over Gaussians).
+
+    Returns dict(img [3,P], abs [3,P], amb [3,P]).
+    """
+    xy, chol, rgb = _as64(xy, chol, rgb)
+    live = ~culled(xy, chol)
+    xy, chol, rgb = xy[live], chol[live], rgb[live]
+    l1, l2, l3 = chol[:, 0], chol[:, 1], chol[:, 2]
+    P = len(px)
+    img = np.zeros((3, P))
+    aab = np.zeros((3, P))
+    amb = np.zeros((3, P))
+    for i in range(P):
+        q = mahalanobis_sq(px[i] + 0.5 - xy[:, 0], py[i] + 0.5 - xy[:, 1], l1, l2, l3)
+        e = np.exp(-0.5 * q)
+        w = np.where(q <= CUTOFF_Q, e, 0.0)
+        band = np.abs(q - CUTOFF_Q) <= AMBIGUOUS_BAND
+        img[:, i] = rgb.T @ w
+        aab[:, i] = np.abs(rgb).T @ w
+        amb[:, i] = np.abs(rgb).T @ np.where(band, e, 0.0)
+    return {"img": img, "abs": aab, "amb": amb}

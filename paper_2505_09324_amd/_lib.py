@@ -1,0 +1,245 @@
+"""ctypes binding of libgs2d.so (the C ABI in include/gs2d.h).
+
+Argument marshalling only: every call checks tensor devices, dtypes, shapes
+and contiguity, converts them to raw device pointers and passes the current
+torch stream.  All computation happens in the HIP library; if the library
+is missing the import of any entry point raises instead of falling back.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_float, c_int32, c_size_t, c_uint32, c_void_p, c_char_p, c_double
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgs2d.so")
+
+GS2D_OK, GS2D_EINVAL, GS2D_ENOSPACE, GS2D_EOVERFLOW, GS2D_EHIP = 0, -1, -2, -3, -4
+STATUS_OVERFLOW, STATUS_CULLED = 1, 2
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("W", c_int32), ("H", c_int32), ("N", c_int32), ("tile", c_int32),
+                ("max_pairs", c_int32)]
+
+
+class Bins(ctypes.Structure):
+    _fields_ = [("geom", c_void_p), ("counts", c_void_p), ("offsets", c_void_p),
+                ("keys", c_void_p), ("tile_start", c_void_p), ("n_pairs", c_void_p),
+                ("status", c_void_p), ("n_culled", c_void_p),
+                ("n_tiles", c_int32), ("tiles_x", c_int32), ("tiles_y", c_int32)]
+
+
+class AdamCfg(ctypes.Structure):
+    _fields_ = [("lr", c_float * 3), ("beta1", c_float), ("beta2", c_float), ("eps", c_float)]
+
+
+class FitOpts(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("check_every", c_int32), ("psnr_target", c_float),
+                ("use_graph", c_int32), ("adam", AdamCfg)]
+
+
+class FitStats(ctypes.Structure):
+    _fields_ = [("iters_run", c_int32), ("iter_hit_target", c_int32), ("final_loss", c_float),
+                ("final_psnr", c_float), ("seconds", c_double), ("status", c_uint32),
+                ("n_culled", c_int32)]
+
+
+class GS2DError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} failed: {status_str(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "gs2d_status_str": (c_char_p, [c_int32]),
+    "gs2d_workspace_bytes": (c_size_t, [POINTER(Shape)]),
+    "gs2d_bins_view": (c_int32, [POINTER(Shape), c_void_p, c_size_t, POINTER(Bins)]),
+    "gs2d_project_bin": (c_int32, [POINTER(Shape), c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gs2d_render_fwd": (c_int32, [POINTER(Shape), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_void_p]),
+    "gs2d_render_bwd": (c_int32, [POINTER(Shape), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_void_p]),
+    "gs2d_adam_step": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, POINTER(AdamCfg), c_void_p, c_int32,
+                                 c_void_p]),
+    "gs2d_fit_frame": (c_int32, [POINTER(Shape), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_size_t,
+                                 POINTER(FitOpts), POINTER(FitStats), c_void_p]),
+}
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def lib():
+    """Load libgs2d.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2505_09324_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_str(code: int) -> str:
+    return lib().gs2d_status_str(int(code)).decode()
+
+
+def _check(fn, code):
+    if code != GS2D_OK:
+        raise GS2DError(fn, code)
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, name, dtype=torch.float32, shape=None, allow_none=False):
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return c_void_p(t.data_ptr())
+
+
+def make_shape(W, H, N, tile=16, max_pairs=None) -> Shape:
+    if max_pairs is None:
+        max_pairs = default_max_pairs(W, H, N, tile)
+    return Shape(int(W), int(H), int(N), int(tile), int(max_pairs))
+
+
+def default_max_pairs(W, H, N, tile) -> int:
+    tx, ty = -(-W // tile), -(-H // tile)
+    return int(min(1 << 30, max(1 << 16, 16 * N + 4 * tx * ty)))
+
+
+def workspace_bytes(shape: Shape) -> int:
+    n = lib().gs2d_workspace_bytes(ctypes.byref(shape))
+    if n == 0:
+        raise GS2DError("gs2d_workspace_bytes", GS2D_EINVAL)
+    return int(n)
+
+
+def alloc_workspace(shape: Shape, device="cuda") -> torch.Tensor:
+    return torch.empty(workspace_bytes(shape), dtype=torch.uint8, device=device)
+
+
+def bins_view(shape: Shape, ws: torch.Tensor) -> Bins:
+    b = Bins()
+    _check("gs2d_bins_view", lib().gs2d_bins_view(ctypes.byref(shape), _ptr(ws, "ws", torch.uint8),
+                                                  ws.numel(), ctypes.byref(b)))
+    return b
+
+
+def _slice(ws: torch.Tensor, ptr: int, count: int, dtype) -> torch.Tensor:
+    off = ptr - ws.data_ptr()
+    nbytes = count * torch.empty((), dtype=dtype).element_size()
+    return ws[off:off + nbytes].view(dtype)
+
+
+def read_bins(shape: Shape, ws: torch.Tensor) -> dict:
+    """Copies of the binning results (host tensors)."""
+    b = bins_view(shape, ws)
+    n_pairs = int(_slice(ws, b.n_pairs, 1, torch.int32).item())
+    keys = _slice(ws, b.keys, n_pairs, torch.int32).cpu().numpy().view("uint32")
+    return {
+        "n_pairs": n_pairs,
+        "keys": keys,
+        "pair_ids": (keys & 0xFFFF).astype("int64"),
+        "pair_tiles": (keys >> 16).astype("int64"),
+        "tile_start": _slice(ws, b.tile_start, b.n_tiles + 1, torch.int32).cpu().numpy().astype("int64"),
+        "counts": _slice(ws, b.counts, shape.N, torch.int32).cpu().numpy().astype("int64"),
+        "offsets": _slice(ws, b.offsets, shape.N + 1, torch.int32).cpu().numpy().astype("int64"),
+        "status": int(_slice(ws, b.status, 1, torch.int32).item()),
+        "n_culled": int(_slice(ws, b.n_culled, 1, torch.int32).item()),
+        "n_tiles": b.n_tiles, "TX": b.tiles_x, "TY": b.tiles_y,
+    }
+
+
+def project_bin(shape: Shape, xy, chol, ws):
+    N = shape.N
+    _check("gs2d_project_bin", lib().gs2d_project_bin(
+        ctypes.byref(shape), _ptr(xy, "xy", shape=(N, 2)), _ptr(chol, "chol", shape=(N, 3)),
+        _ptr(ws, "ws", torch.uint8), ws.numel(), _stream()))
+
+
+def render_fwd(shape: Shape, ws, rgb, target=None, img=None, dl_dimg=None, loss=None):
+    N, H, W = shape.N, shape.H, shape.W
+    _check("gs2d_render_fwd", lib().gs2d_render_fwd(
+        ctypes.byref(shape), _ptr(ws, "ws", torch.uint8), ws.numel(),
+        _ptr(rgb, "rgb", shape=(N, 3)),
+        _ptr(target, "target", shape=(3, H, W), allow_none=True),
+        _ptr(img, "img", shape=(3, H, W), allow_none=True),
+        _ptr(dl_dimg, "dl_dimg", shape=(3, H, W), allow_none=True),
+        _ptr(loss, "loss", shape=(), allow_none=True), _stream()))
+
+
+def render_bwd(shape: Shape, ws, rgb, dl_dimg, g_xy, g_chol, g_rgb):
+    N, H, W = shape.N, shape.H, shape.W
+    _check("gs2d_render_bwd", lib().gs2d_render_bwd(
+        ctypes.byref(shape), _ptr(ws, "ws", torch.uint8), ws.numel(),
+        _ptr(rgb, "rgb", shape=(N, 3)), _ptr(dl_dimg, "dl_dimg", shape=(3, H, W)),
+        _ptr(g_xy, "g_xy", shape=(N, 2)), _ptr(g_chol, "g_chol", shape=(N, 3)),
+        _ptr(g_rgb, "g_rgb", shape=(N, 3)), _stream()))
+
+
+def adam_cfg(lr=(1e-2, 1e-2, 1e-2), beta1=0.9, beta2=0.999, eps=1e-8) -> AdamCfg:
+    if isinstance(lr, (int, float)):
+        lr = (lr, lr, lr)
+    return AdamCfg((c_float * 3)(*lr), beta1, beta2, eps)
+
+
+def adam_step(xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg: AdamCfg, active=None,
+              zero_grads=False):
+    N = xy.shape[0]
+    _check("gs2d_adam_step", lib().gs2d_adam_step(
+        N, _ptr(xy, "xy", shape=(N, 2)), _ptr(chol, "chol", shape=(N, 3)),
+        _ptr(rgb, "rgb", shape=(N, 3)), _ptr(g_xy, "g_xy", shape=(N, 2)),
+        _ptr(g_chol, "g_chol", shape=(N, 3)), _ptr(g_rgb, "g_rgb", shape=(N, 3)),
+        _ptr(m, "m", shape=(8 * N,)), _ptr(v, "v", shape=(8 * N,)),
+        _ptr(step, "step", torch.int32, shape=(2,)), ctypes.byref(cfg),
+        _ptr(active, "active", torch.uint8, shape=(N,), allow_none=True), int(bool(zero_grads)),
+        _stream()))
+
+
+def fit_opts(iters, check_every=50, psnr_target=0.0, use_graph=True, cfg=None) -> FitOpts:
+    return FitOpts(int(iters), int(check_every), float(psnr_target), int(bool(use_graph)),
+                   cfg if cfg is not None else adam_cfg())
+
+
+def fit_frame(shape: Shape, target, xy, chol, rgb, m, v, step, loss_trace, ws, opts: FitOpts,
+              check=True) -> FitStats:
+    N, H, W = shape.N, shape.H, shape.W
+    stats = FitStats()
+    code = lib().gs2d_fit_frame(
+        ctypes.byref(shape), _ptr(target, "target", shape=(3, H, W)),
+        _ptr(xy, "xy", shape=(N, 2)), _ptr(chol, "chol", shape=(N, 3)),
+        _ptr(rgb, "rgb", shape=(N, 3)), _ptr(m, "m", shape=(8 * N,)), _ptr(v, "v", shape=(8 * N,)),
+        _ptr(step, "step", torch.int32, shape=(2,)), _ptr(loss_trace, "loss_trace"),
+        int(loss_trace.numel()), _ptr(ws, "ws", torch.uint8), ws.numel(), ctypes.byref(opts),
+        ctypes.byref(stats), _stream())
+    if check:
+        _check("gs2d_fit_frame", code)
+    stats.code = code
+    return stats

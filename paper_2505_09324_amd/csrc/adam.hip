@@ -1,0 +1,135 @@
+// Fused Adam update over all 8N Gaussian parameters (the optimisation step
+// of the fitting loop), plus small fill kernels.
+//
+//   t = step[0] + 1
+//   m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2
+//   theta <- theta - lr_group * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps)
+//
+// step[0] stays in device memory so a captured graph can replay the update:
+// every block reads it first, then takes a ticket from step[1]; the block
+// holding the last ticket (all others have read step[0] by then) stores t and
+// clears the ticket.  Optionally the kernel clears the gradients after
+// reading them (ready for the next backward pass's atomics), and block 0
+// reduces the per-tile loss partials of this iteration into loss_trace[t-1].
+#include "gs2d_internal.h"
+
+namespace gs2d {
+
+__global__ void __launch_bounds__(256)
+k_adam(int N, float *__restrict__ xy, float *__restrict__ chol, float *__restrict__ rgb,
+       float *__restrict__ g_xy, float *__restrict__ g_chol, float *__restrict__ g_rgb,
+       float *__restrict__ m, float *__restrict__ v, int32_t *__restrict__ step, float lr0,
+       float lr1, float lr2, float b1, float b2, float eps, const uint8_t *__restrict__ active,
+       int zero_grads, const float *__restrict__ loss_part, int n_part, float loss_scale,
+       float *__restrict__ loss_trace, int trace_len) {
+  __shared__ float s_bc1, s_bc2;
+  __shared__ int s_t;
+  __shared__ double red[4];
+  if (threadIdx.x == 0) {
+    const int t = step[0] + 1;
+    s_t = t;
+    s_bc1 = (float)(1.0 - pow((double)b1, (double)t));
+    s_bc2 = (float)(1.0 - pow((double)b2, (double)t));
+  }
+  __syncthreads();
+  const int t = s_t;
+  const float bc1 = s_bc1, bc2 = s_bc2;
+  const int total = 8 * N;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    float *p, *g;
+    float lr;
+    int n;
+    if (e < 2 * N) {
+      p = xy + e;
+      g = g_xy + e;
+      lr = lr0;
+      n = e >> 1;
+    } else if (e < 5 * N) {
+      const int i = e - 2 * N;
+      p = chol + i;
+      g = g_chol + i;
+      lr = lr1;
+      n = i / 3;
+    } else {
+      const int i = e - 5 * N;
+      p = rgb + i;
+      g = g_rgb + i;
+      lr = lr2;
+      n = i / 3;
+    }
+    const float gr = *g;
+    if (zero_grads) *g = 0.f;
+    if (active && active[n] == 0) continue;
+    const float mm = b1 * m[e] + (1.f - b1) * gr;
+    const float vv = b2 * v[e] + (1.f - b2) * gr * gr;
+    m[e] = mm;
+    v[e] = vv;
+    *p = *p - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+  }
+  if (loss_part && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n_part; i += blockDim.x) s += (double)loss_part[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0 && t - 1 < trace_len) {
+      loss_trace[t - 1] = (float)((red[0] + red[1] + red[2] + red[3]) * (double)loss_scale);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const int ticket = atomicAdd(&step[1], 1);
+    if (ticket == (int)gridDim.x - 1) {
+      step[0] = t;
+      step[1] = 0;
+    }
+  }
+}
+
+__global__ void k_fill_zero(float *__restrict__ p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
+
+__global__ void k_fill_zero_u32(uint32_t *__restrict__ p, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+static int adam_blocks(int N) {
+  const int need = (8 * N + 255) / 256;
+  return need < 1024 ? (need > 0 ? need : 1) : 1024;
+}
+
+hipError_t launch_adam(int N, float *xy, float *chol, float *rgb, float *g_xy, float *g_chol,
+                       float *g_rgb, float *m, float *v, int32_t *step, const gs2d_adam_cfg &cfg,
+                       const uint8_t *active, int zero_grads, const float *loss_part,
+                       int n_loss_part, float loss_scale, float *loss_trace, int trace_len,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_adam, dim3(adam_blocks(N)), dim3(256), 0, st, N, xy, chol, rgb, g_xy, g_chol,
+                     g_rgb, m, v, step, cfg.lr[0], cfg.lr[1], cfg.lr[2], cfg.beta1, cfg.beta2,
+                     cfg.eps, active, zero_grads, loss_part, n_loss_part, loss_scale, loss_trace,
+                     trace_len);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(float *p, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  size_t nb = (n + 255) / 256;
+  if (nb > 2048) nb = 2048;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)nb), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero_u32(uint32_t *p, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  size_t nb = (n + 255) / 256;
+  if (nb > 2048) nb = 2048;
+  hipLaunchKernelGGL(k_fill_zero_u32, dim3((unsigned)nb), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace gs2d

@@ -1,0 +1,299 @@
+// Projection and tile binning for the tile-based rasteriser of Eq. 2.
+//
+// Per iteration:  project (one thread per Gaussian)  ->  exclusive scan of
+// tile counts (one block)  ->  key emission  ->  stable LSD radix sort of the
+// keys on their tile bits (8-bit digits; histogram, digit-offset scan,
+// stable scatter)  ->  per-tile ranges.
+//
+// Keys are (tile << 16) | gaussian_index.  Keys are emitted in ascending
+// Gaussian order and the sort is stable on the tile bits, so the result is
+// ascending in (tile, index): unique, hence bit-exact between runs.
+//
+// The box/rectangle arithmetic uses the _rn intrinsics so that no multiply
+// and add are contracted: the tile decision must match its FP32
+// specification exactly.
+#include "gs2d_internal.h"
+
+namespace gs2d {
+
+// ---------------------------------------------------------------- project --
+// counts[n] = number of tiles met, or -1 for a culled Gaussian (the scan
+// turns -1 into 0 and counts the culls).  geom[n] = {mx, my, 1/l1, l2, 1/l3,
+// rx, ry, 0}; rect[n] = {tx0, ty0, tx1, ty1}.
+__global__ void __launch_bounds__(256)
+k_project(int N, int TX, int TY, float inv_tile, const float *__restrict__ xy,
+          const float *__restrict__ chol, float4 *__restrict__ geom, int4 *__restrict__ rect,
+          int *__restrict__ counts) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const float mx = xy[2 * n + 0], my = xy[2 * n + 1];
+  const float l1 = chol[3 * n + 0], l2 = chol[3 * n + 1], l3 = chol[3 * n + 2];
+  const float tiny = 6.103515625e-05f;  // 2^-14
+  const bool finite = isfinite(mx) && isfinite(my) && isfinite(l1) && isfinite(l2) && isfinite(l3);
+  if (!finite || !(fabsf(l1) >= tiny) || !(fabsf(l3) >= tiny)) {
+    counts[n] = -1;
+    rect[n] = make_int4(0, 0, -1, -1);
+    geom[2 * n + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
+    geom[2 * n + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  const float a = __fmul_rn(l2, l2);
+  const float b = __fmul_rn(l3, l3);
+  const float s = __fadd_rn(a, b);
+  const float r = __fsqrt_rn(s);
+  const float ry = __fmul_rn(3.0f, r);
+  const float rx = __fmul_rn(3.0f, fabsf(l1));
+  const float xlo = __fsub_rn(mx, rx), xhi = __fadd_rn(mx, rx);
+  const float ylo = __fsub_rn(my, ry), yhi = __fadd_rn(my, ry);
+  // division by a power of two == multiplication by its exact reciprocal
+  const float fx0 = floorf(__fmul_rn(xlo, inv_tile)), fx1 = floorf(__fmul_rn(xhi, inv_tile));
+  const float fy0 = floorf(__fmul_rn(ylo, inv_tile)), fy1 = floorf(__fmul_rn(yhi, inv_tile));
+  const float lastx = (float)(TX - 1), lasty = (float)(TY - 1);
+  int cnt = 0;
+  int4 rc = make_int4(0, 0, -1, -1);
+  if (!(fx1 < 0.f || fx0 > lastx || fy1 < 0.f || fy0 > lasty)) {
+    rc.x = (int)fmaxf(fx0, 0.f);
+    rc.z = (int)fminf(fx1, lastx);
+    rc.y = (int)fmaxf(fy0, 0.f);
+    rc.w = (int)fminf(fy1, lasty);
+    cnt = (rc.z - rc.x + 1) * (rc.w - rc.y + 1);
+  }
+  counts[n] = cnt;
+  rect[n] = rc;
+  geom[2 * n + 0] = make_float4(mx, my, __fdiv_rn(1.0f, l1), l2);
+  geom[2 * n + 1] = make_float4(__fdiv_rn(1.0f, l3), rx, ry, 0.f);
+}
+
+// ------------------------------------------------------------ block scan --
+// Exclusive scan of one 64-bit value per thread across a block of NT
+// threads.  `lds` holds NT/64 entries.  Returns the exclusive prefix and the
+// block total.
+template <int NT>
+__device__ inline long long block_exclusive_scan(long long v, long long *total, long long *lds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int NW = NT / 64;
+  long long x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    long long y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    long long s = (lane < NW) ? lds[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      long long y = __shfl_up(s, o, 64);
+      if (lane >= o) s += y;
+    }
+    if (lane < NW) lds[lane] = s;
+  }
+  __syncthreads();
+  const long long before = (w > 0) ? lds[w - 1] : 0;
+  *total = lds[NW - 1];
+  __syncthreads();
+  return before + x - v;
+}
+
+// ------------------------------------------------------------ count scan --
+// One block.  offsets[n] = min(sum_{m<n} max(counts[m],0), max_pairs);
+// offsets[N] and misc[MISC_N_PAIRS] = min(total, max_pairs); status bits.
+__global__ void __launch_bounds__(SCAN_BLOCK)
+k_scan_counts(int N, int max_pairs, const int *__restrict__ counts, int *__restrict__ offsets,
+              int *__restrict__ misc) {
+  __shared__ long long lds[SCAN_BLOCK / 64];
+  __shared__ int culled_w[SCAN_BLOCK / 64];
+  const int per = (N + SCAN_BLOCK - 1) / SCAN_BLOCK;
+  const int beg = min(N, threadIdx.x * per), end = min(N, beg + per);
+  long long sum = 0;
+  int culled = 0;
+  for (int i = beg; i < end; ++i) {
+    const int c = counts[i];
+    culled += (c < 0);
+    sum += (c > 0) ? c : 0;
+  }
+  long long total;
+  long long run = block_exclusive_scan<SCAN_BLOCK>(sum, &total, lds);
+  for (int i = beg; i < end; ++i) {
+    offsets[i] = (int)min(run, (long long)max_pairs);
+    const int c = counts[i];
+    run += (c > 0) ? c : 0;
+  }
+  // culled count: wave sums then one thread
+  for (int o = 32; o > 0; o >>= 1) culled += __shfl_xor(culled, o, 64);
+  if ((threadIdx.x & 63) == 0) culled_w[threadIdx.x >> 6] = culled;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int c = 0;
+    for (int w = 0; w < SCAN_BLOCK / 64; ++w) c += culled_w[w];
+    const int np = (int)min(total, (long long)max_pairs);
+    offsets[N] = np;
+    const uint32_t st = (total > (long long)max_pairs ? STATUS_OVERFLOW : 0u) |
+                        (c > 0 ? STATUS_CULLED : 0u);
+    misc[MISC_N_PAIRS] = np;
+    misc[MISC_STATUS] = (int)st;
+    misc[MISC_N_CULLED] = c;
+    misc[MISC_STICKY] |= (int)st;
+  }
+}
+
+// ------------------------------------------------------------- emit keys --
+// One thread per Gaussian writes its keys, row-major over its rectangle, to
+// [offsets[n], offsets[n+1]) (already clamped to the capacity).
+__global__ void __launch_bounds__(256)
+k_emit_keys(int N, int TX, const int4 *__restrict__ rect, const int *__restrict__ offsets,
+            uint32_t *__restrict__ keys) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int beg = offsets[n], end = offsets[n + 1];
+  if (end <= beg) return;
+  const int4 rc = rect[n];
+  int k = beg;
+  for (int ty = rc.y; ty <= rc.w && k < end; ++ty) {
+    for (int tx = rc.x; tx <= rc.z && k < end; ++tx, ++k) {
+      keys[k] = ((uint32_t)(ty * TX + tx) << 16) | (uint32_t)n;
+    }
+  }
+}
+
+// ------------------------------------------------------------ radix sort --
+// Chunk of the key array owned by sort block b (a multiple of SORT_BLOCK).
+__device__ inline void sort_chunk(int n, int G, int b, int *beg, int *end) {
+  int chunk = (n + G - 1) / G;
+  chunk = (chunk + SORT_BLOCK - 1) / SORT_BLOCK * SORT_BLOCK;
+  *beg = min(n, b * chunk);
+  *end = min(n, *beg + chunk);
+}
+
+// Pass histogram: hist[d * G + b] = keys of digit d in chunk b.
+__global__ void __launch_bounds__(SORT_BLOCK)
+k_radix_hist(const uint32_t *__restrict__ keys, const int *__restrict__ misc, int shift, int G,
+             uint32_t *__restrict__ hist) {
+  __shared__ uint32_t h[RADIX];
+  const int b = blockIdx.x;
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int beg, end;
+  sort_chunk(misc[MISC_N_PAIRS], G, b, &beg, &end);
+  for (int i = beg + threadIdx.x; i < end; i += SORT_BLOCK)
+    atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
+  __syncthreads();
+  hist[threadIdx.x * G + b] = h[threadIdx.x];
+}
+
+// Exclusive scan of the G*RADIX histogram in (digit, block) order, in place.
+__global__ void __launch_bounds__(SCAN_BLOCK)
+k_radix_scan(uint32_t *__restrict__ hist, int total_entries) {
+  __shared__ long long lds[SCAN_BLOCK / 64];
+  const int per = (total_entries + SCAN_BLOCK - 1) / SCAN_BLOCK;
+  const int beg = min(total_entries, threadIdx.x * per), end = min(total_entries, beg + per);
+  long long sum = 0;
+  for (int i = beg; i < end; ++i) sum += hist[i];
+  long long total;
+  long long run = block_exclusive_scan<SCAN_BLOCK>(sum, &total, lds);
+  for (int i = beg; i < end; ++i) {
+    const uint32_t c = hist[i];
+    hist[i] = (uint32_t)run;
+    run += c;
+  }
+}
+
+// Stable scatter of chunk b: in input order, each key goes to
+// off[digit] + (earlier keys of the same digit in this chunk).
+__global__ void __launch_bounds__(SORT_BLOCK)
+k_radix_scatter(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                const int *__restrict__ misc, int shift, int G, const uint32_t *__restrict__ hist) {
+  constexpr int NW = SORT_BLOCK / 64;
+  __shared__ uint32_t off[RADIX];
+  __shared__ uint32_t wcnt[NW][RADIX];
+  __shared__ uint32_t wpre[NW][RADIX];
+  const int b = blockIdx.x, tid = threadIdx.x, w = tid >> 6;
+  off[tid] = hist[tid * G + b];
+#pragma unroll
+  for (int k = 0; k < NW; ++k) wcnt[k][tid] = 0;
+  __syncthreads();
+  int beg, end;
+  sort_chunk(misc[MISC_N_PAIRS], G, b, &beg, &end);
+  const unsigned long long lt = lanemask_lt();
+  for (int base = beg; base < end; base += SORT_BLOCK) {
+    const int i = base + tid;
+    const bool valid = i < end;
+    const uint32_t key = valid ? in[i] : 0u;
+    const uint32_t d = (key >> shift) & (RADIX - 1);
+    // lanes of this wave holding the same digit
+    unsigned long long match = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < RADIX_BITS; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const unsigned long long bal = __ballot(on);
+      match &= on ? bal : ~bal;
+    }
+    const uint32_t rank = (uint32_t)__popcll(match & lt);
+    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(match);
+    __syncthreads();
+    {
+      uint32_t s = 0;
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        wpre[k][tid] = s;
+        s += wcnt[k][tid];
+      }
+      wcnt[0][tid] = s;  // reuse row 0 as the sub-tile total of digit tid
+    }
+    __syncthreads();
+    if (valid) out[off[d] + wpre[w][d] + rank] = key;
+    __syncthreads();
+    off[tid] += wcnt[0][tid];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) wcnt[k][tid] = 0;
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------- ranges --
+// tile_start[t] = first index i with tile(keys[i]) >= t, for t in [0, n_tiles].
+__global__ void __launch_bounds__(256)
+k_tile_ranges(const uint32_t *__restrict__ keys, const int *__restrict__ misc, int n_tiles,
+              int *__restrict__ tile_start) {
+  const int n = misc[MISC_N_PAIRS];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
+    const int cur = (i < n) ? (int)(keys[i] >> 16) : n_tiles;
+    const int prev = (i > 0) ? (int)(keys[i - 1] >> 16) : -1;
+    for (int t = prev + 1; t <= cur && t <= n_tiles; ++t) tile_start[t] = i;
+  }
+}
+
+hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, void *ws,
+                          hipStream_t st) {
+  float4 *geom = at<float4>(ws, L.geom);
+  int *counts = at<int>(ws, L.counts);
+  int *offsets = at<int>(ws, L.offsets);
+  int *misc = at<int>(ws, L.misc);
+  int4 *rectp = at<int4>(ws, L.rect);
+  const int nb = (L.N + 255) / 256;
+  hipLaunchKernelGGL(k_project, dim3(nb), dim3(256), 0, st, L.N, L.TX, L.TY, 1.0f / (float)L.T, xy,
+                     chol, geom, rectp, counts);
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(SCAN_BLOCK), 0, st, L.N, L.max_pairs, counts,
+                     offsets, misc);
+  uint32_t *ka = at<uint32_t>(ws, L.keys_a), *kb = at<uint32_t>(ws, L.keys_b);
+  hipLaunchKernelGGL(k_emit_keys, dim3(nb), dim3(256), 0, st, L.N, L.TX, rectp, offsets, ka);
+  uint32_t *hist = at<uint32_t>(ws, L.hist);
+  uint32_t *src = ka, *dst = kb;
+  for (int p = 0; p < L.sort_passes; ++p) {
+    const int shift = 16 + RADIX_BITS * p;
+    hipLaunchKernelGGL(k_radix_hist, dim3(L.sort_blocks), dim3(SORT_BLOCK), 0, st, src, misc, shift,
+                       L.sort_blocks, hist);
+    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(SCAN_BLOCK), 0, st, hist, L.sort_blocks * RADIX);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(L.sort_blocks), dim3(SORT_BLOCK), 0, st, src, dst, misc,
+                       shift, L.sort_blocks, hist);
+    uint32_t *t = src;
+    src = dst;
+    dst = t;
+  }
+  hipLaunchKernelGGL(k_tile_ranges, dim3(512), dim3(256), 0, st, src, misc, L.n_tiles,
+                     at<int>(ws, L.tile_start));
+  return hipGetLastError();
+}
+
+}  // namespace gs2d

@@ -1,0 +1,85 @@
+// Internal definitions shared by the gs2d HIP translation units: workspace
+// layout, kernel declarations and small device helpers.  Not part of the
+// public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "gs2d.h"
+
+namespace gs2d {
+
+// Slots of the small integer block at the end of the workspace.
+enum MiscSlot : int {
+  MISC_N_PAIRS = 0,   // min(total pairs, max_pairs)
+  MISC_STATUS = 1,    // status bits of the last binning
+  MISC_N_CULLED = 2,  // culled Gaussians of the last binning
+  MISC_STICKY = 3,    // OR of MISC_STATUS over a fit call
+  MISC_COUNT = 64
+};
+
+constexpr uint32_t STATUS_OVERFLOW = 1u;
+constexpr uint32_t STATUS_CULLED = 2u;
+
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int SORT_BLOCK = 256;       // threads per sort block (4 waves)
+constexpr int SORT_MAX_BLOCKS = 256;  // sort blocks (each owns one key chunk)
+constexpr int SCAN_BLOCK = 1024;
+
+// Byte offsets of every array inside one frame's workspace.
+struct Layout {
+  int W, H, N, T, max_pairs;
+  int TX, TY, n_tiles;
+  int sort_blocks;     // G: chunks of the key array, one sort block each
+  int sort_passes;     // 8-bit digit passes over the tile bits
+  size_t geom, rect, counts, offsets, keys_a, keys_b, hist, tile_start, loss_part, grads, misc,
+      total;
+  // the buffer holding the sorted keys after all passes
+  size_t keys_sorted() const { return (sort_passes & 1) ? keys_b : keys_a; }
+};
+
+// Returns false if the shape is outside the supported limits.
+bool make_layout(const gs2d_shape &s, Layout *L);
+
+template <typename T>
+inline T *at(void *ws, size_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+// ---- kernels launched by the host code (defined in the .hip files) ----
+
+// Binning (bin.hip).  Each enqueues on `st`.
+hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, void *ws,
+                          hipStream_t st);
+
+// Raster (raster.hip).
+hipError_t launch_render_fwd(const Layout &L, void *ws, const float *rgb, const float *target,
+                             float *img, float *dl_dimg, hipStream_t st);
+hipError_t launch_render_bwd(const Layout &L, void *ws, const float *rgb, const float *dl_dimg,
+                             float *g_xy, float *g_chol, float *g_rgb, hipStream_t st);
+hipError_t launch_render_fused(const Layout &L, void *ws, const float *rgb, const float *target,
+                               float *g_xy, float *g_chol, float *g_rgb, hipStream_t st);
+hipError_t launch_loss_reduce(const Layout &L, void *ws, float *loss, hipStream_t st);
+
+// Optimiser (adam.hip).  loss_part/loss_trace may be NULL; when given, the
+// kernel also reduces the per-tile loss partials into loss_trace[step].
+hipError_t launch_adam(int N, float *xy, float *chol, float *rgb, float *g_xy, float *g_chol,
+                       float *g_rgb, float *m, float *v, int32_t *step, const gs2d_adam_cfg &cfg,
+                       const uint8_t *active, int zero_grads, const float *loss_part,
+                       int n_loss_part, float loss_scale, float *loss_trace, int trace_len,
+                       hipStream_t st);
+
+hipError_t launch_fill_zero(float *p, size_t n, hipStream_t st);
+hipError_t launch_fill_zero_u32(uint32_t *p, size_t n, hipStream_t st);
+
+// ---- device helpers ----
+
+__device__ inline unsigned long long lanemask_lt() {
+  const unsigned lane = __lane_id();
+  return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+}
+
+}  // namespace gs2d
