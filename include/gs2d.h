@@ -144,12 +144,32 @@ int gs2d_render_bwd(const gs2d_shape *shape, void *ws, size_t ws_bytes, const fl
                     const float *dl_dimg, float *g_xy, float *g_chol, float *g_rgb,
                     void *stream);
 
+/* Forward render, MSE and backward render in one pass per tile, the form the
+ * fitting loop runs: Eq. 2 is an order-free sum and every Gaussian that
+ * reaches a pixel is in that pixel's tile list, so each tile renders its
+ * pixels, forms dL/dC = 2 (C - target) / (3HW) in registers and back-
+ * propagates it without dL/dC touching memory.  Gradients (same formulas as
+ * gs2d_render_bwd) are ADDED to g_xy/g_chol/g_rgb: zero them first for plain
+ * gradients.  loss: device float scalar (MSE) or NULL; with NULL the call is
+ * exactly one kernel launch.  Requires gs2d_project_bin on the same
+ * workspace. */
+int gs2d_render_fused(const gs2d_shape *shape, void *ws, size_t ws_bytes, const float *rgb,
+                      const float *target, float *g_xy, float *g_chol, float *g_rgb, float *loss,
+                      void *stream);
+
+/* Number of (pixel, Gaussian) pairs inside the frame with q <= 9 (the terms
+ * the sum of Eq. 2 contains) for the tile lists in `ws`, written to the
+ * device uint64 *out (8-byte aligned).  Used to state the algorithmic work
+ * of a render. */
+int gs2d_count_pairs(const gs2d_shape *shape, void *ws, size_t ws_bytes, uint64_t *out,
+                     void *stream);
+
 /* One Adam step (Kingma & Ba, bias-corrected, eps added to sqrt(v_hat)) on
  * all 8N parameters, the optimiser of the fitting loop (Sec. 3.2, encoding
  * optimisation steps).  m, v: [8N] moments laid out as [xy 2N | chol 3N |
- * rgb 3N].  step: device int32[2]; step[0] is the number of steps taken so
- * far (read, and incremented by one by this call), step[1] is scratch that
- * must be 0 between calls.  active: [N] uint8 or NULL; a Gaussian with
+ * rgb 3N].  step: device int32 scalar, the number of steps taken so far;
+ * the call increments it and uses the new value as t.  active: [N] uint8 or
+ * NULL; a Gaussian with
  * active[n] == 0 keeps its parameters and moments bit-for-bit.
  * zero_grads != 0 clears g_* after reading them. */
 int gs2d_adam_step(int32_t N, float *xy, float *chol, float *rgb, float *g_xy, float *g_chol,
@@ -160,7 +180,7 @@ int gs2d_adam_step(int32_t N, float *xy, float *chol, float *rgb, float *g_xy, f
  * with fused loss and backward render in one pass per tile, Adam} for
  * opts->iters iterations or until the PSNR of an evaluated iteration reaches
  * opts->psnr_target (checked every opts->check_every iterations).
- *   target [3][H][W]; xy/chol/rgb updated in place; m, v [8N] and step[2] as
+ *   target [3][H][W]; xy/chol/rgb updated in place; m, v [8N] and step as
  *   for gs2d_adam_step (continue from their contents: zero them for a cold
  *   start);
  *   loss_trace [trace_len] device floats: loss_trace[k] = MSE at the
@@ -174,6 +194,34 @@ int gs2d_fit_frame(const gs2d_shape *shape, const float *target, float *xy, floa
                    float *rgb, float *m, float *v, int32_t *step, float *loss_trace,
                    int32_t trace_len, void *ws, size_t ws_bytes, const gs2d_fit_opts *opts,
                    gs2d_fit_stats *stats, void *stream);
+
+/* Workspace bytes for gs2d_init_plain on a W x H frame (0 if invalid). */
+size_t gs2d_init_workspace_bytes(int32_t W, int32_t H);
+
+/* Content-aware ROI initialisation (Sec. 3.2.A: Gaussians seeded from the
+ * region of interest, mean at a content location, colour from the frame),
+ * in the form used for synthetic frames: centres are drawn inside the ROI
+ * with probability proportional to q + b + 1, where q = floor(1024 |grad Y|)
+ * (Y = R+G+B, central differences, FP32) and b = (sum_roi q) // (10 R), and
+ * uniformly over the non-ROI pixels outside it.  Draw i of the ROI picks the
+ * first ROI pixel (raster order) whose running weight exceeds
+ * pick_roi[i] mod (total weight); outside draw j picks the
+ * (pick_out[j] mod O)-th non-ROI pixel.  Each Gaussian gets
+ *   mu = pixel centre + jitter,  l = (s, 0, s),
+ *   s = clamp(0.5 sqrt(1 / (n_region * pmf(pixel))), 0.5, 16),
+ *   c' = frame colour * 1 / (2 pi (1/4) (1 - e^-4.5)).
+ * An empty ROI makes the whole frame the ROI; a full ROI makes outside draws
+ * uniform over the frame.
+ *   target [3][H][W] FP32, roi_mask [H][W] uint8 (non-zero = ROI);
+ *   pick_* [n] int64 >= 0 and jit_* [n][2] FP32 in [-0.5, 0.5) are the random
+ *   draws (caller-supplied);
+ *   outputs xy [N][2], chol [N][3], rgb [N][3] with N = n_roi + n_out, ROI
+ *   draws first; picked [N] int32 (nullable) receives each draw's pixel index.
+ * Synchronises `stream` once (reads the region totals) before the last launch. */
+int gs2d_init_plain(int32_t W, int32_t H, const float *target, const uint8_t *roi_mask,
+                    int32_t n_roi, const int64_t *pick_roi, const float *jit_roi, int32_t n_out,
+                    const int64_t *pick_out, const float *jit_out, float *xy, float *chol,
+                    float *rgb, int32_t *picked, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -71,6 +71,13 @@ _SIGS = {
     "gs2d_fit_frame": (c_int32, [POINTER(Shape), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_size_t,
                                  POINTER(FitOpts), POINTER(FitStats), c_void_p]),
+    "gs2d_render_fused": (c_int32, [POINTER(Shape), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p,
+                                    c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gs2d_count_pairs": (c_int32, [POINTER(Shape), c_void_p, c_size_t, c_void_p, c_void_p]),
+    "gs2d_init_workspace_bytes": (c_size_t, [c_int32, c_int32]),
+    "gs2d_init_plain": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
+                                  c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_size_t, c_void_p]),
 }
 
 
@@ -204,6 +211,26 @@ def render_bwd(shape: Shape, ws, rgb, dl_dimg, g_xy, g_chol, g_rgb):
         _ptr(g_rgb, "g_rgb", shape=(N, 3)), _stream()))
 
 
+def render_fused(shape: Shape, ws, rgb, target, g_xy, g_chol, g_rgb, loss=None):
+    """Fused forward + MSE + backward; gradients are accumulated into g_*."""
+    N, H, W = shape.N, shape.H, shape.W
+    _check("gs2d_render_fused", lib().gs2d_render_fused(
+        ctypes.byref(shape), _ptr(ws, "ws", torch.uint8), ws.numel(),
+        _ptr(rgb, "rgb", shape=(N, 3)), _ptr(target, "target", shape=(3, H, W)),
+        _ptr(g_xy, "g_xy", shape=(N, 2)), _ptr(g_chol, "g_chol", shape=(N, 3)),
+        _ptr(g_rgb, "g_rgb", shape=(N, 3)), _ptr(loss, "loss", shape=(), allow_none=True),
+        _stream()))
+
+
+def count_pairs(shape: Shape, ws) -> int:
+    """In-cutoff (pixel, Gaussian) pairs of the current tile lists."""
+    out = torch.zeros(1, dtype=torch.int64, device=ws.device)
+    _check("gs2d_count_pairs", lib().gs2d_count_pairs(
+        ctypes.byref(shape), _ptr(ws, "ws", torch.uint8), ws.numel(), _ptr(out, "out", torch.int64),
+        _stream()))
+    return int(out.item())
+
+
 def adam_cfg(lr=(1e-2, 1e-2, 1e-2), beta1=0.9, beta2=0.999, eps=1e-8) -> AdamCfg:
     if isinstance(lr, (int, float)):
         lr = (lr, lr, lr)
@@ -218,7 +245,7 @@ def adam_step(xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg: AdamCfg, acti
         _ptr(rgb, "rgb", shape=(N, 3)), _ptr(g_xy, "g_xy", shape=(N, 2)),
         _ptr(g_chol, "g_chol", shape=(N, 3)), _ptr(g_rgb, "g_rgb", shape=(N, 3)),
         _ptr(m, "m", shape=(8 * N,)), _ptr(v, "v", shape=(8 * N,)),
-        _ptr(step, "step", torch.int32, shape=(2,)), ctypes.byref(cfg),
+        _ptr(step, "step", torch.int32, shape=(1,)), ctypes.byref(cfg),
         _ptr(active, "active", torch.uint8, shape=(N,), allow_none=True), int(bool(zero_grads)),
         _stream()))
 
@@ -236,10 +263,36 @@ def fit_frame(shape: Shape, target, xy, chol, rgb, m, v, step, loss_trace, ws, o
         ctypes.byref(shape), _ptr(target, "target", shape=(3, H, W)),
         _ptr(xy, "xy", shape=(N, 2)), _ptr(chol, "chol", shape=(N, 3)),
         _ptr(rgb, "rgb", shape=(N, 3)), _ptr(m, "m", shape=(8 * N,)), _ptr(v, "v", shape=(8 * N,)),
-        _ptr(step, "step", torch.int32, shape=(2,)), _ptr(loss_trace, "loss_trace"),
+        _ptr(step, "step", torch.int32, shape=(1,)), _ptr(loss_trace, "loss_trace"),
         int(loss_trace.numel()), _ptr(ws, "ws", torch.uint8), ws.numel(), ctypes.byref(opts),
         ctypes.byref(stats), _stream())
     if check:
         _check("gs2d_fit_frame", code)
     stats.code = code
     return stats
+
+
+def init_plain(target, roi_mask, pick_roi, jit_roi, pick_out, jit_out, ws=None, picked=None):
+    """Content-aware ROI initialisation on the GPU.  Returns (xy, chol, rgb)."""
+    H, W = int(target.shape[1]), int(target.shape[2])
+    n_roi, n_out = int(pick_roi.shape[0]), int(pick_out.shape[0])
+    N = n_roi + n_out
+    need = int(lib().gs2d_init_workspace_bytes(W, H))
+    if need == 0:
+        raise GS2DError("gs2d_init_workspace_bytes", GS2D_EINVAL)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=target.device)
+    xy = torch.empty(N, 2, device=target.device)
+    chol = torch.empty(N, 3, device=target.device)
+    rgb = torch.empty(N, 3, device=target.device)
+    _check("gs2d_init_plain", lib().gs2d_init_plain(
+        W, H, _ptr(target, "target", shape=(3, H, W)),
+        _ptr(roi_mask, "roi_mask", torch.uint8, shape=(H, W)),
+        n_roi, _ptr(pick_roi, "pick_roi", torch.int64, shape=(n_roi,), allow_none=n_roi == 0),
+        _ptr(jit_roi, "jit_roi", shape=(n_roi, 2), allow_none=n_roi == 0),
+        n_out, _ptr(pick_out, "pick_out", torch.int64, shape=(n_out,), allow_none=n_out == 0),
+        _ptr(jit_out, "jit_out", shape=(n_out, 2), allow_none=n_out == 0),
+        _ptr(xy, "xy"), _ptr(chol, "chol"), _ptr(rgb, "rgb"),
+        _ptr(picked, "picked", torch.int32, shape=(N,), allow_none=True),
+        _ptr(ws, "ws", torch.uint8), ws.numel(), _stream()))
+    return xy, chol, rgb

@@ -1,16 +1,17 @@
 // Fused Adam update over all 8N Gaussian parameters (the optimisation step
 // of the fitting loop), plus small fill kernels.
 //
-//   t = step[0] + 1
+//   t = step[0]   (already incremented for this step, see below)
 //   m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2
 //   theta <- theta - lr_group * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps)
 //
-// step[0] stays in device memory so a captured graph can replay the update:
-// every block reads it first, then takes a ticket from step[1]; the block
-// holding the last ticket (all others have read step[0] by then) stores t and
-// clears the ticket.  Optionally the kernel clears the gradients after
-// reading them (ready for the next backward pass's atomics), and block 0
-// reduces the per-tile loss partials of this iteration into loss_trace[t-1].
+// The step count lives in device memory so a captured graph can replay the
+// update.  It is incremented before the Adam kernel runs, by a one-thread
+// kernel for a standalone step, or by the single-block count scan of the
+// binning inside the fitting loop, so the Adam kernel itself only reads it.
+// Optionally the kernel clears the gradients after reading them (ready for
+// the next backward pass's atomics), and block 0 reduces the per-tile loss
+// partials of this iteration into loss_trace[t-1].
 #include "gs2d_internal.h"
 
 namespace gs2d {
@@ -26,7 +27,7 @@ k_adam(int N, float *__restrict__ xy, float *__restrict__ chol, float *__restric
   __shared__ int s_t;
   __shared__ double red[4];
   if (threadIdx.x == 0) {
-    const int t = step[0] + 1;
+    const int t = step[0];
     s_t = t;
     s_bc1 = (float)(1.0 - pow((double)b1, (double)t));
     s_bc2 = (float)(1.0 - pow((double)b2, (double)t));
@@ -76,15 +77,15 @@ k_adam(int N, float *__restrict__ xy, float *__restrict__ chol, float *__restric
       loss_trace[t - 1] = (float)((red[0] + red[1] + red[2] + red[3]) * (double)loss_scale);
     }
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int ticket = atomicAdd(&step[1], 1);
-    if (ticket == (int)gridDim.x - 1) {
-      step[0] = t;
-      step[1] = 0;
-    }
-  }
+}
+
+__global__ void k_step_tick(int32_t *__restrict__ step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) step[0] += 1;
+}
+
+hipError_t launch_step_tick(int32_t *step, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_tick, dim3(1), dim3(64), 0, st, step);
+  return hipGetLastError();
 }
 
 __global__ void k_fill_zero(float *__restrict__ p, size_t n) {

@@ -160,14 +160,49 @@ int gs2d_render_bwd(const gs2d_shape *shape, void *ws, size_t ws_bytes, const fl
   }
 }
 
+int gs2d_render_fused(const gs2d_shape *shape, void *ws, size_t ws_bytes, const float *rgb,
+                      const float *target, float *g_xy, float *g_chol, float *g_rgb, float *loss,
+                      void *stream) {
+  try {
+    Layout L;
+    const int rc = check_ws(shape, ws, ws_bytes, &L);
+    if (rc != GS2D_OK) return rc;
+    if (!rgb || !target || !g_xy || !g_chol || !g_rgb) return GS2D_EINVAL;
+    hipStream_t st = as_stream(stream);
+    hipError_t e = launch_render_fused(L, ws, rgb, target, g_xy, g_chol, g_rgb, st);
+    if (e == hipSuccess && loss) e = launch_loss_reduce(L, ws, loss, st);
+    return hip_status(e);
+  } catch (...) {
+    return GS2D_EHIP;
+  }
+}
+
+int gs2d_count_pairs(const gs2d_shape *shape, void *ws, size_t ws_bytes, uint64_t *out,
+                     void *stream) {
+  try {
+    Layout L;
+    const int rc = check_ws(shape, ws, ws_bytes, &L);
+    if (rc != GS2D_OK) return rc;
+    if (!out || (reinterpret_cast<uintptr_t>(out) & 7)) return GS2D_EINVAL;
+    return hip_status(launch_count_pairs(L, ws, reinterpret_cast<unsigned long long *>(out),
+                                         as_stream(stream)));
+  } catch (...) {
+    return GS2D_EHIP;
+  }
+}
+
 int gs2d_adam_step(int32_t N, float *xy, float *chol, float *rgb, float *g_xy, float *g_chol,
                    float *g_rgb, float *m, float *v, int32_t *step, const gs2d_adam_cfg *cfg,
                    const uint8_t *active, int32_t zero_grads, void *stream) {
   try {
     if (N < 1 || !xy || !chol || !rgb || !g_xy || !g_chol || !g_rgb || !m || !v || !step || !cfg)
       return GS2D_EINVAL;
-    return hip_status(launch_adam(N, xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, *cfg, active,
-                                  zero_grads, nullptr, 0, 0.f, nullptr, 0, as_stream(stream)));
+    hipStream_t st = as_stream(stream);
+    hipError_t e = launch_step_tick(step, st);
+    if (e == hipSuccess)
+      e = launch_adam(N, xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, *cfg, active, zero_grads,
+                      nullptr, 0, 0.f, nullptr, 0, st);
+    return hip_status(e);
   } catch (...) {
     return GS2D_EHIP;
   }
@@ -185,7 +220,7 @@ hipError_t enqueue_iteration(const Layout &L, void *ws, const float *target, flo
                              hipStream_t st) {
   float *g = at<float>(ws, L.grads);
   float *g_xy = g, *g_chol = g + 2 * (size_t)L.N, *g_rgb = g + 5 * (size_t)L.N;
-  hipError_t e = launch_binning(L, xy, chol, ws, st);
+  hipError_t e = launch_binning(L, xy, chol, ws, st, step);
   if (e == hipSuccess) e = launch_render_fused(L, ws, rgb, target, g_xy, g_chol, g_rgb, st);
   if (e == hipSuccess)
     e = launch_adam(L.N, xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg, nullptr, 1,

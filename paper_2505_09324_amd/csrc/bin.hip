@@ -97,30 +97,39 @@ __device__ inline long long block_exclusive_scan(long long v, long long *total, 
 }
 
 // ------------------------------------------------------------ count scan --
-// One block.  offsets[n] = min(sum_{m<n} max(counts[m],0), max_pairs);
-// offsets[N] and misc[MISC_N_PAIRS] = min(total, max_pairs); status bits.
+// One block.  Thread t owns the contiguous segment [t*per, t*per + per) and
+// issues all its loads before using them (they are independent), so the
+// block waits for one memory round trip instead of `per` of them.
+constexpr int SCAN_PER = 64;  // max elements per thread: 64 * 1024 = 65536
+
+// offsets[n] = min(sum_{m<n} max(counts[m],0), max_pairs); offsets[N] and
+// misc[MISC_N_PAIRS] = min(total, max_pairs); status bits; culled count.
+// When `tick` is given its value is incremented once (the fitting loop's
+// step counter, read by the optimiser later in the same iteration).
 __global__ void __launch_bounds__(SCAN_BLOCK)
 k_scan_counts(int N, int max_pairs, const int *__restrict__ counts, int *__restrict__ offsets,
-              int *__restrict__ misc) {
+              int *__restrict__ misc, int *__restrict__ tick) {
   __shared__ long long lds[SCAN_BLOCK / 64];
   __shared__ int culled_w[SCAN_BLOCK / 64];
   const int per = (N + SCAN_BLOCK - 1) / SCAN_BLOCK;
-  const int beg = min(N, threadIdx.x * per), end = min(N, beg + per);
+  const int beg = min(N, (int)threadIdx.x * per), end = min(N, beg + per);
+  int v[SCAN_PER];
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) v[k] = (k < per && beg + k < end) ? counts[beg + k] : 0;
   long long sum = 0;
   int culled = 0;
-  for (int i = beg; i < end; ++i) {
-    const int c = counts[i];
-    culled += (c < 0);
-    sum += (c > 0) ? c : 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    culled += (v[k] < 0);
+    sum += (v[k] > 0) ? v[k] : 0;
   }
   long long total;
   long long run = block_exclusive_scan<SCAN_BLOCK>(sum, &total, lds);
-  for (int i = beg; i < end; ++i) {
-    offsets[i] = (int)min(run, (long long)max_pairs);
-    const int c = counts[i];
-    run += (c > 0) ? c : 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    if (k < per && beg + k < end) offsets[beg + k] = (int)min(run, (long long)max_pairs);
+    run += (v[k] > 0) ? v[k] : 0;
   }
-  // culled count: wave sums then one thread
   for (int o = 32; o > 0; o >>= 1) culled += __shfl_xor(culled, o, 64);
   if ((threadIdx.x & 63) == 0) culled_w[threadIdx.x >> 6] = culled;
   __syncthreads();
@@ -135,6 +144,7 @@ k_scan_counts(int N, int max_pairs, const int *__restrict__ counts, int *__restr
     misc[MISC_STATUS] = (int)st;
     misc[MISC_N_CULLED] = c;
     misc[MISC_STICKY] |= (int)st;
+    if (tick) tick[0] += 1;
   }
 }
 
@@ -182,20 +192,25 @@ k_radix_hist(const uint32_t *__restrict__ keys, const int *__restrict__ misc, in
   hist[threadIdx.x * G + b] = h[threadIdx.x];
 }
 
-// Exclusive scan of the G*RADIX histogram in (digit, block) order, in place.
+// Exclusive scan of the G*RADIX histogram in (digit, block) order, in place
+// (G*RADIX <= SORT_MAX_BLOCKS*RADIX entries, at most SCAN_PER per thread).
 __global__ void __launch_bounds__(SCAN_BLOCK)
 k_radix_scan(uint32_t *__restrict__ hist, int total_entries) {
   __shared__ long long lds[SCAN_BLOCK / 64];
   const int per = (total_entries + SCAN_BLOCK - 1) / SCAN_BLOCK;
-  const int beg = min(total_entries, threadIdx.x * per), end = min(total_entries, beg + per);
+  const int beg = min(total_entries, (int)threadIdx.x * per), end = min(total_entries, beg + per);
+  uint32_t v[SCAN_PER];
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) v[k] = (k < per && beg + k < end) ? hist[beg + k] : 0u;
   long long sum = 0;
-  for (int i = beg; i < end; ++i) sum += hist[i];
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) sum += v[k];
   long long total;
   long long run = block_exclusive_scan<SCAN_BLOCK>(sum, &total, lds);
-  for (int i = beg; i < end; ++i) {
-    const uint32_t c = hist[i];
-    hist[i] = (uint32_t)run;
-    run += c;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    if (k < per && beg + k < end) hist[beg + k] = (uint32_t)run;
+    run += v[k];
   }
 }
 
@@ -265,7 +280,7 @@ k_tile_ranges(const uint32_t *__restrict__ keys, const int *__restrict__ misc, i
 }
 
 hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, void *ws,
-                          hipStream_t st) {
+                          hipStream_t st, int *step_tick) {
   float4 *geom = at<float4>(ws, L.geom);
   int *counts = at<int>(ws, L.counts);
   int *offsets = at<int>(ws, L.offsets);
@@ -275,7 +290,7 @@ hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, v
   hipLaunchKernelGGL(k_project, dim3(nb), dim3(256), 0, st, L.N, L.TX, L.TY, 1.0f / (float)L.T, xy,
                      chol, geom, rectp, counts);
   hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(SCAN_BLOCK), 0, st, L.N, L.max_pairs, counts,
-                     offsets, misc);
+                     offsets, misc, step_tick);
   uint32_t *ka = at<uint32_t>(ws, L.keys_a), *kb = at<uint32_t>(ws, L.keys_b);
   hipLaunchKernelGGL(k_emit_keys, dim3(nb), dim3(256), 0, st, L.N, L.TX, rectp, offsets, ka);
   uint32_t *hist = at<uint32_t>(ws, L.hist);

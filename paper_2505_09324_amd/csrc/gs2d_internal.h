@@ -26,7 +26,7 @@ constexpr uint32_t STATUS_CULLED = 2u;
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int SORT_BLOCK = 256;       // threads per sort block (4 waves)
-constexpr int SORT_MAX_BLOCKS = 256;  // sort blocks (each owns one key chunk)
+constexpr int SORT_MAX_BLOCKS = 128;  // sort blocks (each owns one key chunk)
 constexpr int SCAN_BLOCK = 1024;
 
 // Byte offsets of every array inside one frame's workspace.
@@ -52,8 +52,9 @@ inline T *at(void *ws, size_t off) {
 // ---- kernels launched by the host code (defined in the .hip files) ----
 
 // Binning (bin.hip).  Each enqueues on `st`.
+// step_tick (nullable): a device counter incremented once by the binning.
 hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, void *ws,
-                          hipStream_t st);
+                          hipStream_t st, int *step_tick = nullptr);
 
 // Raster (raster.hip).
 hipError_t launch_render_fwd(const Layout &L, void *ws, const float *rgb, const float *target,
@@ -63,9 +64,13 @@ hipError_t launch_render_bwd(const Layout &L, void *ws, const float *rgb, const 
 hipError_t launch_render_fused(const Layout &L, void *ws, const float *rgb, const float *target,
                                float *g_xy, float *g_chol, float *g_rgb, hipStream_t st);
 hipError_t launch_loss_reduce(const Layout &L, void *ws, float *loss, hipStream_t st);
+hipError_t launch_count_pairs(const Layout &L, void *ws, unsigned long long *out, hipStream_t st);
 
-// Optimiser (adam.hip).  loss_part/loss_trace may be NULL; when given, the
-// kernel also reduces the per-tile loss partials into loss_trace[step].
+// Optimiser (adam.hip).  step[0] must already hold this step's t (>= 1):
+// either launch_step_tick or the binning's tick has run before.
+// loss_part/loss_trace may be NULL; when given, the kernel also reduces the
+// per-tile loss partials into loss_trace[t - 1].
+hipError_t launch_step_tick(int32_t *step, hipStream_t st);
 hipError_t launch_adam(int N, float *xy, float *chol, float *rgb, float *g_xy, float *g_chol,
                        float *g_rgb, float *m, float *v, int32_t *step, const gs2d_adam_cfg &cfg,
                        const uint8_t *active, int zero_grads, const float *loss_part,

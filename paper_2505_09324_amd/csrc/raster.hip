@@ -54,7 +54,12 @@ __device__ inline void stage_chunk(Smem<TILE> &S, const uint32_t *__restrict__ k
   if (j < cnt) {
     const int id = (int)(keys[beg + j] & 0xFFFFu);
     const float4 g0 = geom[2 * id], g1 = geom[2 * id + 1];
-    const float c0 = rgb[3 * id], c1 = rgb[3 * id + 1], c2 = rgb[3 * id + 2];
+    float c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    if (rgb) {  // pair counting stages geometry only
+      c0 = rgb[3 * id];
+      c1 = rgb[3 * id + 1];
+      c2 = rgb[3 * id + 2];
+    }
     S.A[j] = g0;
     S.B[j] = make_float4(g1.x, c0, c1, c2);
     S.id[j] = id;
@@ -91,33 +96,57 @@ __device__ inline int compact_chunk(Smem<TILE> &S, int cnt) {
 }
 
 // Sum of 8 per-lane values over the wavefront; lane L returns the total of
-// value ((L >> 3) & 7).
+// value ((L >> 3) & 7).  Each exchange step halves the number of values a
+// lane carries, so the 64-lane sum of 8 values costs 4+2+1 exchanges and
+// 3 in-row steps:
+//   - across the two 32-lane halves: v_permlane32_swap of (value i, value
+//     i+4) leaves value i of both halves in the low half and value i+4 in the
+//     high half, one add finishes the pair;
+//   - across 16-lane rows: v_permlane16_swap, the same way;
+//   - across 8 lanes inside a row, then within each 8-lane group: DPP
+//     (row_ror:8, row_half_mirror, quad_perm) folded into the adds.
+template <int CTRL>
+__device__ inline float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+__device__ inline void swap32(float x, float y, float &lo_sum_part, float &hi_sum_part) {
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  lo_sum_part = __uint_as_float(r[0]);
+  hi_sum_part = __uint_as_float(r[1]);
+}
+
+__device__ inline void swap16(float x, float y, float &a, float &b) {
+  auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  a = __uint_as_float(r[0]);
+  b = __uint_as_float(r[1]);
+}
+
+constexpr int DPP_ROW_ROR8 = 0x128;
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_QUAD_XOR2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int DPP_QUAD_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
+
 __device__ inline float reduce8_transpose(const float (&a)[8]) {
   const int lane = threadIdx.x & 63;
   float b[4], c[2];
-  {
-    const bool hi = lane & 32;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float keep = hi ? a[i + 4] : a[i];
-      const float send = hi ? a[i] : a[i + 4];
-      b[i] = keep + __shfl_xor(send, 32, 64);
-    }
+  for (int i = 0; i < 4; ++i) {
+    float p, q;
+    swap32(a[i], a[i + 4], p, q);
+    b[i] = p + q;
   }
-  {
-    const bool hi = lane & 16;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const float keep = hi ? b[i + 2] : b[i];
-      const float send = hi ? b[i] : b[i + 2];
-      c[i] = keep + __shfl_xor(send, 16, 64);
-    }
+  for (int i = 0; i < 2; ++i) {
+    float p, q;
+    swap16(b[i], b[i + 2], p, q);
+    c[i] = p + q;
   }
   const bool hi = lane & 8;
-  float d = (hi ? c[1] : c[0]) + __shfl_xor(hi ? c[0] : c[1], 8, 64);
-  d += __shfl_xor(d, 4, 64);
-  d += __shfl_xor(d, 2, 64);
-  d += __shfl_xor(d, 1, 64);
+  float d = (hi ? c[1] : c[0]) + dpp<DPP_ROW_ROR8>(hi ? c[0] : c[1]);
+  d += dpp<DPP_ROW_HALF_MIRROR>(d);
+  d += dpp<DPP_QUAD_XOR2>(d);
+  d += dpp<DPP_QUAD_XOR1>(d);
   return d;
 }
 
@@ -129,11 +158,15 @@ __device__ inline void pixel_of_thread(int tx, int ty, int *px, int *py) {
   *py = ty * TILE + (w / SBX) * 8 + (lane >> 3);
 }
 
-// Forward accumulation over one staged, compacted chunk.
-template <int TILE>
-__device__ inline void fwd_chunk(const Smem<TILE> &S, int len, float pxc, float pyc, float &a0,
-                                 float &a1, float &a2) {
+// Forward accumulation over one staged, compacted chunk.  With KEEP_HITS the
+// wavefront's list is compacted in place to the Gaussians that have at least
+// one in-frame pixel with q <= 9 in this sub-block (the only ones the
+// backward pass needs); returns the new length (else `len`).
+template <int TILE, bool KEEP_HITS>
+__device__ inline int fwd_chunk(Smem<TILE> &S, int len, float pxc, float pyc, bool inside,
+                                float &a0, float &a1, float &a2) {
   const int w = threadIdx.x >> 6;
+  int kept = 0;
   for (int k = 0; k < len; ++k) {
     const int j = S.list[w][k];
     const float4 A = S.A[j], B = S.B[j];
@@ -142,15 +175,25 @@ __device__ inline void fwd_chunk(const Smem<TILE> &S, int len, float pxc, float 
     const float u2 = (dy - A.w * u1) * B.x;
     const float q = u1 * u1 + u2 * u2;
     const float e = __builtin_amdgcn_exp2f(q * NEG_HALF_LOG2E);
-    const float wgt = (q <= CUTOFF_Q) ? e : 0.f;
+    const bool in_cut = q <= CUTOFF_Q;
+    const float wgt = in_cut ? e : 0.f;
     a0 += wgt * B.y;
     a1 += wgt * B.z;
     a2 += wgt * B.w;
+    if (KEEP_HITS) {
+      if (__ballot(in_cut && inside)) {
+        if ((threadIdx.x & 63) == 0) S.list[w][kept] = (uint16_t)j;  // kept <= k
+        ++kept;
+      }
+    }
   }
+  return KEEP_HITS ? kept : len;
 }
 
 // Backward over one staged, compacted chunk; adds into acc[CH][8] in LDS.
-template <int TILE>
+// CHECK_HITS skips (uniformly per wavefront) Gaussians with no lane inside
+// the cutoff, for lists that were not already reduced to such Gaussians.
+template <int TILE, bool CHECK_HITS>
 __device__ inline void bwd_chunk(const Smem<TILE> &S, float *acc, int len, float pxc, float pyc,
                                  float g0, float g1, float g2) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -161,6 +204,7 @@ __device__ inline void bwd_chunk(const Smem<TILE> &S, float *acc, int len, float
     const float u1 = dx * A.z;
     const float u2 = (dy - A.w * u1) * B.x;
     const float q = u1 * u1 + u2 * u2;
+    if (CHECK_HITS && !__ballot(q <= CUTOFF_Q)) continue;  // wave-uniform skip
     const float e = __builtin_amdgcn_exp2f(q * NEG_HALF_LOG2E);
     const float wgt = (q <= CUTOFF_Q) ? e : 0.f;
     const float sn = (g0 * B.y + g1 * B.z + g2 * B.w) * wgt;
@@ -235,7 +279,7 @@ k_render_fwd(FrameArgs f, const float *__restrict__ target, float *__restrict__ 
     __syncthreads();
     const int len = compact_chunk<TILE>(S, cnt);
     __syncthreads();
-    fwd_chunk<TILE>(S, len, pxc, pyc, a0, a1, a2);
+    fwd_chunk<TILE, false>(S, len, pxc, pyc, true, a0, a1, a2);
   }
   const bool inside = px < f.W && py < f.H;
   float l = 0.f;
@@ -293,7 +337,7 @@ k_render_bwd(FrameArgs f, const float *__restrict__ dl_dimg, float *__restrict__
     __syncthreads();
     const int len = compact_chunk<TILE>(S, cnt);
     __syncthreads();
-    bwd_chunk<TILE>(S, acc, len, pxc, pyc, g0, g1, g2);
+    bwd_chunk<TILE, true>(S, acc, len, pxc, pyc, g0, g1, g2);
     __syncthreads();
     flush_grads<TILE>(S, acc, cnt, g_xy, g_chol, g_rgb);
   }
@@ -318,6 +362,8 @@ k_render_fused(FrameArgs f, const float *__restrict__ target, float *__restrict_
   int px, py;
   pixel_of_thread<TILE>(tx, ty, &px, &py);
   const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
+  const bool inside = px < f.W && py < f.H;
+  const bool single = (end - beg) <= CH;  // the whole list fits one LDS chunk
   float a0 = 0.f, a1 = 0.f, a2 = 0.f;
   int len = 0;
   for (int c = beg; c < end; c += CH) {
@@ -327,10 +373,15 @@ k_render_fused(FrameArgs f, const float *__restrict__ target, float *__restrict_
     __syncthreads();
     len = compact_chunk<TILE>(S, cnt);
     __syncthreads();
-    fwd_chunk<TILE>(S, len, pxc, pyc, a0, a1, a2);
+    // a single chunk stays in LDS for the backward pass: keep only the
+    // Gaussians that reach this wavefront's pixels
+    if (single)
+      len = fwd_chunk<TILE, true>(S, len, pxc, pyc, inside, a0, a1, a2);
+    else
+      fwd_chunk<TILE, false>(S, len, pxc, pyc, inside, a0, a1, a2);
   }
   float g0 = 0.f, g1 = 0.f, g2 = 0.f, l = 0.f;
-  if (px < f.W && py < f.H) {
+  if (inside) {
     const size_t HW = (size_t)f.W * f.H, p = (size_t)py * f.W + px;
     const float r0 = a0 - target[p], r1 = a1 - target[HW + p], r2 = a2 - target[2 * HW + p];
     l = r0 * r0 + r1 * r1 + r2 * r2;
@@ -342,7 +393,6 @@ k_render_fused(FrameArgs f, const float *__restrict__ target, float *__restrict_
   const float s = block_sum<TILE>(S, l);
   if (threadIdx.x == 0) loss_part[tile] = s;
   if (beg >= end) return;
-  const bool single = (end - beg) <= CH;  // the staged chunk is still in LDS
   for (int c = beg; c < end; c += CH) {
     const int cnt = min(CH, end - c);
     __syncthreads();
@@ -352,11 +402,50 @@ k_render_fused(FrameArgs f, const float *__restrict__ target, float *__restrict_
     if (!single) {
       len = compact_chunk<TILE>(S, cnt);
       __syncthreads();
+      bwd_chunk<TILE, true>(S, acc, len, pxc, pyc, g0, g1, g2);
+    } else {
+      bwd_chunk<TILE, false>(S, acc, len, pxc, pyc, g0, g1, g2);
     }
-    bwd_chunk<TILE>(S, acc, len, pxc, pyc, g0, g1, g2);
     __syncthreads();
     flush_grads<TILE>(S, acc, cnt, g_xy, g_chol, g_rgb);
   }
+}
+
+// ------------------------------------------------- in-cutoff pair counting --
+// Number of (pixel, Gaussian) pairs with q <= 9 inside the frame: the terms
+// Eq. 2 actually sums (the algorithmic work of one render).
+template <int TILE>
+__global__ void __launch_bounds__(TILE *TILE)
+k_count_pairs(FrameArgs f, unsigned long long *__restrict__ out) {
+  constexpr int CH = Cfg<TILE>::CH;
+  __shared__ Smem<TILE> S;
+  const int tile = blockIdx.x;
+  const int tx = tile % f.TX, ty = tile / f.TX;
+  const int beg = f.tile_start[tile], end = f.tile_start[tile + 1];
+  int px, py;
+  pixel_of_thread<TILE>(tx, ty, &px, &py);
+  const float pxc = (float)px + 0.5f, pyc = (float)py + 0.5f;
+  const bool inside = px < f.W && py < f.H;
+  const int w = threadIdx.x >> 6;
+  unsigned int n = 0;
+  for (int c = beg; c < end; c += CH) {
+    const int cnt = min(CH, end - c);
+    __syncthreads();
+    stage_chunk<TILE>(S, f.keys, c, cnt, tx, ty, f.geom, f.rgb);
+    __syncthreads();
+    const int len = compact_chunk<TILE>(S, cnt);
+    __syncthreads();
+    for (int k = 0; k < len; ++k) {
+      const int j = S.list[w][k];
+      const float4 A = S.A[j], B = S.B[j];
+      const float dx = pxc - A.x, dy = pyc - A.y;
+      const float u1 = dx * A.z;
+      const float u2 = (dy - A.w * u1) * B.x;
+      n += (inside && u1 * u1 + u2 * u2 <= CUTOFF_Q) ? 1u : 0u;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
+  if ((threadIdx.x & 63) == 0 && n) atomicAdd(out, (unsigned long long)n);
 }
 
 // ------------------------------------------------------------- loss reduce --
@@ -428,6 +517,17 @@ hipError_t launch_render_fused(const Layout &L, void *ws, const float *rgb, cons
 #define CALL(TT)                                                                                \
   hipLaunchKernelGGL(k_render_fused<TT>, dim3(L.n_tiles), dim3(TT * TT), 0, st, f, target, lp, \
                      grad_scale(L), g_xy, g_chol, g_rgb)
+  GS2D_TILE_SWITCH(L.T, CALL)
+#undef CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_count_pairs(const Layout &L, void *ws, unsigned long long *out, hipStream_t st) {
+  FrameArgs f = frame_args(L, ws, nullptr);
+  hipError_t e = launch_fill_zero_u32(reinterpret_cast<uint32_t *>(out), 2, st);
+  if (e != hipSuccess) return e;
+#define CALL(TT) \
+  hipLaunchKernelGGL(k_count_pairs<TT>, dim3(L.n_tiles), dim3(TT * TT), 0, st, f, out)
   GS2D_TILE_SWITCH(L.T, CALL)
 #undef CALL
   return hipGetLastError();

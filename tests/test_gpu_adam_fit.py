@@ -53,14 +53,14 @@ def test_adam_step_matches_oracle(t0):
     P = {k: dev(x) for k, x in th.items()}
     G = {k: dev(x) for k, x in g.items()}
     M, V = dev(_flat(m)), dev(_flat(v))
-    step = torch.tensor([t0, 0], dtype=torch.int32, device=DEV)
+    step = torch.tensor([t0], dtype=torch.int32, device=DEV)
     cfg = _lib.adam_cfg((1e-2, 2e-3, 5e-3))
     _lib.adam_step(P["xy"], P["chol"], P["rgb"], G["xy"], G["chol"], G["rgb"], M, V, step, cfg,
                    zero_grads=True)
     torch.cuda.synchronize()
     lr = _f32({"xy": 1e-2, "chol": 2e-3, "rgb": 5e-3})
     th2, m2, v2, t = oracle_adam(th, g, m, v, t0, lr, B1, B2, EPS)
-    assert host(step).tolist() == [t0 + 1, 0]
+    assert host(step).tolist() == [t0 + 1]
     for k in th:
         # relative to theta, plus FP32 rounding of the step itself
         err = np.abs(host(P[k]) - th2[k])
@@ -83,7 +83,7 @@ def test_adam_inactive_bitwise_unchanged():
     G = {k: dev(x) for k, x in g.items()}
     M, V = dev(_flat(m)), dev(_flat(v))
     active = (np.arange(N) % 3 == 0).astype(np.uint8)
-    step = torch.zeros(2, dtype=torch.int32, device=DEV)
+    step = torch.zeros(1, dtype=torch.int32, device=DEV)
     _lib.adam_step(P["xy"], P["chol"], P["rgb"], G["xy"], G["chol"], G["rgb"], M, V, step,
                    _lib.adam_cfg(LR), active=dev(active))
     torch.cuda.synchronize()
@@ -107,7 +107,7 @@ def test_step_parity_teacher_forced_tiny_frame():
     P = {"xy": dev(xy), "chol": dev(chol), "rgb": dev(rgb)}
     M = torch.zeros(8 * N, device=DEV)
     V = torch.zeros(8 * N, device=DEV)
-    step = torch.zeros(2, dtype=torch.int32, device=DEV)
+    step = torch.zeros(1, dtype=torch.int32, device=DEV)
     T = dev(frame)
     cfg = _lib.adam_cfg(LR)
     for k in range(10):
@@ -146,7 +146,7 @@ def test_fit_frame_trajectory_tiny_frame(use_graph):
     P = {"xy": dev(xy), "chol": dev(chol), "rgb": dev(rgb)}
     M = torch.zeros(8 * N, device=DEV)
     V = torch.zeros(8 * N, device=DEV)
-    step = torch.zeros(2, dtype=torch.int32, device=DEV)
+    step = torch.zeros(1, dtype=torch.int32, device=DEV)
     trace = torch.full((64,), -1.0, device=DEV)
     opts = _lib.fit_opts(10, check_every=4, use_graph=use_graph, cfg=_lib.adam_cfg(LR))
     st = _lib.fit_frame(f.shape, dev(frame), P["xy"], P["chol"], P["rgb"], M, V, step, trace,
@@ -165,7 +165,7 @@ def test_fit_frame_stops_at_psnr_and_flags_overflow():
     f = GpuFrame(128, 128, N, 16)
     M = torch.zeros(8 * N, device=DEV)
     V = torch.zeros(8 * N, device=DEV)
-    step = torch.zeros(2, dtype=torch.int32, device=DEV)
+    step = torch.zeros(1, dtype=torch.int32, device=DEV)
     trace = torch.zeros(400, device=DEV)
     P = {"xy": dev(xy), "chol": dev(chol), "rgb": dev(rgb)}
     # PSNR of the initial state is low; a target just above it is met early

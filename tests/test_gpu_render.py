@@ -132,3 +132,32 @@ def test_full_hd_sampled_pixels_and_gaussians():
         r = gradients(sub_xy, chol[n:n + 1], rgb[n:n + 1], full_dl, y1 - y0, x1 - x0)
         got = {"xy": host(gx)[n:n + 1], "chol": host(gc)[n:n + 1], "rgb": host(gr)[n:n + 1]}
         assert_grads_close(got, r)
+
+
+@pytest.mark.parametrize("T", [8, 16, 32])
+def test_fused_render_matches_oracle_and_counts_pairs(T):
+    """Fused forward+MSE+backward: loss and accumulated gradients vs the
+    oracle; the in-cutoff pair count vs the oracle's count."""
+    print(f"fused T={T}", flush=True)
+    from oracle.render import count_pairs_in_cutoff
+    from paper_2505_09324_amd import _lib
+    frame, xy, chol, rgb = _c1()
+    chol[:, 1] = np.random.default_rng(4).uniform(-1, 1, 500).astype(np.float32)
+    f = GpuFrame(128, 128, 500, T)
+    P = [dev(xy), dev(chol), dev(rgb)]
+    _lib.project_bin(f.shape, P[0], P[1], f.ws)
+    g = [torch.zeros(500, d, device="cuda") for d in (2, 3, 3)]
+    loss = torch.empty((), device="cuda")
+    _lib.render_fused(f.shape, f.ws, P[2], dev(frame), *g, loss=loss)
+    torch.cuda.synchronize()
+    img = render_box(xy, chol, rgb, 128, 128, want_bounds=False)["img"]
+    assert float(loss) == pytest.approx(mse(img, frame), rel=1e-4)
+    ref = gradients(xy, chol, rgb, dloss_dimg(img, frame), 128, 128)
+    assert_grads_close({"xy": host(g[0]), "chol": host(g[1]), "rgb": host(g[2])}, ref)
+    # accumulation: a second call doubles the gradients
+    _lib.render_fused(f.shape, f.ws, P[2], dev(frame), *g)
+    torch.cuda.synchronize()
+    assert_grads_close({"xy": host(g[0]) / 2, "chol": host(g[1]) / 2, "rgb": host(g[2]) / 2}, ref)
+    # pairs whose q lies within 1e-4 of the cutoff may fall either way
+    got, want = _lib.count_pairs(f.shape, f.ws), count_pairs_in_cutoff(xy, chol, 128, 128)
+    assert abs(got - want) <= 2, (got, want)
