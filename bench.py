@@ -145,6 +145,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--check-every", type=int, default=50)
     ap.add_argument("--tile", type=int, default=TILE)
+    ap.add_argument("--ppl", type=int, default=1, help="pixels per lane of the raster kernels")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also time the fused kernel for every (tile, ppl) variant (stderr)")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -170,7 +173,7 @@ def main():
     td = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     xy, chol, rgb = _lib.init_plain(T, M8, td(draws.pick_roi), td(draws.jit_roi),
                                     td(draws.pick_out), td(draws.jit_out))
-    shape = _lib.make_shape(W, H, N, args.tile)
+    shape = _lib.make_shape(W, H, N, args.tile, px_per_lane=args.ppl)
     ws = _lib.alloc_workspace(shape)
     m = torch.zeros(8 * N, device=dev)
     v = torch.zeros(8 * N, device=dev)
@@ -220,6 +223,21 @@ def main():
     torch.cuda.synchronize()
     t_adam = e0.elapsed_time(e1) / args.kernel_reps * 1e-3
 
+    if args.sweep:
+        for tt, pp in ((8, 1), (16, 1), (16, 2), (32, 1), (32, 2), (32, 4)):
+            sh = _lib.make_shape(W, H, N, tt, px_per_lane=pp)
+            wsv = _lib.alloc_workspace(sh)
+            _lib.project_bin(sh, xy, chol, wsv)
+            _lib.render_fused(sh, wsv, rgb, T, *g)
+            e0.record()
+            for _ in range(args.kernel_reps):
+                _lib.render_fused(sh, wsv, rgb, T, *g)
+            e1.record()
+            torch.cuda.synchronize()
+            print(f"variant tile={tt} ppl={pp}: {e0.elapsed_time(e1) / args.kernel_reps * 1e3:.1f} us",
+                  file=sys.stderr, flush=True)
+            del wsv
+
     flops = FLOPS_PER_PAIR * p_in
     achieved = flops / t_fused / 1e12
     traffic = traffic_record(kernel_digest())
@@ -239,12 +257,13 @@ def main():
         "config": {"workload": "one 1920x1080 synthetic talking-head-like frame, 30000 Gaussians "
                                "from the content-aware ROI init (70% in ROI), Adam iterations "
                                f"{args.warmup}..{args.warmup + args.steps}",
-                   "W": W, "H": H, "N": N, "tile": args.tile, "lr": list(LR),
+                   "W": W, "H": H, "N": N, "tile": args.tile, "px_per_lane": args.ppl,
+                   "lr": list(LR),
                    "graph_chunk": args.check_every},
         "psnr_final_db": round(psnr_final, 3),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32, 4),
-                     "traffic": traffic, "kernel": "k_render_fused<16>",
+                     "traffic": traffic, "kernel": f"k_render_fused<{args.tile}, {args.ppl}>",
                      "launch_us": round(t_fused * 1e6, 2), "pairs_in_cutoff": p_in,
                      "flops_per_launch": flops},
         "stages_us": {"project_bin": round(t_bin * 1e6, 2), "render_fused": round(t_fused * 1e6, 2),

@@ -50,9 +50,12 @@ typedef enum {
 } gs2d_status;
 
 /* One frame's problem size.  max_pairs is the capacity of the tile-pair
- * list (pairs of (tile, Gaussian) whose 3-sigma box meets the tile). */
+ * list (pairs of (tile, Gaussian) whose 3-sigma box meets the tile).
+ * px_per_lane selects the raster kernel variant: each wavefront covers an
+ * 8 x (8 * px_per_lane) pixel block, i.e. tile^2 / (64 * px_per_lane)
+ * wavefronts per tile; 1, 2 or 4 with 8 * px_per_lane <= tile, 0 = 1. */
 typedef struct {
-  int32_t W, H, N, tile, max_pairs;
+  int32_t W, H, N, tile, max_pairs, px_per_lane;
 } gs2d_shape;
 
 /* Device views into a workspace after gs2d_project_bin (read-only for the
@@ -222,6 +225,67 @@ int gs2d_init_plain(int32_t W, int32_t H, const float *target, const uint8_t *ro
                     int32_t n_roi, const int64_t *pick_roi, const float *jit_roi, int32_t n_out,
                     const int64_t *pick_out, const float *jit_out, float *xy, float *chol,
                     float *rgb, int32_t *picked, void *ws, size_t ws_bytes, void *stream);
+
+/* ---------------------------------------------------------------- batches --
+ * Many frames of different sizes and Gaussian counts fitted in lockstep (the
+ * per-frame encoding loop of Sec. 3.2 applied to independent frames or ROI
+ * crops at once).  Frame f has W x H pixels and N Gaussians; its target is
+ * the f-th [3][H][W] block of the concatenated `targets`, its parameters the
+ * f-th slices of the concatenated xy [sum N][2], chol [sum N][3],
+ * rgb [sum N][3], and its Adam moments the matching slices of m, v laid out
+ * as [xy 2*sum N | chol 3*sum N | rgb 3*sum N].  Each iteration runs the
+ * per-frame binning for all frames, ONE persistent raster launch that pulls
+ * (frame, tile) work items (largest frames first) through an atomic
+ * counter, and one Adam launch over all parameters.  Every frame's tile
+ * lists and image are those of the one-frame path.  `tile` and
+ * `px_per_lane` are as in gs2d_shape and apply to all frames; each frame's
+ * pair capacity is max(65536, 16 N + 4 tiles). */
+typedef struct {
+  int32_t W, H, N;
+} gs2d_frame;
+
+/* Workspace bytes of a batch (0 if invalid: 1 <= n_frames <= 4096, each
+ * frame within the one-frame limits). */
+size_t gs2d_batch_workspace_bytes(int32_t n_frames, const gs2d_frame *frames, int32_t tile,
+                                  int32_t px_per_lane);
+
+/* Fit all frames of a batch for opts->iters iterations (same rules as
+ * gs2d_fit_frame; one shared step counter).  loss_trace is [trace_rows]
+ * [n_frames]: row k holds every frame's MSE at iteration k (= step value
+ * before the update).  The PSNR stop triggers when every frame has reached
+ * opts->psnr_target.  `frames` is a host array. */
+int gs2d_fit_batch(int32_t n_frames, const gs2d_frame *frames, int32_t tile, int32_t px_per_lane,
+                   const float *targets, float *xy, float *chol, float *rgb, float *m, float *v,
+                   int32_t *step, float *loss_trace, int32_t trace_rows, void *ws,
+                   size_t ws_bytes, const gs2d_fit_opts *opts, gs2d_fit_stats *stats,
+                   void *stream);
+
+/* Binning and one persistent fused raster pass of a batch without an
+ * optimiser step: gradients of every frame's MSE are ADDED to g_* (same
+ * layout as the parameters), loss_per_frame [n_frames] (nullable) receives
+ * each frame's MSE.  Synchronises `stream`. */
+int gs2d_batch_render_grads(int32_t n_frames, const gs2d_frame *frames, int32_t tile,
+                            int32_t px_per_lane, const float *targets, const float *xy,
+                            const float *chol, const float *rgb, float *g_xy, float *g_chol,
+                            float *g_rgb, float *loss_per_frame, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/* Device views of frame f's binning inside a batch workspace, in the
+ * one-frame gs2d_bins format.  Host-only. */
+int gs2d_batch_bins_view(int32_t n_frames, const gs2d_frame *frames, int32_t tile,
+                         int32_t px_per_lane, int32_t f, void *ws, size_t ws_bytes,
+                         gs2d_bins *out);
+
+/* Autotuner for a batch: times `reps` rounds of batched binning + persistent
+ * raster for each candidate (cand_tile[i], cand_ppl[i]) with HIP events,
+ * writes the mean ms per round to out_ms[i] and the fastest index to *best.
+ * ws must be large enough for every candidate; grad_scratch holds
+ * 8 * sum(N) floats (overwritten with accumulated garbage gradients). */
+int gs2d_autotune_batch(int32_t n_frames, const gs2d_frame *frames, const float *targets,
+                        const float *xy, const float *chol, const float *rgb, int32_t n_cand,
+                        const int32_t *cand_tile, const int32_t *cand_ppl, int32_t reps,
+                        float *grad_scratch, void *ws, size_t ws_bytes, float *out_ms,
+                        int32_t *best, void *stream);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,7 @@ STATUS_OVERFLOW, STATUS_CULLED = 1, 2
 
 class Shape(ctypes.Structure):
     _fields_ = [("W", c_int32), ("H", c_int32), ("N", c_int32), ("tile", c_int32),
-                ("max_pairs", c_int32)]
+                ("max_pairs", c_int32), ("px_per_lane", c_int32)]
 
 
 class Bins(ctypes.Structure):
@@ -45,6 +45,10 @@ class FitStats(ctypes.Structure):
     _fields_ = [("iters_run", c_int32), ("iter_hit_target", c_int32), ("final_loss", c_float),
                 ("final_psnr", c_float), ("seconds", c_double), ("status", c_uint32),
                 ("n_culled", c_int32)]
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [("W", c_int32), ("H", c_int32), ("N", c_int32)]
 
 
 class GS2DError(RuntimeError):
@@ -74,6 +78,19 @@ _SIGS = {
     "gs2d_render_fused": (c_int32, [POINTER(Shape), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p,
                                     c_void_p, c_void_p, c_void_p, c_void_p]),
     "gs2d_count_pairs": (c_int32, [POINTER(Shape), c_void_p, c_size_t, c_void_p, c_void_p]),
+    "gs2d_batch_workspace_bytes": (c_size_t, [c_int32, POINTER(Frame), c_int32, c_int32]),
+    "gs2d_fit_batch": (c_int32, [c_int32, POINTER(Frame), c_int32, c_int32, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_int32, c_void_p, c_size_t, POINTER(FitOpts), POINTER(FitStats),
+                                 c_void_p]),
+    "gs2d_batch_render_grads": (c_int32, [c_int32, POINTER(Frame), c_int32, c_int32, c_void_p,
+                                          c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                          c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gs2d_batch_bins_view": (c_int32, [c_int32, POINTER(Frame), c_int32, c_int32, c_int32,
+                                       c_void_p, c_size_t, POINTER(Bins)]),
+    "gs2d_autotune_batch": (c_int32, [c_int32, POINTER(Frame), c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p,
+                                      c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),
     "gs2d_init_workspace_bytes": (c_size_t, [c_int32, c_int32]),
     "gs2d_init_plain": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
                                   c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -130,10 +147,10 @@ def _ptr(t, name, dtype=torch.float32, shape=None, allow_none=False):
     return c_void_p(t.data_ptr())
 
 
-def make_shape(W, H, N, tile=16, max_pairs=None) -> Shape:
+def make_shape(W, H, N, tile=16, max_pairs=None, px_per_lane=1) -> Shape:
     if max_pairs is None:
         max_pairs = default_max_pairs(W, H, N, tile)
-    return Shape(int(W), int(H), int(N), int(tile), int(max_pairs))
+    return Shape(int(W), int(H), int(N), int(tile), int(max_pairs), int(px_per_lane))
 
 
 def default_max_pairs(W, H, N, tile) -> int:
@@ -296,3 +313,91 @@ def init_plain(target, roi_mask, pick_roi, jit_roi, pick_out, jit_out, ws=None, 
         _ptr(picked, "picked", torch.int32, shape=(N,), allow_none=True),
         _ptr(ws, "ws", torch.uint8), ws.numel(), _stream()))
     return xy, chol, rgb
+
+
+# ------------------------------------------------------------------ batches --
+def frames_array(sizes):
+    """sizes: list of (W, H, N) -> ctypes array of Frame."""
+    arr = (Frame * len(sizes))()
+    for i, (w, h, n) in enumerate(sizes):
+        arr[i] = Frame(int(w), int(h), int(n))
+    return arr
+
+
+def batch_workspace_bytes(sizes, tile=16, px_per_lane=1) -> int:
+    fr = frames_array(sizes)
+    n = lib().gs2d_batch_workspace_bytes(len(sizes), fr, int(tile), int(px_per_lane))
+    if n == 0:
+        raise GS2DError("gs2d_batch_workspace_bytes", GS2D_EINVAL)
+    return int(n)
+
+
+def _batch_totals(sizes):
+    return sum(n for _, _, n in sizes), sum(3 * w * h for w, h, _ in sizes)
+
+
+def fit_batch(sizes, tile, px_per_lane, targets, xy, chol, rgb, m, v, step, loss_trace, ws,
+              opts: FitOpts, check=True) -> FitStats:
+    F = len(sizes)
+    Nt, Pt = _batch_totals(sizes)
+    if loss_trace.dim() != 2 or loss_trace.shape[1] != F:
+        raise ValueError("loss_trace must be [rows, n_frames]")
+    stats = FitStats()
+    code = lib().gs2d_fit_batch(
+        F, frames_array(sizes), int(tile), int(px_per_lane), _ptr(targets, "targets", shape=(Pt,)),
+        _ptr(xy, "xy", shape=(Nt, 2)), _ptr(chol, "chol", shape=(Nt, 3)),
+        _ptr(rgb, "rgb", shape=(Nt, 3)), _ptr(m, "m", shape=(8 * Nt,)), _ptr(v, "v", shape=(8 * Nt,)),
+        _ptr(step, "step", torch.int32, shape=(1,)), _ptr(loss_trace, "loss_trace"),
+        int(loss_trace.shape[0]), _ptr(ws, "ws", torch.uint8), ws.numel(), ctypes.byref(opts),
+        ctypes.byref(stats), _stream())
+    if check:
+        _check("gs2d_fit_batch", code)
+    stats.code = code
+    return stats
+
+
+def batch_render_grads(sizes, tile, px_per_lane, targets, xy, chol, rgb, g_xy, g_chol, g_rgb, ws,
+                       loss_per_frame=None):
+    F = len(sizes)
+    Nt, Pt = _batch_totals(sizes)
+    _check("gs2d_batch_render_grads", lib().gs2d_batch_render_grads(
+        F, frames_array(sizes), int(tile), int(px_per_lane), _ptr(targets, "targets", shape=(Pt,)),
+        _ptr(xy, "xy", shape=(Nt, 2)), _ptr(chol, "chol", shape=(Nt, 3)),
+        _ptr(rgb, "rgb", shape=(Nt, 3)), _ptr(g_xy, "g_xy", shape=(Nt, 2)),
+        _ptr(g_chol, "g_chol", shape=(Nt, 3)), _ptr(g_rgb, "g_rgb", shape=(Nt, 3)),
+        _ptr(loss_per_frame, "loss_per_frame", shape=(F,), allow_none=True),
+        _ptr(ws, "ws", torch.uint8), ws.numel(), _stream()))
+
+
+def read_batch_bins(sizes, tile, px_per_lane, f, ws) -> dict:
+    b = Bins()
+    _check("gs2d_batch_bins_view", lib().gs2d_batch_bins_view(
+        len(sizes), frames_array(sizes), int(tile), int(px_per_lane), int(f),
+        _ptr(ws, "ws", torch.uint8), ws.numel(), ctypes.byref(b)))
+    N = sizes[f][2]
+    n_pairs = int(_slice(ws, b.n_pairs, 1, torch.int32).item())
+    keys = _slice(ws, b.keys, n_pairs, torch.int32).cpu().numpy().view("uint32")
+    return {"n_pairs": n_pairs, "keys": keys,
+            "tile_start": _slice(ws, b.tile_start, b.n_tiles + 1, torch.int32).cpu().numpy().astype("int64"),
+            "counts": _slice(ws, b.counts, N, torch.int32).cpu().numpy().astype("int64"),
+            "status": int(_slice(ws, b.status, 1, torch.int32).item())}
+
+
+def autotune_batch(sizes, targets, xy, chol, rgb, candidates, reps=5):
+    """Time every (tile, px_per_lane) candidate on this batch; returns
+    (best_index, [ms per round])."""
+    F = len(sizes)
+    Nt, Pt = _batch_totals(sizes)
+    need = max(batch_workspace_bytes(sizes, t, p) for t, p in candidates)
+    ws = torch.empty(need, dtype=torch.uint8, device=xy.device)
+    scratch = torch.zeros(8 * Nt, device=xy.device)
+    ct = (c_int32 * len(candidates))(*[int(t) for t, _ in candidates])
+    cp = (c_int32 * len(candidates))(*[int(p) for _, p in candidates])
+    out = (c_float * len(candidates))()
+    best = c_int32(-1)
+    _check("gs2d_autotune_batch", lib().gs2d_autotune_batch(
+        F, frames_array(sizes), _ptr(targets, "targets", shape=(Pt,)), _ptr(xy, "xy", shape=(Nt, 2)),
+        _ptr(chol, "chol", shape=(Nt, 3)), _ptr(rgb, "rgb", shape=(Nt, 3)), len(candidates), ct, cp,
+        int(reps), _ptr(scratch, "scratch"), _ptr(ws, "ws", torch.uint8), ws.numel(), out,
+        ctypes.byref(best), _stream()))
+    return int(best.value), [float(x) for x in out]

@@ -16,6 +16,9 @@ bool make_layout(const gs2d_shape &s, Layout *L) {
   if (s.W < 1 || s.H < 1 || s.N < 1 || s.N > 65536) return false;
   if (s.tile != 8 && s.tile != 16 && s.tile != 32) return false;
   if (s.max_pairs < 1 || s.max_pairs > (1 << 30)) return false;
+  const int ppl = s.px_per_lane == 0 ? 1 : s.px_per_lane;
+  if (ppl != 1 && ppl != 2 && ppl != 4) return false;
+  if (8 * ppl > s.tile) return false;
   const long long TX = (s.W + (long long)s.tile - 1) / s.tile;
   const long long TY = (s.H + (long long)s.tile - 1) / s.tile;
   if (TX * TY > 65536) return false;
@@ -24,6 +27,7 @@ bool make_layout(const gs2d_shape &s, Layout *L) {
   L->N = s.N;
   L->T = s.tile;
   L->max_pairs = s.max_pairs;
+  L->ppl = ppl;
   L->TX = (int)TX;
   L->TY = (int)TY;
   L->n_tiles = (int)(TX * TY);

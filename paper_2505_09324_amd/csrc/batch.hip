@@ -1,0 +1,811 @@
+// Batched fitting: many frames of different sizes and Gaussian counts fitted
+// in lockstep, one launch per stage per iteration.
+//
+//  - binning runs segmented per frame: one thread per Gaussian of the whole
+//    batch for projection and key emission, one block per frame for the
+//    count scan and for each radix-digit scan, and a block table mapping the
+//    sort blocks to (frame, key chunk) for the histogram/scatter passes;
+//  - the raster is ONE persistent launch per iteration: a grid sized to the
+//    device's resident capacity pulls (frame, tile) work items from a queue
+//    through an atomic counter, largest frames first, and runs the same
+//    fused forward + loss + backward tile code as the one-frame kernel;
+//  - Adam runs over the concatenated parameters of all frames; a per-frame
+//    reduction writes each frame's loss into its column of the trace.
+// Keys, geometry and tile lists stay frame-local (16-bit Gaussian index,
+// frame-local tile id), so every frame's lists are identical to what the
+// one-frame path produces for it alone.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "bin_common.h"
+#include "raster_tile.h"
+
+namespace gs2d {
+
+namespace {
+
+// Device descriptor of one frame of a batch (offsets in elements).
+struct BFrame {
+  int W, H, N, TX, TY, n_tiles, G, cap;
+  long long g_off;     // first Gaussian of the frame in the concatenated arrays
+  long long px_off;    // first float of the frame's target ([3][H][W])
+  long long key_off;   // first key slot
+  long long hist_off;  // first radix histogram entry (RADIX * G entries)
+  long long tile_off;  // first tile of the frame among all tiles of the batch
+};
+
+enum BMisc : int { BM_N_PAIRS = 0, BM_STATUS = 1, BM_N_CULLED = 2, BM_STICKY = 3, BM_STRIDE = 8 };
+
+struct BatchLayout {
+  int F, T, ppl, passes, sort_blocks;
+  long long Ntot, keys_tot, hist_tot, tiles_tot;
+  size_t desc, gframe, blk_frame, blk_chunk, queue, geom, rect, counts, offsets, keys_a, keys_b,
+      hist, tile_start, loss_part, grads, misc, counter, total;
+  std::vector<BFrame> frames;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout *B) {
+  if (F < 1 || F > 4096 || !fr) return false;
+  if (tile != 8 && tile != 16 && tile != 32) return false;
+  const int ppl = ppl_in == 0 ? 1 : ppl_in;
+  if ((ppl != 1 && ppl != 2 && ppl != 4) || 8 * ppl > tile) return false;
+  B->F = F;
+  B->T = tile;
+  B->ppl = ppl;
+  B->frames.resize(F);
+  long long g = 0, px = 0, key = 0, hist = 0, tiles = 0;
+  int blocks = 0, maxbits = 1;
+  for (int f = 0; f < F; ++f) {
+    const gs2d_frame &s = fr[f];
+    if (s.W < 1 || s.H < 1 || s.N < 1 || s.N > 65536) return false;
+    BFrame &d = B->frames[f];
+    d.W = s.W;
+    d.H = s.H;
+    d.N = s.N;
+    d.TX = (s.W + tile - 1) / tile;
+    d.TY = (s.H + tile - 1) / tile;
+    if ((long long)d.TX * d.TY > 65536) return false;
+    d.n_tiles = d.TX * d.TY;
+    const long long cap = std::max<long long>(1 << 16, 16LL * s.N + 4LL * d.n_tiles);
+    if (cap > (1 << 30)) return false;
+    d.cap = (int)cap;
+    d.G = std::max(1, std::min(SORT_MAX_BLOCKS, (d.cap + 2047) / 2048));
+    d.g_off = g;
+    d.px_off = px;
+    d.key_off = key;
+    d.hist_off = hist;
+    d.tile_off = tiles;
+    g += s.N;
+    px += 3LL * s.W * s.H;
+    key += d.cap;
+    hist += (long long)RADIX * d.G;
+    tiles += d.n_tiles;
+    blocks += d.G;
+    int bits = 1;
+    while ((1LL << bits) < (long long)d.n_tiles) ++bits;
+    maxbits = std::max(maxbits, bits);
+  }
+  B->passes = (maxbits + RADIX_BITS - 1) / RADIX_BITS;
+  B->sort_blocks = blocks;
+  B->Ntot = g;
+  B->keys_tot = key;
+  B->hist_tot = hist;
+  B->tiles_tot = tiles;
+  size_t o = 0;
+  auto take = [&o](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  B->desc = take(sizeof(BFrame) * F);
+  B->gframe = take(4 * (size_t)g);
+  B->blk_frame = take(4 * (size_t)blocks);
+  B->blk_chunk = take(4 * (size_t)blocks);
+  B->queue = take(4 * (size_t)tiles);
+  B->geom = take(32 * (size_t)g);
+  B->rect = take(16 * (size_t)g);
+  B->counts = take(4 * (size_t)g);
+  B->offsets = take(4 * ((size_t)g + F));
+  B->keys_a = take(4 * (size_t)key);
+  B->keys_b = take(4 * (size_t)key);
+  B->hist = take(4 * (size_t)hist);
+  B->tile_start = take(4 * ((size_t)tiles + F));
+  B->loss_part = take(4 * (size_t)tiles);
+  B->grads = take(32 * (size_t)g);
+  B->misc = take(4 * (size_t)BM_STRIDE * F);
+  B->counter = take(64);
+  B->total = o;
+  return true;
+}
+
+// ------------------------------------------------------------ binning ----
+__global__ void __launch_bounds__(256)
+k_b_project(long long Ntot, const BFrame *__restrict__ D, const int *__restrict__ gframe, int tile,
+            const float *__restrict__ xy, const float *__restrict__ chol, float4 *__restrict__ geom,
+            int4 *__restrict__ rect, int *__restrict__ counts) {
+  const long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (g >= Ntot) return;
+  const BFrame d = D[gframe[g]];
+  project_gaussian((int)g, d.TX, d.TY, 1.0f / (float)tile, xy, chol, geom, rect, counts);
+}
+
+// One block per frame: offsets of the frame's keys, pair count, status.
+// Block 0 also advances the step counter (when given) and clears the
+// persistent raster's work counter for this iteration.
+__global__ void __launch_bounds__(SCAN_BLOCK)
+k_b_scan_counts(const BFrame *__restrict__ D, const int *__restrict__ counts,
+                int *__restrict__ offsets, int *__restrict__ misc, int *__restrict__ tick,
+                unsigned *__restrict__ work_counter) {
+  __shared__ long long lds[SCAN_BLOCK / 64];
+  __shared__ int culled_w[SCAN_BLOCK / 64];
+  const int f = blockIdx.x;
+  const BFrame d = D[f];
+  const int N = d.N;
+  const int *cnt = counts + d.g_off;
+  int *off = offsets + d.g_off + f;
+  const int per = (N + SCAN_BLOCK - 1) / SCAN_BLOCK;
+  const int beg = min(N, (int)threadIdx.x * per), end = min(N, beg + per);
+  int v[SCAN_PER];
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) v[k] = (k < per && beg + k < end) ? cnt[beg + k] : 0;
+  long long sum = 0;
+  int culled = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    culled += (v[k] < 0);
+    sum += (v[k] > 0) ? v[k] : 0;
+  }
+  long long total;
+  long long run = block_exclusive_scan<SCAN_BLOCK>(sum, &total, lds);
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    if (k < per && beg + k < end) off[beg + k] = (int)min(run, (long long)d.cap);
+    run += (v[k] > 0) ? v[k] : 0;
+  }
+  for (int o = 32; o > 0; o >>= 1) culled += __shfl_xor(culled, o, 64);
+  if ((threadIdx.x & 63) == 0) culled_w[threadIdx.x >> 6] = culled;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int c = 0;
+    for (int w = 0; w < SCAN_BLOCK / 64; ++w) c += culled_w[w];
+    const int np = (int)min(total, (long long)d.cap);
+    off[N] = np;
+    const int st = (total > (long long)d.cap ? (int)STATUS_OVERFLOW : 0) |
+                   (c > 0 ? (int)STATUS_CULLED : 0);
+    int *m = misc + BM_STRIDE * f;
+    m[BM_N_PAIRS] = np;
+    m[BM_STATUS] = st;
+    m[BM_N_CULLED] = c;
+    m[BM_STICKY] |= st;
+    if (f == 0) {
+      if (tick) tick[0] += 1;
+      work_counter[0] = 0u;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_b_emit_keys(long long Ntot, const BFrame *__restrict__ D, const int *__restrict__ gframe,
+              const int4 *__restrict__ rect, const int *__restrict__ offsets,
+              uint32_t *__restrict__ keys) {
+  const long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (g >= Ntot) return;
+  const int f = gframe[g];
+  const BFrame d = D[f];
+  const int n = (int)(g - d.g_off);
+  const int *off = offsets + d.g_off + f;
+  const int beg = off[n], end = off[n + 1];
+  if (end <= beg) return;
+  const int4 rc = rect[g];
+  uint32_t *k = keys + d.key_off;
+  int i = beg;
+  for (int ty = rc.y; ty <= rc.w && i < end; ++ty)
+    for (int tx = rc.x; tx <= rc.z && i < end; ++tx, ++i)
+      k[i] = ((uint32_t)(ty * d.TX + tx) << 16) | (uint32_t)n;
+}
+
+__global__ void __launch_bounds__(SORT_BLOCK)
+k_b_radix_hist(const BFrame *__restrict__ D, const int *__restrict__ blk_frame,
+               const int *__restrict__ blk_chunk, const int *__restrict__ misc,
+               const uint32_t *__restrict__ keys, int shift, uint32_t *__restrict__ hist) {
+  __shared__ uint32_t h[RADIX];
+  const int f = blk_frame[blockIdx.x], c = blk_chunk[blockIdx.x];
+  const BFrame d = D[f];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int beg, end;
+  sort_chunk(misc[BM_STRIDE * f + BM_N_PAIRS], d.G, c, &beg, &end);
+  const uint32_t *k = keys + d.key_off;
+  for (int i = beg + threadIdx.x; i < end; i += SORT_BLOCK)
+    atomicAdd(&h[(k[i] >> shift) & (RADIX - 1)], 1u);
+  __syncthreads();
+  hist[d.hist_off + (long long)threadIdx.x * d.G + c] = h[threadIdx.x];
+}
+
+// One block per frame: exclusive scan of its RADIX * G histogram.
+__global__ void __launch_bounds__(SCAN_BLOCK)
+k_b_radix_scan(const BFrame *__restrict__ D, uint32_t *__restrict__ hist_all) {
+  __shared__ long long lds[SCAN_BLOCK / 64];
+  const BFrame d = D[blockIdx.x];
+  uint32_t *hist = hist_all + d.hist_off;
+  const int total_entries = RADIX * d.G;
+  const int per = (total_entries + SCAN_BLOCK - 1) / SCAN_BLOCK;
+  const int beg = min(total_entries, (int)threadIdx.x * per), end = min(total_entries, beg + per);
+  uint32_t v[SCAN_PER];
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) v[k] = (k < per && beg + k < end) ? hist[beg + k] : 0u;
+  long long sum = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) sum += v[k];
+  long long total;
+  long long run = block_exclusive_scan<SCAN_BLOCK>(sum, &total, lds);
+#pragma unroll
+  for (int k = 0; k < SCAN_PER; ++k) {
+    if (k < per && beg + k < end) hist[beg + k] = (uint32_t)run;
+    run += v[k];
+  }
+}
+
+__global__ void __launch_bounds__(SORT_BLOCK)
+k_b_radix_scatter(const BFrame *__restrict__ D, const int *__restrict__ blk_frame,
+                  const int *__restrict__ blk_chunk, const int *__restrict__ misc,
+                  const uint32_t *__restrict__ in_all, uint32_t *__restrict__ out_all, int shift,
+                  const uint32_t *__restrict__ hist_all) {
+  constexpr int NW = SORT_BLOCK / 64;
+  __shared__ uint32_t off[RADIX];
+  __shared__ uint32_t wcnt[NW][RADIX];
+  __shared__ uint32_t wpre[NW][RADIX];
+  const int f = blk_frame[blockIdx.x], c = blk_chunk[blockIdx.x];
+  const BFrame d = D[f];
+  const uint32_t *in = in_all + d.key_off;
+  uint32_t *out = out_all + d.key_off;
+  const int tid = threadIdx.x, w = tid >> 6;
+  off[tid] = hist_all[d.hist_off + (long long)tid * d.G + c];
+#pragma unroll
+  for (int k = 0; k < NW; ++k) wcnt[k][tid] = 0;
+  __syncthreads();
+  int beg, end;
+  sort_chunk(misc[BM_STRIDE * f + BM_N_PAIRS], d.G, c, &beg, &end);
+  const unsigned long long lt = lanemask_lt();
+  for (int base = beg; base < end; base += SORT_BLOCK) {
+    const int i = base + tid;
+    const bool valid = i < end;
+    const uint32_t key = valid ? in[i] : 0u;
+    const uint32_t dg = (key >> shift) & (RADIX - 1);
+    unsigned long long match = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < RADIX_BITS; ++bit) {
+      const bool on = (dg >> bit) & 1u;
+      const unsigned long long bal = __ballot(on);
+      match &= on ? bal : ~bal;
+    }
+    const uint32_t rank = (uint32_t)__popcll(match & lt);
+    if (valid && rank == 0) wcnt[w][dg] = (uint32_t)__popcll(match);
+    __syncthreads();
+    {
+      uint32_t s = 0;
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        wpre[k][tid] = s;
+        s += wcnt[k][tid];
+      }
+      wcnt[0][tid] = s;
+    }
+    __syncthreads();
+    if (valid) out[off[dg] + wpre[w][dg] + rank] = key;
+    __syncthreads();
+    off[tid] += wcnt[0][tid];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) wcnt[k][tid] = 0;
+    __syncthreads();
+  }
+}
+
+// Grid (RB, F): tile ranges of frame blockIdx.y.
+__global__ void __launch_bounds__(256)
+k_b_tile_ranges(const BFrame *__restrict__ D, const int *__restrict__ misc,
+                const uint32_t *__restrict__ keys_all, int *__restrict__ tile_start_all) {
+  const int f = blockIdx.y;
+  const BFrame d = D[f];
+  const int n = misc[BM_STRIDE * f + BM_N_PAIRS];
+  const uint32_t *keys = keys_all + d.key_off;
+  int *ts = tile_start_all + d.tile_off + f;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
+    const int cur = (i < n) ? (int)(keys[i] >> 16) : d.n_tiles;
+    const int prev = (i > 0) ? (int)(keys[i - 1] >> 16) : -1;
+    for (int t = prev + 1; t <= cur && t <= d.n_tiles; ++t) ts[t] = i;
+  }
+}
+
+// ------------------------------------------------------------- raster ----
+struct BatchRaster {
+  const BFrame *D;
+  const uint32_t *queue;  // (frame << 16) | tile, processing order
+  unsigned n_items;
+  unsigned *counter;
+  const float4 *geom;
+  const uint32_t *keys;
+  const int *tile_start;
+  const float *rgb;
+  const float *targets;
+  float *loss_part;
+  float *g_xy, *g_chol, *g_rgb;
+};
+
+template <int TILE, int PPL>
+__global__ void __launch_bounds__((Cfg<TILE, PPL>::NT))
+k_b_render_persistent(BatchRaster a) {
+  using C = Cfg<TILE, PPL>;
+  __shared__ Smem<C::NW> S;
+  __shared__ float acc[CH * 8];
+  __shared__ unsigned s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1u);
+    __syncthreads();
+    const unsigned item = s_item;
+    __syncthreads();
+    if (item >= a.n_items) break;  // every wavefront leaves together
+    const uint32_t q = a.queue[item];
+    const int f = (int)(q >> 16), t = (int)(q & 0xFFFFu);
+    const BFrame d = a.D[f];
+    FrameArgs fa;
+    fa.W = d.W;
+    fa.H = d.H;
+    fa.TX = d.TX;
+    fa.geom = a.geom + 2 * d.g_off;
+    fa.keys = a.keys + d.key_off;
+    fa.tile_start = a.tile_start + d.tile_off + f;
+    fa.rgb = a.rgb + 3 * d.g_off;
+    const float gs = (float)(2.0 / (3.0 * (double)d.W * (double)d.H));
+    fused_tile<TILE, PPL>(S, acc, fa, t, a.targets + d.px_off, a.loss_part + d.tile_off + t, gs,
+                          a.g_xy + 2 * d.g_off, a.g_chol + 3 * d.g_off, a.g_rgb + 3 * d.g_off);
+  }
+}
+
+// One block per frame: loss of this iteration into trace[(t-1) * F + f].
+__global__ void __launch_bounds__(256)
+k_b_loss(const BFrame *__restrict__ D, int F, const float *__restrict__ loss_part,
+         const int *__restrict__ step, float *__restrict__ trace, int trace_rows) {
+  __shared__ double red[4];
+  const int f = blockIdx.x;
+  const BFrame d = D[f];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < d.n_tiles; i += 256) s += (double)loss_part[d.tile_off + i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int row = step[0] - 1;
+    if (row >= 0 && row < trace_rows)
+      trace[(size_t)row * F + f] =
+          (float)((red[0] + red[1] + red[2] + red[3]) / (3.0 * (double)d.W * (double)d.H));
+  }
+}
+
+// ------------------------------------------------------------- host side --
+struct BatchRun {
+  BatchLayout B;
+  void *ws;
+  int grid;  // persistent raster grid
+};
+
+hipError_t upload_tables(const BatchLayout &B, void *ws, hipStream_t st) {
+  std::vector<int> gframe((size_t)B.Ntot), bf, bc;
+  std::vector<uint32_t> queue;
+  queue.reserve((size_t)B.tiles_tot);
+  for (int f = 0; f < B.F; ++f) {
+    const BFrame &d = B.frames[f];
+    std::fill(gframe.begin() + d.g_off, gframe.begin() + d.g_off + d.N, f);
+    for (int c = 0; c < d.G; ++c) {
+      bf.push_back(f);
+      bc.push_back(c);
+    }
+  }
+  // work order: frames by decreasing area (largest lists first), tiles in order
+  std::vector<int> order(B.F);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return (long long)B.frames[a].W * B.frames[a].H > (long long)B.frames[b].W * B.frames[b].H;
+  });
+  for (int f : order)
+    for (int t = 0; t < B.frames[f].n_tiles; ++t) queue.push_back(((uint32_t)f << 16) | (uint32_t)t);
+  hipError_t e = hipMemcpyAsync(at<char>(ws, B.desc), B.frames.data(), sizeof(BFrame) * B.F,
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(at<char>(ws, B.gframe), gframe.data(), 4 * gframe.size(),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(at<char>(ws, B.blk_frame), bf.data(), 4 * bf.size(), hipMemcpyHostToDevice,
+                       st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(at<char>(ws, B.blk_chunk), bc.data(), 4 * bc.size(), hipMemcpyHostToDevice,
+                       st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(at<char>(ws, B.queue), queue.data(), 4 * queue.size(),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // host vectors go out of scope
+  return e;
+}
+
+template <int TT, int PP>
+int persistent_grid() {
+  int dev = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_b_render_persistent<TT, PP>,
+                                                   Cfg<TT, PP>::NT, 0) != hipSuccess)
+    return 0;
+  return std::max(1, per_cu) * prop.multiProcessorCount;
+}
+
+int batch_grid(const BatchLayout &B) {
+#define CASE(TT, PP) \
+  if (B.T == TT && B.ppl == PP) return persistent_grid<TT, PP>();
+  CASE(8, 1) CASE(16, 1) CASE(16, 2) CASE(32, 1) CASE(32, 2) CASE(32, 4)
+#undef CASE
+  return 0;
+}
+
+// Binning of every frame of the batch.
+hipError_t enqueue_batch_binning(const BatchLayout &B, void *ws, const float *xy, const float *chol,
+                                 int *tick, hipStream_t st) {
+  const BFrame *D = at<const BFrame>(ws, B.desc);
+  const int *gframe = at<const int>(ws, B.gframe);
+  const int *bf = at<const int>(ws, B.blk_frame), *bc = at<const int>(ws, B.blk_chunk);
+  float4 *geom = at<float4>(ws, B.geom);
+  int4 *rect = at<int4>(ws, B.rect);
+  int *counts = at<int>(ws, B.counts), *offsets = at<int>(ws, B.offsets);
+  int *misc = at<int>(ws, B.misc);
+  unsigned *counter = at<unsigned>(ws, B.counter);
+  uint32_t *ka = at<uint32_t>(ws, B.keys_a), *kb = at<uint32_t>(ws, B.keys_b);
+  uint32_t *hist = at<uint32_t>(ws, B.hist);
+  const unsigned nb = (unsigned)((B.Ntot + 255) / 256);
+  hipLaunchKernelGGL(k_b_project, dim3(nb), dim3(256), 0, st, B.Ntot, D, gframe, B.T, xy, chol,
+                     geom, rect, counts);
+  hipLaunchKernelGGL(k_b_scan_counts, dim3(B.F), dim3(SCAN_BLOCK), 0, st, D, counts, offsets, misc,
+                     tick, counter);
+  hipLaunchKernelGGL(k_b_emit_keys, dim3(nb), dim3(256), 0, st, B.Ntot, D, gframe, rect, offsets,
+                     ka);
+  uint32_t *src = ka, *dst = kb;
+  for (int p = 0; p < B.passes; ++p) {
+    const int shift = 16 + RADIX_BITS * p;
+    hipLaunchKernelGGL(k_b_radix_hist, dim3(B.sort_blocks), dim3(SORT_BLOCK), 0, st, D, bf, bc,
+                       misc, src, shift, hist);
+    hipLaunchKernelGGL(k_b_radix_scan, dim3(B.F), dim3(SCAN_BLOCK), 0, st, D, hist);
+    hipLaunchKernelGGL(k_b_radix_scatter, dim3(B.sort_blocks), dim3(SORT_BLOCK), 0, st, D, bf, bc,
+                       misc, src, dst, shift, hist);
+    std::swap(src, dst);
+  }
+  hipLaunchKernelGGL(k_b_tile_ranges, dim3(32, B.F), dim3(256), 0, st, D, misc, src,
+                     at<int>(ws, B.tile_start));
+  return hipGetLastError();
+}
+
+const uint32_t *batch_sorted_keys(const BatchLayout &B, void *ws) {
+  return at<const uint32_t>(ws, (B.passes & 1) ? B.keys_b : B.keys_a);
+}
+
+hipError_t enqueue_batch_raster(const BatchLayout &B, void *ws, int grid, const float *rgb,
+                                const float *targets, float *g_xy, float *g_chol, float *g_rgb,
+                                hipStream_t st) {
+  BatchRaster a;
+  a.D = at<const BFrame>(ws, B.desc);
+  a.queue = at<const uint32_t>(ws, B.queue);
+  a.n_items = (unsigned)B.tiles_tot;
+  a.counter = at<unsigned>(ws, B.counter);
+  a.geom = at<const float4>(ws, B.geom);
+  a.keys = batch_sorted_keys(B, ws);
+  a.tile_start = at<const int>(ws, B.tile_start);
+  a.rgb = rgb;
+  a.targets = targets;
+  a.loss_part = at<float>(ws, B.loss_part);
+  a.g_xy = g_xy;
+  a.g_chol = g_chol;
+  a.g_rgb = g_rgb;
+  bool done = false;
+#define CASE(TT, PP)                                                                          \
+  if (!done && B.T == TT && B.ppl == PP) {                                                    \
+    hipLaunchKernelGGL((k_b_render_persistent<TT, PP>), dim3(grid), dim3(Cfg<TT, PP>::NT), 0, \
+                       st, a);                                                                \
+    done = true;                                                                              \
+  }
+  CASE(8, 1) CASE(16, 1) CASE(16, 2) CASE(32, 1) CASE(32, 2) CASE(32, 4)
+#undef CASE
+  return done ? hipGetLastError() : hipErrorInvalidValue;
+}
+
+hipError_t enqueue_batch_iteration(const BatchLayout &B, void *ws, int grid, const float *targets,
+                                   float *xy, float *chol, float *rgb, float *m, float *v,
+                                   int32_t *step, float *trace, int trace_rows,
+                                   const gs2d_adam_cfg &cfg, hipStream_t st) {
+  float *g = at<float>(ws, B.grads);
+  float *g_xy = g, *g_chol = g + 2 * B.Ntot, *g_rgb = g + 5 * B.Ntot;
+  hipError_t e = enqueue_batch_binning(B, ws, xy, chol, step, st);
+  if (e == hipSuccess) e = enqueue_batch_raster(B, ws, grid, rgb, targets, g_xy, g_chol, g_rgb, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_b_loss, dim3(B.F), dim3(256), 0, st, at<const BFrame>(ws, B.desc), B.F,
+                       at<const float>(ws, B.loss_part), step, trace, trace_rows);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)
+    e = launch_adam((int)B.Ntot, xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg, nullptr, 1,
+                    nullptr, 0, 0.f, nullptr, 0, st);
+  return e;
+}
+
+int check_batch_ws(int F, const gs2d_frame *frames, int tile, int ppl, void *ws, size_t ws_bytes,
+                   BatchLayout *B) {
+  if (!batch_layout(F, frames, tile, ppl, B)) return GS2D_EINVAL;
+  if (B->Ntot > (1LL << 31) / 8) return GS2D_EINVAL;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255)) return GS2D_EINVAL;
+  if (ws_bytes < B->total) return GS2D_ENOSPACE;
+  return GS2D_OK;
+}
+
+struct Owned {
+  hipStream_t s = nullptr;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ~Owned() {
+    if (x) (void)hipGraphExecDestroy(x);
+    if (g) (void)hipGraphDestroy(g);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  }
+};
+
+}  // namespace
+
+}  // namespace gs2d
+
+using namespace gs2d;
+
+extern "C" size_t gs2d_batch_workspace_bytes(int32_t n_frames, const gs2d_frame *frames,
+                                             int32_t tile, int32_t px_per_lane) {
+  try {
+    BatchLayout B;
+    return batch_layout(n_frames, frames, tile, px_per_lane, &B) ? B.total : 0;
+  } catch (...) {
+    return 0;
+  }
+}
+
+extern "C" int gs2d_fit_batch(int32_t n_frames, const gs2d_frame *frames, int32_t tile,
+                              int32_t px_per_lane, const float *targets, float *xy, float *chol,
+                              float *rgb, float *m, float *v, int32_t *step, float *loss_trace,
+                              int32_t trace_rows, void *ws, size_t ws_bytes,
+                              const gs2d_fit_opts *opts, gs2d_fit_stats *stats, void *stream) {
+  try {
+    const auto t0 = std::chrono::steady_clock::now();
+    BatchLayout B;
+    int rc = check_batch_ws(n_frames, frames, tile, px_per_lane, ws, ws_bytes, &B);
+    if (rc != GS2D_OK) return rc;
+    if (!targets || !xy || !chol || !rgb || !m || !v || !step || !loss_trace || !opts)
+      return GS2D_EINVAL;
+    if (opts->iters < 0 || opts->check_every < 1) return GS2D_EINVAL;
+    if (stats) {
+      stats->iters_run = 0;
+      stats->iter_hit_target = -1;
+      stats->final_loss = NAN;
+      stats->final_psnr = NAN;
+      stats->seconds = 0.0;
+      stats->status = 0;
+      stats->n_culled = 0;
+    }
+    if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return GS2D_EHIP;
+    int32_t step0 = 0;
+    if (hipMemcpy(&step0, step, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+      return GS2D_EHIP;
+    if (step0 < 0 || (long long)step0 + opts->iters >= (long long)trace_rows) return GS2D_EINVAL;
+    Owned O;
+    if (hipStreamCreateWithFlags(&O.s, hipStreamNonBlocking) != hipSuccess) return GS2D_EHIP;
+    hipStream_t st = O.s;
+    if (upload_tables(B, ws, st) != hipSuccess) return GS2D_EHIP;
+    const int grid = batch_grid(B);
+    if (grid < 1) return GS2D_EHIP;
+    if (launch_fill_zero_u32(at<uint32_t>(ws, B.misc), (size_t)BM_STRIDE * B.F, st) != hipSuccess ||
+        launch_fill_zero_u32(at<uint32_t>(ws, B.counter), 16, st) != hipSuccess ||
+        launch_fill_zero(at<float>(ws, B.grads), 8 * (size_t)B.Ntot, st) != hipSuccess)
+      return GS2D_EHIP;
+    const int F = B.F;
+    std::vector<float> rows((size_t)opts->check_every * F);
+    std::vector<int> misc_host((size_t)BM_STRIDE * F);
+    int done = 0, graph_k = 0, hit = -1;
+    double last_mean = NAN;
+    uint32_t sticky = 0;
+    while (done < opts->iters) {
+      const int k = std::min(opts->check_every, opts->iters - done);
+      if (opts->use_graph) {
+        if (graph_k != k) {
+          if (O.x) (void)hipGraphExecDestroy(O.x), O.x = nullptr;
+          if (O.g) (void)hipGraphDestroy(O.g), O.g = nullptr;
+          if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return GS2D_EHIP;
+          hipError_t ce = hipSuccess;
+          for (int i = 0; i < k && ce == hipSuccess; ++i)
+            ce = enqueue_batch_iteration(B, ws, grid, targets, xy, chol, rgb, m, v, step,
+                                         loss_trace, trace_rows, opts->adam, st);
+          hipError_t ee = hipStreamEndCapture(st, &O.g);
+          if (ce != hipSuccess || ee != hipSuccess) return GS2D_EHIP;
+          if (hipGraphInstantiate(&O.x, O.g, nullptr, nullptr, 0) != hipSuccess) return GS2D_EHIP;
+          graph_k = k;
+        }
+        if (hipGraphLaunch(O.x, st) != hipSuccess) return GS2D_EHIP;
+      } else {
+        for (int i = 0; i < k; ++i)
+          if (enqueue_batch_iteration(B, ws, grid, targets, xy, chol, rgb, m, v, step, loss_trace,
+                                      trace_rows, opts->adam, st) != hipSuccess)
+            return GS2D_EHIP;
+      }
+      if (hipMemcpyAsync(rows.data(), loss_trace + (size_t)(step0 + done) * F,
+                         sizeof(float) * (size_t)k * F, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipMemcpyAsync(misc_host.data(), at<int>(ws, B.misc), sizeof(int) * misc_host.size(),
+                         hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return GS2D_EHIP;
+      sticky = 0;
+      for (int f = 0; f < F; ++f) sticky |= (uint32_t)misc_host[(size_t)BM_STRIDE * f + BM_STICKY];
+      for (int i = 0; i < k; ++i) {
+        double worst = INFINITY, mean = 0.0;
+        for (int f = 0; f < F; ++f) {
+          const double l = rows[(size_t)i * F + f];
+          mean += l / F;
+          worst = std::min(worst, l > 0 ? 10.0 * std::log10(1.0 / l) : INFINITY);
+        }
+        last_mean = mean;
+        if (hit < 0 && opts->psnr_target > 0.f && worst >= opts->psnr_target) hit = done + i;
+      }
+      done += k;
+      if ((sticky & STATUS_OVERFLOW) || hit >= 0) break;
+    }
+    if (stats) {
+      int culled = 0;
+      for (int f = 0; f < F; ++f) culled += misc_host[(size_t)BM_STRIDE * f + BM_N_CULLED];
+      stats->iters_run = done;
+      stats->iter_hit_target = hit;
+      stats->final_loss = (float)last_mean;
+      stats->final_psnr = last_mean > 0 ? (float)(10.0 * std::log10(1.0 / last_mean)) : INFINITY;
+      stats->status = sticky;
+      stats->n_culled = culled;
+      stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return (sticky & STATUS_OVERFLOW) ? GS2D_EOVERFLOW : GS2D_OK;
+  } catch (...) {
+    return GS2D_EHIP;
+  }
+}
+
+// Binning + persistent raster of a batch (no optimiser step), for
+// inspection and timing: builds every frame's tile lists and accumulates the
+// gradients of the summed per-frame MSE into g_* (not cleared).
+extern "C" int gs2d_batch_render_grads(int32_t n_frames, const gs2d_frame *frames, int32_t tile,
+                                       int32_t px_per_lane, const float *targets, const float *xy,
+                                       const float *chol, const float *rgb, float *g_xy,
+                                       float *g_chol, float *g_rgb, float *loss_per_frame,
+                                       void *ws, size_t ws_bytes, void *stream) {
+  try {
+    BatchLayout B;
+    int rc = check_batch_ws(n_frames, frames, tile, px_per_lane, ws, ws_bytes, &B);
+    if (rc != GS2D_OK) return rc;
+    if (!targets || !xy || !chol || !rgb || !g_xy || !g_chol || !g_rgb) return GS2D_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (upload_tables(B, ws, st) != hipSuccess) return GS2D_EHIP;
+    const int grid = batch_grid(B);
+    if (grid < 1) return GS2D_EHIP;
+    hipError_t e = launch_fill_zero_u32(at<uint32_t>(ws, B.misc), (size_t)BM_STRIDE * B.F, st);
+    if (e == hipSuccess) e = launch_fill_zero_u32(at<uint32_t>(ws, B.counter), 16, st);
+    if (e == hipSuccess)
+      e = enqueue_batch_binning(B, ws, xy, chol, nullptr, st);
+    if (e == hipSuccess)
+      e = enqueue_batch_raster(B, ws, grid, rgb, targets, g_xy, g_chol, g_rgb, st);
+    if (e == hipSuccess && loss_per_frame) {
+      // a step counter of 1 makes k_b_loss write row 0 = loss_per_frame
+      int32_t *one = at<int32_t>(ws, B.counter) + 8;
+      const int32_t h_one = 1;
+      e = hipMemcpyAsync(one, &h_one, sizeof(int32_t), hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_b_loss, dim3(B.F), dim3(256), 0, st, at<const BFrame>(ws, B.desc), B.F,
+                           at<const float>(ws, B.loss_part), one, loss_per_frame, 1);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) e = hipStreamSynchronize(st);  // h_one leaves scope
+    }
+    return e == hipSuccess ? GS2D_OK : GS2D_EHIP;
+  } catch (...) {
+    return GS2D_EHIP;
+  }
+}
+
+// Device views of frame f's binning results inside a batch workspace (after
+// gs2d_batch_render_grads or gs2d_fit_batch), in the one-frame format.
+extern "C" int gs2d_batch_bins_view(int32_t n_frames, const gs2d_frame *frames, int32_t tile,
+                                    int32_t px_per_lane, int32_t f, void *ws, size_t ws_bytes,
+                                    gs2d_bins *out) {
+  try {
+    BatchLayout B;
+    int rc = check_batch_ws(n_frames, frames, tile, px_per_lane, ws, ws_bytes, &B);
+    if (rc != GS2D_OK) return rc;
+    if (!out || f < 0 || f >= n_frames) return GS2D_EINVAL;
+    const BFrame &d = B.frames[f];
+    int *misc = at<int>(ws, B.misc) + BM_STRIDE * f;
+    out->geom = at<const float>(ws, B.geom) + 8 * d.g_off;
+    out->counts = at<const int32_t>(ws, B.counts) + d.g_off;
+    out->offsets = at<const int32_t>(ws, B.offsets) + d.g_off + f;
+    out->keys = batch_sorted_keys(B, ws) + d.key_off;
+    out->tile_start = at<const int32_t>(ws, B.tile_start) + d.tile_off + f;
+    out->n_pairs = misc + BM_N_PAIRS;
+    out->status = reinterpret_cast<const uint32_t *>(misc + BM_STATUS);
+    out->n_culled = misc + BM_N_CULLED;
+    out->n_tiles = d.n_tiles;
+    out->tiles_x = d.TX;
+    out->tiles_y = d.TY;
+    return GS2D_OK;
+  } catch (...) {
+    return GS2D_EHIP;
+  }
+}
+
+// Autotuner: times `reps` rounds of (batched binning + persistent fused
+// raster) for each candidate (tile, px_per_lane) with HIP events and
+// returns the mean milliseconds per round in out_ms[i] and the fastest
+// candidate's index in *best.  ws must hold gs2d_batch_workspace_bytes for
+// every candidate; grad_scratch must hold 8 * sum(N) floats.
+extern "C" int gs2d_autotune_batch(int32_t n_frames, const gs2d_frame *frames,
+                                   const float *targets, const float *xy, const float *chol,
+                                   const float *rgb, int32_t n_cand, const int32_t *cand_tile,
+                                   const int32_t *cand_ppl, int32_t reps, float *grad_scratch,
+                                   void *ws, size_t ws_bytes, float *out_ms, int32_t *best,
+                                   void *stream) {
+  try {
+    if (n_cand < 1 || !cand_tile || !cand_ppl || reps < 1 || !out_ms || !best || !grad_scratch)
+      return GS2D_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    Owned O;
+    if (hipEventCreate(&O.e0) != hipSuccess || hipEventCreate(&O.e1) != hipSuccess)
+      return GS2D_EHIP;
+    float best_ms = INFINITY;
+    *best = -1;
+    for (int c = 0; c < n_cand; ++c) {
+      BatchLayout B;
+      int rc = check_batch_ws(n_frames, frames, cand_tile[c], cand_ppl[c], ws, ws_bytes, &B);
+      if (rc != GS2D_OK) return rc;
+      if (upload_tables(B, ws, st) != hipSuccess) return GS2D_EHIP;
+      const int grid = batch_grid(B);
+      if (grid < 1) return GS2D_EHIP;
+      float *g_xy = grad_scratch, *g_chol = g_xy + 2 * B.Ntot, *g_rgb = g_xy + 5 * B.Ntot;
+      hipError_t e = launch_fill_zero_u32(at<uint32_t>(ws, B.misc), (size_t)BM_STRIDE * B.F, st);
+      if (e == hipSuccess) e = launch_fill_zero_u32(at<uint32_t>(ws, B.counter), 16, st);
+      // one untimed round, then the timed ones
+      for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+        if (r == 1) e = hipEventRecord(O.e0, st);
+        if (e == hipSuccess) e = enqueue_batch_binning(B, ws, xy, chol, nullptr, st);
+        if (e == hipSuccess)
+          e = enqueue_batch_raster(B, ws, grid, rgb, targets, g_xy, g_chol, g_rgb, st);
+      }
+      if (e == hipSuccess) e = hipEventRecord(O.e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(O.e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, O.e0, O.e1);
+      if (e != hipSuccess) return GS2D_EHIP;
+      out_ms[c] = ms / reps;
+      if (out_ms[c] < best_ms) {
+        best_ms = out_ms[c];
+        *best = c;
+      }
+    }
+    return GS2D_OK;
+  } catch (...) {
+    return GS2D_EHIP;
+  }
+}

@@ -32,6 +32,7 @@ constexpr int SCAN_BLOCK = 1024;
 // Byte offsets of every array inside one frame's workspace.
 struct Layout {
   int W, H, N, T, max_pairs;
+  int ppl;             // pixels per lane of the raster kernels (1, 2, 4)
   int TX, TY, n_tiles;
   int sort_blocks;     // G: chunks of the key array, one sort block each
   int sort_passes;     // 8-bit digit passes over the tile bits

@@ -1,0 +1,344 @@
+// Device-side building blocks of the tile rasteriser for Eq. 2 and its
+// backward pass, shared by the one-frame kernels (raster.hip) and the
+// persistent batched kernel (batch.hip).  See raster.hip for the scheme.
+#pragma once
+
+#include "gs2d_internal.h"
+
+namespace gs2d {
+
+constexpr float NEG_HALF_LOG2E = -0.72134752044448170368f;  // -log2(e)/2
+constexpr float CUTOFF_Q = 9.0f;
+constexpr int CH = 256;  // Gaussians staged per LDS chunk
+
+template <int TILE, int PPL>
+struct Cfg {
+  static constexpr int SBH = 8 * PPL;      // sub-block height (px)
+  static constexpr int SBX = TILE / 8;     // sub-blocks per tile row
+  static constexpr int SBY = TILE / SBH;   // sub-block rows per tile
+  static constexpr int NW = SBX * SBY;     // wavefronts per tile
+  static constexpr int NT = NW * 64;       // threads per tile
+  static_assert(SBY >= 1 && NW <= 16, "unsupported tile / pixels-per-lane");
+};
+
+template <int NW>
+struct Smem {
+  float4 A[CH];           // mx, my, 1/l1, l2
+  float4 B[CH];           // 1/l3, c'0, c'1, c'2
+  uint32_t mask[CH];      // bit w: box meets sub-block w
+  int id[CH];
+  uint16_t list[NW][CH];
+  float red[NW];
+};
+
+struct FrameArgs {
+  int W, H, TX;
+  const float4 *geom;
+  const uint32_t *keys;
+  const int *tile_start;
+  const float *rgb;
+};
+
+// Stage keys[beg, beg+cnt) into LDS with their sub-block masks.
+template <int TILE, int PPL>
+__device__ inline void stage_chunk(Smem<Cfg<TILE, PPL>::NW> &S, const uint32_t *__restrict__ keys,
+                                   int beg, int cnt, int tx, int ty,
+                                   const float4 *__restrict__ geom, const float *__restrict__ rgb) {
+  using C = Cfg<TILE, PPL>;
+  constexpr float inv_w = 0.125f, inv_h = 1.0f / (float)C::SBH;
+  for (int j = threadIdx.x; j < cnt; j += C::NT) {
+    const int id = (int)(keys[beg + j] & 0xFFFFu);
+    const float4 g0 = geom[2 * id], g1 = geom[2 * id + 1];
+    float c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    if (rgb) {  // pair counting stages geometry only
+      c0 = rgb[3 * id];
+      c1 = rgb[3 * id + 1];
+      c2 = rgb[3 * id + 2];
+    }
+    S.A[j] = g0;
+    S.B[j] = make_float4(g1.x, c0, c1, c2);
+    S.id[j] = id;
+    const float xlo = __fsub_rn(g0.x, g1.y), xhi = __fadd_rn(g0.x, g1.y);
+    const float ylo = __fsub_rn(g0.y, g1.z), yhi = __fadd_rn(g0.y, g1.z);
+    // sub-block columns/rows met by the box, tile-local
+    const float bx0f = floorf(xlo * inv_w) - (float)(tx * C::SBX);
+    const float bx1f = floorf(xhi * inv_w) - (float)(tx * C::SBX);
+    const float by0f = floorf(ylo * inv_h) - (float)(ty * C::SBY);
+    const float by1f = floorf(yhi * inv_h) - (float)(ty * C::SBY);
+    const int bx0 = (int)fmaxf(bx0f, 0.f), bx1 = (int)fminf(bx1f, (float)(C::SBX - 1));
+    const int by0 = (int)fmaxf(by0f, 0.f), by1 = (int)fminf(by1f, (float)(C::SBY - 1));
+    uint32_t m = 0;
+    for (int by = by0; by <= by1; ++by)
+      for (int bx = bx0; bx <= bx1; ++bx) m |= 1u << (by * C::SBX + bx);
+    S.mask[j] = m;
+  }
+}
+
+// Each wavefront builds its list of staged Gaussians; returns its length.
+template <int NW>
+__device__ inline int compact_chunk(Smem<NW> &S, int cnt) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const unsigned long long lt = lanemask_lt();
+  int len = 0;
+  for (int j0 = 0; j0 < cnt; j0 += 64) {
+    const int j = j0 + lane;
+    const bool hit = (j < cnt) && ((S.mask[j] >> w) & 1u);
+    const unsigned long long bal = __ballot(hit);
+    if (hit) S.list[w][len + __popcll(bal & lt)] = (uint16_t)j;
+    len += __popcll(bal);
+  }
+  return len;
+}
+
+// ---- wavefront reduction of 8 values ----
+// Sum of 8 per-lane values over the wavefront; lane L returns the total of
+// value ((L >> 3) & 7).  Each exchange halves the number of values a lane
+// carries:
+//   - across the two 32-lane halves, v_permlane32_swap of (value i, value
+//     i+4) leaves value i of both halves in the low half and value i+4 of
+//     both halves in the high half; one add finishes the pair;
+//   - across 16-lane rows, v_permlane16_swap, the same way;
+//   - across 8 lanes inside a row and then within each 8-lane group, DPP
+//     (row_ror:8, row_half_mirror, quad_perm) folded into the adds.
+template <int CTRL>
+__device__ inline float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+constexpr int DPP_ROW_ROR8 = 0x128;
+constexpr int DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_QUAD_XOR2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int DPP_QUAD_XOR1 = 0xB1;  // quad_perm [1,0,3,2]
+
+__device__ inline float reduce8_transpose(const float (&a)[8]) {
+  const int lane = threadIdx.x & 63;
+  float b[4], c[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a[i]), __float_as_uint(a[i + 4]),
+                                              false, false);
+    b[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(b[i]), __float_as_uint(b[i + 2]),
+                                              false, false);
+    c[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  const bool hi = lane & 8;
+  float d = (hi ? c[1] : c[0]) + dpp<DPP_ROW_ROR8>(hi ? c[0] : c[1]);
+  d += dpp<DPP_ROW_HALF_MIRROR>(d);
+  d += dpp<DPP_QUAD_XOR2>(d);
+  d += dpp<DPP_QUAD_XOR1>(d);
+  return d;
+}
+
+// Pixel column and first row of this thread.
+template <int TILE, int PPL>
+__device__ inline void pixel_of_thread(int tx, int ty, int *px, int *py0) {
+  using C = Cfg<TILE, PPL>;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  *px = tx * TILE + (w % C::SBX) * 8 + (lane & 7);
+  *py0 = ty * TILE + (w / C::SBX) * C::SBH + (lane >> 3) * PPL;
+}
+
+// Forward accumulation over one staged, compacted chunk.  With KEEP_HITS the
+// wavefront's list is compacted in place to the Gaussians that have at least
+// one in-frame pixel with q <= 9 in this sub-block (the only ones the
+// backward pass needs); returns the new length (else `len`).
+template <int NW, int PPL, bool KEEP_HITS>
+__device__ inline int fwd_chunk(Smem<NW> &S, int len, float pxc, float pyc0, unsigned inside,
+                                float (&acc)[PPL][3]) {
+  const int w = threadIdx.x >> 6;
+  int kept = 0;
+  for (int k = 0; k < len; ++k) {
+    const int j = S.list[w][k];
+    const float4 A = S.A[j], B = S.B[j];
+    const float u1 = (pxc - A.x) * A.z;
+    const float u1s = u1 * u1;
+    const float base = (pyc0 - A.y) - A.w * u1;
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < PPL; ++r) {
+      const float u2 = (base + (float)r) * B.x;
+      const float q = u1s + u2 * u2;
+      const float e = __builtin_amdgcn_exp2f(q * NEG_HALF_LOG2E);
+      const bool in_cut = q <= CUTOFF_Q;
+      const float wgt = in_cut ? e : 0.f;
+      acc[r][0] += wgt * B.y;
+      acc[r][1] += wgt * B.z;
+      acc[r][2] += wgt * B.w;
+      any |= in_cut && ((inside >> r) & 1u);
+    }
+    if (KEEP_HITS) {
+      if (__ballot(any)) {
+        if ((threadIdx.x & 63) == 0) S.list[w][kept] = (uint16_t)j;  // kept <= k
+        ++kept;
+      }
+    }
+  }
+  return KEEP_HITS ? kept : len;
+}
+
+// Backward over one staged, compacted chunk; adds into acc[CH][8] in LDS.
+// CHECK_HITS skips (uniformly per wavefront) Gaussians with no pixel inside
+// the cutoff, for lists that were not already reduced to such Gaussians.
+template <int NW, int PPL, bool CHECK_HITS>
+__device__ inline void bwd_chunk(const Smem<NW> &S, float *acc, int len, float pxc, float pyc0,
+                                 const float (&g)[PPL][3]) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int k = 0; k < len; ++k) {
+    const int j = S.list[w][k];
+    const float4 A = S.A[j], B = S.B[j];
+    const float u1 = (pxc - A.x) * A.z;
+    const float u1s = u1 * u1;
+    const float base = (pyc0 - A.y) - A.w * u1;
+    float u2[PPL], q[PPL];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < PPL; ++r) {
+      u2[r] = (base + (float)r) * B.x;
+      q[r] = u1s + u2[r] * u2[r];
+      any |= q[r] <= CUTOFF_Q;
+    }
+    if (CHECK_HITS && !__ballot(any)) continue;  // wavefront-uniform skip
+    float s1 = 0.f, s2 = 0.f, s3 = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+#pragma unroll
+    for (int r = 0; r < PPL; ++r) {
+      const float e = __builtin_amdgcn_exp2f(q[r] * NEG_HALF_LOG2E);
+      const float wgt = (q[r] <= CUTOFF_Q) ? e : 0.f;
+      const float sn = (g[r][0] * B.y + g[r][1] * B.z + g[r][2] * B.w) * wgt;
+      const float v2 = u2[r] * B.x;
+      const float v1 = (u1 - A.w * v2) * A.z;
+      const float t2 = sn * v2;
+      s1 += sn * v1;
+      s2 += t2;
+      s3 += t2 * u2[r];
+      c0 += g[r][0] * wgt;
+      c1 += g[r][1] * wgt;
+      c2 += g[r][2] * wgt;
+    }
+    // dL/dl1 = sum s v1 u1 and dL/dl2 = sum s v2 u1: u1 is common to the lane
+    const float vals[8] = {s1, s2, s1 * u1, s2 * u1, s3, c0, c1, c2};
+    const float red = reduce8_transpose(vals);
+    if ((lane & 7) == 0) atomicAdd(&acc[j * 8 + (lane >> 3)], red);
+  }
+}
+
+// Flush the LDS accumulators of a chunk to the global gradients.
+template <int NT, int NW>
+__device__ inline void flush_grads(const Smem<NW> &S, const float *acc, int cnt,
+                                   float *__restrict__ g_xy, float *__restrict__ g_chol,
+                                   float *__restrict__ g_rgb) {
+  for (int j = threadIdx.x; j < cnt; j += NT) {
+    const int id = S.id[j];
+    const float *a = acc + j * 8;
+    if (a[0] != 0.f) atomicAdd(&g_xy[2 * id + 0], a[0]);
+    if (a[1] != 0.f) atomicAdd(&g_xy[2 * id + 1], a[1]);
+    if (a[2] != 0.f) atomicAdd(&g_chol[3 * id + 0], a[2]);
+    if (a[3] != 0.f) atomicAdd(&g_chol[3 * id + 1], a[3]);
+    if (a[4] != 0.f) atomicAdd(&g_chol[3 * id + 2], a[4]);
+    if (a[5] != 0.f) atomicAdd(&g_rgb[3 * id + 0], a[5]);
+    if (a[6] != 0.f) atomicAdd(&g_rgb[3 * id + 1], a[6]);
+    if (a[7] != 0.f) atomicAdd(&g_rgb[3 * id + 2], a[7]);
+  }
+}
+
+// Block sum of one float per thread; the result is valid in thread 0.
+template <int NW>
+__device__ inline float block_sum(Smem<NW> &S, float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) S.red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  float s = 0.f;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < NW; ++w) s += S.red[w];
+  return s;
+}
+
+// Bit r set: pixel row r of this lane lies inside the frame.
+template <int PPL>
+__device__ inline unsigned inside_mask(const FrameArgs &f, int px, int py0) {
+  unsigned m = 0;
+#pragma unroll
+  for (int r = 0; r < PPL; ++r) m |= (px < f.W && py0 + r < f.H) ? (1u << r) : 0u;
+  return m;
+}
+
+
+// ------------------------------------------- fused forward + loss + backward --
+// Eq. 2 is an order-free sum and every Gaussian reaching a pixel is in that
+// pixel's tile list, so a tile can finish its forward pass, form
+// dL/dC = 2 (C - target) / (3HW) in registers and run its backward pass
+// without dL/dC ever reaching memory.  One call processes one tile with the
+// whole workgroup; the block sum of its squared residuals goes to *loss_slot.
+template <int TILE, int PPL>
+__device__ inline void fused_tile(Smem<Cfg<TILE, PPL>::NW> &S, float *acc, const FrameArgs &f,
+                                  int tile, const float *__restrict__ target,
+                                  float *__restrict__ loss_slot, float grad_scale,
+                                  float *__restrict__ g_xy, float *__restrict__ g_chol,
+                                  float *__restrict__ g_rgb) {
+  using C = Cfg<TILE, PPL>;
+  const int tx = tile % f.TX, ty = tile / f.TX;
+  const int beg = f.tile_start[tile], end = f.tile_start[tile + 1];
+  int px, py0;
+  pixel_of_thread<TILE, PPL>(tx, ty, &px, &py0);
+  const float pxc = (float)px + 0.5f, pyc0 = (float)py0 + 0.5f;
+  const unsigned inside = inside_mask<PPL>(f, px, py0);
+  const bool single = (end - beg) <= CH;  // the whole list fits one LDS chunk
+  float a[PPL][3] = {};
+  int len = 0;
+  for (int c = beg; c < end; c += CH) {
+    const int cnt = min(CH, end - c);
+    __syncthreads();
+    stage_chunk<TILE, PPL>(S, f.keys, c, cnt, tx, ty, f.geom, f.rgb);
+    __syncthreads();
+    len = compact_chunk<C::NW>(S, cnt);
+    __syncthreads();
+    // a single chunk stays in LDS for the backward pass: keep only the
+    // Gaussians that reach this wavefront's pixels
+    if (single)
+      len = fwd_chunk<C::NW, PPL, true>(S, len, pxc, pyc0, inside, a);
+    else
+      fwd_chunk<C::NW, PPL, false>(S, len, pxc, pyc0, inside, a);
+  }
+  float g[PPL][3];
+  float l = 0.f;
+  const size_t HW = (size_t)f.W * f.H;
+#pragma unroll
+  for (int r = 0; r < PPL; ++r) {
+    g[r][0] = g[r][1] = g[r][2] = 0.f;
+    if ((inside >> r) & 1u) {
+      const size_t p = (size_t)(py0 + r) * f.W + px;
+      const float r0 = a[r][0] - target[p], r1 = a[r][1] - target[HW + p],
+                  r2 = a[r][2] - target[2 * HW + p];
+      l += r0 * r0 + r1 * r1 + r2 * r2;
+      g[r][0] = r0 * grad_scale;
+      g[r][1] = r1 * grad_scale;
+      g[r][2] = r2 * grad_scale;
+    }
+  }
+  __syncthreads();
+  const float s = block_sum<C::NW>(S, l);
+  if (threadIdx.x == 0) *loss_slot = s;
+  if (beg >= end) return;
+  for (int c = beg; c < end; c += CH) {
+    const int cnt = min(CH, end - c);
+    __syncthreads();
+    if (!single) stage_chunk<TILE, PPL>(S, f.keys, c, cnt, tx, ty, f.geom, f.rgb);
+    for (int i = threadIdx.x; i < CH * 8; i += C::NT) acc[i] = 0.f;
+    __syncthreads();
+    if (!single) {
+      len = compact_chunk<C::NW>(S, cnt);
+      __syncthreads();
+      bwd_chunk<C::NW, PPL, true>(S, acc, len, pxc, pyc0, g);
+    } else {
+      bwd_chunk<C::NW, PPL, false>(S, acc, len, pxc, pyc0, g);
+    }
+    __syncthreads();
+    flush_grads<C::NT, C::NW>(S, acc, cnt, g_xy, g_chol, g_rgb);
+  }
+}
+
+
+}  // namespace gs2d

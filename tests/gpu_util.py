@@ -23,8 +23,8 @@ def host(t):
 class GpuFrame:
     """Shape + workspace for one frame on the GPU."""
 
-    def __init__(self, W, H, N, tile=16, max_pairs=None):
-        self.shape = _lib.make_shape(W, H, N, tile, max_pairs)
+    def __init__(self, W, H, N, tile=16, max_pairs=None, ppl=1):
+        self.shape = _lib.make_shape(W, H, N, tile, max_pairs, ppl)
         self.ws = _lib.alloc_workspace(self.shape)
         self.W, self.H, self.N = W, H, N
 
@@ -73,3 +73,7 @@ def assert_grads_close(gpu, ref, rel=1e-3):
         bad = err > bound
         assert not bad.any(), (f"g_{k}: {bad.sum()} elements out of tolerance; worst err "
                                f"{err[bad].max():.3e}")
+
+
+# every compiled raster variant: (tile, pixels per lane)
+VARIANTS = [(8, 1), (16, 1), (16, 2), (32, 1), (32, 2), (32, 4)]

@@ -48,9 +48,11 @@ def test_workspace_bytes_validation(lib):
     assert n > 0 and n % 256 == 0
     bigger = _lib.make_shape(1920, 1080, 30000, 16, max_pairs=ok.max_pairs * 2)
     assert _lib.workspace_bytes(bigger) > n
-    for bad in (_lib.Shape(0, 10, 5, 16, 100), _lib.Shape(10, 10, 0, 16, 100),
-                _lib.Shape(10, 10, 70000, 16, 100), _lib.Shape(10, 10, 5, 12, 100),
-                _lib.Shape(10, 10, 5, 16, 0), _lib.Shape(8192, 8192, 5, 8, 100)):
+    for bad in (_lib.Shape(0, 10, 5, 16, 100, 1), _lib.Shape(10, 10, 0, 16, 100, 1),
+                _lib.Shape(10, 10, 70000, 16, 100, 1), _lib.Shape(10, 10, 5, 12, 100, 1),
+                _lib.Shape(10, 10, 5, 16, 0, 1), _lib.Shape(8192, 8192, 5, 8, 100, 1),
+                _lib.Shape(64, 64, 5, 8, 100, 2), _lib.Shape(64, 64, 5, 16, 100, 3),
+                _lib.Shape(64, 64, 5, 32, 100, 8)):
         assert lib.gs2d_workspace_bytes(ctypes.byref(bad)) == 0
 
 

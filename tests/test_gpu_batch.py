@@ -1,0 +1,124 @@
+"""Batched fitting: the persistent (frame, tile) raster and the segmented
+per-frame binning against the oracle, frame by frame, and the autotuner."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.binning import bin_gaussians
+from oracle.fit import fit as oracle_fit
+from oracle.grads import gradients
+from oracle.loss import dloss_dimg, mse
+from oracle.render import render_box
+from paper_2505_09324_amd import _lib, synth
+from gpu_util import DEV, VARIANTS, assert_grads_close, dev, host
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [(96, 64, 300), (130, 77, 700), (64, 64, 200), (200, 120, 1500), (50, 40, 100)]
+
+
+def _batch_inputs(sizes, seed):
+    frames, params = [], []
+    for i, (w, h, n) in enumerate(sizes):
+        f, _ = synth.make_frame(w, h, seed=seed + i)
+        xy, chol, rgb = synth.random_gaussians(n, w, h, seed=seed + 100 + i, scale_lo=0.8,
+                                               scale_hi=5.0)
+        chol[:, 1] = np.random.default_rng(seed + 200 + i).uniform(-1.5, 1.5, n).astype(np.float32)
+        frames.append(f)
+        params.append((xy, chol, rgb))
+    targets = np.concatenate([f.ravel() for f in frames])
+    cat = [np.concatenate([p[k] for p in params]) for k in range(3)]
+    return frames, params, targets, cat
+
+
+def _split(a, sizes, per):
+    out, o = [], 0
+    for _, _, n in sizes:
+        out.append(a[o:o + n * per].reshape(n, per) if per > 1 else a[o:o + n])
+        o += n * per
+    return out
+
+
+@pytest.mark.parametrize("T,ppl", VARIANTS)
+def test_batch_render_matches_oracle_per_frame(T, ppl):
+    print(f"batch render T={T} ppl={ppl}", flush=True)
+    frames, params, targets, cat = _batch_inputs(SMALL, 500)
+    Nt = sum(n for _, _, n in SMALL)
+    ws = torch.empty(_lib.batch_workspace_bytes(SMALL, T, ppl), dtype=torch.uint8, device=DEV)
+    g = [torch.zeros(Nt, d, device=DEV) for d in (2, 3, 3)]
+    loss = torch.zeros(len(SMALL), device=DEV)
+    _lib.batch_render_grads(SMALL, T, ppl, dev(targets), dev(cat[0]), dev(cat[1]), dev(cat[2]),
+                            *g, ws, loss_per_frame=loss)
+    torch.cuda.synchronize()
+    gx = _split(host(g[0]).ravel(), SMALL, 2)
+    gc = _split(host(g[1]).ravel(), SMALL, 3)
+    gr = _split(host(g[2]).ravel(), SMALL, 3)
+    for f, ((w, h, n), frame, (xy, chol, rgb)) in enumerate(zip(SMALL, frames, params)):
+        b = _lib.read_batch_bins(SMALL, T, ppl, f, ws)
+        ob = bin_gaussians(xy, chol, w, h, T)
+        np.testing.assert_array_equal(b["keys"].astype(np.int64),
+                                      ob["pair_tiles"] * 65536 + ob["pair_ids"])
+        np.testing.assert_array_equal(b["tile_start"], ob["tile_start"])
+        img = render_box(xy, chol, rgb, h, w, want_bounds=False)["img"]
+        assert float(loss[f]) == pytest.approx(mse(img, frame), rel=1e-4)
+        ref = gradients(xy, chol, rgb, dloss_dimg(img, frame), h, w)
+        assert_grads_close({"xy": gx[f], "chol": gc[f], "rgb": gr[f]}, ref)
+
+
+def test_fit_batch_trajectories_match_oracle():
+    """10 lockstep Adam steps: every frame's loss trace vs the oracle loop
+    run on that frame alone (1e-3 relative)."""
+    print("fit batch trajectory", flush=True)
+    sizes = SMALL[:3]
+    frames, params, targets, cat = _batch_inputs(sizes, 600)
+    Nt = sum(n for _, _, n in sizes)
+    ws = torch.empty(_lib.batch_workspace_bytes(sizes, 16, 1), dtype=torch.uint8, device=DEV)
+    P = [dev(c) for c in cat]
+    m = torch.zeros(8 * Nt, device=DEV)
+    v = torch.zeros(8 * Nt, device=DEV)
+    step = torch.zeros(1, dtype=torch.int32, device=DEV)
+    trace = torch.full((32, len(sizes)), -1.0, device=DEV)
+    st = _lib.fit_batch(sizes, 16, 1, dev(targets), *P, m, v, step, trace, ws,
+                        _lib.fit_opts(10, 5, cfg=_lib.adam_cfg(1e-2)))
+    assert st.iters_run == 10 and int(step[0]) == 10
+    tr = host(trace)
+    for f, (frame, (xy, chol, rgb)) in enumerate(zip(frames, params)):
+        _, losses = oracle_fit(xy, chol, rgb, frame, 10, lr=1e-2)
+        np.testing.assert_allclose(tr[:10, f], losses, rtol=1e-3)
+    assert np.all(tr[10:] == -1.0)
+
+
+def test_autotuner_and_full_batch_workload():
+    """The 48-frame batched workload (sizes drawn from 320x240 .. 1920x1080,
+    3k-50k Gaussians from the content-aware init): the autotuner times every
+    variant; 3 lockstep iterations run without overflow; one small frame's
+    bins and loss match the oracle."""
+    print("full batch", flush=True)
+    from paper_2505_09324_amd import workloads
+    sizes, targets, xy, chol, rgb, frames_np = workloads.batch_inputs(48, seed=400, device=DEV)
+    cands = [(8, 1), (16, 1), (16, 2), (32, 2)]
+    best, ms = _lib.autotune_batch(sizes, targets, xy, chol, rgb, cands, reps=2)
+    assert 0 <= best < len(cands) and all(x > 0 for x in ms)
+    T, ppl = cands[best]
+    Nt = sum(n for _, _, n in sizes)
+    ws = torch.empty(_lib.batch_workspace_bytes(sizes, T, ppl), dtype=torch.uint8, device=DEV)
+    x0, c0, r0 = xy.clone(), chol.clone(), rgb.clone()
+    m = torch.zeros(8 * Nt, device=DEV)
+    v = torch.zeros(8 * Nt, device=DEV)
+    step = torch.zeros(1, dtype=torch.int32, device=DEV)
+    trace = torch.zeros((8, len(sizes)), device=DEV)
+    st = _lib.fit_batch(sizes, T, ppl, targets, xy, chol, rgb, m, v, step, trace, ws,
+                        _lib.fit_opts(3, 3, cfg=_lib.adam_cfg((2e-2, 5e-3, 5e-3))))
+    assert st.code == 0 and st.iters_run == 3
+    f = min(range(len(sizes)), key=lambda i: sizes[i][0] * sizes[i][1])
+    w, h, n = sizes[f]
+    off = sum(s[2] for s in sizes[:f])
+    pxy, pch, prgb = (host(t)[off:off + n] for t in (x0, c0, r0))
+    img = render_box(pxy, pch, prgb, h, w, want_bounds=False)["img"]
+    assert float(trace[0, f]) == pytest.approx(mse(img, frames_np[f]), rel=1e-4)
+    # bins of the final state of that frame
+    g = [torch.zeros(Nt, d, device=DEV) for d in (2, 3, 3)]
+    _lib.batch_render_grads(sizes, T, ppl, targets, xy, chol, rgb, *g, ws)
+    b = _lib.read_batch_bins(sizes, T, ppl, f, ws)
+    ob = bin_gaussians(host(xy)[off:off + n], host(chol)[off:off + n], w, h, T)
+    np.testing.assert_array_equal(b["keys"].astype(np.int64), ob["pair_tiles"] * 65536 + ob["pair_ids"])

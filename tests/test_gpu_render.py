@@ -11,7 +11,7 @@ from oracle.grads import gradients
 from oracle.loss import dloss_dimg, mse
 from oracle.render import render_box, render_bruteforce, render_pixels
 from paper_2505_09324_amd import synth
-from gpu_util import GpuFrame, assert_grads_close, assert_pixels_close, dev, host
+from gpu_util import VARIANTS, GpuFrame, assert_grads_close, assert_pixels_close, dev, host
 
 pytestmark = pytest.mark.gpu
 
@@ -22,11 +22,11 @@ def _c1():
     return frame, xy, chol, rgb
 
 
-@pytest.mark.parametrize("T", [8, 16, 32])
-def test_forward_tiny_frame(T):
-    print(f"fwd tiny T={T}", flush=True)
+@pytest.mark.parametrize("T,ppl", VARIANTS)
+def test_forward_tiny_frame(T, ppl):
+    print(f"fwd tiny T={T} ppl={ppl}", flush=True)
     frame, xy, chol, rgb = _c1()
-    f = GpuFrame(128, 128, 500, T)
+    f = GpuFrame(128, 128, 500, T, ppl=ppl)
     img, dl, loss = f.forward(dev(xy), dev(chol), dev(rgb), dev(frame))
     ref = render_bruteforce(xy, chol, rgb, 128, 128)
     assert_pixels_close(host(img), ref)
@@ -61,20 +61,21 @@ def test_forward_ragged_frame_long_lists():
     xy, chol, rgb = synth.random_gaussians(N, W, H, seed=12, scale_lo=2.0, scale_hi=9.0)
     chol[:, 1] = np.random.default_rng(2).uniform(-3, 3, N).astype(np.float32)
     rgb -= 0.5
-    for T in (8, 16, 32):
-        f = GpuFrame(W, H, N, T)
+    ref = render_box(xy, chol, rgb, H, W)
+    for T, ppl in VARIANTS:
+        f = GpuFrame(W, H, N, T, ppl=ppl)
         b = f.bin(dev(xy), dev(chol))
         assert np.diff(b["tile_start"]).max() > 256
         img, _, _ = f.forward(dev(xy), dev(chol), dev(rgb))
-        assert_pixels_close(host(img), render_box(xy, chol, rgb, H, W), what=f"T={T}")
+        assert_pixels_close(host(img), ref, what=f"T={T} ppl={ppl}")
 
 
-@pytest.mark.parametrize("T", [8, 16, 32])
-def test_backward_tiny_frame(T):
-    print(f"bwd tiny T={T}", flush=True)
+@pytest.mark.parametrize("T,ppl", VARIANTS)
+def test_backward_tiny_frame(T, ppl):
+    print(f"bwd tiny T={T} ppl={ppl}", flush=True)
     frame, xy, chol, rgb = _c1()
     chol[:, 1] = np.random.default_rng(4).uniform(-1, 1, 500).astype(np.float32)
-    f = GpuFrame(128, 128, 500, T)
+    f = GpuFrame(128, 128, 500, T, ppl=ppl)
     dl = dloss_dimg(render_box(xy, chol, rgb, 128, 128, want_bounds=False)["img"], frame)
     f.forward(dev(xy), dev(chol), dev(rgb))
     gx, gc, gr = f.backward(dev(rgb), dev(dl.astype(np.float32)))
@@ -90,8 +91,8 @@ def test_backward_long_lists():
     target = np.random.default_rng(8).uniform(0, 1, (3, H, W)).astype(np.float32)
     dl = dloss_dimg(render_box(xy, chol, rgb, H, W, want_bounds=False)["img"], target).astype(np.float32)
     ref = gradients(xy, chol, rgb, dl, H, W)
-    for T in (8, 16, 32):
-        f = GpuFrame(W, H, N, T)
+    for T, ppl in VARIANTS:
+        f = GpuFrame(W, H, N, T, ppl=ppl)
         f.forward(dev(xy), dev(chol), dev(rgb))
         gx, gc, gr = f.backward(dev(rgb), dev(dl))
         assert_grads_close({"xy": host(gx), "chol": host(gc), "rgb": host(gr)}, ref)
@@ -134,16 +135,16 @@ def test_full_hd_sampled_pixels_and_gaussians():
         assert_grads_close(got, r)
 
 
-@pytest.mark.parametrize("T", [8, 16, 32])
-def test_fused_render_matches_oracle_and_counts_pairs(T):
+@pytest.mark.parametrize("T,ppl", VARIANTS)
+def test_fused_render_matches_oracle_and_counts_pairs(T, ppl):
     """Fused forward+MSE+backward: loss and accumulated gradients vs the
     oracle; the in-cutoff pair count vs the oracle's count."""
-    print(f"fused T={T}", flush=True)
+    print(f"fused T={T} ppl={ppl}", flush=True)
     from oracle.render import count_pairs_in_cutoff
     from paper_2505_09324_amd import _lib
     frame, xy, chol, rgb = _c1()
     chol[:, 1] = np.random.default_rng(4).uniform(-1, 1, 500).astype(np.float32)
-    f = GpuFrame(128, 128, 500, T)
+    f = GpuFrame(128, 128, 500, T, ppl=ppl)
     P = [dev(xy), dev(chol), dev(rgb)]
     _lib.project_bin(f.shape, P[0], P[1], f.ws)
     g = [torch.zeros(500, d, device="cuda") for d in (2, 3, 3)]
