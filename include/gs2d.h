@@ -287,6 +287,69 @@ int gs2d_autotune_batch(int32_t n_frames, const gs2d_frame *frames, const float 
                         float *grad_scratch, void *ws, size_t ws_bytes, float *out_ms,
                         int32_t *best, void *stream);
 
+/* --------------------------------------------------- learned initialiser --
+ * A per-tile convolutional regressor standing in for the paper's Gaussian
+ * attribute regressor (Sec. 3.2.B): input [H][W] frame + residual against
+ * the previous frame, 4 x (conv3x3 stride 2, 64 channels, ReLU), a conv3x3
+ * head with 73 channels per 16x16 tile = 9 count logits (0..8 Gaussians)
+ * + 8 slots x 8 parameters (mu_x = x0 + 16 sigmoid(p0), mu_y = y0 + 16
+ * sigmoid(p1), l1 = exp(p2), l2 = p3, l3 = exp(p4), colour p5..p7).  It is
+ * trained with a per-tile cross-entropy on the count plus a Chamfer set loss
+ * on the slots (the paper's remedy for unordered Gaussians), on Gaussians the
+ * fitter produced.  BF16 weights and activations, FP32 accumulation on MFMA.
+ *
+ * Buffers (caller-owned, device): master FP32 weights [param_count]; BF16
+ * weight copies [bf16_weight_count] (uint16); workspace
+ * [cnn_workspace_bytes] holding activations, the head output, the current
+ * training targets and gradients of activations.  H, W >= 16. */
+size_t gs2d_cnn_param_count(int32_t H, int32_t W);
+size_t gs2d_cnn_workspace_bytes(int32_t H, int32_t W);
+size_t gs2d_cnn_bf16_weight_count(int32_t H, int32_t W);
+/* info[12] = {Hin, Win, Cin, Hout, Wout, Cout, stride, relu, rows, K, w_off,
+ * b_off} of layer 0..4; the master weights of a layer are a [rows][K] matrix
+ * at w_off with K index = tap * Cin + ci (tap = 3 ky + kx), bias at b_off. */
+int gs2d_cnn_layer_info(int32_t H, int32_t W, int32_t layer, int32_t *info);
+/* He-normal weights from caller-supplied N(0,1) draws [param_count]; 0 bias. */
+int gs2d_cnn_init_params(int32_t H, int32_t W, const float *normal_draws, float *master,
+                         void *stream);
+/* Refresh the BF16 copies (forward and transposed layouts) from master. */
+int gs2d_cnn_sync_weights(int32_t H, int32_t W, const float *master, uint16_t *wbf16,
+                          void *stream);
+/* Forward pass; frame/prev [3][H][W] FP32 (prev NULL: zero residual);
+ * head_out [73][TY][TX] FP32 (nullable; the head also stays in ws). */
+int gs2d_cnn_forward(int32_t H, int32_t W, const float *frame, const float *prev,
+                     const float *master, const uint16_t *wbf16, float *head_out, void *ws,
+                     size_t ws_bytes, void *stream);
+/* Per-tile training targets from N fitted Gaussians (stored in ws): the
+ * Gaussians whose centre lies in the tile, at most 8, the heaviest by
+ * |l1 l3| |c'|^2 (ties to the lower index).  scratch: >= 2*4N + 4*256*G +
+ * 4*(tiles+1) + 256 bytes, 256-aligned.  Synchronises `stream`. */
+int gs2d_cnn_targets(int32_t H, int32_t W, int32_t N, const float *xy, const float *chol,
+                     const float *rgb, void *ws, size_t ws_bytes, void *scratch,
+                     size_t scratch_bytes, void *stream);
+/* Copy the stored targets out: counts [tiles] int32, vectors [tiles][8][8]
+ * (slot s < count: the target in loss units, else 0). */
+int gs2d_cnn_read_targets(int32_t H, int32_t W, const void *ws, size_t ws_bytes, int32_t *counts,
+                          float *vectors, void *stream);
+/* Loss of the last forward pass against the stored targets and the backward
+ * pass: weight and bias gradients are ADDED to grad [param_count];
+ * loss3 (nullable) = {total, mean CE, mean Chamfer}. */
+int gs2d_cnn_backward(int32_t H, int32_t W, const float *master, const uint16_t *wbf16,
+                      float *grad, float *loss3, void *ws, size_t ws_bytes, void *stream);
+/* Adam on the master weights (step: device int32 counter, incremented),
+ * decoupled weight decay, clears grad, refreshes the BF16 copies. */
+int gs2d_cnn_adam(int32_t H, int32_t W, float *master, float *grad, float *m, float *v,
+                  int32_t *step, float lr, float weight_decay, uint16_t *wbf16, void *stream);
+/* Decode the last forward pass into N Gaussians: per tile argmax count and
+ * that many slots, in tile order; kept up to N and topped up from the plain
+ * initialisation plain_* [N]; the plain initialisation is used entirely when
+ * fewer than N/2 Gaussians are predicted or any value is non-finite.
+ * n_predicted: device int32, the number of predicted Gaussians used. */
+int gs2d_cnn_decode(int32_t H, int32_t W, int32_t N, const float *plain_xy,
+                    const float *plain_chol, const float *plain_rgb, float *xy, float *chol,
+                    float *rgb, int32_t *n_predicted, void *ws, size_t ws_bytes, void *scratch,
+                    size_t scratch_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -91,6 +91,25 @@ _SIGS = {
     "gs2d_autotune_batch": (c_int32, [c_int32, POINTER(Frame), c_void_p, c_void_p, c_void_p,
                                       c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p,
                                       c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),
+    "gs2d_cnn_param_count": (c_size_t, [c_int32, c_int32]),
+    "gs2d_cnn_workspace_bytes": (c_size_t, [c_int32, c_int32]),
+    "gs2d_cnn_bf16_weight_count": (c_size_t, [c_int32, c_int32]),
+    "gs2d_cnn_layer_info": (c_int32, [c_int32, c_int32, c_int32, c_void_p]),
+    "gs2d_cnn_init_params": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
+    "gs2d_cnn_sync_weights": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
+    "gs2d_cnn_forward": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gs2d_cnn_targets": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]),
+    "gs2d_cnn_read_targets": (c_int32, [c_int32, c_int32, c_void_p, c_size_t, c_void_p, c_void_p,
+                                        c_void_p]),
+    "gs2d_cnn_backward": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                    c_void_p, c_size_t, c_void_p]),
+    "gs2d_cnn_adam": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                c_void_p, c_float, c_float, c_void_p, c_void_p]),
+    "gs2d_cnn_decode": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                                  c_void_p, c_size_t, c_void_p]),
     "gs2d_init_workspace_bytes": (c_size_t, [c_int32, c_int32]),
     "gs2d_init_plain": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
                                   c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -401,3 +420,133 @@ def autotune_batch(sizes, targets, xy, chol, rgb, candidates, reps=5):
         int(reps), _ptr(scratch, "scratch"), _ptr(ws, "ws", torch.uint8), ws.numel(), out,
         ctypes.byref(best), _stream()))
     return int(best.value), [float(x) for x in out]
+
+
+# -------------------------------------------------------- learned initialiser --
+class CNNInit:
+    """Device state of the per-tile regressor for H x W frames: FP32 master
+    weights, their BF16 (and transposed BF16) copies, Adam moments, the
+    activation workspace.  Every method is one or a few C ABI calls."""
+
+    def __init__(self, H, W, seed=7, device="cuda"):
+        from . import synth
+        L = lib()
+        self.H, self.W = int(H), int(W)
+        self.n_params = int(L.gs2d_cnn_param_count(self.H, self.W))
+        if self.n_params == 0:
+            raise GS2DError("gs2d_cnn_param_count", GS2D_EINVAL)
+        self.master = torch.zeros(self.n_params, device=device)
+        draws = torch.from_numpy(synth.random_normal(self.n_params, seed)).to(device)
+        _check("gs2d_cnn_init_params", L.gs2d_cnn_init_params(
+            self.H, self.W, _ptr(draws, "draws"), _ptr(self.master, "master"), _stream()))
+        self.wbf16 = torch.zeros(int(L.gs2d_cnn_bf16_weight_count(self.H, self.W)), dtype=torch.int16,
+                                 device=device)
+        self.sync()
+        self.ws = torch.empty(int(L.gs2d_cnn_workspace_bytes(self.H, self.W)), dtype=torch.uint8,
+                              device=device)
+        self.grad = torch.zeros_like(self.master)
+        self.m = torch.zeros_like(self.master)
+        self.v = torch.zeros_like(self.master)
+        self.step_count = torch.zeros(1, dtype=torch.int32, device=device)
+        self.scratch = torch.empty(1 << 20, dtype=torch.uint8, device=device)
+        self.loss3 = torch.zeros(3, device=device)
+        hd = self.layer_info(4)
+        self.TY, self.TX = hd["Hout"], hd["Wout"]
+
+    def sync(self):
+        _check("gs2d_cnn_sync_weights", lib().gs2d_cnn_sync_weights(
+            self.H, self.W, _ptr(self.master, "master"), _ptr(self.wbf16, "wbf16", torch.int16),
+            _stream()))
+
+    def layer_info(self, i):
+        info = (c_int32 * 12)()
+        _check("gs2d_cnn_layer_info", lib().gs2d_cnn_layer_info(self.H, self.W, i, info))
+        keys = ("Hin", "Win", "Cin", "Hout", "Wout", "Cout", "stride", "relu", "Mpad", "Kf",
+                "w_off", "b_off")
+        return dict(zip(keys, list(info)))
+
+    def forward(self, frame, prev=None, head_out=None):
+        _check("gs2d_cnn_forward", lib().gs2d_cnn_forward(
+            self.H, self.W, _ptr(frame, "frame", shape=(3, self.H, self.W)),
+            _ptr(prev, "prev", shape=(3, self.H, self.W), allow_none=True),
+            _ptr(self.master, "master"), _ptr(self.wbf16, "wbf16", torch.int16),
+            _ptr(head_out, "head_out", allow_none=True), _ptr(self.ws, "ws", torch.uint8),
+            self.ws.numel(), _stream()))
+
+    def set_targets(self, xy, chol, rgb):
+        N = xy.shape[0]
+        need = 2 * (((4 * N + 255) // 256) * 256) + (1 << 18) + 4 * (self.TX * self.TY + 1) + 4096
+        if self.scratch.numel() < need:
+            self.scratch = torch.empty(need, dtype=torch.uint8, device=xy.device)
+        _check("gs2d_cnn_targets", lib().gs2d_cnn_targets(
+            self.H, self.W, N, _ptr(xy, "xy", shape=(N, 2)), _ptr(chol, "chol", shape=(N, 3)),
+            _ptr(rgb, "rgb", shape=(N, 3)), _ptr(self.ws, "ws", torch.uint8), self.ws.numel(),
+            _ptr(self.scratch, "scratch", torch.uint8), self.scratch.numel(), _stream()))
+
+    def read_targets(self):
+        n = self.TX * self.TY
+        counts = torch.zeros(n, dtype=torch.int32, device=self.ws.device)
+        vec = torch.zeros(n, 8, 8, device=self.ws.device)
+        _check("gs2d_cnn_read_targets", lib().gs2d_cnn_read_targets(
+            self.H, self.W, _ptr(self.ws, "ws", torch.uint8), self.ws.numel(),
+            _ptr(counts, "counts", torch.int32), _ptr(vec, "vec"), _stream()))
+        return counts, vec
+
+    def backward(self):
+        """Head loss + full backward; gradients ADDED to self.grad (cleared by step)."""
+        _check("gs2d_cnn_backward", lib().gs2d_cnn_backward(
+            self.H, self.W, _ptr(self.master, "master"), _ptr(self.wbf16, "wbf16", torch.int16),
+            _ptr(self.grad, "grad"), _ptr(self.loss3, "loss3"), _ptr(self.ws, "ws", torch.uint8),
+            self.ws.numel(), _stream()))
+        return self.loss3
+
+    def step(self, lr=1e-3, weight_decay=0.0):
+        _check("gs2d_cnn_adam", lib().gs2d_cnn_adam(
+            self.H, self.W, _ptr(self.master, "master"), _ptr(self.grad, "grad"),
+            _ptr(self.m, "m"), _ptr(self.v, "v"), _ptr(self.step_count, "step", torch.int32),
+            float(lr), float(weight_decay), _ptr(self.wbf16, "wbf16", torch.int16), _stream()))
+
+    def decode(self, N, plain_xy, plain_chol, plain_rgb):
+        dev = plain_xy.device
+        xy = torch.empty(N, 2, device=dev)
+        chol = torch.empty(N, 3, device=dev)
+        rgb = torch.empty(N, 3, device=dev)
+        npred = torch.zeros(1, dtype=torch.int32, device=dev)
+        _check("gs2d_cnn_decode", lib().gs2d_cnn_decode(
+            self.H, self.W, int(N), _ptr(plain_xy, "plain_xy", shape=(N, 2)),
+            _ptr(plain_chol, "plain_chol", shape=(N, 3)), _ptr(plain_rgb, "plain_rgb", shape=(N, 3)),
+            _ptr(xy, "xy"), _ptr(chol, "chol"), _ptr(rgb, "rgb"), _ptr(npred, "npred", torch.int32),
+            _ptr(self.ws, "ws", torch.uint8), self.ws.numel(),
+            _ptr(self.scratch, "scratch", torch.uint8), self.scratch.numel(), _stream()))
+        return xy, chol, rgb, npred
+
+    def oracle_params(self):
+        """Master weights as a list of (w [Cout, Cin, 3, 3], b [Cout]) numpy
+        arrays in the oracle's layout (input layer: 6 real channels)."""
+        import numpy as np
+        mw = self.master.detach().cpu().numpy()
+        out = []
+        for i in range(5):
+            d = self.layer_info(i)
+            cin_real = 6 if i == 0 else d["Cin"]
+            M = mw[d["w_off"]:d["w_off"] + d["Mpad"] * d["Kf"]].reshape(d["Mpad"], d["Kf"])
+            w = np.zeros((d["Cout"], cin_real, 3, 3), np.float32)
+            for tap in range(9):
+                w[:, :, tap // 3, tap % 3] = M[:d["Cout"], tap * d["Cin"]:tap * d["Cin"] + cin_real]
+            b = mw[d["b_off"]:d["b_off"] + d["Cout"]].copy()
+            out.append((w, b))
+        return out
+
+    def oracle_grads(self):
+        import numpy as np
+        gw = self.grad.detach().cpu().numpy()
+        out = []
+        for i in range(5):
+            d = self.layer_info(i)
+            cin_real = 6 if i == 0 else d["Cin"]
+            M = gw[d["w_off"]:d["w_off"] + d["Mpad"] * d["Kf"]].reshape(d["Mpad"], d["Kf"])
+            w = np.zeros((d["Cout"], cin_real, 3, 3), np.float32)
+            for tap in range(9):
+                w[:, :, tap // 3, tap % 3] = M[:d["Cout"], tap * d["Cin"]:tap * d["Cin"] + cin_real]
+            out.append((w, gw[d["b_off"]:d["b_off"] + d["Cout"]].copy()))
+        return out

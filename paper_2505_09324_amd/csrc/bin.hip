@@ -232,4 +232,27 @@ hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, v
   return hipGetLastError();
 }
 
+hipError_t launch_radix_sort_tiles(uint32_t *a, uint32_t *b, const int *misc, int G, uint32_t *hist,
+                                   int passes, hipStream_t st, const uint32_t **sorted) {
+  uint32_t *src = a, *dst = b;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 16 + RADIX_BITS * p;
+    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(SORT_BLOCK), 0, st, src, misc, shift, G, hist);
+    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(SCAN_BLOCK), 0, st, hist, G * RADIX);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(SORT_BLOCK), 0, st, src, dst, misc, shift, G,
+                       hist);
+    uint32_t *t = src;
+    src = dst;
+    dst = t;
+  }
+  *sorted = src;
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_ranges(const uint32_t *keys, const int *misc, int n_tiles, int *tile_start,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_tile_ranges, dim3(256), dim3(256), 0, st, keys, misc, n_tiles, tile_start);
+  return hipGetLastError();
+}
+
 }  // namespace gs2d

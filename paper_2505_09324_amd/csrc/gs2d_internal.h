@@ -57,6 +57,14 @@ inline T *at(void *ws, size_t off) {
 hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, void *ws,
                           hipStream_t st, int *step_tick = nullptr);
 
+// Stable LSD radix sort of keys on bits [16, 16 + 8*passes) with G sort
+// blocks; misc[0] holds the key count.  *sorted receives a or b.
+hipError_t launch_radix_sort_tiles(uint32_t *a, uint32_t *b, const int *misc, int G, uint32_t *hist,
+                                   int passes, hipStream_t st, const uint32_t **sorted);
+// tile_start[t] for sorted keys; misc[0] holds the key count.
+hipError_t launch_tile_ranges(const uint32_t *keys, const int *misc, int n_tiles, int *tile_start,
+                              hipStream_t st);
+
 // Raster (raster.hip).
 hipError_t launch_render_fwd(const Layout &L, void *ws, const float *rgb, const float *target,
                              float *img, float *dl_dimg, hipStream_t st);
