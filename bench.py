@@ -144,8 +144,10 @@ def main():
     ap.add_argument("--steps", type=int, default=1950)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--check-every", type=int, default=50)
-    ap.add_argument("--tile", type=int, default=TILE)
-    ap.add_argument("--ppl", type=int, default=1, help="pixels per lane of the raster kernels")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="tile size (8/16/32); 0 = choose with the autotuner")
+    ap.add_argument("--ppl", type=int, default=0,
+                    help="pixels per lane of the raster kernels (1/2/4); 0 = autotuner")
     ap.add_argument("--sweep", action="store_true",
                     help="also time the fused kernel for every (tile, ppl) variant (stderr)")
     ap.add_argument("--kernel-reps", type=int, default=50)
@@ -173,6 +175,12 @@ def main():
     td = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     xy, chol, rgb = _lib.init_plain(T, M8, td(draws.pick_roi), td(draws.jit_roi),
                                     td(draws.pick_out), td(draws.jit_out))
+    tune = None
+    if args.tile == 0 or args.ppl == 0:
+        cands = [(8, 1), (16, 1), (16, 2), (32, 1), (32, 2), (32, 4)]
+        best, ms = _lib.autotune_batch([(W, H, N)], T.reshape(-1), xy, chol, rgb, cands, reps=5)
+        args.tile, args.ppl = cands[best]
+        tune = {f"{t}/{p}": round(x * 1e3, 1) for (t, p), x in zip(cands, ms)}
     shape = _lib.make_shape(W, H, N, args.tile, px_per_lane=args.ppl)
     ws = _lib.alloc_workspace(shape)
     m = torch.zeros(8 * N, device=dev)
@@ -269,6 +277,7 @@ def main():
         "stages_us": {"project_bin": round(t_bin * 1e6, 2), "render_fused": round(t_fused * 1e6, 2),
                       "adam": round(t_adam * 1e6, 2)},
         "n_pairs": n_pairs,
+        "autotune_us_per_round": tune,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

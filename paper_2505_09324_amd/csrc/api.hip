@@ -47,6 +47,7 @@ bool make_layout(const gs2d_shape &s, Layout *L) {
   L->rect = take(N * 16);
   L->counts = take(N * 4);
   L->offsets = take((N + 1) * 4);
+  L->blocks = take(4096);  // per-projection-block sums (<= 256 blocks): 2 x int, 1 x int64
   L->keys_a = take((size_t)s.max_pairs * 4);
   L->keys_b = take((size_t)s.max_pairs * 4);
   L->hist = take((size_t)RADIX * L->sort_blocks * 4);

@@ -30,6 +30,8 @@ namespace {
 // Device descriptor of one frame of a batch (offsets in elements).
 struct BFrame {
   int W, H, N, TX, TY, n_tiles, G, cap;
+  int nb;              // projection blocks of BIN_BLOCK Gaussians
+  int blk_off;         // first projection block of the frame
   long long g_off;     // first Gaussian of the frame in the concatenated arrays
   long long px_off;    // first float of the frame's target ([3][H][W])
   long long key_off;   // first key slot
@@ -40,10 +42,10 @@ struct BFrame {
 enum BMisc : int { BM_N_PAIRS = 0, BM_STATUS = 1, BM_N_CULLED = 2, BM_STICKY = 3, BM_STRIDE = 8 };
 
 struct BatchLayout {
-  int F, T, ppl, passes, sort_blocks;
+  int F, T, ppl, passes, sort_blocks, proj_blocks;
   long long Ntot, keys_tot, hist_tot, tiles_tot;
-  size_t desc, gframe, blk_frame, blk_chunk, queue, geom, rect, counts, offsets, keys_a, keys_b,
-      hist, tile_start, loss_part, grads, misc, counter, total;
+  size_t desc, gframe, blk_frame, blk_chunk, pblk_frame, queue, geom, rect, counts, offsets,
+      bsum, bcull, boff, keys_a, keys_b, hist, tile_start, loss_part, grads, misc, counter, total;
   std::vector<BFrame> frames;
 };
 
@@ -59,7 +61,7 @@ bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout
   B->ppl = ppl;
   B->frames.resize(F);
   long long g = 0, px = 0, key = 0, hist = 0, tiles = 0;
-  int blocks = 0, maxbits = 1;
+  int blocks = 0, pblocks = 0, maxbits = 1;
   for (int f = 0; f < F; ++f) {
     const gs2d_frame &s = fr[f];
     if (s.W < 1 || s.H < 1 || s.N < 1 || s.N > 65536) return false;
@@ -75,6 +77,9 @@ bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout
     if (cap > (1 << 30)) return false;
     d.cap = (int)cap;
     d.G = std::max(1, std::min(SORT_MAX_BLOCKS, (d.cap + 2047) / 2048));
+    d.nb = (s.N + BIN_BLOCK - 1) / BIN_BLOCK;
+    d.blk_off = pblocks;
+    pblocks += d.nb;
     d.g_off = g;
     d.px_off = px;
     d.key_off = key;
@@ -92,6 +97,7 @@ bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout
   }
   B->passes = (maxbits + RADIX_BITS - 1) / RADIX_BITS;
   B->sort_blocks = blocks;
+  B->proj_blocks = pblocks;
   B->Ntot = g;
   B->keys_tot = key;
   B->hist_tot = hist;
@@ -106,11 +112,15 @@ bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout
   B->gframe = take(4 * (size_t)g);
   B->blk_frame = take(4 * (size_t)blocks);
   B->blk_chunk = take(4 * (size_t)blocks);
+  B->pblk_frame = take(4 * (size_t)pblocks);
   B->queue = take(4 * (size_t)tiles);
   B->geom = take(32 * (size_t)g);
   B->rect = take(16 * (size_t)g);
   B->counts = take(4 * (size_t)g);
   B->offsets = take(4 * ((size_t)g + F));
+  B->bsum = take(4 * (size_t)pblocks);
+  B->bcull = take(4 * (size_t)pblocks);
+  B->boff = take(8 * (size_t)pblocks);
   B->keys_a = take(4 * (size_t)key);
   B->keys_b = take(4 * (size_t)key);
   B->hist = take(4 * (size_t)hist);
@@ -124,63 +134,42 @@ bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout
 }
 
 // ------------------------------------------------------------ binning ----
-__global__ void __launch_bounds__(256)
-k_b_project(long long Ntot, const BFrame *__restrict__ D, const int *__restrict__ gframe, int tile,
+// Projection blocks never straddle frames: block b covers Gaussians
+// [b - blk_off, ...) * BIN_BLOCK of frame pblk_frame[b].
+__global__ void __launch_bounds__(BIN_BLOCK)
+k_b_project(const BFrame *__restrict__ D, const int *__restrict__ pblk_frame, int tile,
             const float *__restrict__ xy, const float *__restrict__ chol, float4 *__restrict__ geom,
-            int4 *__restrict__ rect, int *__restrict__ counts) {
-  const long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (g >= Ntot) return;
-  const BFrame d = D[gframe[g]];
-  project_gaussian((int)g, d.TX, d.TY, 1.0f / (float)tile, xy, chol, geom, rect, counts);
+            int4 *__restrict__ rect, int *__restrict__ counts, int *__restrict__ bsum,
+            int *__restrict__ bcull) {
+  const BFrame d = D[pblk_frame[blockIdx.x]];
+  const int c = blockIdx.x - d.blk_off;
+  const long long g = d.g_off;
+  project_block(c * BIN_BLOCK, d.N, d.TX, d.TY, 1.0f / (float)tile, xy + 2 * g, chol + 3 * g,
+                geom + 2 * g, rect + g, counts + g, bsum + blockIdx.x, bcull + blockIdx.x);
 }
 
-// One block per frame: offsets of the frame's keys, pair count, status.
-// Block 0 also advances the step counter (when given) and clears the
-// persistent raster's work counter for this iteration.
-__global__ void __launch_bounds__(SCAN_BLOCK)
-k_b_scan_counts(const BFrame *__restrict__ D, const int *__restrict__ counts,
+// One block per frame: scan of the frame's projection-block sums, pair
+// count, status.  Block 0 also advances the step counter (when given) and
+// clears the persistent raster's work counter for this iteration.
+__global__ void __launch_bounds__(BIN_BLOCK)
+k_b_scan_blocks(const BFrame *__restrict__ D, const int *__restrict__ bsum,
+                const int *__restrict__ bcull, long long *__restrict__ boff,
                 int *__restrict__ offsets, int *__restrict__ misc, int *__restrict__ tick,
                 unsigned *__restrict__ work_counter) {
-  __shared__ long long lds[SCAN_BLOCK / 64];
-  __shared__ int culled_w[SCAN_BLOCK / 64];
   const int f = blockIdx.x;
   const BFrame d = D[f];
-  const int N = d.N;
-  const int *cnt = counts + d.g_off;
-  int *off = offsets + d.g_off + f;
-  const int per = (N + SCAN_BLOCK - 1) / SCAN_BLOCK;
-  const int beg = min(N, (int)threadIdx.x * per), end = min(N, beg + per);
-  int v[SCAN_PER];
-#pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) v[k] = (k < per && beg + k < end) ? cnt[beg + k] : 0;
-  long long sum = 0;
-  int culled = 0;
-#pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) {
-    culled += (v[k] < 0);
-    sum += (v[k] > 0) ? v[k] : 0;
-  }
   long long total;
-  long long run = block_exclusive_scan<SCAN_BLOCK>(sum, &total, lds);
-#pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) {
-    if (k < per && beg + k < end) off[beg + k] = (int)min(run, (long long)d.cap);
-    run += (v[k] > 0) ? v[k] : 0;
-  }
-  for (int o = 32; o > 0; o >>= 1) culled += __shfl_xor(culled, o, 64);
-  if ((threadIdx.x & 63) == 0) culled_w[threadIdx.x >> 6] = culled;
-  __syncthreads();
+  int culled;
+  scan_block_sums(d.nb, bsum + d.blk_off, bcull + d.blk_off, boff + d.blk_off, &total, &culled);
   if (threadIdx.x == 0) {
-    int c = 0;
-    for (int w = 0; w < SCAN_BLOCK / 64; ++w) c += culled_w[w];
     const int np = (int)min(total, (long long)d.cap);
-    off[N] = np;
+    offsets[d.g_off + f + d.N] = np;
     const int st = (total > (long long)d.cap ? (int)STATUS_OVERFLOW : 0) |
-                   (c > 0 ? (int)STATUS_CULLED : 0);
+                   (culled > 0 ? (int)STATUS_CULLED : 0);
     int *m = misc + BM_STRIDE * f;
     m[BM_N_PAIRS] = np;
     m[BM_STATUS] = st;
-    m[BM_N_CULLED] = c;
+    m[BM_N_CULLED] = culled;
     m[BM_STICKY] |= st;
     if (f == 0) {
       if (tick) tick[0] += 1;
@@ -189,24 +178,16 @@ k_b_scan_counts(const BFrame *__restrict__ D, const int *__restrict__ counts,
   }
 }
 
-__global__ void __launch_bounds__(256)
-k_b_emit_keys(long long Ntot, const BFrame *__restrict__ D, const int *__restrict__ gframe,
-              const int4 *__restrict__ rect, const int *__restrict__ offsets,
+__global__ void __launch_bounds__(BIN_BLOCK)
+k_b_emit_keys(const BFrame *__restrict__ D, const int *__restrict__ pblk_frame,
+              const int4 *__restrict__ rect, const int *__restrict__ counts,
+              const long long *__restrict__ boff, int *__restrict__ offsets,
               uint32_t *__restrict__ keys) {
-  const long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (g >= Ntot) return;
-  const int f = gframe[g];
+  const int f = pblk_frame[blockIdx.x];
   const BFrame d = D[f];
-  const int n = (int)(g - d.g_off);
-  const int *off = offsets + d.g_off + f;
-  const int beg = off[n], end = off[n + 1];
-  if (end <= beg) return;
-  const int4 rc = rect[g];
-  uint32_t *k = keys + d.key_off;
-  int i = beg;
-  for (int ty = rc.y; ty <= rc.w && i < end; ++ty)
-    for (int tx = rc.x; tx <= rc.z && i < end; ++tx, ++i)
-      k[i] = ((uint32_t)(ty * d.TX + tx) << 16) | (uint32_t)n;
+  const int c = blockIdx.x - d.blk_off;
+  emit_block(c * BIN_BLOCK, d.N, d.TX, boff[blockIdx.x], d.cap, rect + d.g_off, counts + d.g_off,
+             offsets + d.g_off + f, keys + d.key_off);
 }
 
 __global__ void __launch_bounds__(SORT_BLOCK)
@@ -230,25 +211,8 @@ k_b_radix_hist(const BFrame *__restrict__ D, const int *__restrict__ blk_frame,
 // One block per frame: exclusive scan of its RADIX * G histogram.
 __global__ void __launch_bounds__(SCAN_BLOCK)
 k_b_radix_scan(const BFrame *__restrict__ D, uint32_t *__restrict__ hist_all) {
-  __shared__ long long lds[SCAN_BLOCK / 64];
   const BFrame d = D[blockIdx.x];
-  uint32_t *hist = hist_all + d.hist_off;
-  const int total_entries = RADIX * d.G;
-  const int per = (total_entries + SCAN_BLOCK - 1) / SCAN_BLOCK;
-  const int beg = min(total_entries, (int)threadIdx.x * per), end = min(total_entries, beg + per);
-  uint32_t v[SCAN_PER];
-#pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) v[k] = (k < per && beg + k < end) ? hist[beg + k] : 0u;
-  long long sum = 0;
-#pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) sum += v[k];
-  long long total;
-  long long run = block_exclusive_scan<SCAN_BLOCK>(sum, &total, lds);
-#pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) {
-    if (k < per && beg + k < end) hist[beg + k] = (uint32_t)run;
-    run += v[k];
-  }
+  scan_u32_block(hist_all + d.hist_off, RADIX * d.G);
 }
 
 __global__ void __launch_bounds__(SORT_BLOCK)
@@ -395,7 +359,7 @@ struct BatchRun {
 };
 
 hipError_t upload_tables(const BatchLayout &B, void *ws, hipStream_t st) {
-  std::vector<int> gframe((size_t)B.Ntot), bf, bc;
+  std::vector<int> gframe((size_t)B.Ntot), bf, bc, pf;
   std::vector<uint32_t> queue;
   queue.reserve((size_t)B.tiles_tot);
   for (int f = 0; f < B.F; ++f) {
@@ -405,6 +369,7 @@ hipError_t upload_tables(const BatchLayout &B, void *ws, hipStream_t st) {
       bf.push_back(f);
       bc.push_back(c);
     }
+    for (int c = 0; c < d.nb; ++c) pf.push_back(f);
   }
   // work order: frames by decreasing area (largest lists first), tiles in order
   std::vector<int> order(B.F);
@@ -424,6 +389,9 @@ hipError_t upload_tables(const BatchLayout &B, void *ws, hipStream_t st) {
                        st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(at<char>(ws, B.blk_chunk), bc.data(), 4 * bc.size(), hipMemcpyHostToDevice,
+                       st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(at<char>(ws, B.pblk_frame), pf.data(), 4 * pf.size(), hipMemcpyHostToDevice,
                        st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(at<char>(ws, B.queue), queue.data(), 4 * queue.size(),
@@ -456,7 +424,6 @@ int batch_grid(const BatchLayout &B) {
 hipError_t enqueue_batch_binning(const BatchLayout &B, void *ws, const float *xy, const float *chol,
                                  int *tick, hipStream_t st) {
   const BFrame *D = at<const BFrame>(ws, B.desc);
-  const int *gframe = at<const int>(ws, B.gframe);
   const int *bf = at<const int>(ws, B.blk_frame), *bc = at<const int>(ws, B.blk_chunk);
   float4 *geom = at<float4>(ws, B.geom);
   int4 *rect = at<int4>(ws, B.rect);
@@ -465,13 +432,15 @@ hipError_t enqueue_batch_binning(const BatchLayout &B, void *ws, const float *xy
   unsigned *counter = at<unsigned>(ws, B.counter);
   uint32_t *ka = at<uint32_t>(ws, B.keys_a), *kb = at<uint32_t>(ws, B.keys_b);
   uint32_t *hist = at<uint32_t>(ws, B.hist);
-  const unsigned nb = (unsigned)((B.Ntot + 255) / 256);
-  hipLaunchKernelGGL(k_b_project, dim3(nb), dim3(256), 0, st, B.Ntot, D, gframe, B.T, xy, chol,
-                     geom, rect, counts);
-  hipLaunchKernelGGL(k_b_scan_counts, dim3(B.F), dim3(SCAN_BLOCK), 0, st, D, counts, offsets, misc,
-                     tick, counter);
-  hipLaunchKernelGGL(k_b_emit_keys, dim3(nb), dim3(256), 0, st, B.Ntot, D, gframe, rect, offsets,
-                     ka);
+  const int *pf = at<const int>(ws, B.pblk_frame);
+  int *bsum = at<int>(ws, B.bsum), *bcull = at<int>(ws, B.bcull);
+  long long *boff = at<long long>(ws, B.boff);
+  hipLaunchKernelGGL(k_b_project, dim3(B.proj_blocks), dim3(BIN_BLOCK), 0, st, D, pf, B.T, xy, chol,
+                     geom, rect, counts, bsum, bcull);
+  hipLaunchKernelGGL(k_b_scan_blocks, dim3(B.F), dim3(BIN_BLOCK), 0, st, D, bsum, bcull, boff,
+                     offsets, misc, tick, counter);
+  hipLaunchKernelGGL(k_b_emit_keys, dim3(B.proj_blocks), dim3(BIN_BLOCK), 0, st, D, pf, rect, counts,
+                     boff, offsets, ka);
   uint32_t *src = ka, *dst = kb;
   for (int p = 0; p < B.passes; ++p) {
     const int shift = 16 + RADIX_BITS * p;

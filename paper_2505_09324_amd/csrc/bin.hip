@@ -17,83 +17,48 @@
 namespace gs2d {
 
 // ---------------------------------------------------------------- project --
-__global__ void __launch_bounds__(256)
+// One thread per Gaussian; each block also writes the sum of its tile counts
+// and of its culled Gaussians (bsum/bcull[block]).
+__global__ void __launch_bounds__(BIN_BLOCK)
 k_project(int N, int TX, int TY, float inv_tile, const float *__restrict__ xy,
           const float *__restrict__ chol, float4 *__restrict__ geom, int4 *__restrict__ rect,
-          int *__restrict__ counts) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  project_gaussian(n, TX, TY, inv_tile, xy, chol, geom, rect, counts);
+          int *__restrict__ counts, int *__restrict__ bsum, int *__restrict__ bcull) {
+  project_block(blockIdx.x * BIN_BLOCK, N, TX, TY, inv_tile, xy, chol, geom, rect, counts,
+                bsum + blockIdx.x, bcull + blockIdx.x);
 }
 
-// ------------------------------------------------------------ count scan --
-// One block.  Thread t owns the contiguous segment [t*per, t*per + per) and
-// issues all its loads before using them (they are independent), so the
-// block waits for one memory round trip instead of `per` of them.
-
-// offsets[n] = min(sum_{m<n} max(counts[m],0), max_pairs); offsets[N] and
-// misc[MISC_N_PAIRS] = min(total, max_pairs); status bits; culled count.
-// When `tick` is given its value is incremented once (the fitting loop's
-// step counter, read by the optimiser later in the same iteration).
-__global__ void __launch_bounds__(SCAN_BLOCK)
-k_scan_counts(int N, int max_pairs, const int *__restrict__ counts, int *__restrict__ offsets,
-              int *__restrict__ misc, int *__restrict__ tick) {
-  __shared__ long long lds[SCAN_BLOCK / 64];
-  __shared__ int culled_w[SCAN_BLOCK / 64];
-  const int per = (N + SCAN_BLOCK - 1) / SCAN_BLOCK;
-  const int beg = min(N, (int)threadIdx.x * per), end = min(N, beg + per);
-  int v[SCAN_PER];
-#pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) v[k] = (k < per && beg + k < end) ? counts[beg + k] : 0;
-  long long sum = 0;
-  int culled = 0;
-#pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) {
-    culled += (v[k] < 0);
-    sum += (v[k] > 0) ? v[k] : 0;
-  }
+// ---------------------------------------------------------- block sum scan --
+// One block: exclusive scan of the per-block pair counts (boff), total pair
+// count n_pairs = min(total, max_pairs) and offsets[N], status bits, culled
+// count.  When `tick` is given its value is incremented once (the fitting
+// loop's step counter, read by the optimiser later in the same iteration).
+__global__ void __launch_bounds__(BIN_BLOCK)
+k_scan_blocks(int N, int nb, int max_pairs, const int *__restrict__ bsum,
+              const int *__restrict__ bcull, long long *__restrict__ boff,
+              int *__restrict__ offsets, int *__restrict__ misc, int *__restrict__ tick) {
   long long total;
-  long long run = block_exclusive_scan<SCAN_BLOCK>(sum, &total, lds);
-#pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) {
-    if (k < per && beg + k < end) offsets[beg + k] = (int)min(run, (long long)max_pairs);
-    run += (v[k] > 0) ? v[k] : 0;
-  }
-  for (int o = 32; o > 0; o >>= 1) culled += __shfl_xor(culled, o, 64);
-  if ((threadIdx.x & 63) == 0) culled_w[threadIdx.x >> 6] = culled;
-  __syncthreads();
+  int culled;
+  scan_block_sums(nb, bsum, bcull, boff, &total, &culled);
   if (threadIdx.x == 0) {
-    int c = 0;
-    for (int w = 0; w < SCAN_BLOCK / 64; ++w) c += culled_w[w];
     const int np = (int)min(total, (long long)max_pairs);
     offsets[N] = np;
     const uint32_t st = (total > (long long)max_pairs ? STATUS_OVERFLOW : 0u) |
-                        (c > 0 ? STATUS_CULLED : 0u);
+                        (culled > 0 ? STATUS_CULLED : 0u);
     misc[MISC_N_PAIRS] = np;
     misc[MISC_STATUS] = (int)st;
-    misc[MISC_N_CULLED] = c;
+    misc[MISC_N_CULLED] = culled;
     misc[MISC_STICKY] |= (int)st;
     if (tick) tick[0] += 1;
   }
 }
 
 // ------------------------------------------------------------- emit keys --
-// One thread per Gaussian writes its keys, row-major over its rectangle, to
-// [offsets[n], offsets[n+1]) (already clamped to the capacity).
-__global__ void __launch_bounds__(256)
-k_emit_keys(int N, int TX, const int4 *__restrict__ rect, const int *__restrict__ offsets,
-            uint32_t *__restrict__ keys) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  const int beg = offsets[n], end = offsets[n + 1];
-  if (end <= beg) return;
-  const int4 rc = rect[n];
-  int k = beg;
-  for (int ty = rc.y; ty <= rc.w && k < end; ++ty) {
-    for (int tx = rc.x; tx <= rc.z && k < end; ++tx, ++k) {
-      keys[k] = ((uint32_t)(ty * TX + tx) << 16) | (uint32_t)n;
-    }
-  }
+__global__ void __launch_bounds__(BIN_BLOCK)
+k_emit_keys(int N, int TX, int max_pairs, const int4 *__restrict__ rect,
+            const int *__restrict__ counts, const long long *__restrict__ boff,
+            int *__restrict__ offsets, uint32_t *__restrict__ keys) {
+  emit_block(blockIdx.x * BIN_BLOCK, N, TX, boff[blockIdx.x], max_pairs, rect, counts, offsets,
+             keys);
 }
 
 // ------------------------------------------------------------ radix sort --
@@ -113,26 +78,10 @@ k_radix_hist(const uint32_t *__restrict__ keys, const int *__restrict__ misc, in
   hist[threadIdx.x * G + b] = h[threadIdx.x];
 }
 
-// Exclusive scan of the G*RADIX histogram in (digit, block) order, in place
-// (G*RADIX <= SORT_MAX_BLOCKS*RADIX entries, at most SCAN_PER per thread).
+// Exclusive scan of the G*RADIX histogram in (digit, block) order, in place.
 __global__ void __launch_bounds__(SCAN_BLOCK)
 k_radix_scan(uint32_t *__restrict__ hist, int total_entries) {
-  __shared__ long long lds[SCAN_BLOCK / 64];
-  const int per = (total_entries + SCAN_BLOCK - 1) / SCAN_BLOCK;
-  const int beg = min(total_entries, (int)threadIdx.x * per), end = min(total_entries, beg + per);
-  uint32_t v[SCAN_PER];
-#pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) v[k] = (k < per && beg + k < end) ? hist[beg + k] : 0u;
-  long long sum = 0;
-#pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) sum += v[k];
-  long long total;
-  long long run = block_exclusive_scan<SCAN_BLOCK>(sum, &total, lds);
-#pragma unroll
-  for (int k = 0; k < SCAN_PER; ++k) {
-    if (k < per && beg + k < end) hist[beg + k] = (uint32_t)run;
-    run += v[k];
-  }
+  scan_u32_block(hist, total_entries);
 }
 
 // Stable scatter of chunk b: in input order, each key goes to
@@ -206,14 +155,18 @@ hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, v
   int *counts = at<int>(ws, L.counts);
   int *offsets = at<int>(ws, L.offsets);
   int *misc = at<int>(ws, L.misc);
-  int4 *rectp = at<int4>(ws, L.rect);
-  const int nb = (L.N + 255) / 256;
-  hipLaunchKernelGGL(k_project, dim3(nb), dim3(256), 0, st, L.N, L.TX, L.TY, 1.0f / (float)L.T, xy,
-                     chol, geom, rectp, counts);
-  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(SCAN_BLOCK), 0, st, L.N, L.max_pairs, counts,
-                     offsets, misc, step_tick);
+  int4 *rect = at<int4>(ws, L.rect);
+  int *bsum = at<int>(ws, L.blocks);
+  int *bcull = bsum + 256;
+  long long *boff = at<long long>(ws, L.blocks + 2048);
+  const int nb = (L.N + BIN_BLOCK - 1) / BIN_BLOCK;
+  hipLaunchKernelGGL(k_project, dim3(nb), dim3(BIN_BLOCK), 0, st, L.N, L.TX, L.TY,
+                     1.0f / (float)L.T, xy, chol, geom, rect, counts, bsum, bcull);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(BIN_BLOCK), 0, st, L.N, nb, L.max_pairs, bsum,
+                     bcull, boff, offsets, misc, step_tick);
   uint32_t *ka = at<uint32_t>(ws, L.keys_a), *kb = at<uint32_t>(ws, L.keys_b);
-  hipLaunchKernelGGL(k_emit_keys, dim3(nb), dim3(256), 0, st, L.N, L.TX, rectp, offsets, ka);
+  hipLaunchKernelGGL(k_emit_keys, dim3(nb), dim3(BIN_BLOCK), 0, st, L.N, L.TX, L.max_pairs, rect,
+                     counts, boff, offsets, ka);
   uint32_t *hist = at<uint32_t>(ws, L.hist);
   uint32_t *src = ka, *dst = kb;
   for (int p = 0; p < L.sort_passes; ++p) {

@@ -6,7 +6,11 @@
 
 namespace gs2d {
 
-constexpr int SCAN_PER = 64;  // max elements per scan thread: 64 * 1024 = 65536
+constexpr int BIN_BLOCK = 256;  // threads of the projection / emission blocks
+// Radix digit-offset scan: SORT_MAX_BLOCKS * RADIX entries over SCAN_BLOCK
+// threads, at most this many per thread (kept in 32-bit registers).
+constexpr int RADIX_SCAN_PER = (SORT_MAX_BLOCKS * RADIX + SCAN_BLOCK - 1) / SCAN_BLOCK;
+static_assert(RADIX_SCAN_PER * (SCAN_BLOCK / 64) <= 64 * 8, "wave-total table too small");
 
 // Projection of Gaussian n (index into xy/chol and the outputs).
 // counts[n] = number of tiles met, or -1 for a culled Gaussian (the scan
@@ -86,6 +90,186 @@ __device__ inline long long block_exclusive_scan(long long v, long long *total, 
   *total = lds[NW - 1];
   __syncthreads();
   return before + x - v;
+}
+
+
+// Exclusive scan of one int per thread over a block of NT threads; `lds`
+// holds NT/64 ints.  Returns the prefix; *total receives the block sum.
+template <int NT>
+__device__ inline int block_exclusive_scan_i32(int v, int *total, int *lds) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int NW = NT / 64;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    int s = (lane < NW) ? lds[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(s, o, 64);
+      if (lane >= o) s += y;
+    }
+    if (lane < NW) lds[lane] = s;
+  }
+  __syncthreads();
+  const int before = (w > 0) ? lds[w - 1] : 0;
+  *total = lds[NW - 1];
+  __syncthreads();
+  return before + x - v;
+}
+
+// Projection of the block's Gaussians [base, base + BIN_BLOCK) of an array
+// of N, plus the block's sum of tile counts and of culled Gaussians.
+__device__ inline void project_block(int base, int N, int TX, int TY, float inv_tile,
+                                     const float *__restrict__ xy, const float *__restrict__ chol,
+                                     float4 *__restrict__ geom, int4 *__restrict__ rect,
+                                     int *__restrict__ counts, int *__restrict__ bsum,
+                                     int *__restrict__ bcull) {
+  __shared__ int red[2][BIN_BLOCK / 64];
+  const int n = base + (int)threadIdx.x;
+  int c = 0, cull = 0;
+  if (n < N) {
+    project_gaussian(n, TX, TY, inv_tile, xy, chol, geom, rect, counts);
+    const int v = counts[n];
+    c = v > 0 ? v : 0;
+    cull = v < 0;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    c += __shfl_xor(c, o, 64);
+    cull += __shfl_xor(cull, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = c;
+    red[1][threadIdx.x >> 6] = cull;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int a = 0, b = 0;
+    for (int w = 0; w < BIN_BLOCK / 64; ++w) {
+      a += red[0][w];
+      b += red[1][w];
+    }
+    *bsum = a;
+    *bcull = b;
+  }
+}
+
+// Key emission of the block's Gaussians [base, base + BIN_BLOCK): each
+// Gaussian's first key slot is block_off (the exclusive prefix of all
+// earlier blocks) plus the block-local exclusive prefix of the counts;
+// slots at or beyond `cap` are dropped.  offsets[n] receives the clamped
+// first slot; keys are (tile << 16) | n, row-major over the rectangle.
+__device__ inline void emit_block(int base, int N, int TX, long long block_off, int cap,
+                                  const int4 *__restrict__ rect, const int *__restrict__ counts,
+                                  int *__restrict__ offsets, uint32_t *__restrict__ keys) {
+  __shared__ int lds[BIN_BLOCK / 64];
+  const int n = base + (int)threadIdx.x;
+  int c = 0;
+  if (n < N) {
+    const int v = counts[n];
+    c = v > 0 ? v : 0;
+  }
+  int tot;
+  const int local = block_exclusive_scan_i32<BIN_BLOCK>(c, &tot, lds);
+  if (n >= N) return;
+  const long long start = block_off + local;
+  const int beg = (int)min(start, (long long)cap);
+  const int end = (int)min(start + c, (long long)cap);
+  offsets[n] = beg;
+  if (end <= beg) return;
+  const int4 rc = rect[n];
+  int k = beg;
+  for (int ty = rc.y; ty <= rc.w && k < end; ++ty)
+    for (int tx = rc.x; tx <= rc.z && k < end; ++tx, ++k)
+      keys[k] = ((uint32_t)(ty * TX + tx) << 16) | (uint32_t)n;
+}
+
+// Exclusive scan of up to BIN_BLOCK per-block sums (one block of BIN_BLOCK
+// threads): boff[b] for b < nb; returns the totals in *pairs and *culled
+// (valid in every thread).
+__device__ inline void scan_block_sums(int nb, const int *__restrict__ bsum,
+                                       const int *__restrict__ bcull, long long *__restrict__ boff,
+                                       long long *pairs, int *culled) {
+  __shared__ long long lds[BIN_BLOCK / 64];
+  __shared__ int cl[BIN_BLOCK / 64];
+  const int b = threadIdx.x;
+  const long long v = (b < nb) ? bsum[b] : 0;
+  int c = (b < nb) ? bcull[b] : 0;
+  long long total;
+  const long long ex = block_exclusive_scan<BIN_BLOCK>(v, &total, lds);
+  if (b < nb) boff[b] = ex;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) cl[threadIdx.x >> 6] = c;
+  __syncthreads();
+  int cs = 0;
+  for (int w = 0; w < BIN_BLOCK / 64; ++w) cs += cl[w];
+  *pairs = total;
+  *culled = cs;
+}
+
+// In-place exclusive scan of `total` <= RADIX_SCAN_PER * SCAN_BLOCK 32-bit
+// entries by one block of SCAN_BLOCK threads.  Entry e = k * SCAN_BLOCK + t
+// lives in register k of thread t, so every load and store of a wavefront
+// touches 64 consecutive words.  Each register column is scanned inside the
+// wavefronts, the (column, wavefront) totals are scanned by one wavefront in
+// (column, wavefront) order, and every thread adds its base back.
+__device__ inline void scan_u32_block(uint32_t *__restrict__ a, int total) {
+  constexpr int NW = SCAN_BLOCK / 64;
+  constexpr int NTOT = RADIX_SCAN_PER * NW;  // <= 512
+  __shared__ uint32_t tot[NTOT];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  uint32_t v[RADIX_SCAN_PER], inc[RADIX_SCAN_PER];
+#pragma unroll
+  for (int k = 0; k < RADIX_SCAN_PER; ++k) {
+    const int e = k * SCAN_BLOCK + t;
+    v[k] = (e < total) ? a[e] : 0u;
+  }
+#pragma unroll
+  for (int k = 0; k < RADIX_SCAN_PER; ++k) {
+    uint32_t x = v[k];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    inc[k] = x;
+    if (lane == 63) tot[k * NW + w] = x;
+  }
+  __syncthreads();
+  if (w == 0) {
+    // lane l scans entries [8l, 8l + 8) of the (column, wavefront) totals
+    uint32_t loc[8], s = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = lane * 8 + j;
+      loc[j] = (i < NTOT) ? tot[i] : 0u;
+      s += loc[j];
+    }
+    uint32_t x = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    uint32_t run = x - s;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = lane * 8 + j;
+      if (i < NTOT) tot[i] = run;
+      run += loc[j];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < RADIX_SCAN_PER; ++k) {
+    const int e = k * SCAN_BLOCK + t;
+    if (e < total) a[e] = tot[k * NW + w] + inc[k] - v[k];
+  }
 }
 
 // Chunk of the key array owned by sort block b (a multiple of SORT_BLOCK).

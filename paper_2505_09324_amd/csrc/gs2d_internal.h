@@ -36,8 +36,8 @@ struct Layout {
   int TX, TY, n_tiles;
   int sort_blocks;     // G: chunks of the key array, one sort block each
   int sort_passes;     // 8-bit digit passes over the tile bits
-  size_t geom, rect, counts, offsets, keys_a, keys_b, hist, tile_start, loss_part, grads, misc,
-      total;
+  size_t geom, rect, counts, offsets, blocks, keys_a, keys_b, hist, tile_start, loss_part, grads,
+      misc, total;
   // the buffer holding the sorted keys after all passes
   size_t keys_sorted() const { return (sort_passes & 1) ? keys_b : keys_a; }
 };
