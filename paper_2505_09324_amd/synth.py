@@ -181,3 +181,42 @@ def random_normal(shape, seed: int, std: float = 1.0) -> np.ndarray:
 def random_uniform(shape, seed: int, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(lo, hi, size=shape).astype(np.float32)
+
+
+def make_frame_torch(W: int, H: int, seed: int, t: int | None = None, device="cuda"):
+    """The same synthetic frame as make_frame, evaluated in FP32 with torch on
+    `device` (fast enough to stream training sequences).  Values agree with
+    make_frame to FP32 rounding.  Returns (frame [3,H,W] float32,
+    roi_mask [H,W] bool)."""
+    import torch
+    sp = scene_params(seed)
+    ys = torch.arange(H, device=device, dtype=torch.float32)[:, None] + 0.5
+    xs = torch.arange(W, device=device, dtype=torch.float32)[None, :] + 0.5
+    ct, st = math.cos(sp.theta_bg), math.sin(sp.theta_bg)
+    corners = [(0, 0), (W, 0), (0, H), (W, H)]
+    proj = [cx * ct + cy * st for cx, cy in corners]
+    tmin, tmax = min(proj), max(proj)
+    tt = (xs * ct + ys * st - tmin) / (tmax - tmin)
+    c0 = torch.tensor(sp.c0, device=device, dtype=torch.float32)[:, None, None]
+    c1 = torch.tensor(sp.c1, device=device, dtype=torch.float32)[:, None, None]
+    bg = c0 + (c1 - c0) * tt[None]
+    cx, cy, th = subject_pose(W, H, t)
+    a = SUBJECT_AX * W
+    b = SUBJECT_AY * H
+    dx = xs - cx
+    dy = ys - cy
+    cth, sth = math.cos(th), math.sin(th)
+    u = cth * dx + sth * dy
+    v = -sth * dx + cth * dy
+    tex = []
+    for k in range(3):
+        acc = torch.zeros((H, W), device=device)
+        for j in range(3):
+            acc = acc + torch.sin(2.0 * math.pi * (float(sp.freqs[j, 0]) * u + float(sp.freqs[j, 1]) * v)
+                                  + float(sp.phases[j, k]))
+        tex.append(torch.clamp(float(sp.cs[k]) + TEXTURE_AMPLITUDE * acc, 0.0, 1.0))
+    tex = torch.stack(tex)
+    rho = torch.sqrt((u / a) ** 2 + (v / b) ** 2)
+    alpha = torch.clamp(0.5 - (rho - 1.0) * min(a, b) / 1.5, 0.0, 1.0)
+    img = alpha[None] * tex + (1.0 - alpha[None]) * bg
+    return img.contiguous(), (rho <= 1.0)

@@ -177,16 +177,167 @@ def run_video(n_frames=60, W=1920, H=1080, N=30000, iters_first=2000, iters_rest
     }
 
 
+# ------------------------------------------------------ learned initialiser --
+def plain_init_dev(frame, mask, N, seed):
+    """Content-aware init from device tensors (frame [3,H,W], mask [H,W])."""
+    d = synth.init_draws(N, seed=seed)
+    dev = frame.device
+    return _lib.init_plain(frame, mask.to(torch.uint8).contiguous(), _dev(d.pick_roi, dev),
+                           _dev(d.jit_roi, dev), _dev(d.pick_out, dev), _dev(d.jit_out, dev))
+
+
+def fit_to_target(shape, ws, target, params, psnr_target, cap, check_every, cfg):
+    """Fit in place until PSNR >= target (checked every `check_every`) or
+    `cap` iterations; returns (iterations to target or None, iterations run)."""
+    N = shape.N
+    dev = target.device
+    m = torch.zeros(8 * N, device=dev)
+    v = torch.zeros(8 * N, device=dev)
+    step = torch.zeros(1, dtype=torch.int32, device=dev)
+    trace = torch.zeros(cap + check_every + 8, device=dev)
+    st = _lib.fit_frame(shape, target, *params, m, v, step, trace, ws,
+                        _lib.fit_opts(cap, check_every, psnr_target, cfg=cfg))
+    hit = int(st.iter_hit_target)
+    return (hit if hit >= 0 else None), int(st.iters_run)
+
+
+def make_training_set(seqs, n_frames, W, H, N, iters_first, iters_rest, device, lr=LR_DEFAULT,
+                      log=print):
+    """Fitted Gaussians of every frame of the training sequences (frame 0
+    from the content-aware init, later frames warm-started), the targets the
+    learned initialiser is trained on."""
+    shape = _lib.make_shape(W, H, N, 32, px_per_lane=2)
+    ws = _lib.alloc_workspace(shape, device)
+    cfg = _lib.adam_cfg(lr)
+    samples = []
+    for si, seed in enumerate(seqs):
+        params = None
+        for t in range(n_frames):
+            f, m = synth.make_frame_torch(W, H, seed, t, device)
+            if params is None:
+                params = [p.contiguous() for p in plain_init_dev(f, m, N, seed + 7919)]
+                iters = iters_first
+            else:
+                iters = iters_rest
+            mm = torch.zeros(8 * N, device=device)
+            vv = torch.zeros(8 * N, device=device)
+            step = torch.zeros(1, dtype=torch.int32, device=device)
+            trace = torch.zeros(iters + 8, device=device)
+            _lib.fit_frame(shape, f, *params, mm, vv, step, trace, ws,
+                           _lib.fit_opts(iters, 50, cfg=cfg))
+            samples.append((seed, t, [p.clone() for p in params]))
+        log(f"training sequence {si + 1}/{len(seqs)} fitted: last PSNR "
+            f"{psnr(float(trace[iters - 1])):.2f} dB")
+    return samples
+
+
+def train_initialiser(net, samples, W, H, epochs, lr, device, log=print, seed=0):
+    rng = np.random.default_rng(seed)
+    hist = []
+    for ep in range(epochs):
+        order = rng.permutation(len(samples))
+        tot = 0.0
+        for i, k in enumerate(order):
+            sd, t, params = samples[k]
+            f, _ = synth.make_frame_torch(W, H, sd, t, device)
+            prev = synth.make_frame_torch(W, H, sd, t - 1, device)[0] if t > 0 else None
+            net.forward(f, prev)
+            net.set_targets(*params)
+            loss = net.backward()
+            net.step(lr=lr)
+            tot += float(loss[0])
+        hist.append(tot / len(samples))
+        log(f"epoch {ep + 1}/{epochs}: mean loss {hist[-1]:.4f}")
+    return hist
+
+
+def run_learned(train_seqs=34, frames_per_seq=60, max_samples=2000, epochs=3, eval_frames=60,
+                W=1920, H=1080, N=30000, psnr_target=35.0, cap=10000, check_every=10,
+                iters_first=2000, iters_rest=200, lr_cnn=1e-3, device="cuda", log=print):
+    """Train the per-tile initialiser on fitter outputs, then compare time and
+    iterations to `psnr_target` on a held-out sequence for four arms:
+    A plain init every frame, L learned init every frame, B plain init on
+    frame 0 then warm start, C learned init on frame 0 then warm start."""
+    t_all = time.perf_counter()
+    seqs = [5000 + i for i in range(train_seqs)]
+    samples = make_training_set(seqs, frames_per_seq, W, H, N, iters_first, iters_rest, device,
+                                log=log)[:max_samples]
+    t_data = time.perf_counter() - t_all
+    net = _lib.CNNInit(H, W, seed=11, device=device)
+    t0 = time.perf_counter()
+    hist = train_initialiser(net, samples, W, H, epochs, lr_cnn, device, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del samples
+    # held-out evaluation
+    shape = _lib.make_shape(W, H, N, 32, px_per_lane=2)
+    ws = _lib.alloc_workspace(shape, device)
+    cfg = _lib.adam_cfg(LR_DEFAULT)
+    eval_seed = 5999
+    frames = [synth.make_frame_torch(W, H, eval_seed, t, device) for t in range(eval_frames)]
+
+    def init_for(arm, t):
+        f, m = frames[t]
+        plain = [p.contiguous() for p in plain_init_dev(f, m, N, eval_seed + 31 * t + 1)]
+        if arm in ("A", "B"):
+            return plain
+        prev = frames[t - 1][0] if t > 0 else None
+        net.forward(f, prev)
+        xy, chol, rgb, npred = net.decode(N, *plain)
+        return [xy, chol, rgb]
+
+    res = {}
+    for arm in ("A", "L", "B", "C"):
+        recs = []
+        params = None
+        for t in range(eval_frames):
+            f = frames[t][0]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if arm in ("A", "L") or params is None:
+                params = init_for(arm, t)
+            hit, run = fit_to_target(shape, ws, f, params, psnr_target, cap, check_every, cfg)
+            torch.cuda.synchronize()
+            recs.append({"iters": hit, "seconds": time.perf_counter() - t0, "iters_run": run})
+        ok = [r for r in recs if r["iters"] is not None]
+        res[arm] = {"frames_reaching_target": len(ok),
+                    "mean_seconds": float(np.mean([r["seconds"] for r in recs])),
+                    "mean_iters_to_target": float(np.mean([r["iters"] for r in ok])) if ok else None,
+                    "frame0_seconds": recs[0]["seconds"], "frame0_iters": recs[0]["iters"]}
+        log(f"arm {arm}: {res[arm]}")
+    ratio = lambda a, b: (res[a]["mean_seconds"] / res[b]["mean_seconds"])
+    return {
+        "workload": f"learned per-tile initialiser trained on {min(max_samples, train_seqs * frames_per_seq)} "
+                    f"fitter outputs ({train_seqs} sequences x {frames_per_seq} frames, {W}x{H}, "
+                    f"N={N}), {epochs} epochs; evaluated on {eval_frames} held-out frames",
+        "target_psnr_db": psnr_target, "arms": res,
+        "C_over_A_seconds": ratio("C", "A"), "C_over_B_seconds": ratio("C", "B"),
+        "L_over_A_seconds": ratio("L", "A"),
+        "train_loss_per_epoch": hist, "data_seconds": t_data, "train_seconds": t_train,
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["batch", "video"])
+    ap.add_argument("which", choices=["batch", "video", "learned"])
     ap.add_argument("--frames", type=int, default=None)
     ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--train-seqs", type=int, default=34)
+    ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--eval-frames", type=int, default=60)
+    ap.add_argument("--size", type=str, default="1920x1080")
+    ap.add_argument("--N", type=int, default=30000)
     args = ap.parse_args(argv)
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
     if args.which == "batch":
         out = run_batch(n_frames=args.frames or 48, iters=args.iters or 300)
-    else:
+    elif args.which == "video":
         out = run_video(n_frames=args.frames or 60, iters_rest=args.iters or 200)
+    else:
+        W, H = (int(x) for x in args.size.split("x"))
+        out = run_learned(train_seqs=args.train_seqs, frames_per_seq=args.frames or 60,
+                          epochs=args.epochs, eval_frames=args.eval_frames, W=W, H=H, N=args.N,
+                          log=log)
     print(json.dumps(out), flush=True)
 
 
