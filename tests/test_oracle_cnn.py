@@ -144,3 +144,92 @@ def test_tile_targets_selection():
     assert sorted(t) == [0, 1]
     assert t[0].shape == (8, 8)           # 10 in tile 0, the 8 heaviest kept
     assert t[1][0, 0] == pytest.approx((20.0 - 16) / 16)
+
+
+def _logit(p):
+    return math.log(p / (1.0 - p))
+
+
+def test_decode_inverts_the_slot_parameterisation():
+    """A head written from known Gaussians by inverting the documented slot
+    parameterisation (centre = tile origin + T sigmoid, scales = exp, count =
+    argmax of one-hot logits) must decode to exactly those Gaussians, in tile
+    order then slot order, topped up from the plain set."""
+    T, W, H = 16, 48, 32
+    TX, TY = W // T, H // T
+    rng = np.random.default_rng(3)
+    head = np.zeros((cnn.HEAD_CH, TY, TX))
+    expect = []
+    counts = {0: 2, 1: 0, 2: 3, 3: 1, 4: 0, 5: 2}
+    for t in range(TX * TY):
+        ty, tx = divmod(t, TX)
+        k = counts[t]
+        head[:9, ty, tx] = -1.0
+        head[k, ty, tx] = 5.0
+        for s in range(k):
+            fx, fy = rng.uniform(0.1, 0.9, 2)
+            l1, l3 = rng.uniform(0.5, 4.0, 2)
+            l2 = rng.uniform(-1, 1)
+            c = rng.uniform(0, 1, 3)
+            head[9 + 8 * s:9 + 8 * s + 8, ty, tx] = (_logit(fx), _logit(fy), math.log(l1), l2,
+                                                      math.log(l3), *c)
+            expect.append((tx * T + T * fx, ty * T + T * fy, l1, l2, l3, *c))
+        # slots beyond the count carry garbage that must be ignored
+        for s in range(k, 8):
+            head[9 + 8 * s:9 + 8 * s + 8, ty, tx] = 1e3
+    expect = np.array(expect)
+    n_pred = len(expect)                  # 8
+    N = 12
+    plain = (rng.uniform(0, 40, (N, 2)), rng.uniform(1, 2, (N, 3)), rng.uniform(0, 1, (N, 3)))
+    xy, chol, rgb, used = cnn.decode(head, N, plain, T)
+    assert used == n_pred
+    np.testing.assert_allclose(xy[:n_pred], expect[:, 0:2], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(chol[:n_pred], expect[:, 2:5], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(rgb[:n_pred], expect[:, 5:8], rtol=1e-12, atol=1e-12)
+    # top-up: the first N - n_pred plain Gaussians, in order
+    np.testing.assert_array_equal(xy[n_pred:], plain[0][:N - n_pred])
+    np.testing.assert_array_equal(chol[n_pred:], plain[1][:N - n_pred])
+    # more predictions than N: trimmed to the first N in tile order
+    xy2, _, _, used2 = cnn.decode(head, 5, plain, T)
+    assert used2 == 5
+    np.testing.assert_allclose(xy2, expect[:5, 0:2], rtol=1e-12, atol=1e-12)
+    # fewer than N/2 predictions: the plain set unchanged
+    big = (np.zeros((40, 2)), np.ones((40, 3)), np.zeros((40, 3)))
+    xy3, chol3, _, used3 = cnn.decode(head, 40, big, T)
+    assert used3 == 0 and np.array_equal(xy3, big[0]) and np.array_equal(chol3, big[1])
+    # a non-finite prediction also falls back
+    bad = head.copy()
+    bad[9 + 3, 0, 0] = np.nan
+    _, _, _, used4 = cnn.decode(bad, N, plain, T)
+    assert used4 == 0
+
+
+def test_targets_round_trip_through_decode():
+    """tile_targets and decode use the same tile-local encoding: a head
+    built from the targets (one-hot counts, slots by inverting the encoding)
+    decodes back to the selected Gaussians."""
+    T, W, H = 16, 64, 48
+    rng = np.random.default_rng(9)
+    n = 60
+    xy = np.stack([rng.uniform(0, W, n), rng.uniform(0, H, n)], 1)
+    chol = np.stack([rng.uniform(0.5, 3, n), rng.uniform(-1, 1, n), rng.uniform(0.5, 3, n)], 1)
+    rgb = rng.uniform(0, 1, (n, 3))
+    tg = cnn.tile_targets(xy, chol, rgb, W, H, T)
+    TX, TY = W // T, H // T
+    head = np.full((cnn.HEAD_CH, TY, TX), 0.0)
+    head[:9] = -1.0
+    expect = []
+    for t in range(TX * TY):
+        ty, tx = divmod(t, TX)
+        v = tg.get(t, np.zeros((0, 8)))
+        head[len(v), ty, tx] = 3.0
+        for s, row in enumerate(v):
+            head[9 + 8 * s:9 + 8 * s + 8, ty, tx] = (_logit(row[0]), _logit(row[1]), *row[2:])
+            expect.append(row)
+    m = len(expect)
+    got_xy, got_chol, got_rgb, used = cnn.decode(head, m, (xy, chol, rgb), T)
+    assert used == m
+    # every selected Gaussian comes back, and nothing else
+    pts = {tuple(np.round(r, 9)) for r in np.concatenate([got_xy, got_chol, got_rgb], 1)}
+    src = {tuple(np.round(np.concatenate([xy[i], chol[i], rgb[i]]), 9)) for i in range(n)}
+    assert pts <= src and len(pts) == m
