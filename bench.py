@@ -132,7 +132,7 @@ def traffic_record(kernel_src_digest: str):
 def kernel_digest():
     import hashlib
     h = hashlib.sha256()
-    for fn in ("raster.hip", "gs2d_internal.h"):
+    for fn in ("raster.hip", "raster_tile.h", "gs2d_internal.h"):
         with open(os.path.join(HERE, "paper_2505_09324_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     return h.hexdigest()

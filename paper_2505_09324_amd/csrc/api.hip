@@ -34,8 +34,10 @@ bool make_layout(const gs2d_shape &s, Layout *L) {
   int bits = 1;
   while ((1LL << bits) < (long long)L->n_tiles) ++bits;
   L->sort_passes = (bits + RADIX_BITS - 1) / RADIX_BITS;
-  int G = (s.max_pairs + 2047) / 2048;
-  L->sort_blocks = G < 1 ? 1 : (G > SORT_MAX_BLOCKS ? SORT_MAX_BLOCKS : G);
+  // about one sort chunk per 256 Gaussians (chunks hold ~3 keys per Gaussian)
+  const int G = (s.N + 255) / 256;
+  L->sort_blocks = G > SORT_MAX_BLOCKS ? SORT_MAX_BLOCKS : G;
+  L->tile_count_words = (L->n_tiles + 3) & ~3;
   size_t o = 0;
   auto take = [&o](size_t bytes) {
     const size_t at = o;
@@ -47,11 +49,14 @@ bool make_layout(const gs2d_shape &s, Layout *L) {
   L->rect = take(N * 16);
   L->counts = take(N * 4);
   L->offsets = take((N + 1) * 4);
-  L->blocks = take(4096);  // per-projection-block sums (<= 256 blocks): 2 x int, 1 x int64
+  L->blocks = take(2048);  // per-projection-block sums (<= 256 blocks): pairs, culled
   L->keys_a = take((size_t)s.max_pairs * 4);
   L->keys_b = take((size_t)s.max_pairs * 4);
-  L->hist = take((size_t)RADIX * L->sort_blocks * 4);
+  // cleared by every binning: two passes' histograms, then the tile counts
+  L->hist = take((size_t)RADIX * L->sort_blocks * 4 * 2);
+  L->tile_count = take((size_t)L->tile_count_words * 4);
   L->tile_start = take(((size_t)L->n_tiles + 1) * 4);
+  L->tile_order = take((size_t)L->n_tiles * 4);
   L->loss_part = take((size_t)L->n_tiles * 4);
   L->grads = take(N * 8 * 4);
   L->misc = take(MISC_COUNT * 4);

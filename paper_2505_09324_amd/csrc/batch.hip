@@ -1,10 +1,11 @@
 // Batched fitting: many frames of different sizes and Gaussian counts fitted
 // in lockstep, one launch per stage per iteration.
 //
-//  - binning runs segmented per frame: one thread per Gaussian of the whole
-//    batch for projection and key emission, one block per frame for the
-//    count scan and for each radix-digit scan, and a block table mapping the
-//    sort blocks to (frame, key chunk) for the histogram/scatter passes;
+//  - binning runs segmented per frame with the same four launches as one
+//    frame (project, emit, one scatter per radix pass): one thread per
+//    Gaussian of the whole batch for projection and key emission, a block
+//    table mapping the sort blocks to (frame, key chunk) for the scatter
+//    passes, and one extra block per frame for the tile ranges;
 //  - the raster is ONE persistent launch per iteration: a grid sized to the
 //    device's resident capacity pulls (frame, tile) work items from a queue
 //    through an atomic counter, largest frames first, and runs the same
@@ -35,7 +36,7 @@ struct BFrame {
   long long g_off;     // first Gaussian of the frame in the concatenated arrays
   long long px_off;    // first float of the frame's target ([3][H][W])
   long long key_off;   // first key slot
-  long long hist_off;  // first radix histogram entry (RADIX * G entries)
+  long long hist_off;  // first radix histogram word (two passes of RADIX * G words)
   long long tile_off;  // first tile of the frame among all tiles of the batch
 };
 
@@ -44,8 +45,10 @@ enum BMisc : int { BM_N_PAIRS = 0, BM_STATUS = 1, BM_N_CULLED = 2, BM_STICKY = 3
 struct BatchLayout {
   int F, T, ppl, passes, sort_blocks, proj_blocks;
   long long Ntot, keys_tot, hist_tot, tiles_tot;
-  size_t desc, gframe, blk_frame, blk_chunk, pblk_frame, queue, geom, rect, counts, offsets,
-      bsum, bcull, boff, keys_a, keys_b, hist, tile_start, loss_part, grads, misc, counter, total;
+  size_t desc, blk_frame, blk_chunk, pblk_frame, queue, geom, rect, counts, offsets, bsum, bcull,
+      keys_a, keys_b, hist, tile_count, tile_start, tile_order, loss_part, grads, misc, counter,
+      total;
+  long long zero4;  // uint4 words cleared by every binning (histograms, tile counts)
   std::vector<BFrame> frames;
 };
 
@@ -76,7 +79,7 @@ bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout
     const long long cap = std::max<long long>(1 << 16, 16LL * s.N + 4LL * d.n_tiles);
     if (cap > (1 << 30)) return false;
     d.cap = (int)cap;
-    d.G = std::max(1, std::min(SORT_MAX_BLOCKS, (d.cap + 2047) / 2048));
+    d.G = std::min(SORT_MAX_BLOCKS, (s.N + 255) / 256);
     d.nb = (s.N + BIN_BLOCK - 1) / BIN_BLOCK;
     d.blk_off = pblocks;
     pblocks += d.nb;
@@ -88,7 +91,7 @@ bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout
     g += s.N;
     px += 3LL * s.W * s.H;
     key += d.cap;
-    hist += (long long)RADIX * d.G;
+    hist += 2LL * RADIX * d.G;
     tiles += d.n_tiles;
     blocks += d.G;
     int bits = 1;
@@ -109,7 +112,6 @@ bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout
     return at;
   };
   B->desc = take(sizeof(BFrame) * F);
-  B->gframe = take(4 * (size_t)g);
   B->blk_frame = take(4 * (size_t)blocks);
   B->blk_chunk = take(4 * (size_t)blocks);
   B->pblk_frame = take(4 * (size_t)pblocks);
@@ -120,11 +122,13 @@ bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout
   B->offsets = take(4 * ((size_t)g + F));
   B->bsum = take(4 * (size_t)pblocks);
   B->bcull = take(4 * (size_t)pblocks);
-  B->boff = take(8 * (size_t)pblocks);
   B->keys_a = take(4 * (size_t)key);
   B->keys_b = take(4 * (size_t)key);
   B->hist = take(4 * (size_t)hist);
+  B->tile_count = take(4 * (((size_t)tiles + 3) & ~(size_t)3));
+  B->zero4 = (long long)(B->tile_count + 4 * (((size_t)tiles + 3) & ~(size_t)3) - B->hist) / 16;
   B->tile_start = take(4 * ((size_t)tiles + F));
+  B->tile_order = take(4 * (size_t)tiles);
   B->loss_part = take(4 * (size_t)tiles);
   B->grads = take(32 * (size_t)g);
   B->misc = take(4 * (size_t)BM_STRIDE * F);
@@ -140,29 +144,35 @@ __global__ void __launch_bounds__(BIN_BLOCK)
 k_b_project(const BFrame *__restrict__ D, const int *__restrict__ pblk_frame, int tile,
             const float *__restrict__ xy, const float *__restrict__ chol, float4 *__restrict__ geom,
             int4 *__restrict__ rect, int *__restrict__ counts, int *__restrict__ bsum,
-            int *__restrict__ bcull) {
+            int *__restrict__ bcull, uint4 *__restrict__ zero, long long n4) {
   const BFrame d = D[pblk_frame[blockIdx.x]];
   const int c = blockIdx.x - d.blk_off;
   const long long g = d.g_off;
   project_block(c * BIN_BLOCK, d.N, d.TX, d.TY, 1.0f / (float)tile, xy + 2 * g, chol + 3 * g,
                 geom + 2 * g, rect + g, counts + g, bsum + blockIdx.x, bcull + blockIdx.x);
+  clear_u4(zero, n4);
 }
 
-// One block per frame: scan of the frame's projection-block sums, pair
-// count, status.  Block 0 also advances the step counter (when given) and
+// Key emission of projection block b of frame f: prefix of its pair count
+// among the frame's blocks, then the keys and the frame's first-pass
+// histogram and tile counts.  The frame's first block publishes its pair
+// count and status; block 0 also advances the step counter (when given) and
 // clears the persistent raster's work counter for this iteration.
 __global__ void __launch_bounds__(BIN_BLOCK)
-k_b_scan_blocks(const BFrame *__restrict__ D, const int *__restrict__ bsum,
-                const int *__restrict__ bcull, long long *__restrict__ boff,
-                int *__restrict__ offsets, int *__restrict__ misc, int *__restrict__ tick,
-                unsigned *__restrict__ work_counter) {
-  const int f = blockIdx.x;
+k_b_emit_keys(const BFrame *__restrict__ D, const int *__restrict__ pblk_frame,
+              const int4 *__restrict__ rect, const int *__restrict__ counts,
+              const int *__restrict__ bsum, const int *__restrict__ bcull,
+              int *__restrict__ offsets, uint32_t *__restrict__ keys, uint32_t *__restrict__ hist,
+              uint32_t *__restrict__ tile_count, int *__restrict__ misc, int *__restrict__ tick,
+              unsigned *__restrict__ work_counter) {
+  const int f = pblk_frame[blockIdx.x];
   const BFrame d = D[f];
-  long long total;
+  const int c = blockIdx.x - d.blk_off;
+  long long pre, total;
   int culled;
-  scan_block_sums(d.nb, bsum + d.blk_off, bcull + d.blk_off, boff + d.blk_off, &total, &culled);
-  if (threadIdx.x == 0) {
-    const int np = (int)min(total, (long long)d.cap);
+  block_sum_prefix(d.nb, c, bsum + d.blk_off, bcull + d.blk_off, &pre, &total, &culled);
+  const int np = (int)min(total, (long long)d.cap);
+  if (c == 0 && threadIdx.x == 0) {
     offsets[d.g_off + f + d.N] = np;
     const int st = (total > (long long)d.cap ? (int)STATUS_OVERFLOW : 0) |
                    (culled > 0 ? (int)STATUS_CULLED : 0);
@@ -176,125 +186,46 @@ k_b_scan_blocks(const BFrame *__restrict__ D, const int *__restrict__ bsum,
       work_counter[0] = 0u;
     }
   }
+  emit_block(c * BIN_BLOCK, d.N, d.TX, pre, np, d.G, rect + d.g_off, counts + d.g_off,
+             offsets + d.g_off + f, keys + d.key_off, hist + d.hist_off, tile_count + d.tile_off);
 }
 
-__global__ void __launch_bounds__(BIN_BLOCK)
-k_b_emit_keys(const BFrame *__restrict__ D, const int *__restrict__ pblk_frame,
-              const int4 *__restrict__ rect, const int *__restrict__ counts,
-              const long long *__restrict__ boff, int *__restrict__ offsets,
-              uint32_t *__restrict__ keys) {
-  const int f = pblk_frame[blockIdx.x];
-  const BFrame d = D[f];
-  const int c = blockIdx.x - d.blk_off;
-  emit_block(c * BIN_BLOCK, d.N, d.TX, boff[blockIdx.x], d.cap, rect + d.g_off, counts + d.g_off,
-             offsets + d.g_off + f, keys + d.key_off);
-}
-
-__global__ void __launch_bounds__(SORT_BLOCK)
-k_b_radix_hist(const BFrame *__restrict__ D, const int *__restrict__ blk_frame,
-               const int *__restrict__ blk_chunk, const int *__restrict__ misc,
-               const uint32_t *__restrict__ keys, int shift, uint32_t *__restrict__ hist) {
-  __shared__ uint32_t h[RADIX];
-  const int f = blk_frame[blockIdx.x], c = blk_chunk[blockIdx.x];
-  const BFrame d = D[f];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  int beg, end;
-  sort_chunk(misc[BM_STRIDE * f + BM_N_PAIRS], d.G, c, &beg, &end);
-  const uint32_t *k = keys + d.key_off;
-  for (int i = beg + threadIdx.x; i < end; i += SORT_BLOCK)
-    atomicAdd(&h[(k[i] >> shift) & (RADIX - 1)], 1u);
-  __syncthreads();
-  hist[d.hist_off + (long long)threadIdx.x * d.G + c] = h[threadIdx.x];
-}
-
-// One block per frame: exclusive scan of its RADIX * G histogram.
-__global__ void __launch_bounds__(SCAN_BLOCK)
-k_b_radix_scan(const BFrame *__restrict__ D, uint32_t *__restrict__ hist_all) {
-  const BFrame d = D[blockIdx.x];
-  scan_u32_block(hist_all + d.hist_off, RADIX * d.G);
-}
-
+// Blocks [0, n_sort): stable scatter of chunk blk_chunk[b] of frame
+// blk_frame[b] for the pass at `shift` (pass index p: histogram p of the
+// frame; NEXT also counts histogram p + 1).  LAST: blocks n_sort + f compute
+// frame f's tile_start and tile order from its tile counts.
+template <bool NEXT, bool LAST>
 __global__ void __launch_bounds__(SORT_BLOCK)
 k_b_radix_scatter(const BFrame *__restrict__ D, const int *__restrict__ blk_frame,
-                  const int *__restrict__ blk_chunk, const int *__restrict__ misc,
-                  const uint32_t *__restrict__ in_all, uint32_t *__restrict__ out_all, int shift,
-                  const uint32_t *__restrict__ hist_all) {
-  constexpr int NW = SORT_BLOCK / 64;
-  __shared__ uint32_t off[RADIX];
-  __shared__ uint32_t wcnt[NW][RADIX];
-  __shared__ uint32_t wpre[NW][RADIX];
+                  const int *__restrict__ blk_chunk, int n_sort, const int *__restrict__ misc,
+                  const uint32_t *__restrict__ in_all, uint32_t *__restrict__ out_all, int pass,
+                  uint32_t *__restrict__ hist_all, const uint32_t *__restrict__ tile_count,
+                  int *__restrict__ tile_start_all, int *__restrict__ tile_order_all) {
+  if (LAST && (int)blockIdx.x >= n_sort) {
+    const int f = blockIdx.x - n_sort;
+    const BFrame d = D[f];
+    tile_starts(tile_count + d.tile_off, d.n_tiles, tile_start_all + d.tile_off + f);
+    __syncthreads();
+    tile_order_by_count(tile_count + d.tile_off, d.n_tiles, tile_order_all + d.tile_off);
+    return;
+  }
   const int f = blk_frame[blockIdx.x], c = blk_chunk[blockIdx.x];
   const BFrame d = D[f];
-  const uint32_t *in = in_all + d.key_off;
-  uint32_t *out = out_all + d.key_off;
-  const int tid = threadIdx.x, w = tid >> 6;
-  off[tid] = hist_all[d.hist_off + (long long)tid * d.G + c];
-#pragma unroll
-  for (int k = 0; k < NW; ++k) wcnt[k][tid] = 0;
-  __syncthreads();
-  int beg, end;
-  sort_chunk(misc[BM_STRIDE * f + BM_N_PAIRS], d.G, c, &beg, &end);
-  const unsigned long long lt = lanemask_lt();
-  for (int base = beg; base < end; base += SORT_BLOCK) {
-    const int i = base + tid;
-    const bool valid = i < end;
-    const uint32_t key = valid ? in[i] : 0u;
-    const uint32_t dg = (key >> shift) & (RADIX - 1);
-    unsigned long long match = __ballot(valid);
-#pragma unroll
-    for (int bit = 0; bit < RADIX_BITS; ++bit) {
-      const bool on = (dg >> bit) & 1u;
-      const unsigned long long bal = __ballot(on);
-      match &= on ? bal : ~bal;
-    }
-    const uint32_t rank = (uint32_t)__popcll(match & lt);
-    if (valid && rank == 0) wcnt[w][dg] = (uint32_t)__popcll(match);
-    __syncthreads();
-    {
-      uint32_t s = 0;
-#pragma unroll
-      for (int k = 0; k < NW; ++k) {
-        wpre[k][tid] = s;
-        s += wcnt[k][tid];
-      }
-      wcnt[0][tid] = s;
-    }
-    __syncthreads();
-    if (valid) out[off[dg] + wpre[w][dg] + rank] = key;
-    __syncthreads();
-    off[tid] += wcnt[0][tid];
-#pragma unroll
-    for (int k = 0; k < NW; ++k) wcnt[k][tid] = 0;
-    __syncthreads();
-  }
-}
-
-// Grid (RB, F): tile ranges of frame blockIdx.y.
-__global__ void __launch_bounds__(256)
-k_b_tile_ranges(const BFrame *__restrict__ D, const int *__restrict__ misc,
-                const uint32_t *__restrict__ keys_all, int *__restrict__ tile_start_all) {
-  const int f = blockIdx.y;
-  const BFrame d = D[f];
-  const int n = misc[BM_STRIDE * f + BM_N_PAIRS];
-  const uint32_t *keys = keys_all + d.key_off;
-  int *ts = tile_start_all + d.tile_off + f;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
-    const int cur = (i < n) ? (int)(keys[i] >> 16) : d.n_tiles;
-    const int prev = (i > 0) ? (int)(keys[i - 1] >> 16) : -1;
-    for (int t = prev + 1; t <= cur && t <= d.n_tiles; ++t) ts[t] = i;
-  }
+  uint32_t *h = hist_all + d.hist_off + (long long)pass * RADIX * d.G;
+  scatter_chunk<NEXT>(in_all + d.key_off, out_all + d.key_off, misc[BM_STRIDE * f + BM_N_PAIRS],
+                      d.G, c, 16 + RADIX_BITS * pass, h, h + (long long)RADIX * d.G);
 }
 
 // ------------------------------------------------------------- raster ----
 struct BatchRaster {
   const BFrame *D;
-  const uint32_t *queue;  // (frame << 16) | tile, processing order
+  const uint32_t *queue;  // (frame << 16) | i: the frame's i-th tile in its tile order
   unsigned n_items;
   unsigned *counter;
   const float4 *geom;
   const uint32_t *keys;
   const int *tile_start;
+  const int *tile_order;
   const float *rgb;
   const float *targets;
   float *loss_part;
@@ -315,8 +246,9 @@ k_b_render_persistent(BatchRaster a) {
     __syncthreads();
     if (item >= a.n_items) break;  // every wavefront leaves together
     const uint32_t q = a.queue[item];
-    const int f = (int)(q >> 16), t = (int)(q & 0xFFFFu);
+    const int f = (int)(q >> 16);
     const BFrame d = a.D[f];
+    const int t = a.tile_order[d.tile_off + (int)(q & 0xFFFFu)];
     FrameArgs fa;
     fa.W = d.W;
     fa.H = d.H;
@@ -359,19 +291,19 @@ struct BatchRun {
 };
 
 hipError_t upload_tables(const BatchLayout &B, void *ws, hipStream_t st) {
-  std::vector<int> gframe((size_t)B.Ntot), bf, bc, pf;
+  std::vector<int> bf, bc, pf;
   std::vector<uint32_t> queue;
   queue.reserve((size_t)B.tiles_tot);
   for (int f = 0; f < B.F; ++f) {
     const BFrame &d = B.frames[f];
-    std::fill(gframe.begin() + d.g_off, gframe.begin() + d.g_off + d.N, f);
     for (int c = 0; c < d.G; ++c) {
       bf.push_back(f);
       bc.push_back(c);
     }
     for (int c = 0; c < d.nb; ++c) pf.push_back(f);
   }
-  // work order: frames by decreasing area (largest lists first), tiles in order
+  // work order: frames by decreasing area (largest lists first), then each
+  // frame's tiles in the order the binning computes (longest lists first)
   std::vector<int> order(B.F);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -381,9 +313,6 @@ hipError_t upload_tables(const BatchLayout &B, void *ws, hipStream_t st) {
     for (int t = 0; t < B.frames[f].n_tiles; ++t) queue.push_back(((uint32_t)f << 16) | (uint32_t)t);
   hipError_t e = hipMemcpyAsync(at<char>(ws, B.desc), B.frames.data(), sizeof(BFrame) * B.F,
                                 hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(at<char>(ws, B.gframe), gframe.data(), 4 * gframe.size(),
-                       hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(at<char>(ws, B.blk_frame), bf.data(), 4 * bf.size(), hipMemcpyHostToDevice,
                        st);
@@ -432,27 +361,25 @@ hipError_t enqueue_batch_binning(const BatchLayout &B, void *ws, const float *xy
   unsigned *counter = at<unsigned>(ws, B.counter);
   uint32_t *ka = at<uint32_t>(ws, B.keys_a), *kb = at<uint32_t>(ws, B.keys_b);
   uint32_t *hist = at<uint32_t>(ws, B.hist);
+  uint32_t *tcount = at<uint32_t>(ws, B.tile_count);
+  int *tstart = at<int>(ws, B.tile_start);
+  int *torder = at<int>(ws, B.tile_order);
   const int *pf = at<const int>(ws, B.pblk_frame);
   int *bsum = at<int>(ws, B.bsum), *bcull = at<int>(ws, B.bcull);
-  long long *boff = at<long long>(ws, B.boff);
   hipLaunchKernelGGL(k_b_project, dim3(B.proj_blocks), dim3(BIN_BLOCK), 0, st, D, pf, B.T, xy, chol,
-                     geom, rect, counts, bsum, bcull);
-  hipLaunchKernelGGL(k_b_scan_blocks, dim3(B.F), dim3(BIN_BLOCK), 0, st, D, bsum, bcull, boff,
-                     offsets, misc, tick, counter);
+                     geom, rect, counts, bsum, bcull, at<uint4>(ws, B.hist), B.zero4);
   hipLaunchKernelGGL(k_b_emit_keys, dim3(B.proj_blocks), dim3(BIN_BLOCK), 0, st, D, pf, rect, counts,
-                     boff, offsets, ka);
-  uint32_t *src = ka, *dst = kb;
-  for (int p = 0; p < B.passes; ++p) {
-    const int shift = 16 + RADIX_BITS * p;
-    hipLaunchKernelGGL(k_b_radix_hist, dim3(B.sort_blocks), dim3(SORT_BLOCK), 0, st, D, bf, bc,
-                       misc, src, shift, hist);
-    hipLaunchKernelGGL(k_b_radix_scan, dim3(B.F), dim3(SCAN_BLOCK), 0, st, D, hist);
-    hipLaunchKernelGGL(k_b_radix_scatter, dim3(B.sort_blocks), dim3(SORT_BLOCK), 0, st, D, bf, bc,
-                       misc, src, dst, shift, hist);
-    std::swap(src, dst);
+                     bsum, bcull, offsets, ka, hist, tcount, misc, tick, counter);
+  const int ns = B.sort_blocks;
+  if (B.passes == 1) {
+    hipLaunchKernelGGL((k_b_radix_scatter<false, true>), dim3(ns + B.F), dim3(SORT_BLOCK), 0, st, D,
+                       bf, bc, ns, misc, ka, kb, 0, hist, tcount, tstart, torder);
+  } else {
+    hipLaunchKernelGGL((k_b_radix_scatter<true, false>), dim3(ns), dim3(SORT_BLOCK), 0, st, D, bf,
+                       bc, ns, misc, ka, kb, 0, hist, nullptr, nullptr, nullptr);
+    hipLaunchKernelGGL((k_b_radix_scatter<false, true>), dim3(ns + B.F), dim3(SORT_BLOCK), 0, st, D,
+                       bf, bc, ns, misc, kb, ka, 1, hist, tcount, tstart, torder);
   }
-  hipLaunchKernelGGL(k_b_tile_ranges, dim3(32, B.F), dim3(256), 0, st, D, misc, src,
-                     at<int>(ws, B.tile_start));
   return hipGetLastError();
 }
 
@@ -471,6 +398,7 @@ hipError_t enqueue_batch_raster(const BatchLayout &B, void *ws, int grid, const 
   a.geom = at<const float4>(ws, B.geom);
   a.keys = batch_sorted_keys(B, ws);
   a.tile_start = at<const int>(ws, B.tile_start);
+  a.tile_order = at<const int>(ws, B.tile_order);
   a.rgb = rgb;
   a.targets = targets;
   a.loss_part = at<float>(ws, B.loss_part);

@@ -1,9 +1,20 @@
 // Projection and tile binning for the tile-based rasteriser of Eq. 2.
 //
-// Per iteration:  project (one thread per Gaussian)  ->  exclusive scan of
-// tile counts (one block)  ->  key emission  ->  stable LSD radix sort of the
-// keys on their tile bits (8-bit digits; histogram, digit-offset scan,
-// stable scatter)  ->  per-tile ranges.
+// Per iteration, four launches:
+//   project   one thread per Gaussian: box, tile rectangle, tile count, and
+//             per-block sums; also clears the histograms below;
+//   emit      every block scans the (<= 256) block sums for its own prefix,
+//             writes its Gaussians' keys, and counts them into the first
+//             radix pass's per-chunk digit histogram and into per-tile
+//             counts (integer atomics: order-independent, exact);
+//   scatter   one launch per 8-bit digit pass of the stable LSD radix sort
+//             on the tile bits: each block derives its chunk's digit
+//             offsets from the histogram rows itself, scatters stably, and
+//             (all passes but the last) counts its keys into the next
+//             pass's histogram at their output slots; the last pass carries
+//             one extra block that turns the per-tile counts into tile
+//             ranges and into the raster's tile order (largest lists
+//             first).
 //
 // Keys are (tile << 16) | gaussian_index.  Keys are emitted in ascending
 // Gaussian order and the sort is stable on the tile bits, so the result is
@@ -18,29 +29,35 @@ namespace gs2d {
 
 // ---------------------------------------------------------------- project --
 // One thread per Gaussian; each block also writes the sum of its tile counts
-// and of its culled Gaussians (bsum/bcull[block]).
+// and of its culled Gaussians (bsum/bcull[block]) and clears its share of
+// the n4 uint4 words at `zero` (histograms and tile counts).
 __global__ void __launch_bounds__(BIN_BLOCK)
 k_project(int N, int TX, int TY, float inv_tile, const float *__restrict__ xy,
           const float *__restrict__ chol, float4 *__restrict__ geom, int4 *__restrict__ rect,
-          int *__restrict__ counts, int *__restrict__ bsum, int *__restrict__ bcull) {
+          int *__restrict__ counts, int *__restrict__ bsum, int *__restrict__ bcull,
+          uint4 *__restrict__ zero, long long n4) {
   project_block(blockIdx.x * BIN_BLOCK, N, TX, TY, inv_tile, xy, chol, geom, rect, counts,
                 bsum + blockIdx.x, bcull + blockIdx.x);
+  clear_u4(zero, n4);
 }
 
-// ---------------------------------------------------------- block sum scan --
-// One block: exclusive scan of the per-block pair counts (boff), total pair
-// count n_pairs = min(total, max_pairs) and offsets[N], status bits, culled
-// count.  When `tick` is given its value is incremented once (the fitting
-// loop's step counter, read by the optimiser later in the same iteration).
+// ------------------------------------------------------------- emit keys --
+// Block b: prefix of its pair count among all nb blocks, then key emission.
+// Block 0 also publishes the pair count n_pairs = min(total, max_pairs),
+// offsets[N], the status bits and the culled count; when `tick` is given its
+// value is incremented once (the fitting loop's step counter, read by the
+// optimiser later in the same iteration).
 __global__ void __launch_bounds__(BIN_BLOCK)
-k_scan_blocks(int N, int nb, int max_pairs, const int *__restrict__ bsum,
-              const int *__restrict__ bcull, long long *__restrict__ boff,
-              int *__restrict__ offsets, int *__restrict__ misc, int *__restrict__ tick) {
-  long long total;
+k_emit_keys(int N, int TX, int nb, int max_pairs, int G, const int4 *__restrict__ rect,
+            const int *__restrict__ counts, const int *__restrict__ bsum,
+            const int *__restrict__ bcull, int *__restrict__ offsets, uint32_t *__restrict__ keys,
+            uint32_t *__restrict__ hist0, uint32_t *__restrict__ tile_count,
+            int *__restrict__ misc, int *__restrict__ tick) {
+  long long pre, total;
   int culled;
-  scan_block_sums(nb, bsum, bcull, boff, &total, &culled);
-  if (threadIdx.x == 0) {
-    const int np = (int)min(total, (long long)max_pairs);
+  block_sum_prefix(nb, blockIdx.x, bsum, bcull, &pre, &total, &culled);
+  const int np = (int)min(total, (long long)max_pairs);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     offsets[N] = np;
     const uint32_t st = (total > (long long)max_pairs ? STATUS_OVERFLOW : 0u) |
                         (culled > 0 ? STATUS_CULLED : 0u);
@@ -50,90 +67,34 @@ k_scan_blocks(int N, int nb, int max_pairs, const int *__restrict__ bsum,
     misc[MISC_STICKY] |= (int)st;
     if (tick) tick[0] += 1;
   }
-}
-
-// ------------------------------------------------------------- emit keys --
-__global__ void __launch_bounds__(BIN_BLOCK)
-k_emit_keys(int N, int TX, int max_pairs, const int4 *__restrict__ rect,
-            const int *__restrict__ counts, const long long *__restrict__ boff,
-            int *__restrict__ offsets, uint32_t *__restrict__ keys) {
-  emit_block(blockIdx.x * BIN_BLOCK, N, TX, boff[blockIdx.x], max_pairs, rect, counts, offsets,
-             keys);
+  emit_block(blockIdx.x * BIN_BLOCK, N, TX, pre, np, G, rect, counts, offsets, keys, hist0,
+             tile_count);
 }
 
 // ------------------------------------------------------------ radix sort --
-// Pass histogram: hist[d * G + b] = keys of digit d in chunk b.
+// Per-chunk histogram of one pass (used when no earlier kernel counted it).
 __global__ void __launch_bounds__(SORT_BLOCK)
 k_radix_hist(const uint32_t *__restrict__ keys, const int *__restrict__ misc, int shift, int G,
              uint32_t *__restrict__ hist) {
-  __shared__ uint32_t h[RADIX];
-  const int b = blockIdx.x;
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  int beg, end;
-  sort_chunk(misc[MISC_N_PAIRS], G, b, &beg, &end);
-  for (int i = beg + threadIdx.x; i < end; i += SORT_BLOCK)
-    atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
-  __syncthreads();
-  hist[threadIdx.x * G + b] = h[threadIdx.x];
+  chunk_histogram(keys, misc[MISC_N_PAIRS], G, blockIdx.x, shift, hist);
 }
 
-// Exclusive scan of the G*RADIX histogram in (digit, block) order, in place.
-__global__ void __launch_bounds__(SCAN_BLOCK)
-k_radix_scan(uint32_t *__restrict__ hist, int total_entries) {
-  scan_u32_block(hist, total_entries);
-}
-
-// Stable scatter of chunk b: in input order, each key goes to
-// off[digit] + (earlier keys of the same digit in this chunk).
+// Blocks [0, G): stable scatter of one chunk (NEXT: also count the next
+// pass's histogram).  LAST: block G computes tile_start and the tile order
+// from tile_count.
+template <bool NEXT, bool LAST>
 __global__ void __launch_bounds__(SORT_BLOCK)
 k_radix_scatter(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
-                const int *__restrict__ misc, int shift, int G, const uint32_t *__restrict__ hist) {
-  constexpr int NW = SORT_BLOCK / 64;
-  __shared__ uint32_t off[RADIX];
-  __shared__ uint32_t wcnt[NW][RADIX];
-  __shared__ uint32_t wpre[NW][RADIX];
-  const int b = blockIdx.x, tid = threadIdx.x, w = tid >> 6;
-  off[tid] = hist[tid * G + b];
-#pragma unroll
-  for (int k = 0; k < NW; ++k) wcnt[k][tid] = 0;
-  __syncthreads();
-  int beg, end;
-  sort_chunk(misc[MISC_N_PAIRS], G, b, &beg, &end);
-  const unsigned long long lt = lanemask_lt();
-  for (int base = beg; base < end; base += SORT_BLOCK) {
-    const int i = base + tid;
-    const bool valid = i < end;
-    const uint32_t key = valid ? in[i] : 0u;
-    const uint32_t d = (key >> shift) & (RADIX - 1);
-    // lanes of this wave holding the same digit
-    unsigned long long match = __ballot(valid);
-#pragma unroll
-    for (int bit = 0; bit < RADIX_BITS; ++bit) {
-      const bool on = (d >> bit) & 1u;
-      const unsigned long long bal = __ballot(on);
-      match &= on ? bal : ~bal;
-    }
-    const uint32_t rank = (uint32_t)__popcll(match & lt);
-    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(match);
+                const int *__restrict__ misc, int shift, int G, const uint32_t *__restrict__ hist,
+                uint32_t *__restrict__ hist_next, const uint32_t *__restrict__ tile_count,
+                int n_tiles, int *__restrict__ tile_start, int *__restrict__ tile_order) {
+  if (LAST && (int)blockIdx.x == G) {
+    tile_starts(tile_count, n_tiles, tile_start);
     __syncthreads();
-    {
-      uint32_t s = 0;
-#pragma unroll
-      for (int k = 0; k < NW; ++k) {
-        wpre[k][tid] = s;
-        s += wcnt[k][tid];
-      }
-      wcnt[0][tid] = s;  // reuse row 0 as the sub-tile total of digit tid
-    }
-    __syncthreads();
-    if (valid) out[off[d] + wpre[w][d] + rank] = key;
-    __syncthreads();
-    off[tid] += wcnt[0][tid];
-#pragma unroll
-    for (int k = 0; k < NW; ++k) wcnt[k][tid] = 0;
-    __syncthreads();
+    tile_order_by_count(tile_count, n_tiles, tile_order);
+    return;
   }
+  scatter_chunk<NEXT>(in, out, misc[MISC_N_PAIRS], G, blockIdx.x, shift, hist, hist_next);
 }
 
 // --------------------------------------------------------------- ranges --
@@ -157,31 +118,30 @@ hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, v
   int *misc = at<int>(ws, L.misc);
   int4 *rect = at<int4>(ws, L.rect);
   int *bsum = at<int>(ws, L.blocks);
-  int *bcull = bsum + 256;
-  long long *boff = at<long long>(ws, L.blocks + 2048);
+  int *bcull = bsum + BIN_BLOCK;
+  uint32_t *hist0 = at<uint32_t>(ws, L.hist);
+  uint32_t *hist1 = hist0 + (size_t)RADIX * L.sort_blocks;
+  uint32_t *tcount = at<uint32_t>(ws, L.tile_count);
+  int *tstart = at<int>(ws, L.tile_start);
+  int *torder = at<int>(ws, L.tile_order);
+  const long long n4 = (long long)(L.tile_count + 4 * (size_t)L.tile_count_words - L.hist) / 16;
   const int nb = (L.N + BIN_BLOCK - 1) / BIN_BLOCK;
+  const int G = L.sort_blocks;
   hipLaunchKernelGGL(k_project, dim3(nb), dim3(BIN_BLOCK), 0, st, L.N, L.TX, L.TY,
-                     1.0f / (float)L.T, xy, chol, geom, rect, counts, bsum, bcull);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(BIN_BLOCK), 0, st, L.N, nb, L.max_pairs, bsum,
-                     bcull, boff, offsets, misc, step_tick);
+                     1.0f / (float)L.T, xy, chol, geom, rect, counts, bsum, bcull,
+                     at<uint4>(ws, L.hist), n4);
   uint32_t *ka = at<uint32_t>(ws, L.keys_a), *kb = at<uint32_t>(ws, L.keys_b);
-  hipLaunchKernelGGL(k_emit_keys, dim3(nb), dim3(BIN_BLOCK), 0, st, L.N, L.TX, L.max_pairs, rect,
-                     counts, boff, offsets, ka);
-  uint32_t *hist = at<uint32_t>(ws, L.hist);
-  uint32_t *src = ka, *dst = kb;
-  for (int p = 0; p < L.sort_passes; ++p) {
-    const int shift = 16 + RADIX_BITS * p;
-    hipLaunchKernelGGL(k_radix_hist, dim3(L.sort_blocks), dim3(SORT_BLOCK), 0, st, src, misc, shift,
-                       L.sort_blocks, hist);
-    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(SCAN_BLOCK), 0, st, hist, L.sort_blocks * RADIX);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(L.sort_blocks), dim3(SORT_BLOCK), 0, st, src, dst, misc,
-                       shift, L.sort_blocks, hist);
-    uint32_t *t = src;
-    src = dst;
-    dst = t;
+  hipLaunchKernelGGL(k_emit_keys, dim3(nb), dim3(BIN_BLOCK), 0, st, L.N, L.TX, nb, L.max_pairs, G,
+                     rect, counts, bsum, bcull, offsets, ka, hist0, tcount, misc, step_tick);
+  if (L.sort_passes == 1) {
+    hipLaunchKernelGGL((k_radix_scatter<false, true>), dim3(G + 1), dim3(SORT_BLOCK), 0, st, ka,
+                       kb, misc, 16, G, hist0, nullptr, tcount, L.n_tiles, tstart, torder);
+  } else {
+    hipLaunchKernelGGL((k_radix_scatter<true, false>), dim3(G), dim3(SORT_BLOCK), 0, st, ka, kb,
+                       misc, 16, G, hist0, hist1, nullptr, 0, nullptr, nullptr);
+    hipLaunchKernelGGL((k_radix_scatter<false, true>), dim3(G + 1), dim3(SORT_BLOCK), 0, st, kb,
+                       ka, misc, 16 + RADIX_BITS, G, hist1, nullptr, tcount, L.n_tiles, tstart, torder);
   }
-  hipLaunchKernelGGL(k_tile_ranges, dim3(512), dim3(256), 0, st, src, misc, L.n_tiles,
-                     at<int>(ws, L.tile_start));
   return hipGetLastError();
 }
 
@@ -191,9 +151,8 @@ hipError_t launch_radix_sort_tiles(uint32_t *a, uint32_t *b, const int *misc, in
   for (int p = 0; p < passes; ++p) {
     const int shift = 16 + RADIX_BITS * p;
     hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(SORT_BLOCK), 0, st, src, misc, shift, G, hist);
-    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(SCAN_BLOCK), 0, st, hist, G * RADIX);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(SORT_BLOCK), 0, st, src, dst, misc, shift, G,
-                       hist);
+    hipLaunchKernelGGL((k_radix_scatter<false, false>), dim3(G), dim3(SORT_BLOCK), 0, st, src, dst,
+                       misc, shift, G, hist, nullptr, nullptr, 0, nullptr, nullptr);
     uint32_t *t = src;
     src = dst;
     dst = t;

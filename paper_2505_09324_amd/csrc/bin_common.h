@@ -7,10 +7,8 @@
 namespace gs2d {
 
 constexpr int BIN_BLOCK = 256;  // threads of the projection / emission blocks
-// Radix digit-offset scan: SORT_MAX_BLOCKS * RADIX entries over SCAN_BLOCK
-// threads, at most this many per thread (kept in 32-bit registers).
-constexpr int RADIX_SCAN_PER = (SORT_MAX_BLOCKS * RADIX + SCAN_BLOCK - 1) / SCAN_BLOCK;
-static_assert(RADIX_SCAN_PER * (SCAN_BLOCK / 64) <= 64 * 8, "wave-total table too small");
+static_assert(BIN_BLOCK * BIN_BLOCK >= 65536, "emission scans at most BIN_BLOCK block sums");
+static_assert(SORT_BLOCK == RADIX, "scatter threads map one-to-one onto digits");
 
 // Projection of Gaussian n (index into xy/chol and the outputs).
 // counts[n] = number of tiles met, or -1 for a culled Gaussian (the scan
@@ -159,14 +157,64 @@ __device__ inline void project_block(int base, int N, int TX, int TY, float inv_
   }
 }
 
+// Grid-stride clear of n4 uint4 words (one call per thread of a grid).
+__device__ inline void clear_u4(uint4 *__restrict__ p, long long n4) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Keys per sort chunk when n keys are split over G chunks: a multiple of
+// SORT_BLOCK, never zero.
+__device__ inline int chunk_len(int n, int G) {
+  const int c = (n + G - 1) / G;
+  return max(SORT_BLOCK, (c + SORT_BLOCK - 1) / SORT_BLOCK * SORT_BLOCK);
+}
+
+// Chunk [beg, end) of the key array owned by sort block b.
+__device__ inline void sort_chunk(int n, int G, int b, int *beg, int *end) {
+  const int chunk = chunk_len(n, G);
+  *beg = min(n, b * chunk);
+  *end = min(n, *beg + chunk);
+}
+
+// One block of BIN_BLOCK threads: the exclusive prefix of entry b among the
+// nb <= BIN_BLOCK per-block pair counts, their total and the total of the
+// culled counts (valid in every thread).
+__device__ inline void block_sum_prefix(int nb, int b, const int *__restrict__ bsum,
+                                        const int *__restrict__ bcull, long long *prefix,
+                                        long long *total, int *culled) {
+  __shared__ long long lds[BIN_BLOCK / 64];
+  __shared__ long long pre_b;
+  __shared__ int cl[BIN_BLOCK / 64];
+  const int t = threadIdx.x;
+  const long long v = (t < nb) ? bsum[t] : 0;
+  int c = (t < nb) ? bcull[t] : 0;
+  long long tot;
+  const long long ex = block_exclusive_scan<BIN_BLOCK>(v, &tot, lds);
+  if (t == b) pre_b = ex;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((t & 63) == 0) cl[t >> 6] = c;
+  __syncthreads();
+  int cs = 0;
+  for (int w = 0; w < BIN_BLOCK / 64; ++w) cs += cl[w];
+  *prefix = pre_b;
+  *total = tot;
+  *culled = cs;
+}
+
 // Key emission of the block's Gaussians [base, base + BIN_BLOCK): each
 // Gaussian's first key slot is block_off (the exclusive prefix of all
 // earlier blocks) plus the block-local exclusive prefix of the counts;
-// slots at or beyond `cap` are dropped.  offsets[n] receives the clamped
-// first slot; keys are (tile << 16) | n, row-major over the rectangle.
-__device__ inline void emit_block(int base, int N, int TX, long long block_off, int cap,
+// slots at or beyond n_keys (= min(total, capacity)) are dropped.
+// offsets[n] receives the clamped first slot; keys are (tile << 16) | n,
+// row-major over the rectangle.  Every emitted key also counts into
+// hist0[chunk * RADIX + (tile & 0xFF)] (chunk = slot / chunk_len(n_keys, G):
+// the first radix pass's per-chunk histogram) and into tile_count[tile].
+__device__ inline void emit_block(int base, int N, int TX, long long block_off, int n_keys, int G,
                                   const int4 *__restrict__ rect, const int *__restrict__ counts,
-                                  int *__restrict__ offsets, uint32_t *__restrict__ keys) {
+                                  int *__restrict__ offsets, uint32_t *__restrict__ keys,
+                                  uint32_t *__restrict__ hist0, uint32_t *__restrict__ tile_count) {
   __shared__ int lds[BIN_BLOCK / 64];
   const int n = base + (int)threadIdx.x;
   int c = 0;
@@ -178,106 +226,209 @@ __device__ inline void emit_block(int base, int N, int TX, long long block_off, 
   const int local = block_exclusive_scan_i32<BIN_BLOCK>(c, &tot, lds);
   if (n >= N) return;
   const long long start = block_off + local;
-  const int beg = (int)min(start, (long long)cap);
-  const int end = (int)min(start + c, (long long)cap);
+  const int beg = (int)min(start, (long long)n_keys);
+  const int end = (int)min(start + c, (long long)n_keys);
   offsets[n] = beg;
   if (end <= beg) return;
+  const int chunk = chunk_len(n_keys, G);
+  int ck = beg / chunk;
+  int next = (ck + 1) * chunk;
   const int4 rc = rect[n];
   int k = beg;
   for (int ty = rc.y; ty <= rc.w && k < end; ++ty)
-    for (int tx = rc.x; tx <= rc.z && k < end; ++tx, ++k)
-      keys[k] = ((uint32_t)(ty * TX + tx) << 16) | (uint32_t)n;
+    for (int tx = rc.x; tx <= rc.z && k < end; ++tx, ++k) {
+      const uint32_t tile = (uint32_t)(ty * TX + tx);
+      keys[k] = (tile << 16) | (uint32_t)n;
+      if (k == next) {
+        ++ck;
+        next += chunk;
+      }
+      atomicAdd(&hist0[ck * RADIX + (tile & (RADIX - 1))], 1u);
+      atomicAdd(&tile_count[tile], 1u);
+    }
 }
 
-// Exclusive scan of up to BIN_BLOCK per-block sums (one block of BIN_BLOCK
-// threads): boff[b] for b < nb; returns the totals in *pairs and *culled
-// (valid in every thread).
-__device__ inline void scan_block_sums(int nb, const int *__restrict__ bsum,
-                                       const int *__restrict__ bcull, long long *__restrict__ boff,
-                                       long long *pairs, int *culled) {
-  __shared__ long long lds[BIN_BLOCK / 64];
-  __shared__ int cl[BIN_BLOCK / 64];
-  const int b = threadIdx.x;
-  const long long v = (b < nb) ? bsum[b] : 0;
-  int c = (b < nb) ? bcull[b] : 0;
-  long long total;
-  const long long ex = block_exclusive_scan<BIN_BLOCK>(v, &total, lds);
-  if (b < nb) boff[b] = ex;
-  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
-  if ((threadIdx.x & 63) == 0) cl[threadIdx.x >> 6] = c;
+// Per-chunk histogram of one radix pass, block-major: hist[b * RADIX + d] =
+// keys of digit d in chunk b (zero for an empty chunk).
+__device__ inline void chunk_histogram(const uint32_t *__restrict__ keys, int n, int G, int b,
+                                       int shift, uint32_t *__restrict__ hist) {
+  __shared__ uint32_t h[RADIX];
+  h[threadIdx.x] = 0;
   __syncthreads();
-  int cs = 0;
-  for (int w = 0; w < BIN_BLOCK / 64; ++w) cs += cl[w];
-  *pairs = total;
-  *culled = cs;
+  int beg, end;
+  sort_chunk(n, G, b, &beg, &end);
+  for (int i = beg + threadIdx.x; i < end; i += SORT_BLOCK)
+    atomicAdd(&h[(keys[i] >> shift) & (RADIX - 1)], 1u);
+  __syncthreads();
+  hist[b * RADIX + threadIdx.x] = h[threadIdx.x];
 }
 
-// In-place exclusive scan of `total` <= RADIX_SCAN_PER * SCAN_BLOCK 32-bit
-// entries by one block of SCAN_BLOCK threads.  Entry e = k * SCAN_BLOCK + t
-// lives in register k of thread t, so every load and store of a wavefront
-// touches 64 consecutive words.  Each register column is scanned inside the
-// wavefronts, the (column, wavefront) totals are scanned by one wavefront in
-// (column, wavefront) order, and every thread adds its base back.
-__device__ inline void scan_u32_block(uint32_t *__restrict__ a, int total) {
-  constexpr int NW = SCAN_BLOCK / 64;
-  constexpr int NTOT = RADIX_SCAN_PER * NW;  // <= 512
-  __shared__ uint32_t tot[NTOT];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  uint32_t v[RADIX_SCAN_PER], inc[RADIX_SCAN_PER];
-#pragma unroll
-  for (int k = 0; k < RADIX_SCAN_PER; ++k) {
-    const int e = k * SCAN_BLOCK + t;
-    v[k] = (e < total) ? a[e] : 0u;
-  }
-#pragma unroll
-  for (int k = 0; k < RADIX_SCAN_PER; ++k) {
-    uint32_t x = v[k];
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
+// Digit offsets of chunk b for one radix pass, by one block of SORT_BLOCK
+// threads: off[d] = (keys of every digit < d in all chunks) + (keys of digit
+// d in the chunks before b), from the block-major histogram of `rows`
+// non-empty chunks.  Each wavefront sums every fourth row with one 16-byte
+// load per lane (a row is 1 KiB), so the rows are read coalesced and
+// in parallel; the partial sums meet in LDS.  Ends with a barrier.
+__device__ inline void chunk_digit_offsets(const uint32_t *__restrict__ hist, int rows, int b,
+                                           uint32_t *__restrict__ off) {
+  constexpr int NW = SORT_BLOCK / 64;
+  __shared__ uint32_t ptot[NW][RADIX];
+  __shared__ uint32_t ppre[NW][RADIX];
+  __shared__ int lds[NW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint4 *h4 = reinterpret_cast<const uint4 *>(hist);
+  uint4 tot = make_uint4(0u, 0u, 0u, 0u), pre = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll 4
+  for (int r = w; r < rows; r += NW) {
+    const uint4 h = h4[r * (RADIX / 4) + lane];
+    tot.x += h.x;
+    tot.y += h.y;
+    tot.z += h.z;
+    tot.w += h.w;
+    if (r < b) {
+      pre.x += h.x;
+      pre.y += h.y;
+      pre.z += h.z;
+      pre.w += h.w;
     }
-    inc[k] = x;
-    if (lane == 63) tot[k * NW + w] = x;
   }
+  reinterpret_cast<uint4 *>(ptot[w])[lane] = tot;
+  reinterpret_cast<uint4 *>(ppre[w])[lane] = pre;
   __syncthreads();
-  if (w == 0) {
-    // lane l scans entries [8l, 8l + 8) of the (column, wavefront) totals
-    uint32_t loc[8], s = 0;
+  const int d = threadIdx.x;
+  uint32_t T = 0, P = 0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int i = lane * 8 + j;
-      loc[j] = (i < NTOT) ? tot[i] : 0u;
-      s += loc[j];
-    }
-    uint32_t x = s;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
-    uint32_t run = x - s;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int i = lane * 8 + j;
-      if (i < NTOT) tot[i] = run;
-      run += loc[j];
-    }
+  for (int k = 0; k < NW; ++k) {
+    T += ptot[k][d];
+    P += ppre[k][d];
   }
+  int all;
+  const int ex = block_exclusive_scan_i32<SORT_BLOCK>((int)T, &all, lds);
+  off[d] = (uint32_t)ex + P;
   __syncthreads();
+}
+
+// Stable scatter of chunk b of one radix pass (keys in[0, n) sorted on the
+// digit at `shift`, G chunks): in input order, each key goes to
+// off[digit] + (earlier keys of the same digit in this chunk).  With
+// hist_next, every key also counts into the next pass's per-chunk
+// histogram at its output slot.
+template <bool NEXT>
+__device__ inline void scatter_chunk(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                     int n, int G, int b, int shift,
+                                     const uint32_t *__restrict__ hist,
+                                     uint32_t *__restrict__ hist_next) {
+  constexpr int NW = SORT_BLOCK / 64;
+  __shared__ uint32_t off[RADIX];
+  __shared__ uint32_t wcnt[NW][RADIX];
+  __shared__ uint32_t wpre[NW][RADIX];
+  const int chunk = chunk_len(n, G);
+  const int beg = min(n, b * chunk), end = min(n, beg + chunk);
+  if (beg >= end) return;  // uniform over the block
+  const int tid = threadIdx.x, w = tid >> 6;
 #pragma unroll
-  for (int k = 0; k < RADIX_SCAN_PER; ++k) {
-    const int e = k * SCAN_BLOCK + t;
-    if (e < total) a[e] = tot[k * NW + w] + inc[k] - v[k];
+  for (int k = 0; k < NW; ++k) wcnt[k][tid] = 0;
+  chunk_digit_offsets(hist, (n + chunk - 1) / chunk, b, off);
+  const unsigned long long lt = lanemask_lt();
+  for (int base = beg; base < end; base += SORT_BLOCK) {
+    const int i = base + tid;
+    const bool valid = i < end;
+    const uint32_t key = valid ? in[i] : 0u;
+    const uint32_t d = (key >> shift) & (RADIX - 1);
+    // lanes of this wave holding the same digit
+    unsigned long long match = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < RADIX_BITS; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const unsigned long long bal = __ballot(on);
+      match &= on ? bal : ~bal;
+    }
+    const uint32_t rank = (uint32_t)__popcll(match & lt);
+    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(match);
+    __syncthreads();
+    {
+      uint32_t s = 0;
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        wpre[k][tid] = s;
+        s += wcnt[k][tid];
+      }
+      wcnt[0][tid] = s;  // reuse row 0 as the sub-tile total of digit tid
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t p = off[d] + wpre[w][d] + rank;
+      out[p] = key;
+      if (NEXT)
+        atomicAdd(&hist_next[(p / (uint32_t)chunk) * RADIX + ((key >> (shift + RADIX_BITS)) & (RADIX - 1))],
+                  1u);
+    }
+    __syncthreads();
+    off[tid] += wcnt[0][tid];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) wcnt[k][tid] = 0;
+    __syncthreads();
   }
 }
 
-// Chunk of the key array owned by sort block b (a multiple of SORT_BLOCK).
-__device__ inline void sort_chunk(int n, int G, int b, int *beg, int *end) {
-  int chunk = (n + G - 1) / G;
-  chunk = (chunk + SORT_BLOCK - 1) / SORT_BLOCK * SORT_BLOCK;
-  *beg = min(n, b * chunk);
-  *end = min(n, *beg + chunk);
+// One block of SORT_BLOCK threads: tile_start[t] = sum of tile_count[0, t)
+// for t in [0, n_tiles] (the first slot of every tile's run in the sorted
+// key array).  Rounds of 8 consecutive counts per thread.
+__device__ inline void tile_starts(const uint32_t *__restrict__ tile_count, int n_tiles,
+                                   int *__restrict__ tile_start) {
+  constexpr int PER = 8;
+  __shared__ int lds[SORT_BLOCK / 64];
+  int carry = 0;
+  for (int base = 0; base < n_tiles; base += SORT_BLOCK * PER) {
+    const int t0 = base + (int)threadIdx.x * PER;
+    int v[PER], s = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      v[j] = (t0 + j < n_tiles) ? (int)tile_count[t0 + j] : 0;
+      s += v[j];
+    }
+    int round_total;
+    int run = carry + block_exclusive_scan_i32<SORT_BLOCK>(s, &round_total, lds);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      if (t0 + j < n_tiles) tile_start[t0 + j] = run;
+      run += v[j];
+    }
+    carry += round_total;
+  }
+  if (threadIdx.x == 0) tile_start[n_tiles] = carry;
+}
+
+// Bucket of a tile's pair count for the launch order: four buckets per
+// power of two, bucket 0 for the largest counts.
+__device__ inline int count_bucket(uint32_t c) {
+  const uint32_t x = c + 1u;  // >= 1
+  const int k = 31 - __clz((int)x);
+  const int f = k >= 2 ? (int)((x >> (k - 2)) & 3u) : (int)((x << (2 - k)) & 3u);
+  return 127 - (4 * k + f);
+}
+
+// One block of SORT_BLOCK threads: order[0, n_tiles) = the tiles by
+// decreasing pair count (bucketed as above; any order inside a bucket).
+// The raster processes tiles in this order, so the longest tiles start
+// first and short ones fill the end of the launch.
+__device__ inline void tile_order_by_count(const uint32_t *__restrict__ tile_count, int n_tiles,
+                                           int *__restrict__ order) {
+  constexpr int NBK = 128;
+  static_assert(NBK <= SORT_BLOCK, "one bucket per thread");
+  __shared__ int bk[NBK];
+  __shared__ int lds[SORT_BLOCK / 64];
+  if (threadIdx.x < NBK) bk[threadIdx.x] = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += SORT_BLOCK) atomicAdd(&bk[count_bucket(tile_count[t])], 1);
+  __syncthreads();
+  const int v = (threadIdx.x < NBK) ? bk[threadIdx.x] : 0;
+  int all;
+  const int ex = block_exclusive_scan_i32<SORT_BLOCK>(v, &all, lds);
+  if (threadIdx.x < NBK) bk[threadIdx.x] = ex;
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += SORT_BLOCK)
+    order[atomicAdd(&bk[count_bucket(tile_count[t])], 1)] = t;
 }
 
 }  // namespace gs2d

@@ -34,10 +34,11 @@ struct Layout {
   int W, H, N, T, max_pairs;
   int ppl;             // pixels per lane of the raster kernels (1, 2, 4)
   int TX, TY, n_tiles;
-  int sort_blocks;     // G: chunks of the key array, one sort block each
-  int sort_passes;     // 8-bit digit passes over the tile bits
-  size_t geom, rect, counts, offsets, blocks, keys_a, keys_b, hist, tile_start, loss_part, grads,
-      misc, total;
+  int sort_blocks;       // G: chunks of the key array, one sort block each
+  int sort_passes;       // 8-bit digit passes over the tile bits
+  int tile_count_words;  // n_tiles rounded up to a multiple of 4
+  size_t geom, rect, counts, offsets, blocks, keys_a, keys_b, hist, tile_count, tile_start,
+      tile_order, loss_part, grads, misc, total;
   // the buffer holding the sorted keys after all passes
   size_t keys_sorted() const { return (sort_passes & 1) ? keys_b : keys_a; }
 };
@@ -58,7 +59,8 @@ hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, v
                           hipStream_t st, int *step_tick = nullptr);
 
 // Stable LSD radix sort of keys on bits [16, 16 + 8*passes) with G sort
-// blocks; misc[0] holds the key count.  *sorted receives a or b.
+// blocks; misc[0] holds the key count; hist holds RADIX * G words.
+// *sorted receives a or b.
 hipError_t launch_radix_sort_tiles(uint32_t *a, uint32_t *b, const int *misc, int G, uint32_t *hist,
                                    int passes, hipStream_t st, const uint32_t **sorted);
 // tile_start[t] for sorted keys; misc[0] holds the key count.

@@ -202,23 +202,25 @@ __device__ inline void bwd_chunk(const Smem<NW> &S, float *acc, int len, float p
       any |= q[r] <= CUTOFF_Q;
     }
     if (CHECK_HITS && !__ballot(any)) continue;  // wavefront-uniform skip
-    float s1 = 0.f, s2 = 0.f, s3 = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
+    float s0 = 0.f, s2 = 0.f, s3 = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
 #pragma unroll
     for (int r = 0; r < PPL; ++r) {
       const float e = __builtin_amdgcn_exp2f(q[r] * NEG_HALF_LOG2E);
       const float wgt = (q[r] <= CUTOFF_Q) ? e : 0.f;
       const float sn = (g[r][0] * B.y + g[r][1] * B.z + g[r][2] * B.w) * wgt;
       const float v2 = u2[r] * B.x;
-      const float v1 = (u1 - A.w * v2) * A.z;
       const float t2 = sn * v2;
-      s1 += sn * v1;
+      s0 += sn;
       s2 += t2;
       s3 += t2 * u2[r];
       c0 += g[r][0] * wgt;
       c1 += g[r][1] * wgt;
       c2 += g[r][2] * wgt;
     }
-    // dL/dl1 = sum s v1 u1 and dL/dl2 = sum s v2 u1: u1 is common to the lane
+    // v1 = (u1 - l2 v2) / l1 with u1 common to the lane's pixels, so
+    // sum s v1 = (u1 sum s - l2 sum s v2) / l1; likewise dL/dl1 = sum s v1 u1
+    // and dL/dl2 = sum s v2 u1 take the lane's u1 once
+    const float s1 = (u1 * s0 - A.w * s2) * A.z;
     const float vals[8] = {s1, s2, s1 * u1, s2 * u1, s3, c0, c1, c2};
     const float red = reduce8_transpose(vals);
     if ((lane & 7) == 0) atomicAdd(&acc[j * 8 + (lane >> 3)], red);
