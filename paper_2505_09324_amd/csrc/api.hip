@@ -33,11 +33,14 @@ bool make_layout(const gs2d_shape &s, Layout *L) {
   L->n_tiles = (int)(TX * TY);
   int bits = 1;
   while ((1LL << bits) < (long long)L->n_tiles) ++bits;
-  L->sort_passes = (bits + RADIX_BITS - 1) / RADIX_BITS;
+  // at most 2048 tiles: one pass on the whole tile index, else 8-bit passes
+  L->wide = L->n_tiles <= 2048;
+  L->digit_bits = bits < 8 ? 8 : bits;
+  L->D = 1 << L->digit_bits;
+  L->sort_passes = L->wide ? 1 : (bits + RADIX_BITS - 1) / RADIX_BITS;
   // about one sort chunk per 256 Gaussians (chunks hold ~3 keys per Gaussian)
   const int G = (s.N + 255) / 256;
   L->sort_blocks = G > SORT_MAX_BLOCKS ? SORT_MAX_BLOCKS : G;
-  L->tile_count_words = (L->n_tiles + 3) & ~3;
   size_t o = 0;
   auto take = [&o](size_t bytes) {
     const size_t at = o;
@@ -52,11 +55,11 @@ bool make_layout(const gs2d_shape &s, Layout *L) {
   L->blocks = take(2048);  // per-projection-block sums (<= 256 blocks): pairs, culled
   L->keys_a = take((size_t)s.max_pairs * 4);
   L->keys_b = take((size_t)s.max_pairs * 4);
-  // cleared by every binning: two passes' histograms, then the tile counts
-  L->hist = take((size_t)RADIX * L->sort_blocks * 4 * 2);
-  L->tile_count = take((size_t)L->tile_count_words * 4);
+  // radix histogram rows: one per emission block (<= 256 rows of 256 words,
+  // or <= 64 rows of up to 2048 words on the single-pass path), then one
+  // per sort chunk of the second pass (<= 128 rows of 256 words)
+  L->hist = take((size_t)RADIX * 256 * 4 * 2);
   L->tile_start = take(((size_t)L->n_tiles + 1) * 4);
-  L->tile_order = take((size_t)L->n_tiles * 4);
   L->loss_part = take((size_t)L->n_tiles * 4);
   L->grads = take(N * 8 * 4);
   L->misc = take(MISC_COUNT * 4);

@@ -1,11 +1,11 @@
 // Batched fitting: many frames of different sizes and Gaussian counts fitted
 // in lockstep, one launch per stage per iteration.
 //
-//  - binning runs segmented per frame with the same four launches as one
-//    frame (project, emit, one scatter per radix pass): one thread per
-//    Gaussian of the whole batch for projection and key emission, a block
-//    table mapping the sort blocks to (frame, key chunk) for the scatter
-//    passes, and one extra block per frame for the tile ranges;
+//  - binning runs segmented per frame with the same launches as one frame:
+//    one thread per Gaussian of the whole batch for projection and key
+//    emission, the first radix pass over each emission block's keys, a
+//    block table mapping the second pass's blocks to (frame, key chunk),
+//    and a (block, frame) grid for the tile ranges;
 //  - the raster is ONE persistent launch per iteration: a grid sized to the
 //    device's resident capacity pulls (frame, tile) work items from a queue
 //    through an atomic counter, largest frames first, and runs the same
@@ -36,7 +36,7 @@ struct BFrame {
   long long g_off;     // first Gaussian of the frame in the concatenated arrays
   long long px_off;    // first float of the frame's target ([3][H][W])
   long long key_off;   // first key slot
-  long long hist_off;  // first radix histogram word (two passes of RADIX * G words)
+  long long hist_off;  // first word of the frame's second-pass histogram (RADIX * G)
   long long tile_off;  // first tile of the frame among all tiles of the batch
 };
 
@@ -46,9 +46,7 @@ struct BatchLayout {
   int F, T, ppl, passes, sort_blocks, proj_blocks;
   long long Ntot, keys_tot, hist_tot, tiles_tot;
   size_t desc, blk_frame, blk_chunk, pblk_frame, queue, geom, rect, counts, offsets, bsum, bcull,
-      keys_a, keys_b, hist, tile_count, tile_start, tile_order, loss_part, grads, misc, counter,
-      total;
-  long long zero4;  // uint4 words cleared by every binning (histograms, tile counts)
+      keys_a, keys_b, hist, hist2, tile_start, loss_part, grads, misc, counter, total;
   std::vector<BFrame> frames;
 };
 
@@ -91,7 +89,7 @@ bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout
     g += s.N;
     px += 3LL * s.W * s.H;
     key += d.cap;
-    hist += 2LL * RADIX * d.G;
+    hist += (long long)RADIX * d.G;
     tiles += d.n_tiles;
     blocks += d.G;
     int bits = 1;
@@ -124,11 +122,9 @@ bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout
   B->bcull = take(4 * (size_t)pblocks);
   B->keys_a = take(4 * (size_t)key);
   B->keys_b = take(4 * (size_t)key);
-  B->hist = take(4 * (size_t)hist);
-  B->tile_count = take(4 * (((size_t)tiles + 3) & ~(size_t)3));
-  B->zero4 = (long long)(B->tile_count + 4 * (((size_t)tiles + 3) & ~(size_t)3) - B->hist) / 16;
+  B->hist = take(4 * (size_t)RADIX * pblocks);
+  B->hist2 = take(4 * (size_t)hist);
   B->tile_start = take(4 * ((size_t)tiles + F));
-  B->tile_order = take(4 * (size_t)tiles);
   B->loss_part = take(4 * (size_t)tiles);
   B->grads = take(32 * (size_t)g);
   B->misc = take(4 * (size_t)BM_STRIDE * F);
@@ -144,18 +140,17 @@ __global__ void __launch_bounds__(BIN_BLOCK)
 k_b_project(const BFrame *__restrict__ D, const int *__restrict__ pblk_frame, int tile,
             const float *__restrict__ xy, const float *__restrict__ chol, float4 *__restrict__ geom,
             int4 *__restrict__ rect, int *__restrict__ counts, int *__restrict__ bsum,
-            int *__restrict__ bcull, uint4 *__restrict__ zero, long long n4) {
+            int *__restrict__ bcull) {
   const BFrame d = D[pblk_frame[blockIdx.x]];
   const int c = blockIdx.x - d.blk_off;
   const long long g = d.g_off;
   project_block(c * BIN_BLOCK, d.N, d.TX, d.TY, 1.0f / (float)tile, xy + 2 * g, chol + 3 * g,
                 geom + 2 * g, rect + g, counts + g, bsum + blockIdx.x, bcull + blockIdx.x);
-  clear_u4(zero, n4);
 }
 
 // Key emission of projection block b of frame f: prefix of its pair count
-// among the frame's blocks, then the keys and the frame's first-pass
-// histogram and tile counts.  The frame's first block publishes its pair
+// among the frame's blocks, then the keys and histogram row b of the first
+// radix pass.  The frame's first block publishes its pair
 // count and status; block 0 also advances the step counter (when given) and
 // clears the persistent raster's work counter for this iteration.
 __global__ void __launch_bounds__(BIN_BLOCK)
@@ -163,8 +158,7 @@ k_b_emit_keys(const BFrame *__restrict__ D, const int *__restrict__ pblk_frame,
               const int4 *__restrict__ rect, const int *__restrict__ counts,
               const int *__restrict__ bsum, const int *__restrict__ bcull,
               int *__restrict__ offsets, uint32_t *__restrict__ keys, uint32_t *__restrict__ hist,
-              uint32_t *__restrict__ tile_count, int *__restrict__ misc, int *__restrict__ tick,
-              unsigned *__restrict__ work_counter) {
+              int *__restrict__ misc, int *__restrict__ tick, unsigned *__restrict__ work_counter) {
   const int f = pblk_frame[blockIdx.x];
   const BFrame d = D[f];
   const int c = blockIdx.x - d.blk_off;
@@ -186,46 +180,73 @@ k_b_emit_keys(const BFrame *__restrict__ D, const int *__restrict__ pblk_frame,
       work_counter[0] = 0u;
     }
   }
-  emit_block(c * BIN_BLOCK, d.N, d.TX, pre, np, d.G, rect + d.g_off, counts + d.g_off,
-             offsets + d.g_off + f, keys + d.key_off, hist + d.hist_off, tile_count + d.tile_off);
+  emit_block(c * BIN_BLOCK, d.N, d.TX, pre, np, rect + d.g_off, counts + d.g_off,
+             offsets + d.g_off + f, keys + d.key_off, hist + (size_t)blockIdx.x * RADIX);
 }
 
-// Blocks [0, n_sort): stable scatter of chunk blk_chunk[b] of frame
-// blk_frame[b] for the pass at `shift` (pass index p: histogram p of the
-// frame; NEXT also counts histogram p + 1).  LAST: blocks n_sort + f compute
-// frame f's tile_start and tile order from its tile counts.
-template <bool NEXT, bool LAST>
+// First radix pass: block b scatters the keys emission block b wrote.
 __global__ void __launch_bounds__(SORT_BLOCK)
-k_b_radix_scatter(const BFrame *__restrict__ D, const int *__restrict__ blk_frame,
-                  const int *__restrict__ blk_chunk, int n_sort, const int *__restrict__ misc,
-                  const uint32_t *__restrict__ in_all, uint32_t *__restrict__ out_all, int pass,
-                  uint32_t *__restrict__ hist_all, const uint32_t *__restrict__ tile_count,
-                  int *__restrict__ tile_start_all, int *__restrict__ tile_order_all) {
-  if (LAST && (int)blockIdx.x >= n_sort) {
-    const int f = blockIdx.x - n_sort;
-    const BFrame d = D[f];
-    tile_starts(tile_count + d.tile_off, d.n_tiles, tile_start_all + d.tile_off + f);
-    __syncthreads();
-    tile_order_by_count(tile_count + d.tile_off, d.n_tiles, tile_order_all + d.tile_off);
-    return;
-  }
+k_b_scatter_first(const BFrame *__restrict__ D, const int *__restrict__ pblk_frame,
+                  const int *__restrict__ misc, const int *__restrict__ bsum,
+                  const int *__restrict__ bcull, const uint32_t *__restrict__ in_all,
+                  uint32_t *__restrict__ out_all, const uint32_t *__restrict__ hist) {
+  const int f = pblk_frame[blockIdx.x];
+  const BFrame d = D[f];
+  const int c = blockIdx.x - d.blk_off;
+  long long pre, total;
+  int culled;
+  block_sum_prefix(d.nb, c, bsum + d.blk_off, bcull + d.blk_off, &pre, &total, &culled);
+  const long long n = misc[BM_STRIDE * f + BM_N_PAIRS];
+  const int beg = (int)min(pre, n), end = (int)min(pre + bsum[blockIdx.x], n);
+  scatter_chunk(in_all + d.key_off, out_all + d.key_off, beg, end, d.nb, c, 16,
+                hist + (size_t)d.blk_off * RADIX);
+}
+
+// Second pass over the frame's G fixed chunks: histogram, then scatter.
+__global__ void __launch_bounds__(SORT_BLOCK)
+k_b_radix_hist(const BFrame *__restrict__ D, const int *__restrict__ blk_frame,
+               const int *__restrict__ blk_chunk, const int *__restrict__ misc,
+               const uint32_t *__restrict__ keys, int shift, uint32_t *__restrict__ hist) {
   const int f = blk_frame[blockIdx.x], c = blk_chunk[blockIdx.x];
   const BFrame d = D[f];
-  uint32_t *h = hist_all + d.hist_off + (long long)pass * RADIX * d.G;
-  scatter_chunk<NEXT>(in_all + d.key_off, out_all + d.key_off, misc[BM_STRIDE * f + BM_N_PAIRS],
-                      d.G, c, 16 + RADIX_BITS * pass, h, h + (long long)RADIX * d.G);
+  chunk_histogram(keys + d.key_off, misc[BM_STRIDE * f + BM_N_PAIRS], d.G, c, shift,
+                  hist + d.hist_off);
+}
+
+__global__ void __launch_bounds__(SORT_BLOCK)
+k_b_radix_scatter(const BFrame *__restrict__ D, const int *__restrict__ blk_frame,
+                  const int *__restrict__ blk_chunk, const int *__restrict__ misc,
+                  const uint32_t *__restrict__ in_all, uint32_t *__restrict__ out_all, int shift,
+                  const uint32_t *__restrict__ hist) {
+  const int f = blk_frame[blockIdx.x], c = blk_chunk[blockIdx.x];
+  const BFrame d = D[f];
+  const int n = misc[BM_STRIDE * f + BM_N_PAIRS];
+  const int chunk = chunk_len(n, d.G);
+  int beg, end;
+  sort_chunk(n, d.G, c, &beg, &end);
+  scatter_chunk(in_all + d.key_off, out_all + d.key_off, beg, end, (n + chunk - 1) / chunk, c,
+                shift, hist + d.hist_off);
+}
+
+// Grid (RB, F): tile ranges of frame blockIdx.y.
+__global__ void __launch_bounds__(256)
+k_b_tile_ranges(const BFrame *__restrict__ D, const int *__restrict__ misc,
+                const uint32_t *__restrict__ keys_all, int *__restrict__ tile_start_all) {
+  const int f = blockIdx.y;
+  const BFrame d = D[f];
+  tile_ranges(keys_all + d.key_off, misc[BM_STRIDE * f + BM_N_PAIRS], d.n_tiles,
+              tile_start_all + d.tile_off + f);
 }
 
 // ------------------------------------------------------------- raster ----
 struct BatchRaster {
   const BFrame *D;
-  const uint32_t *queue;  // (frame << 16) | i: the frame's i-th tile in its tile order
+  const uint32_t *queue;  // (frame << 16) | tile, processing order
   unsigned n_items;
   unsigned *counter;
   const float4 *geom;
   const uint32_t *keys;
   const int *tile_start;
-  const int *tile_order;
   const float *rgb;
   const float *targets;
   float *loss_part;
@@ -246,9 +267,8 @@ k_b_render_persistent(BatchRaster a) {
     __syncthreads();
     if (item >= a.n_items) break;  // every wavefront leaves together
     const uint32_t q = a.queue[item];
-    const int f = (int)(q >> 16);
+    const int f = (int)(q >> 16), t = (int)(q & 0xFFFFu);
     const BFrame d = a.D[f];
-    const int t = a.tile_order[d.tile_off + (int)(q & 0xFFFFu)];
     FrameArgs fa;
     fa.W = d.W;
     fa.H = d.H;
@@ -302,8 +322,7 @@ hipError_t upload_tables(const BatchLayout &B, void *ws, hipStream_t st) {
     }
     for (int c = 0; c < d.nb; ++c) pf.push_back(f);
   }
-  // work order: frames by decreasing area (largest lists first), then each
-  // frame's tiles in the order the binning computes (longest lists first)
+  // work order: frames by decreasing area (largest lists first), tiles in order
   std::vector<int> order(B.F);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -360,26 +379,25 @@ hipError_t enqueue_batch_binning(const BatchLayout &B, void *ws, const float *xy
   int *misc = at<int>(ws, B.misc);
   unsigned *counter = at<unsigned>(ws, B.counter);
   uint32_t *ka = at<uint32_t>(ws, B.keys_a), *kb = at<uint32_t>(ws, B.keys_b);
-  uint32_t *hist = at<uint32_t>(ws, B.hist);
-  uint32_t *tcount = at<uint32_t>(ws, B.tile_count);
-  int *tstart = at<int>(ws, B.tile_start);
-  int *torder = at<int>(ws, B.tile_order);
+  uint32_t *hist = at<uint32_t>(ws, B.hist), *hist2 = at<uint32_t>(ws, B.hist2);
   const int *pf = at<const int>(ws, B.pblk_frame);
   int *bsum = at<int>(ws, B.bsum), *bcull = at<int>(ws, B.bcull);
   hipLaunchKernelGGL(k_b_project, dim3(B.proj_blocks), dim3(BIN_BLOCK), 0, st, D, pf, B.T, xy, chol,
-                     geom, rect, counts, bsum, bcull, at<uint4>(ws, B.hist), B.zero4);
+                     geom, rect, counts, bsum, bcull);
   hipLaunchKernelGGL(k_b_emit_keys, dim3(B.proj_blocks), dim3(BIN_BLOCK), 0, st, D, pf, rect, counts,
-                     bsum, bcull, offsets, ka, hist, tcount, misc, tick, counter);
-  const int ns = B.sort_blocks;
-  if (B.passes == 1) {
-    hipLaunchKernelGGL((k_b_radix_scatter<false, true>), dim3(ns + B.F), dim3(SORT_BLOCK), 0, st, D,
-                       bf, bc, ns, misc, ka, kb, 0, hist, tcount, tstart, torder);
-  } else {
-    hipLaunchKernelGGL((k_b_radix_scatter<true, false>), dim3(ns), dim3(SORT_BLOCK), 0, st, D, bf,
-                       bc, ns, misc, ka, kb, 0, hist, nullptr, nullptr, nullptr);
-    hipLaunchKernelGGL((k_b_radix_scatter<false, true>), dim3(ns + B.F), dim3(SORT_BLOCK), 0, st, D,
-                       bf, bc, ns, misc, kb, ka, 1, hist, tcount, tstart, torder);
+                     bsum, bcull, offsets, ka, hist, misc, tick, counter);
+  hipLaunchKernelGGL(k_b_scatter_first, dim3(B.proj_blocks), dim3(SORT_BLOCK), 0, st, D, pf, misc,
+                     bsum, bcull, ka, kb, hist);
+  const uint32_t *sorted = kb;
+  if (B.passes == 2) {
+    hipLaunchKernelGGL(k_b_radix_hist, dim3(B.sort_blocks), dim3(SORT_BLOCK), 0, st, D, bf, bc,
+                       misc, kb, 16 + RADIX_BITS, hist2);
+    hipLaunchKernelGGL(k_b_radix_scatter, dim3(B.sort_blocks), dim3(SORT_BLOCK), 0, st, D, bf, bc,
+                       misc, kb, ka, 16 + RADIX_BITS, hist2);
+    sorted = ka;
   }
+  hipLaunchKernelGGL(k_b_tile_ranges, dim3(32, B.F), dim3(256), 0, st, D, misc, sorted,
+                     at<int>(ws, B.tile_start));
   return hipGetLastError();
 }
 
@@ -398,7 +416,6 @@ hipError_t enqueue_batch_raster(const BatchLayout &B, void *ws, int grid, const 
   a.geom = at<const float4>(ws, B.geom);
   a.keys = batch_sorted_keys(B, ws);
   a.tile_start = at<const int>(ws, B.tile_start);
-  a.tile_order = at<const int>(ws, B.tile_order);
   a.rgb = rgb;
   a.targets = targets;
   a.loss_part = at<float>(ws, B.loss_part);

@@ -1,20 +1,26 @@
 // Projection and tile binning for the tile-based rasteriser of Eq. 2.
 //
-// Per iteration, four launches:
+// Frames of at most 2048 tiles take a single radix pass whose digit is the
+// whole tile index:
+//   project   (1024-thread blocks) box, tile rectangle, count, block sums;
+//   emit      every block scans the (<= 64) block sums for its prefix,
+//             writes its keys and their per-tile histogram row (LDS);
+//   scatter   block b stably scatters emission block b's keys; it derives
+//             its per-tile offsets from the histogram rows, and block 0
+//             writes tile_start from the per-tile totals.
+// Larger frames use two 8-bit passes:
 //   project   one thread per Gaussian: box, tile rectangle, tile count, and
-//             per-block sums; also clears the histograms below;
-//   emit      every block scans the (<= 256) block sums for its own prefix,
-//             writes its Gaussians' keys, and counts them into the first
-//             radix pass's per-chunk digit histogram and into per-tile
-//             counts (integer atomics: order-independent, exact);
-//   scatter   one launch per 8-bit digit pass of the stable LSD radix sort
-//             on the tile bits: each block derives its chunk's digit
-//             offsets from the histogram rows itself, scatters stably, and
-//             (all passes but the last) counts its keys into the next
-//             pass's histogram at their output slots; the last pass carries
-//             one extra block that turns the per-tile counts into tile
-//             ranges and into the raster's tile order (largest lists
-//             first).
+//             per-block sums;
+//   emit      every block scans the (<= 256) block sums for its own prefix
+//             and writes its Gaussians' keys; its keys are one chunk of the
+//             first radix pass, whose digit histogram it counts in LDS;
+//   scatter   stable scatter of each emission block's chunk on the low tile
+//             byte, digit offsets computed inside the block from the
+//             histogram rows;
+//   [hist, scatter]  the second pass (high tile byte) when there are more
+//             than 256 tiles, over fixed chunks;
+//   ranges    tile_start from the sorted keys.
+// No kernel uses global atomics or a single-block serial scan.
 //
 // Keys are (tile << 16) | gaussian_index.  Keys are emitted in ascending
 // Gaussian order and the sort is stable on the tile bits, so the result is
@@ -29,30 +35,27 @@ namespace gs2d {
 
 // ---------------------------------------------------------------- project --
 // One thread per Gaussian; each block also writes the sum of its tile counts
-// and of its culled Gaussians (bsum/bcull[block]) and clears its share of
-// the n4 uint4 words at `zero` (histograms and tile counts).
+// and of its culled Gaussians (bsum/bcull[block]).
 __global__ void __launch_bounds__(BIN_BLOCK)
 k_project(int N, int TX, int TY, float inv_tile, const float *__restrict__ xy,
           const float *__restrict__ chol, float4 *__restrict__ geom, int4 *__restrict__ rect,
-          int *__restrict__ counts, int *__restrict__ bsum, int *__restrict__ bcull,
-          uint4 *__restrict__ zero, long long n4) {
+          int *__restrict__ counts, int *__restrict__ bsum, int *__restrict__ bcull) {
   project_block(blockIdx.x * BIN_BLOCK, N, TX, TY, inv_tile, xy, chol, geom, rect, counts,
                 bsum + blockIdx.x, bcull + blockIdx.x);
-  clear_u4(zero, n4);
 }
 
 // ------------------------------------------------------------- emit keys --
-// Block b: prefix of its pair count among all nb blocks, then key emission.
-// Block 0 also publishes the pair count n_pairs = min(total, max_pairs),
-// offsets[N], the status bits and the culled count; when `tick` is given its
-// value is incremented once (the fitting loop's step counter, read by the
-// optimiser later in the same iteration).
+// Block b: prefix of its pair count among all nb blocks, then key emission
+// and the first pass's histogram row b.  Block 0 also publishes the pair
+// count n_pairs = min(total, max_pairs), offsets[N], the status bits and the
+// culled count; when `tick` is given its value is incremented once (the
+// fitting loop's step counter, read by the optimiser later in the same
+// iteration).
 __global__ void __launch_bounds__(BIN_BLOCK)
-k_emit_keys(int N, int TX, int nb, int max_pairs, int G, const int4 *__restrict__ rect,
+k_emit_keys(int N, int TX, int nb, int max_pairs, const int4 *__restrict__ rect,
             const int *__restrict__ counts, const int *__restrict__ bsum,
             const int *__restrict__ bcull, int *__restrict__ offsets, uint32_t *__restrict__ keys,
-            uint32_t *__restrict__ hist0, uint32_t *__restrict__ tile_count,
-            int *__restrict__ misc, int *__restrict__ tick) {
+            uint32_t *__restrict__ hist, int *__restrict__ misc, int *__restrict__ tick) {
   long long pre, total;
   int culled;
   block_sum_prefix(nb, blockIdx.x, bsum, bcull, &pre, &total, &culled);
@@ -67,47 +70,88 @@ k_emit_keys(int N, int TX, int nb, int max_pairs, int G, const int4 *__restrict_
     misc[MISC_STICKY] |= (int)st;
     if (tick) tick[0] += 1;
   }
-  emit_block(blockIdx.x * BIN_BLOCK, N, TX, pre, np, G, rect, counts, offsets, keys, hist0,
-             tile_count);
+  emit_block(blockIdx.x * BIN_BLOCK, N, TX, pre, np, rect, counts, offsets, keys,
+             hist + (size_t)blockIdx.x * RADIX);
+}
+
+// ------------------------------------------------------- single-pass path --
+__global__ void __launch_bounds__(WIDE_BLOCK)
+k_project_wide(int N, int TX, int TY, float inv_tile, const float *__restrict__ xy,
+               const float *__restrict__ chol, float4 *__restrict__ geom, int4 *__restrict__ rect,
+               int *__restrict__ counts, int *__restrict__ bsum, int *__restrict__ bcull) {
+  project_block<WIDE_BLOCK>(blockIdx.x * WIDE_BLOCK, N, TX, TY, inv_tile, xy, chol, geom, rect,
+                            counts, bsum + blockIdx.x, bcull + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(WIDE_BLOCK)
+k_emit_wide(int N, int TX, int nb, int max_pairs, int D, const int4 *__restrict__ rect,
+            const int *__restrict__ counts, const int *__restrict__ bsum,
+            const int *__restrict__ bcull, int *__restrict__ offsets, uint32_t *__restrict__ keys,
+            uint32_t *__restrict__ hist, int *__restrict__ misc, int *__restrict__ tick) {
+  long long pre, total;
+  int culled;
+  block_sum_prefix<WIDE_BLOCK>(nb, blockIdx.x, bsum, bcull, &pre, &total, &culled);
+  const int np = (int)min(total, (long long)max_pairs);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    offsets[N] = np;
+    const uint32_t st = (total > (long long)max_pairs ? STATUS_OVERFLOW : 0u) |
+                        (culled > 0 ? STATUS_CULLED : 0u);
+    misc[MISC_N_PAIRS] = np;
+    misc[MISC_STATUS] = (int)st;
+    misc[MISC_N_CULLED] = culled;
+    misc[MISC_STICKY] |= (int)st;
+    if (tick) tick[0] += 1;
+  }
+  emit_block_wide(blockIdx.x * WIDE_BLOCK, N, TX, pre, np, D, rect, counts, offsets, keys,
+                  hist + (size_t)blockIdx.x * D);
+}
+
+__global__ void __launch_bounds__(WIDE_SCATTER)
+k_scatter_wide(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+               const int *__restrict__ misc, int nb, int D, int bits, int n_tiles,
+               const int *__restrict__ bsum, const int *__restrict__ bcull,
+               const uint32_t *__restrict__ hist, int *__restrict__ tile_start) {
+  scatter_chunk_wide(in, out, nb, blockIdx.x / WIDE_SPLIT, blockIdx.x % WIDE_SPLIT, D, bits,
+                     misc[MISC_N_PAIRS], n_tiles, bsum, bcull, hist, tile_start);
 }
 
 // ------------------------------------------------------------ radix sort --
-// Per-chunk histogram of one pass (used when no earlier kernel counted it).
+// First pass: block b scatters the keys emission block b wrote (its range
+// recomputed from the block sums), on the low tile byte.
+__global__ void __launch_bounds__(SORT_BLOCK)
+k_scatter_first(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                const int *__restrict__ misc, int nb, const int *__restrict__ bsum,
+                const int *__restrict__ bcull, const uint32_t *__restrict__ hist) {
+  long long pre, total;
+  int culled;
+  block_sum_prefix(nb, blockIdx.x, bsum, bcull, &pre, &total, &culled);
+  const long long n = misc[MISC_N_PAIRS];
+  const int beg = (int)min(pre, n), end = (int)min(pre + bsum[blockIdx.x], n);
+  scatter_chunk(in, out, beg, end, nb, blockIdx.x, 16, hist);
+}
+
+// Later passes over G fixed chunks: per-chunk histogram, then scatter.
 __global__ void __launch_bounds__(SORT_BLOCK)
 k_radix_hist(const uint32_t *__restrict__ keys, const int *__restrict__ misc, int shift, int G,
              uint32_t *__restrict__ hist) {
   chunk_histogram(keys, misc[MISC_N_PAIRS], G, blockIdx.x, shift, hist);
 }
 
-// Blocks [0, G): stable scatter of one chunk (NEXT: also count the next
-// pass's histogram).  LAST: block G computes tile_start and the tile order
-// from tile_count.
-template <bool NEXT, bool LAST>
 __global__ void __launch_bounds__(SORT_BLOCK)
 k_radix_scatter(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
-                const int *__restrict__ misc, int shift, int G, const uint32_t *__restrict__ hist,
-                uint32_t *__restrict__ hist_next, const uint32_t *__restrict__ tile_count,
-                int n_tiles, int *__restrict__ tile_start, int *__restrict__ tile_order) {
-  if (LAST && (int)blockIdx.x == G) {
-    tile_starts(tile_count, n_tiles, tile_start);
-    __syncthreads();
-    tile_order_by_count(tile_count, n_tiles, tile_order);
-    return;
-  }
-  scatter_chunk<NEXT>(in, out, misc[MISC_N_PAIRS], G, blockIdx.x, shift, hist, hist_next);
+                const int *__restrict__ misc, int shift, int G, const uint32_t *__restrict__ hist) {
+  const int n = misc[MISC_N_PAIRS];
+  const int chunk = chunk_len(n, G);
+  int beg, end;
+  sort_chunk(n, G, blockIdx.x, &beg, &end);
+  scatter_chunk(in, out, beg, end, (n + chunk - 1) / chunk, blockIdx.x, shift, hist);
 }
 
 // --------------------------------------------------------------- ranges --
-// tile_start[t] = first index i with tile(keys[i]) >= t, for t in [0, n_tiles].
 __global__ void __launch_bounds__(256)
 k_tile_ranges(const uint32_t *__restrict__ keys, const int *__restrict__ misc, int n_tiles,
               int *__restrict__ tile_start) {
-  const int n = misc[MISC_N_PAIRS];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
-    const int cur = (i < n) ? (int)(keys[i] >> 16) : n_tiles;
-    const int prev = (i > 0) ? (int)(keys[i - 1] >> 16) : -1;
-    for (int t = prev + 1; t <= cur && t <= n_tiles; ++t) tile_start[t] = i;
-  }
+  tile_ranges(keys, misc[MISC_N_PAIRS], n_tiles, tile_start);
 }
 
 hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, void *ws,
@@ -119,29 +163,38 @@ hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, v
   int4 *rect = at<int4>(ws, L.rect);
   int *bsum = at<int>(ws, L.blocks);
   int *bcull = bsum + BIN_BLOCK;
-  uint32_t *hist0 = at<uint32_t>(ws, L.hist);
-  uint32_t *hist1 = hist0 + (size_t)RADIX * L.sort_blocks;
-  uint32_t *tcount = at<uint32_t>(ws, L.tile_count);
-  int *tstart = at<int>(ws, L.tile_start);
-  int *torder = at<int>(ws, L.tile_order);
-  const long long n4 = (long long)(L.tile_count + 4 * (size_t)L.tile_count_words - L.hist) / 16;
-  const int nb = (L.N + BIN_BLOCK - 1) / BIN_BLOCK;
-  const int G = L.sort_blocks;
-  hipLaunchKernelGGL(k_project, dim3(nb), dim3(BIN_BLOCK), 0, st, L.N, L.TX, L.TY,
-                     1.0f / (float)L.T, xy, chol, geom, rect, counts, bsum, bcull,
-                     at<uint4>(ws, L.hist), n4);
+  uint32_t *hist = at<uint32_t>(ws, L.hist);
   uint32_t *ka = at<uint32_t>(ws, L.keys_a), *kb = at<uint32_t>(ws, L.keys_b);
-  hipLaunchKernelGGL(k_emit_keys, dim3(nb), dim3(BIN_BLOCK), 0, st, L.N, L.TX, nb, L.max_pairs, G,
-                     rect, counts, bsum, bcull, offsets, ka, hist0, tcount, misc, step_tick);
-  if (L.sort_passes == 1) {
-    hipLaunchKernelGGL((k_radix_scatter<false, true>), dim3(G + 1), dim3(SORT_BLOCK), 0, st, ka,
-                       kb, misc, 16, G, hist0, nullptr, tcount, L.n_tiles, tstart, torder);
-  } else {
-    hipLaunchKernelGGL((k_radix_scatter<true, false>), dim3(G), dim3(SORT_BLOCK), 0, st, ka, kb,
-                       misc, 16, G, hist0, hist1, nullptr, 0, nullptr, nullptr);
-    hipLaunchKernelGGL((k_radix_scatter<false, true>), dim3(G + 1), dim3(SORT_BLOCK), 0, st, kb,
-                       ka, misc, 16 + RADIX_BITS, G, hist1, nullptr, tcount, L.n_tiles, tstart, torder);
+  if (L.wide) {
+    const int nbw = (L.N + WIDE_BLOCK - 1) / WIDE_BLOCK;
+    hipLaunchKernelGGL(k_project_wide, dim3(nbw), dim3(WIDE_BLOCK), 0, st, L.N, L.TX, L.TY,
+                       1.0f / (float)L.T, xy, chol, geom, rect, counts, bsum, bcull);
+    hipLaunchKernelGGL(k_emit_wide, dim3(nbw), dim3(WIDE_BLOCK), 0, st, L.N, L.TX, nbw,
+                       L.max_pairs, L.D, rect, counts, bsum, bcull, offsets, ka, hist, misc,
+                       step_tick);
+    hipLaunchKernelGGL(k_scatter_wide, dim3(nbw * WIDE_SPLIT), dim3(WIDE_SCATTER), 0, st, ka, kb,
+                       misc, nbw, L.D,
+                       L.digit_bits, L.n_tiles, bsum, bcull, hist, at<int>(ws, L.tile_start));
+    return hipGetLastError();
   }
+  const int nb = (L.N + BIN_BLOCK - 1) / BIN_BLOCK;
+  hipLaunchKernelGGL(k_project, dim3(nb), dim3(BIN_BLOCK), 0, st, L.N, L.TX, L.TY,
+                     1.0f / (float)L.T, xy, chol, geom, rect, counts, bsum, bcull);
+  hipLaunchKernelGGL(k_emit_keys, dim3(nb), dim3(BIN_BLOCK), 0, st, L.N, L.TX, nb, L.max_pairs,
+                     rect, counts, bsum, bcull, offsets, ka, hist, misc, step_tick);
+  hipLaunchKernelGGL(k_scatter_first, dim3(nb), dim3(SORT_BLOCK), 0, st, ka, kb, misc, nb, bsum,
+                     bcull, hist);
+  const uint32_t *sorted = kb;
+  if (L.sort_passes == 2) {
+    const int G = L.sort_blocks;
+    hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(SORT_BLOCK), 0, st, kb, misc, 16 + RADIX_BITS,
+                       G, hist);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(SORT_BLOCK), 0, st, kb, ka, misc,
+                       16 + RADIX_BITS, G, hist);
+    sorted = ka;
+  }
+  hipLaunchKernelGGL(k_tile_ranges, dim3(256), dim3(256), 0, st, sorted, misc, L.n_tiles,
+                     at<int>(ws, L.tile_start));
   return hipGetLastError();
 }
 
@@ -151,8 +204,8 @@ hipError_t launch_radix_sort_tiles(uint32_t *a, uint32_t *b, const int *misc, in
   for (int p = 0; p < passes; ++p) {
     const int shift = 16 + RADIX_BITS * p;
     hipLaunchKernelGGL(k_radix_hist, dim3(G), dim3(SORT_BLOCK), 0, st, src, misc, shift, G, hist);
-    hipLaunchKernelGGL((k_radix_scatter<false, false>), dim3(G), dim3(SORT_BLOCK), 0, st, src, dst,
-                       misc, shift, G, hist, nullptr, nullptr, 0, nullptr, nullptr);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(G), dim3(SORT_BLOCK), 0, st, src, dst, misc, shift, G,
+                       hist);
     uint32_t *t = src;
     src = dst;
     dst = t;

@@ -10,6 +10,14 @@ constexpr int BIN_BLOCK = 256;  // threads of the projection / emission blocks
 static_assert(BIN_BLOCK * BIN_BLOCK >= 65536, "emission scans at most BIN_BLOCK block sums");
 static_assert(SORT_BLOCK == RADIX, "scatter threads map one-to-one onto digits");
 
+// Single-pass binning (frames of at most WIDE_MAX_TILES tiles): the whole
+// tile index is one radix digit.
+constexpr int WIDE_BLOCK = 1024;      // threads of its projection / emission blocks
+constexpr int WIDE_MAX_TILES = 2048;  // largest digit range (11 bits)
+constexpr int WIDE_SCATTER = 512;     // threads of its scatter blocks
+constexpr int WIDE_SPLIT = 4;         // scatter blocks per emission chunk
+static_assert(WIDE_BLOCK * 64 >= 65536, "at most 64 emission blocks per frame");
+
 // Projection of Gaussian n (index into xy/chol and the outputs).
 // counts[n] = number of tiles met, or -1 for a culled Gaussian (the scan
 // turns -1 into 0 and counts the culls).  geom[n] = {mx, my, 1/l1, l2, 1/l3,
@@ -121,14 +129,15 @@ __device__ inline int block_exclusive_scan_i32(int v, int *total, int *lds) {
   return before + x - v;
 }
 
-// Projection of the block's Gaussians [base, base + BIN_BLOCK) of an array
-// of N, plus the block's sum of tile counts and of culled Gaussians.
+// Projection of the block's Gaussians [base, base + NT) of an array of N,
+// plus the block's sum of tile counts and of culled Gaussians.
+template <int NT = BIN_BLOCK>
 __device__ inline void project_block(int base, int N, int TX, int TY, float inv_tile,
                                      const float *__restrict__ xy, const float *__restrict__ chol,
                                      float4 *__restrict__ geom, int4 *__restrict__ rect,
                                      int *__restrict__ counts, int *__restrict__ bsum,
                                      int *__restrict__ bcull) {
-  __shared__ int red[2][BIN_BLOCK / 64];
+  __shared__ int red[2][NT / 64];
   const int n = base + (int)threadIdx.x;
   int c = 0, cull = 0;
   if (n < N) {
@@ -148,20 +157,13 @@ __device__ inline void project_block(int base, int N, int TX, int TY, float inv_
   __syncthreads();
   if (threadIdx.x == 0) {
     int a = 0, b = 0;
-    for (int w = 0; w < BIN_BLOCK / 64; ++w) {
+    for (int w = 0; w < NT / 64; ++w) {
       a += red[0][w];
       b += red[1][w];
     }
     *bsum = a;
     *bcull = b;
   }
-}
-
-// Grid-stride clear of n4 uint4 words (one call per thread of a grid).
-__device__ inline void clear_u4(uint4 *__restrict__ p, long long n4) {
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride)
-    p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // Keys per sort chunk when n keys are split over G chunks: a multiple of
@@ -178,26 +180,27 @@ __device__ inline void sort_chunk(int n, int G, int b, int *beg, int *end) {
   *end = min(n, *beg + chunk);
 }
 
-// One block of BIN_BLOCK threads: the exclusive prefix of entry b among the
-// nb <= BIN_BLOCK per-block pair counts, their total and the total of the
-// culled counts (valid in every thread).
+// One block of NT threads: the exclusive prefix of entry b among the
+// nb <= NT per-block pair counts, their total and the total of the culled
+// counts (valid in every thread).
+template <int NT = BIN_BLOCK>
 __device__ inline void block_sum_prefix(int nb, int b, const int *__restrict__ bsum,
                                         const int *__restrict__ bcull, long long *prefix,
                                         long long *total, int *culled) {
-  __shared__ long long lds[BIN_BLOCK / 64];
+  __shared__ long long lds[NT / 64];
   __shared__ long long pre_b;
-  __shared__ int cl[BIN_BLOCK / 64];
+  __shared__ int cl[NT / 64];
   const int t = threadIdx.x;
   const long long v = (t < nb) ? bsum[t] : 0;
   int c = (t < nb) ? bcull[t] : 0;
   long long tot;
-  const long long ex = block_exclusive_scan<BIN_BLOCK>(v, &tot, lds);
+  const long long ex = block_exclusive_scan<NT>(v, &tot, lds);
   if (t == b) pre_b = ex;
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
   if ((t & 63) == 0) cl[t >> 6] = c;
   __syncthreads();
   int cs = 0;
-  for (int w = 0; w < BIN_BLOCK / 64; ++w) cs += cl[w];
+  for (int w = 0; w < NT / 64; ++w) cs += cl[w];
   *prefix = pre_b;
   *total = tot;
   *culled = cs;
@@ -208,14 +211,17 @@ __device__ inline void block_sum_prefix(int nb, int b, const int *__restrict__ b
 // earlier blocks) plus the block-local exclusive prefix of the counts;
 // slots at or beyond n_keys (= min(total, capacity)) are dropped.
 // offsets[n] receives the clamped first slot; keys are (tile << 16) | n,
-// row-major over the rectangle.  Every emitted key also counts into
-// hist0[chunk * RADIX + (tile & 0xFF)] (chunk = slot / chunk_len(n_keys, G):
-// the first radix pass's per-chunk histogram) and into tile_count[tile].
-__device__ inline void emit_block(int base, int N, int TX, long long block_off, int n_keys, int G,
+// row-major over the rectangle.  The block's keys form one chunk of the
+// first radix pass: hist_row[d] receives how many of them have low tile
+// byte d (counted in LDS, written with plain stores).
+__device__ inline void emit_block(int base, int N, int TX, long long block_off, int n_keys,
                                   const int4 *__restrict__ rect, const int *__restrict__ counts,
                                   int *__restrict__ offsets, uint32_t *__restrict__ keys,
-                                  uint32_t *__restrict__ hist0, uint32_t *__restrict__ tile_count) {
+                                  uint32_t *__restrict__ hist_row) {
+  static_assert(BIN_BLOCK == RADIX, "one histogram bin per thread");
   __shared__ int lds[BIN_BLOCK / 64];
+  __shared__ uint32_t h[RADIX];
+  h[threadIdx.x] = 0;
   const int n = base + (int)threadIdx.x;
   int c = 0;
   if (n < N) {
@@ -223,29 +229,25 @@ __device__ inline void emit_block(int base, int N, int TX, long long block_off, 
     c = v > 0 ? v : 0;
   }
   int tot;
-  const int local = block_exclusive_scan_i32<BIN_BLOCK>(c, &tot, lds);
-  if (n >= N) return;
-  const long long start = block_off + local;
-  const int beg = (int)min(start, (long long)n_keys);
-  const int end = (int)min(start + c, (long long)n_keys);
-  offsets[n] = beg;
-  if (end <= beg) return;
-  const int chunk = chunk_len(n_keys, G);
-  int ck = beg / chunk;
-  int next = (ck + 1) * chunk;
-  const int4 rc = rect[n];
-  int k = beg;
-  for (int ty = rc.y; ty <= rc.w && k < end; ++ty)
-    for (int tx = rc.x; tx <= rc.z && k < end; ++tx, ++k) {
-      const uint32_t tile = (uint32_t)(ty * TX + tx);
-      keys[k] = (tile << 16) | (uint32_t)n;
-      if (k == next) {
-        ++ck;
-        next += chunk;
-      }
-      atomicAdd(&hist0[ck * RADIX + (tile & (RADIX - 1))], 1u);
-      atomicAdd(&tile_count[tile], 1u);
+  const int local = block_exclusive_scan_i32<BIN_BLOCK>(c, &tot, lds);  // ends with a barrier
+  if (n < N) {
+    const long long start = block_off + local;
+    const int beg = (int)min(start, (long long)n_keys);
+    const int end = (int)min(start + c, (long long)n_keys);
+    offsets[n] = beg;
+    if (end > beg) {
+      const int4 rc = rect[n];
+      int k = beg;
+      for (int ty = rc.y; ty <= rc.w && k < end; ++ty)
+        for (int tx = rc.x; tx <= rc.z && k < end; ++tx, ++k) {
+          const uint32_t tile = (uint32_t)(ty * TX + tx);
+          keys[k] = (tile << 16) | (uint32_t)n;
+          atomicAdd(&h[tile & (RADIX - 1)], 1u);
+        }
     }
+  }
+  __syncthreads();
+  hist_row[threadIdx.x] = h[threadIdx.x];
 }
 
 // Per-chunk histogram of one radix pass, block-major: hist[b * RADIX + d] =
@@ -308,127 +310,284 @@ __device__ inline void chunk_digit_offsets(const uint32_t *__restrict__ hist, in
   __syncthreads();
 }
 
-// Stable scatter of chunk b of one radix pass (keys in[0, n) sorted on the
-// digit at `shift`, G chunks): in input order, each key goes to
-// off[digit] + (earlier keys of the same digit in this chunk).  With
-// hist_next, every key also counts into the next pass's per-chunk
-// histogram at its output slot.
-template <bool NEXT>
+// Stable scatter of chunk b = keys in[beg, end) for one radix pass (keys
+// sorted on the digit at `shift`; `rows` chunks in order, block-major
+// histogram): in input order, each key goes to off[digit] + (earlier keys
+// of the same digit in this chunk).
 __device__ inline void scatter_chunk(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
-                                     int n, int G, int b, int shift,
-                                     const uint32_t *__restrict__ hist,
-                                     uint32_t *__restrict__ hist_next) {
+                                     int beg, int end, int rows, int b, int shift,
+                                     const uint32_t *__restrict__ hist) {
   constexpr int NW = SORT_BLOCK / 64;
   __shared__ uint32_t off[RADIX];
   __shared__ uint32_t wcnt[NW][RADIX];
   __shared__ uint32_t wpre[NW][RADIX];
-  const int chunk = chunk_len(n, G);
-  const int beg = min(n, b * chunk), end = min(n, beg + chunk);
   if (beg >= end) return;  // uniform over the block
   const int tid = threadIdx.x, w = tid >> 6;
 #pragma unroll
   for (int k = 0; k < NW; ++k) wcnt[k][tid] = 0;
-  chunk_digit_offsets(hist, (n + chunk - 1) / chunk, b, off);
+  chunk_digit_offsets(hist, rows, b, off);
   const unsigned long long lt = lanemask_lt();
-  for (int base = beg; base < end; base += SORT_BLOCK) {
-    const int i = base + tid;
-    const bool valid = i < end;
-    const uint32_t key = valid ? in[i] : 0u;
-    const uint32_t d = (key >> shift) & (RADIX - 1);
-    // lanes of this wave holding the same digit
-    unsigned long long match = __ballot(valid);
+  // the chunk's keys are loaded into registers KPT sub-tiles at a time, all
+  // loads issued together (indices clamped into the chunk)
+  constexpr int KPT = 8;
+  for (int gbase = beg; gbase < end; gbase += KPT * SORT_BLOCK) {
+    uint32_t kreg[KPT];
 #pragma unroll
-    for (int bit = 0; bit < RADIX_BITS; ++bit) {
-      const bool on = (d >> bit) & 1u;
-      const unsigned long long bal = __ballot(on);
-      match &= on ? bal : ~bal;
-    }
-    const uint32_t rank = (uint32_t)__popcll(match & lt);
-    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(match);
-    __syncthreads();
-    {
-      uint32_t s = 0;
+    for (int j = 0; j < KPT; ++j) kreg[j] = in[min(gbase + j * SORT_BLOCK + tid, end - 1)];
 #pragma unroll
-      for (int k = 0; k < NW; ++k) {
-        wpre[k][tid] = s;
-        s += wcnt[k][tid];
+    for (int j = 0; j < KPT; ++j) {
+      const int base = gbase + j * SORT_BLOCK;
+      if (base >= end) break;  // uniform over the block
+      const bool valid = base + tid < end;
+      const uint32_t key = kreg[j];
+      const uint32_t d = (key >> shift) & (RADIX - 1);
+      // lanes of this wave holding the same digit
+      unsigned long long match = __ballot(valid);
+#pragma unroll
+      for (int bit = 0; bit < RADIX_BITS; ++bit) {
+        const bool on = (d >> bit) & 1u;
+        const unsigned long long bal = __ballot(on);
+        match &= on ? bal : ~bal;
       }
-      wcnt[0][tid] = s;  // reuse row 0 as the sub-tile total of digit tid
-    }
-    __syncthreads();
-    if (valid) {
-      const uint32_t p = off[d] + wpre[w][d] + rank;
-      out[p] = key;
-      if (NEXT)
-        atomicAdd(&hist_next[(p / (uint32_t)chunk) * RADIX + ((key >> (shift + RADIX_BITS)) & (RADIX - 1))],
-                  1u);
-    }
-    __syncthreads();
-    off[tid] += wcnt[0][tid];
+      const uint32_t rank = (uint32_t)__popcll(match & lt);
+      if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(match);
+      __syncthreads();
+      {
+        uint32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < NW; ++k) wcnt[k][tid] = 0;
-    __syncthreads();
+        for (int k = 0; k < NW; ++k) {
+          wpre[k][tid] = s;
+          s += wcnt[k][tid];
+        }
+        wcnt[0][tid] = s;  // reuse row 0 as the sub-tile total of digit tid
+      }
+      __syncthreads();
+      if (valid) out[off[d] + wpre[w][d] + rank] = key;
+      __syncthreads();
+      off[tid] += wcnt[0][tid];
+#pragma unroll
+      for (int k = 0; k < NW; ++k) wcnt[k][tid] = 0;
+      __syncthreads();
+    }
   }
 }
 
-// One block of SORT_BLOCK threads: tile_start[t] = sum of tile_count[0, t)
-// for t in [0, n_tiles] (the first slot of every tile's run in the sorted
-// key array).  Rounds of 8 consecutive counts per thread.
-__device__ inline void tile_starts(const uint32_t *__restrict__ tile_count, int n_tiles,
+// tile_start[t] = first index i with tile(keys[i]) >= t, for t in
+// [0, n_tiles], over sorted keys[0, n); grid-stride over i.
+__device__ inline void tile_ranges(const uint32_t *__restrict__ keys, int n, int n_tiles,
                                    int *__restrict__ tile_start) {
-  constexpr int PER = 8;
-  __shared__ int lds[SORT_BLOCK / 64];
-  int carry = 0;
-  for (int base = 0; base < n_tiles; base += SORT_BLOCK * PER) {
-    const int t0 = base + (int)threadIdx.x * PER;
-    int v[PER], s = 0;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      v[j] = (t0 + j < n_tiles) ? (int)tile_count[t0 + j] : 0;
-      s += v[j];
-    }
-    int round_total;
-    int run = carry + block_exclusive_scan_i32<SORT_BLOCK>(s, &round_total, lds);
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      if (t0 + j < n_tiles) tile_start[t0 + j] = run;
-      run += v[j];
-    }
-    carry += round_total;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
+    const int cur = (i < n) ? (int)(keys[i] >> 16) : n_tiles;
+    const int prev = (i > 0) ? (int)(keys[i - 1] >> 16) : -1;
+    for (int t = prev + 1; t <= cur && t <= n_tiles; ++t) tile_start[t] = i;
   }
-  if (threadIdx.x == 0) tile_start[n_tiles] = carry;
 }
 
-// Bucket of a tile's pair count for the launch order: four buckets per
-// power of two, bucket 0 for the largest counts.
-__device__ inline int count_bucket(uint32_t c) {
-  const uint32_t x = c + 1u;  // >= 1
-  const int k = 31 - __clz((int)x);
-  const int f = k >= 2 ? (int)((x >> (k - 2)) & 3u) : (int)((x << (2 - k)) & 3u);
-  return 127 - (4 * k + f);
+// ------------------------------------------------------ single-pass path --
+// Key emission as emit_block, by blocks of WIDE_BLOCK threads; the block's
+// keys are one chunk of the single radix pass whose digit is the whole tile
+// index: hist_row[t] (t < D) receives how many of them fall in tile t.
+__device__ inline void emit_block_wide(int base, int N, int TX, long long block_off, int n_keys,
+                                       int D, const int4 *__restrict__ rect,
+                                       const int *__restrict__ counts, int *__restrict__ offsets,
+                                       uint32_t *__restrict__ keys,
+                                       uint32_t *__restrict__ hist_row) {
+  __shared__ int lds[WIDE_BLOCK / 64];
+  __shared__ uint32_t h[WIDE_MAX_TILES];
+  for (int d = threadIdx.x; d < D; d += WIDE_BLOCK) h[d] = 0;
+  const int n = base + (int)threadIdx.x;
+  int c = 0;
+  if (n < N) {
+    const int v = counts[n];
+    c = v > 0 ? v : 0;
+  }
+  int tot;
+  const int local = block_exclusive_scan_i32<WIDE_BLOCK>(c, &tot, lds);  // ends with a barrier
+  if (n < N) {
+    const long long start = block_off + local;
+    const int beg = (int)min(start, (long long)n_keys);
+    const int end = (int)min(start + c, (long long)n_keys);
+    offsets[n] = beg;
+    if (end > beg) {
+      const int4 rc = rect[n];
+      int k = beg;
+      for (int ty = rc.y; ty <= rc.w && k < end; ++ty)
+        for (int tx = rc.x; tx <= rc.z && k < end; ++tx, ++k) {
+          const uint32_t tile = (uint32_t)(ty * TX + tx);
+          keys[k] = (tile << 16) | (uint32_t)n;
+          atomicAdd(&h[tile], 1u);
+        }
+    }
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < D; d += WIDE_BLOCK) hist_row[d] = h[d];
 }
 
-// One block of SORT_BLOCK threads: order[0, n_tiles) = the tiles by
-// decreasing pair count (bucketed as above; any order inside a bucket).
-// The raster processes tiles in this order, so the longest tiles start
-// first and short ones fill the end of the launch.
-__device__ inline void tile_order_by_count(const uint32_t *__restrict__ tile_count, int n_tiles,
-                                           int *__restrict__ order) {
-  constexpr int NBK = 128;
-  static_assert(NBK <= SORT_BLOCK, "one bucket per thread");
-  __shared__ int bk[NBK];
-  __shared__ int lds[SORT_BLOCK / 64];
-  if (threadIdx.x < NBK) bk[threadIdx.x] = 0;
-  __syncthreads();
-  for (int t = threadIdx.x; t < n_tiles; t += SORT_BLOCK) atomicAdd(&bk[count_bucket(tile_count[t])], 1);
-  __syncthreads();
-  const int v = (threadIdx.x < NBK) ? bk[threadIdx.x] : 0;
+// Stable scatter of part `part` (of WIDE_SPLIT equal parts) of chunk b (the
+// keys emission block b wrote) on the whole tile index (D = 2^bits >=
+// n_tiles digits) by one block of WIDE_SCATTER threads, from the `nb`
+// histogram rows (row r = chunk r, D words each); the chunk's earlier parts
+// are counted into the offsets with LDS atomics.
+// Each key goes to (keys of lower tiles in all chunks) + (keys of its tile
+// in earlier chunks) + (earlier keys of its tile in this chunk).  Block 0
+// also writes tile_start[0, n_tiles] (the per-tile totals' exclusive
+// prefix; n at the end).  Ranking inside a sub-tile of WIDE_SCATTER keys:
+// every lane ORs its lane bit into a per-(wavefront, tile) 64-bit mask in
+// LDS; its own wavefront's mask gives its rank among equal tiles (lanes
+// below it) and the other wavefronts' masks the count of its tile in
+// earlier wavefronts; only the masks that were set are cleared.  The
+// histogram loads are issued before the chunk bounds are
+// known so that their latency overlaps the block-sum prefix.
+__device__ inline void scatter_chunk_wide(const uint32_t *__restrict__ in,
+                                          uint32_t *__restrict__ out, int nb, int b, int part,
+                                          int D,
+                                          int bits, int n, int n_tiles,
+                                          const int *__restrict__ bsum,
+                                          const int *__restrict__ bcull,
+                                          const uint32_t *__restrict__ hist,
+                                          int *__restrict__ tile_start) {
+  constexpr int NT = WIDE_SCATTER, NW = NT / 64, RB = 16;
+  static_assert(NT * 4 == WIDE_MAX_TILES, "one uint4 column of digits per thread at most");
+  __shared__ uint32_t off[WIDE_MAX_TILES];
+  __shared__ unsigned long long wmask[NW][WIDE_MAX_TILES];
+  __shared__ uint4 fold[2][NT];
+  __shared__ int lds[NW];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  {
+    uint4 *t4 = reinterpret_cast<uint4 *>(&wmask[0][0]);
+    for (int i = tid; i < NW * WIDE_MAX_TILES / 2; i += NT) t4[i] = make_uint4(0u, 0u, 0u, 0u);
+  }
+  // digit totals and the prefix over earlier chunks: thread t owns digits
+  // [4 cq, 4 cq + 4) of column cq = t % C (C = D / 4 uint4 columns) over the
+  // rows r = t / C, t / C + K, ... (K = NT / C row groups)
+  const int C = D / 4, K = NT / C;
+  const int cq = tid % C, r0 = tid / C;
+  const uint4 *h4 = reinterpret_cast<const uint4 *>(hist);
+  uint4 h[RB];
+#pragma unroll
+  for (int j = 0; j < RB; ++j) h[j] = h4[(size_t)min(r0 + j * K, nb - 1) * C + cq];
+  long long pre_keys, total;
+  int culled;
+  block_sum_prefix<NT>(nb, b, bsum, bcull, &pre_keys, &total, &culled);
+  const int cbeg = (int)min(pre_keys, (long long)n);
+  const int cend = (int)min(pre_keys + bsum[b], (long long)n);
+  const int q = (cend - cbeg + WIDE_SPLIT - 1) / WIDE_SPLIT;
+  const int beg = min(cbeg + part * q, cend), end = min(beg + q, cend);
+  const bool first = b == 0 && part == 0;  // writes tile_start
+  if (beg >= end && !first) return;  // uniform over the block
+  // the chunk's keys into registers (KPT sub-tiles, loads issued together)
+  constexpr int KPT = 16;
+  uint32_t kreg[KPT];
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) kreg[j] = (beg < end) ? in[min(beg + j * NT + tid, end - 1)] : 0u;
+  uint4 tot = make_uint4(0u, 0u, 0u, 0u), pre = make_uint4(0u, 0u, 0u, 0u);
+  for (int rb = r0;;) {
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      const int r = rb + j * K;
+      const uint32_t in_rows = r < nb ? 1u : 0u, earlier = r < b ? 1u : 0u;
+      tot.x += in_rows * h[j].x;
+      tot.y += in_rows * h[j].y;
+      tot.z += in_rows * h[j].z;
+      tot.w += in_rows * h[j].w;
+      pre.x += earlier * h[j].x;
+      pre.y += earlier * h[j].y;
+      pre.z += earlier * h[j].z;
+      pre.w += earlier * h[j].w;
+    }
+    rb += RB * K;
+    if (rb >= nb) break;
+#pragma unroll
+    for (int j = 0; j < RB; ++j) h[j] = h4[(size_t)min(rb + j * K, nb - 1) * C + cq];
+  }
+  // fold the K row groups of each column (C * K = NT)
+  if (K > 1) {
+    fold[0][tid] = tot;
+    fold[1][tid] = pre;
+    __syncthreads();
+    if (r0 == 0) {
+      for (int k = 1; k < K; ++k) {
+        const uint4 a = fold[0][k * C + cq], p = fold[1][k * C + cq];
+        tot.x += a.x;
+        tot.y += a.y;
+        tot.z += a.z;
+        tot.w += a.w;
+        pre.x += p.x;
+        pre.y += p.y;
+        pre.z += p.z;
+        pre.w += p.w;
+      }
+    }
+  }
+  // threads with r0 == 0 (tid < C) hold digits [4 tid, 4 tid + 4); the
+  // block scan runs over all NT threads with zeros beyond C
+  const uint32_t tsum = (r0 == 0) ? (tot.x + tot.y + tot.z + tot.w) : 0u;
   int all;
-  const int ex = block_exclusive_scan_i32<SORT_BLOCK>(v, &all, lds);
-  if (threadIdx.x < NBK) bk[threadIdx.x] = ex;
+  const uint32_t ex = (uint32_t)block_exclusive_scan_i32<NT>((int)tsum, &all, lds);
+  if (r0 == 0) {
+    const uint32_t b0 = ex, b1 = b0 + tot.x, b2 = b1 + tot.y, b3 = b2 + tot.z;
+    const int d = 4 * cq;
+    off[d + 0] = b0 + pre.x;
+    off[d + 1] = b1 + pre.y;
+    off[d + 2] = b2 + pre.z;
+    off[d + 3] = b3 + pre.w;
+    if (first) {
+      if (d + 0 < n_tiles) tile_start[d + 0] = (int)b0;
+      if (d + 1 < n_tiles) tile_start[d + 1] = (int)b1;
+      if (d + 2 < n_tiles) tile_start[d + 2] = (int)b2;
+      if (d + 3 < n_tiles) tile_start[d + 3] = (int)b3;
+    }
+  }
+  if (first && tid == 0) tile_start[n_tiles] = n;
   __syncthreads();
-  for (int t = threadIdx.x; t < n_tiles; t += SORT_BLOCK)
-    order[atomicAdd(&bk[count_bucket(tile_count[t])], 1)] = t;
+  // keys of this chunk's earlier parts precede this part's keys of the
+  // same tile
+  if (beg > cbeg) {
+#pragma unroll 4
+    for (int i = cbeg + tid; i < beg; i += NT) atomicAdd(&off[in[i] >> 16], 1u);
+    __syncthreads();
+  }
+  const unsigned long long lt = lanemask_lt();
+  const unsigned long long me = 1ull << lane;
+  for (int gbase = beg; gbase < end; gbase += KPT * NT) {
+    if (gbase != beg) {
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) kreg[j] = in[min(gbase + j * NT + tid, end - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+      const int base = gbase + j * NT;
+      if (base >= end) break;  // uniform over the block
+      const bool valid = base + tid < end;
+      const uint32_t key = kreg[j];
+      const uint32_t d = key >> 16;
+      if (valid) atomicOr(&wmask[w][d], me);
+      __syncthreads();
+      uint32_t before = 0, after = 0, rank = 0, cnt = 0;
+      if (valid) {
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+          const unsigned long long m = wmask[k][d];
+          const uint32_t c = (uint32_t)__popcll(m);
+          before += (k < w) ? c : 0u;
+          after += (k > w) ? c : 0u;
+          if (k == w) {
+            rank = (uint32_t)__popcll(m & lt);
+            cnt = c;
+          }
+        }
+        out[off[d] + before + rank] = key;
+      }
+      __syncthreads();
+      // the lowest lane of the last wavefront holding tile d advances its
+      // offset; the lowest lane of each wavefront clears its mask
+      if (valid && rank == 0) {
+        if (after == 0) off[d] += before + cnt;
+        wmask[w][d] = 0ull;
+      }
+      __syncthreads();
+    }
+  }
 }
 
 }  // namespace gs2d

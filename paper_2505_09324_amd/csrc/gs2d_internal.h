@@ -34,11 +34,13 @@ struct Layout {
   int W, H, N, T, max_pairs;
   int ppl;             // pixels per lane of the raster kernels (1, 2, 4)
   int TX, TY, n_tiles;
-  int sort_blocks;       // G: chunks of the key array, one sort block each
-  int sort_passes;       // 8-bit digit passes over the tile bits
-  int tile_count_words;  // n_tiles rounded up to a multiple of 4
-  size_t geom, rect, counts, offsets, blocks, keys_a, keys_b, hist, tile_count, tile_start,
-      tile_order, loss_part, grads, misc, total;
+  int sort_blocks;  // G: fixed chunks of the key array in the second pass
+  int sort_passes;  // radix passes over the tile bits (1 or 2)
+  bool wide;        // single pass whose digit is the whole tile index
+  int digit_bits;   // bits of that digit (8..11), D = 2^digit_bits
+  int D;
+  size_t geom, rect, counts, offsets, blocks, keys_a, keys_b, hist, tile_start, loss_part, grads,
+      misc, total;
   // the buffer holding the sorted keys after all passes
   size_t keys_sorted() const { return (sort_passes & 1) ? keys_b : keys_a; }
 };

@@ -123,14 +123,12 @@ template <int TILE, int PPL>
 __global__ void __launch_bounds__((Cfg<TILE, PPL>::NT))
 k_render_fused(FrameArgs f, const float *__restrict__ target, float *__restrict__ loss_part,
                float grad_scale, float *__restrict__ g_xy, float *__restrict__ g_chol,
-               float *__restrict__ g_rgb, const int *__restrict__ tile_order) {
+               float *__restrict__ g_rgb) {
   using C = Cfg<TILE, PPL>;
   __shared__ Smem<C::NW> S;
   __shared__ float acc[CH * 8];
-  // tiles in the binning's order (longest lists first) for a short tail
-  const int tile = tile_order[blockIdx.x];
-  fused_tile<TILE, PPL>(S, acc, f, tile, target, loss_part + tile, grad_scale, g_xy, g_chol,
-                        g_rgb);
+  fused_tile<TILE, PPL>(S, acc, f, (int)blockIdx.x, target, loss_part + blockIdx.x, grad_scale,
+                        g_xy, g_chol, g_rgb);
 }
 
 // ------------------------------------------------- in-cutoff pair counting --
@@ -242,8 +240,7 @@ hipError_t launch_render_fused(const Layout &L, void *ws, const float *rgb, cons
 #define CALL(TT, PP)                                                                           \
   if (!done && L.T == TT && L.ppl == PP) {                                                     \
     hipLaunchKernelGGL((k_render_fused<TT, PP>), dim3(L.n_tiles), dim3(Cfg<TT, PP>::NT), 0, st, \
-                       f, target, lp, grad_scale(L), g_xy, g_chol, g_rgb,                      \
-                       at<const int>(ws, L.tile_order));                                       \
+                       f, target, lp, grad_scale(L), g_xy, g_chol, g_rgb);                     \
     done = true;                                                                               \
   }
   GS2D_VARIANTS(CALL)
