@@ -201,6 +201,22 @@ def fit_to_target(shape, ws, target, params, psnr_target, cap, check_every, cfg)
     return (hit if hit >= 0 else None), int(st.iters_run)
 
 
+def psnr_curve(shape, ws, target, params, budget, points, cfg):
+    """PSNR of a cold fit at the given iteration counts (trace entry k is the
+    loss of the parameters after k updates), run for `budget` iterations
+    without a stop rule, on copies of `params`."""
+    N = shape.N
+    dev = target.device
+    p = [q.clone() for q in params]
+    m = torch.zeros(8 * N, device=dev)
+    v = torch.zeros(8 * N, device=dev)
+    step = torch.zeros(1, dtype=torch.int32, device=dev)
+    trace = torch.zeros(budget + 8, device=dev)
+    _lib.fit_frame(shape, target, *p, m, v, step, trace, ws, _lib.fit_opts(budget, 50, cfg=cfg))
+    tr = trace.cpu().numpy()
+    return {int(k): psnr(float(tr[min(k, budget - 1)])) for k in points}
+
+
 def make_training_set(seqs, n_frames, W, H, N, iters_first, iters_rest, device, lr=LR_DEFAULT,
                       log=print):
     """Fitted Gaussians of every frame of the training sequences (frame 0
@@ -251,7 +267,7 @@ def train_initialiser(net, samples, W, H, epochs, lr, device, log=print, seed=0)
     return hist
 
 
-def run_learned(train_seqs=34, frames_per_seq=60, max_samples=2000, epochs=3, eval_frames=60,
+def run_learned(train_seqs=34, frames_per_seq=60, max_samples=2000, epochs=6, eval_frames=60,
                 W=1920, H=1080, N=30000, psnr_target=35.0, cap=10000, check_every=10,
                 iters_first=2000, iters_rest=200, lr_cnn=1e-3, device="cuda", log=print):
     """Train the per-tile initialiser on fitter outputs, then compare time and
@@ -276,6 +292,8 @@ def run_learned(train_seqs=34, frames_per_seq=60, max_samples=2000, epochs=3, ev
     eval_seed = 5999
     frames = [synth.make_frame_torch(W, H, eval_seed, t, device) for t in range(eval_frames)]
 
+    npred_log = {}
+
     def init_for(arm, t):
         f, m = frames[t]
         plain = [p.contiguous() for p in plain_init_dev(f, m, N, eval_seed + 31 * t + 1)]
@@ -284,7 +302,22 @@ def run_learned(train_seqs=34, frames_per_seq=60, max_samples=2000, epochs=3, ev
         prev = frames[t - 1][0] if t > 0 else None
         net.forward(f, prev)
         xy, chol, rgb, npred = net.decode(N, *plain)
+        npred_log[t] = int(npred.item())
         return [xy, chol, rgb]
+
+    # PSNR at a fixed iteration budget from cold starts: plain vs learned init
+    points = (0, 50, 100, 200)
+    budget = {"plain": {k: [] for k in points}, "learned": {k: [] for k in points}}
+    for t in range(eval_frames):
+        f = frames[t][0]
+        for name, arm in (("plain", "A"), ("learned", "L")):
+            curve = psnr_curve(shape, ws, f, init_for(arm, t), 201, points, cfg)
+            for k in points:
+                budget[name][k].append(curve[k])
+    budget_mean = {name: {k: float(np.mean(v)) for k, v in d.items()} for name, d in budget.items()}
+    log(f"PSNR at fixed budgets (mean over {eval_frames} frames): {budget_mean}")
+    log(f"learned decode: predicted Gaussians per frame (N={N}): "
+        f"{[npred_log[t] for t in sorted(npred_log)]}")
 
     res = {}
     for arm in ("A", "L", "B", "C"):
@@ -313,6 +346,8 @@ def run_learned(train_seqs=34, frames_per_seq=60, max_samples=2000, epochs=3, ev
         "target_psnr_db": psnr_target, "arms": res,
         "C_over_A_seconds": ratio("C", "A"), "C_over_B_seconds": ratio("C", "B"),
         "L_over_A_seconds": ratio("L", "A"),
+        "psnr_at_budget_cold": budget_mean,
+        "learned_predicted_per_frame": [npred_log[t] for t in sorted(npred_log)],
         "train_loss_per_epoch": hist, "data_seconds": t_data, "train_seconds": t_train,
     }
 
@@ -323,7 +358,7 @@ def main(argv=None):
     ap.add_argument("--frames", type=int, default=None)
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--train-seqs", type=int, default=34)
-    ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--eval-frames", type=int, default=60)
     ap.add_argument("--size", type=str, default="1920x1080")
     ap.add_argument("--N", type=int, default=30000)
