@@ -118,7 +118,7 @@ def cpu_baseline(iters: int):
 def traffic_record(kernel_src_digest: str):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(HERE, "profiles", "render_fused_1080p_30k_traffic.json")
+    path = os.path.join(HERE, "profiles", "render_fused_1080p_30k_traffic.txt")
     try:
         with open(path) as f:
             rec = json.load(f)
