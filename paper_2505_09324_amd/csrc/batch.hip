@@ -254,7 +254,7 @@ struct BatchRaster {
 };
 
 template <int TILE, int PPL>
-__global__ void __launch_bounds__((Cfg<TILE, PPL>::NT))
+__global__ void __launch_bounds__((Cfg<TILE, PPL>::NT)) GS2D_RASTER_OCCUPANCY
 k_b_render_persistent(BatchRaster a) {
   using C = Cfg<TILE, PPL>;
   __shared__ Smem<C::NW> S;

@@ -25,7 +25,7 @@ namespace gs2d {
 
 // ----------------------------------------------------------------- forward --
 template <int TILE, int PPL>
-__global__ void __launch_bounds__((Cfg<TILE, PPL>::NT))
+__global__ void __launch_bounds__((Cfg<TILE, PPL>::NT)) GS2D_RASTER_OCCUPANCY
 k_render_fwd(FrameArgs f, const float *__restrict__ target, float *__restrict__ img,
              float *__restrict__ dl_dimg, float *__restrict__ loss_part, float grad_scale) {
   using C = Cfg<TILE, PPL>;
@@ -78,7 +78,7 @@ k_render_fwd(FrameArgs f, const float *__restrict__ target, float *__restrict__ 
 
 // ---------------------------------------------------------------- backward --
 template <int TILE, int PPL>
-__global__ void __launch_bounds__((Cfg<TILE, PPL>::NT))
+__global__ void __launch_bounds__((Cfg<TILE, PPL>::NT)) GS2D_RASTER_OCCUPANCY
 k_render_bwd(FrameArgs f, const float *__restrict__ dl_dimg, float *__restrict__ g_xy,
              float *__restrict__ g_chol, float *__restrict__ g_rgb) {
   using C = Cfg<TILE, PPL>;
@@ -120,7 +120,7 @@ k_render_bwd(FrameArgs f, const float *__restrict__ dl_dimg, float *__restrict__
 
 // ------------------------------------------- fused forward + loss + backward --
 template <int TILE, int PPL>
-__global__ void __launch_bounds__((Cfg<TILE, PPL>::NT))
+__global__ void __launch_bounds__((Cfg<TILE, PPL>::NT)) GS2D_RASTER_OCCUPANCY
 k_render_fused(FrameArgs f, const float *__restrict__ target, float *__restrict__ loss_part,
                float grad_scale, float *__restrict__ g_xy, float *__restrict__ g_chol,
                float *__restrict__ g_rgb) {
@@ -160,7 +160,7 @@ k_count_pairs(FrameArgs f, unsigned long long *__restrict__ out) {
       const float4 A = S.A[j], B = S.B[j];
       const float u1 = (pxc - A.x) * A.z;
       const float u2 = ((pyc - A.y) - A.w * u1) * B.x;
-      n += (inside && u1 * u1 + u2 * u2 <= CUTOFF_Q) ? 1u : 0u;
+      n += (inside && u1 * u1 + u2 * u2 <= CUTOFF_QS) ? 1u : 0u;
     }
   }
   for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);

@@ -7,9 +7,22 @@
 
 namespace gs2d {
 
-constexpr float NEG_HALF_LOG2E = -0.72134752044448170368f;  // -log2(e)/2
-constexpr float CUTOFF_Q = 9.0f;
+// exp(-q/2) = exp2(-q h) with h = log2(e)/2.  Staging multiplies 1/l1 and
+// 1/l3 by sqrt(h) and divides l2 by it, so the per-pixel quantities are
+// u' = sqrt(h) u and q' = h q: the exponent needs no multiply and the cutoff
+// q <= 9 becomes q' <= 9 h.  Gradients summed in these units are rescaled
+// by 1/h (mean) and 1/h^1.5 (Cholesky vector) when flushed.
+constexpr float EXP_SCALE = 0.84932180028801904f;     // sqrt(log2(e)/2)
+constexpr float CUTOFF_QS = 6.4921276840003355f;      // 9 log2(e)/2
+constexpr float INV_H = 1.3862943611198906f;          // 2 / log2(e)
+constexpr float INV_H15 = 1.6322368749392462f;        // (2 / log2(e))^1.5
 constexpr int CH = 256;  // Gaussians staged per LDS chunk
+
+// Raster kernels are compiled for 8 wavefronts per SIMD (at most 64 VGPRs
+// where the LDS allows it): with 512-thread tiles that is 4 workgroups per
+// CU, the wave-slot limit, which the latency of staging and the barriers
+// between a tile's phases need.
+#define GS2D_RASTER_OCCUPANCY __attribute__((amdgpu_waves_per_eu(8, 8)))
 
 template <int TILE, int PPL>
 struct Cfg {
@@ -25,7 +38,7 @@ template <int NW>
 struct Smem {
   float4 A[CH];           // mx, my, 1/l1, l2
   float4 B[CH];           // 1/l3, c'0, c'1, c'2
-  uint32_t mask[CH];      // bit w: box meets sub-block w
+  uint16_t mask[CH];      // bit w: box meets sub-block w (at most 16)
   int id[CH];
   uint16_t list[NW][CH];
   float red[NW];
@@ -55,8 +68,8 @@ __device__ inline void stage_chunk(Smem<Cfg<TILE, PPL>::NW> &S, const uint32_t *
       c1 = rgb[3 * id + 1];
       c2 = rgb[3 * id + 2];
     }
-    S.A[j] = g0;
-    S.B[j] = make_float4(g1.x, c0, c1, c2);
+    S.A[j] = make_float4(g0.x, g0.y, g0.z * EXP_SCALE, g0.w * (1.0f / EXP_SCALE));
+    S.B[j] = make_float4(g1.x * EXP_SCALE, c0, c1, c2);
     S.id[j] = id;
     const float xlo = __fsub_rn(g0.x, g1.y), xhi = __fadd_rn(g0.x, g1.y);
     const float ylo = __fsub_rn(g0.y, g1.z), yhi = __fadd_rn(g0.y, g1.z);
@@ -70,7 +83,7 @@ __device__ inline void stage_chunk(Smem<Cfg<TILE, PPL>::NW> &S, const uint32_t *
     uint32_t m = 0;
     for (int by = by0; by <= by1; ++by)
       for (int bx = bx0; bx <= bx1; ++bx) m |= 1u << (by * C::SBX + bx);
-    S.mask[j] = m;
+    S.mask[j] = (uint16_t)m;
   }
 }
 
@@ -162,8 +175,8 @@ __device__ inline int fwd_chunk(Smem<NW> &S, int len, float pxc, float pyc0, uns
     for (int r = 0; r < PPL; ++r) {
       const float u2 = (base + (float)r) * B.x;
       const float q = u1s + u2 * u2;
-      const float e = __builtin_amdgcn_exp2f(q * NEG_HALF_LOG2E);
-      const bool in_cut = q <= CUTOFF_Q;
+      const float e = __builtin_amdgcn_exp2f(-q);
+      const bool in_cut = q <= CUTOFF_QS;
       const float wgt = in_cut ? e : 0.f;
       acc[r][0] += wgt * B.y;
       acc[r][1] += wgt * B.z;
@@ -199,14 +212,14 @@ __device__ inline void bwd_chunk(const Smem<NW> &S, float *acc, int len, float p
     for (int r = 0; r < PPL; ++r) {
       u2[r] = (base + (float)r) * B.x;
       q[r] = u1s + u2[r] * u2[r];
-      any |= q[r] <= CUTOFF_Q;
+      any |= q[r] <= CUTOFF_QS;
     }
     if (CHECK_HITS && !__ballot(any)) continue;  // wavefront-uniform skip
     float s0 = 0.f, s2 = 0.f, s3 = 0.f, c0 = 0.f, c1 = 0.f, c2 = 0.f;
 #pragma unroll
     for (int r = 0; r < PPL; ++r) {
-      const float e = __builtin_amdgcn_exp2f(q[r] * NEG_HALF_LOG2E);
-      const float wgt = (q[r] <= CUTOFF_Q) ? e : 0.f;
+      const float e = __builtin_amdgcn_exp2f(-q[r]);
+      const float wgt = (q[r] <= CUTOFF_QS) ? e : 0.f;
       const float sn = (g[r][0] * B.y + g[r][1] * B.z + g[r][2] * B.w) * wgt;
       const float v2 = u2[r] * B.x;
       const float t2 = sn * v2;
@@ -219,7 +232,9 @@ __device__ inline void bwd_chunk(const Smem<NW> &S, float *acc, int len, float p
     }
     // v1 = (u1 - l2 v2) / l1 with u1 common to the lane's pixels, so
     // sum s v1 = (u1 sum s - l2 sum s v2) / l1; likewise dL/dl1 = sum s v1 u1
-    // and dL/dl2 = sum s v2 u1 take the lane's u1 once
+    // and dL/dl2 = sum s v2 u1 take the lane's u1 once.  In the staged units
+    // (u' = sqrt(h) u, v2' = h v2) these sums come out as h dL/dmu and
+    // h^1.5 dL/dl; flush_grads rescales them.
     const float s1 = (u1 * s0 - A.w * s2) * A.z;
     const float vals[8] = {s1, s2, s1 * u1, s2 * u1, s3, c0, c1, c2};
     const float red = reduce8_transpose(vals);
@@ -235,11 +250,11 @@ __device__ inline void flush_grads(const Smem<NW> &S, const float *acc, int cnt,
   for (int j = threadIdx.x; j < cnt; j += NT) {
     const int id = S.id[j];
     const float *a = acc + j * 8;
-    if (a[0] != 0.f) atomicAdd(&g_xy[2 * id + 0], a[0]);
-    if (a[1] != 0.f) atomicAdd(&g_xy[2 * id + 1], a[1]);
-    if (a[2] != 0.f) atomicAdd(&g_chol[3 * id + 0], a[2]);
-    if (a[3] != 0.f) atomicAdd(&g_chol[3 * id + 1], a[3]);
-    if (a[4] != 0.f) atomicAdd(&g_chol[3 * id + 2], a[4]);
+    if (a[0] != 0.f) atomicAdd(&g_xy[2 * id + 0], a[0] * INV_H);
+    if (a[1] != 0.f) atomicAdd(&g_xy[2 * id + 1], a[1] * INV_H);
+    if (a[2] != 0.f) atomicAdd(&g_chol[3 * id + 0], a[2] * INV_H15);
+    if (a[3] != 0.f) atomicAdd(&g_chol[3 * id + 1], a[3] * INV_H15);
+    if (a[4] != 0.f) atomicAdd(&g_chol[3 * id + 2], a[4] * INV_H15);
     if (a[5] != 0.f) atomicAdd(&g_rgb[3 * id + 0], a[5]);
     if (a[6] != 0.f) atomicAdd(&g_rgb[3 * id + 1], a[6]);
     if (a[7] != 0.f) atomicAdd(&g_rgb[3 * id + 2], a[7]);
