@@ -29,8 +29,7 @@ k_adam(int N, float *__restrict__ xy, float *__restrict__ chol, float *__restric
   if (threadIdx.x == 0) {
     const int t = step[0];
     s_t = t;
-    s_bc1 = (float)(1.0 - pow((double)b1, (double)t));
-    s_bc2 = (float)(1.0 - pow((double)b2, (double)t));
+    adam_bias(t, b1, b2, &s_bc1, &s_bc2);
   }
   __syncthreads();
   const int t = s_t;
@@ -61,11 +60,7 @@ k_adam(int N, float *__restrict__ xy, float *__restrict__ chol, float *__restric
     const float gr = *g;
     if (zero_grads) *g = 0.f;
     if (active && active[n] == 0) continue;
-    const float mm = b1 * m[e] + (1.f - b1) * gr;
-    const float vv = b2 * v[e] + (1.f - b2) * gr * gr;
-    m[e] = mm;
-    v[e] = vv;
-    *p = *p - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+    *p = adam_update(*p, gr, m + e, v + e, lr, b1, b2, eps, bc1, bc2);
   }
   if (loss_part && blockIdx.x == 0) {
     double s = 0.0;

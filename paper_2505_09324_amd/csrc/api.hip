@@ -225,20 +225,30 @@ int gs2d_adam_step(int32_t N, float *xy, float *chol, float *rgb, float *g_xy, f
 
 namespace {
 
-// One fitting iteration: binning, fused render/loss/backward, Adam (which
-// clears the gradients and records the loss of this iteration).
-hipError_t enqueue_iteration(const Layout &L, void *ws, const float *target, float *xy,
-                             float *chol, float *rgb, float *m, float *v, int32_t *step,
-                             float *trace, int trace_len, const gs2d_adam_cfg &cfg,
-                             hipStream_t st) {
+// k fitting iterations: binning, fused render/loss/backward and Adam (which
+// clears the gradients and records the iteration's loss) each.  The Adam
+// step of iteration i < k - 1 runs inside the first binning kernel of
+// iteration i + 1; the last one runs on its own, so that after the k
+// iterations the parameters, moments, step count and loss trace are those
+// of k complete steps.
+hipError_t enqueue_iterations(const Layout &L, void *ws, const float *target, float *xy,
+                              float *chol, float *rgb, float *m, float *v, int32_t *step,
+                              float *trace, int trace_len, const gs2d_adam_cfg &cfg, int k,
+                              hipStream_t st) {
   float *g = at<float>(ws, L.grads);
   float *g_xy = g, *g_chol = g + 2 * (size_t)L.N, *g_rgb = g + 5 * (size_t)L.N;
-  hipError_t e = launch_binning(L, xy, chol, ws, st, step);
-  if (e == hipSuccess) e = launch_render_fused(L, ws, rgb, target, g_xy, g_chol, g_rgb, st);
-  if (e == hipSuccess)
+  const float loss_scale = (float)(1.0 / (3.0 * L.W * (double)L.H));
+  const PendingAdam pending{xy,    chol, rgb,  g_xy, g_chol, g_rgb, m,         v,
+                            step,  cfg,  at<const float>(ws, L.loss_part), L.n_tiles,
+                            loss_scale, trace, trace_len};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < k && e == hipSuccess; ++i) {
+    e = launch_binning(L, xy, chol, ws, st, step, i > 0 ? &pending : nullptr);
+    if (e == hipSuccess) e = launch_render_fused(L, ws, rgb, target, g_xy, g_chol, g_rgb, st);
+  }
+  if (e == hipSuccess && k > 0)
     e = launch_adam(L.N, xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg, nullptr, 1,
-                    at<const float>(ws, L.loss_part), L.n_tiles,
-                    (float)(1.0 / (3.0 * L.W * (double)L.H)), trace, trace_len, st);
+                    at<const float>(ws, L.loss_part), L.n_tiles, loss_scale, trace, trace_len, st);
   return e;
 }
 
@@ -305,10 +315,8 @@ extern "C" int gs2d_fit_frame(const gs2d_shape *shape, const float *target, floa
           if (G.g) (void)hipGraphDestroy(G.g), G.g = nullptr;
           if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return GS2D_EHIP;
-          hipError_t ce = hipSuccess;
-          for (int i = 0; i < k && ce == hipSuccess; ++i)
-            ce = enqueue_iteration(L, ws, target, xy, chol, rgb, m, v, step, loss_trace, trace_len,
-                                   opts->adam, st);
+          const hipError_t ce = enqueue_iterations(L, ws, target, xy, chol, rgb, m, v, step,
+                                                   loss_trace, trace_len, opts->adam, k, st);
           hipError_t ee = hipStreamEndCapture(st, &G.g);
           if (ce != hipSuccess || ee != hipSuccess) return GS2D_EHIP;
           if (hipGraphInstantiate(&G.x, G.g, nullptr, nullptr, 0) != hipSuccess) return GS2D_EHIP;
@@ -316,10 +324,9 @@ extern "C" int gs2d_fit_frame(const gs2d_shape *shape, const float *target, floa
         }
         if (hipGraphLaunch(G.x, st) != hipSuccess) return GS2D_EHIP;
       } else {
-        for (int i = 0; i < k; ++i)
-          if (enqueue_iteration(L, ws, target, xy, chol, rgb, m, v, step, loss_trace, trace_len,
-                                opts->adam, st) != hipSuccess)
-            return GS2D_EHIP;
+        if (enqueue_iterations(L, ws, target, xy, chol, rgb, m, v, step, loss_trace, trace_len,
+                               opts->adam, k, st) != hipSuccess)
+          return GS2D_EHIP;
       }
       if (hipMemcpyAsync(trace_host.data(), loss_trace + step0 + done, sizeof(float) * k,
                          hipMemcpyDeviceToHost, st) != hipSuccess)

@@ -75,22 +75,89 @@ k_emit_keys(int N, int TX, int nb, int max_pairs, const int4 *__restrict__ rect,
 }
 
 // ------------------------------------------------------- single-pass path --
-__global__ void __launch_bounds__(WIDE_BLOCK)
+__global__ void __launch_bounds__(WIDE_PROJ)
 k_project_wide(int N, int TX, int TY, float inv_tile, const float *__restrict__ xy,
                const float *__restrict__ chol, float4 *__restrict__ geom, int4 *__restrict__ rect,
                int *__restrict__ counts, int *__restrict__ bsum, int *__restrict__ bcull) {
-  project_block<WIDE_BLOCK>(blockIdx.x * WIDE_BLOCK, N, TX, TY, inv_tile, xy, chol, geom, rect,
-                            counts, bsum + blockIdx.x, bcull + blockIdx.x);
+  project_block<WIDE_PROJ>(blockIdx.x * WIDE_PROJ, N, TX, TY, inv_tile, xy, chol, geom, rect,
+                           counts, bsum + blockIdx.x, bcull + blockIdx.x);
+}
+
+// The previous iteration's optimiser step fused with the projection: one
+// thread per Gaussian applies Adam to its 8 parameters (gradients cleared)
+// and projects the updated Gaussian from its registers.  One extra block
+// (blockIdx.x == gridDim.x - 1) reduces the previous iteration's loss
+// partials into the trace.
+__global__ void __launch_bounds__(WIDE_PROJ)
+k_adam_project_wide(int N, int TX, int TY, float inv_tile, PendingAdam a,
+                    float4 *__restrict__ geom, int4 *__restrict__ rect, int *__restrict__ counts,
+                    int *__restrict__ bsum, int *__restrict__ bcull) {
+  __shared__ float s_bc1, s_bc2;
+  __shared__ int s_t;
+  __shared__ double red[WIDE_PROJ / 64];
+  if (threadIdx.x == 0) {
+    s_t = a.step[0];
+    adam_bias(s_t, a.cfg.beta1, a.cfg.beta2, &s_bc1, &s_bc2);
+  }
+  __syncthreads();
+  if (blockIdx.x == gridDim.x - 1) {  // the loss of the previous iteration
+    double s = 0.0;
+    for (int i = threadIdx.x; i < a.n_part; i += WIDE_PROJ) s += (double)a.loss_part[i];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0 && s_t - 1 < a.trace_len) {
+      double tot = 0.0;
+      for (int w = 0; w < WIDE_PROJ / 64; ++w) tot += red[w];
+      a.trace[s_t - 1] = (float)(tot * (double)a.loss_scale);
+    }
+    return;
+  }
+  const float bc1 = s_bc1, bc2 = s_bc2, b1 = a.cfg.beta1, b2 = a.cfg.beta2, eps = a.cfg.eps;
+  const int n = blockIdx.x * WIDE_PROJ + threadIdx.x;
+  int v = 0;
+  if (n < N) {
+    const size_t N2 = 2 * (size_t)N, N5 = 5 * (size_t)N;
+    float p[8];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const size_t i = 2 * (size_t)n + c;
+      const float g = a.g_xy[i];
+      a.g_xy[i] = 0.f;
+      p[c] = adam_update(a.xy[i], g, a.m + i, a.v + i, a.cfg.lr[0], b1, b2, eps, bc1, bc2);
+      a.xy[i] = p[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const size_t i = 3 * (size_t)n + c;
+      const float g = a.g_chol[i];
+      a.g_chol[i] = 0.f;
+      p[2 + c] =
+          adam_update(a.chol[i], g, a.m + N2 + i, a.v + N2 + i, a.cfg.lr[1], b1, b2, eps, bc1, bc2);
+      a.chol[i] = p[2 + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const size_t i = 3 * (size_t)n + c;
+      const float g = a.g_rgb[i];
+      a.g_rgb[i] = 0.f;
+      a.rgb[i] =
+          adam_update(a.rgb[i], g, a.m + N5 + i, a.v + N5 + i, a.cfg.lr[2], b1, b2, eps, bc1, bc2);
+    }
+    v = project_values(n, TX, TY, inv_tile, p[0], p[1], p[2], p[3], p[4], geom, rect, counts);
+  }
+  block_count_sums<WIDE_PROJ>(v, bsum + blockIdx.x, bcull + blockIdx.x);
 }
 
 __global__ void __launch_bounds__(WIDE_BLOCK)
-k_emit_wide(int N, int TX, int nb, int max_pairs, int D, const int4 *__restrict__ rect,
+k_emit_wide(int N, int TX, int nbp, int max_pairs, int D, const int4 *__restrict__ rect,
             const int *__restrict__ counts, const int *__restrict__ bsum,
             const int *__restrict__ bcull, int *__restrict__ offsets, uint32_t *__restrict__ keys,
             uint32_t *__restrict__ hist, int *__restrict__ misc, int *__restrict__ tick) {
-  long long pre, total;
+  long long pre, end_keys, total;
   int culled;
-  block_sum_prefix<WIDE_BLOCK>(nb, blockIdx.x, bsum, bcull, &pre, &total, &culled);
+  chunk_bounds<WIDE_BLOCK>(nbp, blockIdx.x, WIDE_GROUP, bsum, bcull, &pre, &end_keys, &total,
+                           &culled);
   const int np = (int)min(total, (long long)max_pairs);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     offsets[N] = np;
@@ -108,10 +175,10 @@ k_emit_wide(int N, int TX, int nb, int max_pairs, int D, const int4 *__restrict_
 
 __global__ void __launch_bounds__(WIDE_SCATTER)
 k_scatter_wide(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
-               const int *__restrict__ misc, int nb, int D, int bits, int n_tiles,
+               const int *__restrict__ misc, int nb, int nbp, int D, int bits, int n_tiles,
                const int *__restrict__ bsum, const int *__restrict__ bcull,
                const uint32_t *__restrict__ hist, int *__restrict__ tile_start) {
-  scatter_chunk_wide(in, out, nb, blockIdx.x / WIDE_SPLIT, blockIdx.x % WIDE_SPLIT, D, bits,
+  scatter_chunk_wide(in, out, nb, nbp, blockIdx.x / WIDE_SPLIT, blockIdx.x % WIDE_SPLIT, D, bits,
                      misc[MISC_N_PAIRS], n_tiles, bsum, bcull, hist, tile_start);
 }
 
@@ -155,7 +222,7 @@ k_tile_ranges(const uint32_t *__restrict__ keys, const int *__restrict__ misc, i
 }
 
 hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, void *ws,
-                          hipStream_t st, int *step_tick) {
+                          hipStream_t st, int *step_tick, const PendingAdam *adam) {
   float4 *geom = at<float4>(ws, L.geom);
   int *counts = at<int>(ws, L.counts);
   int *offsets = at<int>(ws, L.offsets);
@@ -166,16 +233,28 @@ hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, v
   uint32_t *hist = at<uint32_t>(ws, L.hist);
   uint32_t *ka = at<uint32_t>(ws, L.keys_a), *kb = at<uint32_t>(ws, L.keys_b);
   if (L.wide) {
-    const int nbw = (L.N + WIDE_BLOCK - 1) / WIDE_BLOCK;
-    hipLaunchKernelGGL(k_project_wide, dim3(nbw), dim3(WIDE_BLOCK), 0, st, L.N, L.TX, L.TY,
-                       1.0f / (float)L.T, xy, chol, geom, rect, counts, bsum, bcull);
-    hipLaunchKernelGGL(k_emit_wide, dim3(nbw), dim3(WIDE_BLOCK), 0, st, L.N, L.TX, nbw,
+    const int nbw = (L.N + WIDE_BLOCK - 1) / WIDE_BLOCK;  // chunks
+    const int nbp = (L.N + WIDE_PROJ - 1) / WIDE_PROJ;    // projection blocks
+    if (adam)
+      hipLaunchKernelGGL(k_adam_project_wide, dim3(nbp + 1), dim3(WIDE_PROJ), 0, st, L.N, L.TX, L.TY,
+                         1.0f / (float)L.T, *adam, geom, rect, counts, bsum, bcull);
+    else
+      hipLaunchKernelGGL(k_project_wide, dim3(nbp), dim3(WIDE_PROJ), 0, st, L.N, L.TX, L.TY,
+                         1.0f / (float)L.T, xy, chol, geom, rect, counts, bsum, bcull);
+    hipLaunchKernelGGL(k_emit_wide, dim3(nbw), dim3(WIDE_BLOCK), 0, st, L.N, L.TX, nbp,
                        L.max_pairs, L.D, rect, counts, bsum, bcull, offsets, ka, hist, misc,
                        step_tick);
     hipLaunchKernelGGL(k_scatter_wide, dim3(nbw * WIDE_SPLIT), dim3(WIDE_SCATTER), 0, st, ka, kb,
-                       misc, nbw, L.D,
+                       misc, nbw, nbp, L.D,
                        L.digit_bits, L.n_tiles, bsum, bcull, hist, at<int>(ws, L.tile_start));
     return hipGetLastError();
+  }
+  if (adam) {
+    const PendingAdam &a = *adam;
+    const hipError_t e = launch_adam(L.N, a.xy, a.chol, a.rgb, a.g_xy, a.g_chol, a.g_rgb, a.m, a.v,
+                                     const_cast<int32_t *>(a.step), a.cfg, nullptr, 1, a.loss_part,
+                                     a.n_part, a.loss_scale, a.trace, a.trace_len, st);
+    if (e != hipSuccess) return e;
   }
   const int nb = (L.N + BIN_BLOCK - 1) / BIN_BLOCK;
   hipLaunchKernelGGL(k_project, dim3(nb), dim3(BIN_BLOCK), 0, st, L.N, L.TX, L.TY,

@@ -12,7 +12,9 @@ static_assert(SORT_BLOCK == RADIX, "scatter threads map one-to-one onto digits")
 
 // Single-pass binning (frames of at most WIDE_MAX_TILES tiles): the whole
 // tile index is one radix digit.
-constexpr int WIDE_BLOCK = 1024;      // threads of its projection / emission blocks
+constexpr int WIDE_BLOCK = 1024;      // threads of its emission blocks (one chunk each)
+constexpr int WIDE_PROJ = 256;        // threads of its projection blocks
+constexpr int WIDE_GROUP = WIDE_BLOCK / WIDE_PROJ;  // projection blocks per chunk
 constexpr int WIDE_MAX_TILES = 2048;  // largest digit range (11 bits)
 constexpr int WIDE_SCATTER = 512;     // threads of its scatter blocks
 constexpr int WIDE_SPLIT = 4;         // scatter blocks per emission chunk
@@ -24,12 +26,9 @@ static_assert(WIDE_BLOCK * 64 >= 65536, "at most 64 emission blocks per frame");
 // rx, ry, 0}; rect[n] = {tx0, ty0, tx1, ty1}.  The box/rectangle arithmetic
 // uses the _rn intrinsics so that no multiply and add are contracted: the
 // tile decision must match its FP32 specification exactly.
-__device__ inline void project_gaussian(int n, int TX, int TY, float inv_tile,
-                                        const float *__restrict__ xy,
-                                        const float *__restrict__ chol, float4 *__restrict__ geom,
-                                        int4 *__restrict__ rect, int *__restrict__ counts) {
-  const float mx = xy[2 * n + 0], my = xy[2 * n + 1];
-  const float l1 = chol[3 * n + 0], l2 = chol[3 * n + 1], l3 = chol[3 * n + 2];
+__device__ inline int project_values(int n, int TX, int TY, float inv_tile, float mx, float my,
+                                     float l1, float l2, float l3, float4 *__restrict__ geom,
+                                     int4 *__restrict__ rect, int *__restrict__ counts) {
   const float tiny = 6.103515625e-05f;  // 2^-14
   const bool finite = isfinite(mx) && isfinite(my) && isfinite(l1) && isfinite(l2) && isfinite(l3);
   if (!finite || !(fabsf(l1) >= tiny) || !(fabsf(l3) >= tiny)) {
@@ -37,7 +36,7 @@ __device__ inline void project_gaussian(int n, int TX, int TY, float inv_tile,
     rect[n] = make_int4(0, 0, -1, -1);
     geom[2 * n + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
     geom[2 * n + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-    return;
+    return -1;
   }
   const float a = __fmul_rn(l2, l2);
   const float b = __fmul_rn(l3, l3);
@@ -64,6 +63,15 @@ __device__ inline void project_gaussian(int n, int TX, int TY, float inv_tile,
   rect[n] = rc;
   geom[2 * n + 0] = make_float4(mx, my, __fdiv_rn(1.0f, l1), l2);
   geom[2 * n + 1] = make_float4(__fdiv_rn(1.0f, l3), rx, ry, 0.f);
+  return cnt;
+}
+
+__device__ inline int project_gaussian(int n, int TX, int TY, float inv_tile,
+                                       const float *__restrict__ xy, const float *__restrict__ chol,
+                                       float4 *__restrict__ geom, int4 *__restrict__ rect,
+                                       int *__restrict__ counts) {
+  return project_values(n, TX, TY, inv_tile, xy[2 * n + 0], xy[2 * n + 1], chol[3 * n + 0],
+                        chol[3 * n + 1], chol[3 * n + 2], geom, rect, counts);
 }
 
 // ------------------------------------------------------------ block scan --
@@ -129,23 +137,12 @@ __device__ inline int block_exclusive_scan_i32(int v, int *total, int *lds) {
   return before + x - v;
 }
 
-// Projection of the block's Gaussians [base, base + NT) of an array of N,
-// plus the block's sum of tile counts and of culled Gaussians.
-template <int NT = BIN_BLOCK>
-__device__ inline void project_block(int base, int N, int TX, int TY, float inv_tile,
-                                     const float *__restrict__ xy, const float *__restrict__ chol,
-                                     float4 *__restrict__ geom, int4 *__restrict__ rect,
-                                     int *__restrict__ counts, int *__restrict__ bsum,
-                                     int *__restrict__ bcull) {
+// Block sums of the tile counts (v > 0) and of the culled Gaussians
+// (v < 0) of one value per thread, written by thread 0.
+template <int NT>
+__device__ inline void block_count_sums(int v, int *__restrict__ bsum, int *__restrict__ bcull) {
   __shared__ int red[2][NT / 64];
-  const int n = base + (int)threadIdx.x;
-  int c = 0, cull = 0;
-  if (n < N) {
-    project_gaussian(n, TX, TY, inv_tile, xy, chol, geom, rect, counts);
-    const int v = counts[n];
-    c = v > 0 ? v : 0;
-    cull = v < 0;
-  }
+  int c = v > 0 ? v : 0, cull = v < 0;
   for (int o = 32; o > 0; o >>= 1) {
     c += __shfl_xor(c, o, 64);
     cull += __shfl_xor(cull, o, 64);
@@ -165,6 +162,21 @@ __device__ inline void project_block(int base, int N, int TX, int TY, float inv_
     *bcull = b;
   }
 }
+
+// Projection of the block's Gaussians [base, base + NT) of an array of N,
+// plus the block's sum of tile counts and of culled Gaussians.
+template <int NT = BIN_BLOCK>
+__device__ inline void project_block(int base, int N, int TX, int TY, float inv_tile,
+                                     const float *__restrict__ xy, const float *__restrict__ chol,
+                                     float4 *__restrict__ geom, int4 *__restrict__ rect,
+                                     int *__restrict__ counts, int *__restrict__ bsum,
+                                     int *__restrict__ bcull) {
+  const int n = base + (int)threadIdx.x;
+  int v = 0;
+  if (n < N) v = project_gaussian(n, TX, TY, inv_tile, xy, chol, geom, rect, counts);
+  block_count_sums<NT>(v, bsum, bcull);
+}
+
 
 // Keys per sort chunk when n keys are split over G chunks: a multiple of
 // SORT_BLOCK, never zero.
@@ -202,6 +214,37 @@ __device__ inline void block_sum_prefix(int nb, int b, const int *__restrict__ b
   int cs = 0;
   for (int w = 0; w < NT / 64; ++w) cs += cl[w];
   *prefix = pre_b;
+  *total = tot;
+  *culled = cs;
+}
+
+// One block of NT threads: the exclusive prefixes at entries g * b and
+// min(g * (b + 1), nbp) of the nbp <= NT per-block pair counts (the first
+// and one-past-last key slot of chunk b, which spans g projection blocks),
+// their total and the total of the culled counts (valid in every thread).
+template <int NT>
+__device__ inline void chunk_bounds(int nbp, int b, int g, const int *__restrict__ bsum,
+                                    const int *__restrict__ bcull, long long *lo, long long *hi,
+                                    long long *total, int *culled) {
+  __shared__ long long lds[NT / 64];
+  __shared__ long long s_lo, s_hi;
+  __shared__ int cl[NT / 64];
+  const int t = threadIdx.x;
+  const long long v = (t < nbp) ? bsum[t] : 0;
+  int c = (t < nbp) ? bcull[t] : 0;
+  long long tot;
+  const long long ex = block_exclusive_scan<NT>(v, &tot, lds);
+  const int i0 = g * b, i1 = min(g * (b + 1), nbp);
+  if (t == i0) s_lo = ex;
+  if (t == i1) s_hi = ex;
+  if (t == 0 && i1 >= nbp) s_hi = tot;
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((t & 63) == 0) cl[t >> 6] = c;
+  __syncthreads();
+  int cs = 0;
+  for (int w = 0; w < NT / 64; ++w) cs += cl[w];
+  *lo = s_lo;
+  *hi = s_hi;
   *total = tot;
   *culled = cs;
 }
@@ -424,10 +467,11 @@ __device__ inline void emit_block_wide(int base, int N, int TX, long long block_
 }
 
 // Stable scatter of part `part` (of WIDE_SPLIT equal parts) of chunk b (the
-// keys emission block b wrote) on the whole tile index (D = 2^bits >=
-// n_tiles digits) by one block of WIDE_SCATTER threads, from the `nb`
-// histogram rows (row r = chunk r, D words each); the chunk's earlier parts
-// are counted into the offsets with LDS atomics.
+// keys emission block b wrote; its bounds from the nbp projection-block
+// sums) on the whole tile index (D = 2^bits >= n_tiles digits) by one block
+// of WIDE_SCATTER threads, from the `nb` histogram rows (row r = chunk r, D
+// words each); the chunk's earlier parts are counted into the offsets with
+// LDS atomics.
 // Each key goes to (keys of lower tiles in all chunks) + (keys of its tile
 // in earlier chunks) + (earlier keys of its tile in this chunk).  Block 0
 // also writes tile_start[0, n_tiles] (the per-tile totals' exclusive
@@ -439,8 +483,8 @@ __device__ inline void emit_block_wide(int base, int N, int TX, long long block_
 // histogram loads are issued before the chunk bounds are
 // known so that their latency overlaps the block-sum prefix.
 __device__ inline void scatter_chunk_wide(const uint32_t *__restrict__ in,
-                                          uint32_t *__restrict__ out, int nb, int b, int part,
-                                          int D,
+                                          uint32_t *__restrict__ out, int nb, int nbp, int b,
+                                          int part, int D,
                                           int bits, int n, int n_tiles,
                                           const int *__restrict__ bsum,
                                           const int *__restrict__ bcull,
@@ -466,11 +510,11 @@ __device__ inline void scatter_chunk_wide(const uint32_t *__restrict__ in,
   uint4 h[RB];
 #pragma unroll
   for (int j = 0; j < RB; ++j) h[j] = h4[(size_t)min(r0 + j * K, nb - 1) * C + cq];
-  long long pre_keys, total;
+  long long pre_keys, end_keys, total;
   int culled;
-  block_sum_prefix<NT>(nb, b, bsum, bcull, &pre_keys, &total, &culled);
+  chunk_bounds<NT>(nbp, b, WIDE_GROUP, bsum, bcull, &pre_keys, &end_keys, &total, &culled);
   const int cbeg = (int)min(pre_keys, (long long)n);
-  const int cend = (int)min(pre_keys + bsum[b], (long long)n);
+  const int cend = (int)min(end_keys, (long long)n);
   const int q = (cend - cbeg + WIDE_SPLIT - 1) / WIDE_SPLIT;
   const int beg = min(cbeg + part * q, cend), end = min(beg + q, cend);
   const bool first = b == 0 && part == 0;  // writes tile_start

@@ -45,6 +45,44 @@ struct Layout {
   size_t keys_sorted() const { return (sort_passes & 1) ? keys_b : keys_a; }
 };
 
+// Adam on one parameter (Kingma and Ba, as the fitting loop uses it): with
+// bias corrections bc1 = 1 - b1^t, bc2 = 1 - b2^t,
+//   m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2;
+//   theta <- theta - lr (m / bc1) / (sqrt(v / bc2) + eps).
+// Shared by the standalone optimiser kernel and the fused
+// optimiser-plus-projection kernel so both round identically.
+__device__ inline float adam_update(float theta, float g, float *__restrict__ m,
+                                    float *__restrict__ v, float lr, float b1, float b2, float eps,
+                                    float bc1, float bc2) {
+  const float mm = b1 * *m + (1.f - b1) * g;
+  const float vv = b2 * *v + (1.f - b2) * g * g;
+  *m = mm;
+  *v = vv;
+  return theta - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+}
+
+// Bias corrections of step t, evaluated in FP64 and rounded once.
+__device__ inline void adam_bias(int t, float b1, float b2, float *bc1, float *bc2) {
+  *bc1 = (float)(1.0 - pow((double)b1, (double)t));
+  *bc2 = (float)(1.0 - pow((double)b2, (double)t));
+}
+
+// The optimiser step of the previous iteration, applied by the first
+// binning kernel of the next one (the fitting loop's fused form): Adam over
+// the 8 parameters of each Gaussian with step t = step[0], gradients cleared,
+// and the previous iteration's loss partials reduced into trace[t - 1].
+struct PendingAdam {
+  float *xy, *chol, *rgb;
+  float *g_xy, *g_chol, *g_rgb, *m, *v;
+  const int32_t *step;
+  gs2d_adam_cfg cfg;
+  const float *loss_part;
+  int n_part;
+  float loss_scale;
+  float *trace;
+  int trace_len;
+};
+
 // Returns false if the shape is outside the supported limits.
 bool make_layout(const gs2d_shape &s, Layout *L);
 
@@ -57,8 +95,11 @@ inline T *at(void *ws, size_t off) {
 
 // Binning (bin.hip).  Each enqueues on `st`.
 // step_tick (nullable): a device counter incremented once by the binning.
+// adam (nullable): apply that optimiser step to xy/chol/rgb first (the
+// projection then reads the updated parameters).
 hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, void *ws,
-                          hipStream_t st, int *step_tick = nullptr);
+                          hipStream_t st, int *step_tick = nullptr,
+                          const PendingAdam *adam = nullptr);
 
 // Stable LSD radix sort of keys on bits [16, 16 + 8*passes) with G sort
 // blocks; misc[0] holds the key count; hist holds RADIX * G words.

@@ -303,6 +303,16 @@ __device__ inline void fused_tile(Smem<Cfg<TILE, PPL>::NW> &S, float *acc, const
   const float pxc = (float)px + 0.5f, pyc0 = (float)py0 + 0.5f;
   const unsigned inside = inside_mask<PPL>(f, px, py0);
   const bool single = (end - beg) <= CH;  // the whole list fits one LDS chunk
+  // the target pixels are loaded first, their latency hidden by the staging
+  const size_t HW = (size_t)f.W * f.H;
+  float tg[PPL][3];
+#pragma unroll
+  for (int r = 0; r < PPL; ++r) {
+    const size_t p = ((inside >> r) & 1u) ? (size_t)(py0 + r) * f.W + px : 0;
+    tg[r][0] = target[p];
+    tg[r][1] = target[HW + p];
+    tg[r][2] = target[2 * HW + p];
+  }
   float a[PPL][3] = {};
   int len = 0;
   for (int c = beg; c < end; c += CH) {
@@ -321,14 +331,11 @@ __device__ inline void fused_tile(Smem<Cfg<TILE, PPL>::NW> &S, float *acc, const
   }
   float g[PPL][3];
   float l = 0.f;
-  const size_t HW = (size_t)f.W * f.H;
 #pragma unroll
   for (int r = 0; r < PPL; ++r) {
     g[r][0] = g[r][1] = g[r][2] = 0.f;
     if ((inside >> r) & 1u) {
-      const size_t p = (size_t)(py0 + r) * f.W + px;
-      const float r0 = a[r][0] - target[p], r1 = a[r][1] - target[HW + p],
-                  r2 = a[r][2] - target[2 * HW + p];
+      const float r0 = a[r][0] - tg[r][0], r1 = a[r][1] - tg[r][1], r2 = a[r][2] - tg[r][2];
       l += r0 * r0 + r1 * r1 + r2 * r2;
       g[r][0] = r0 * grad_scale;
       g[r][1] = r1 * grad_scale;
