@@ -64,7 +64,7 @@ k_adam(int N, float *__restrict__ xy, float *__restrict__ chol, float *__restric
   }
   if (loss_part && blockIdx.x == 0) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < n_part; i += blockDim.x) s += (double)loss_part[i];
+    s = thread_sum_parts(loss_part, n_part);
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();

@@ -60,7 +60,8 @@ bool make_layout(const gs2d_shape &s, Layout *L) {
   // per sort chunk of the second pass (<= 128 rows of 256 words)
   L->hist = take((size_t)RADIX * 256 * 4 * 2);
   L->tile_start = take(((size_t)L->n_tiles + 1) * 4);
-  L->loss_part = take((size_t)L->n_tiles * 4);
+  L->loss_parts = L->n_tiles * (s.tile / 8) * (s.tile / (8 * ppl));
+  L->loss_part = take((size_t)L->loss_parts * 4);
   L->grads = take(N * 8 * 4);
   L->misc = take(MISC_COUNT * 4);
   L->total = o;
@@ -239,7 +240,7 @@ hipError_t enqueue_iterations(const Layout &L, void *ws, const float *target, fl
   float *g_xy = g, *g_chol = g + 2 * (size_t)L.N, *g_rgb = g + 5 * (size_t)L.N;
   const float loss_scale = (float)(1.0 / (3.0 * L.W * (double)L.H));
   const PendingAdam pending{xy,    chol, rgb,  g_xy, g_chol, g_rgb, m,         v,
-                            step,  cfg,  at<const float>(ws, L.loss_part), L.n_tiles,
+                            step,  cfg,  at<const float>(ws, L.loss_part), L.loss_parts,
                             loss_scale, trace, trace_len};
   hipError_t e = hipSuccess;
   for (int i = 0; i < k && e == hipSuccess; ++i) {
@@ -248,7 +249,8 @@ hipError_t enqueue_iterations(const Layout &L, void *ws, const float *target, fl
   }
   if (e == hipSuccess && k > 0)
     e = launch_adam(L.N, xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg, nullptr, 1,
-                    at<const float>(ws, L.loss_part), L.n_tiles, loss_scale, trace, trace_len, st);
+                    at<const float>(ws, L.loss_part), L.loss_parts, loss_scale, trace, trace_len,
+                    st);
   return e;
 }
 

@@ -44,6 +44,7 @@ enum BMisc : int { BM_N_PAIRS = 0, BM_STATUS = 1, BM_N_CULLED = 2, BM_STICKY = 3
 
 struct BatchLayout {
   int F, T, ppl, passes, sort_blocks, proj_blocks;
+  int nw;  // raster wavefronts per tile: loss partials per tile
   long long Ntot, keys_tot, hist_tot, tiles_tot;
   size_t desc, blk_frame, blk_chunk, pblk_frame, queue, geom, rect, counts, offsets, bsum, bcull,
       keys_a, keys_b, hist, hist2, tile_start, loss_part, grads, misc, counter, total;
@@ -60,6 +61,7 @@ bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout
   B->F = F;
   B->T = tile;
   B->ppl = ppl;
+  B->nw = (tile / 8) * (tile / (8 * ppl));
   B->frames.resize(F);
   long long g = 0, px = 0, key = 0, hist = 0, tiles = 0;
   int blocks = 0, pblocks = 0, maxbits = 1;
@@ -125,7 +127,7 @@ bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout
   B->hist = take(4 * (size_t)RADIX * pblocks);
   B->hist2 = take(4 * (size_t)hist);
   B->tile_start = take(4 * ((size_t)tiles + F));
-  B->loss_part = take(4 * (size_t)tiles);
+  B->loss_part = take(4 * (size_t)tiles * B->nw);
   B->grads = take(32 * (size_t)g);
   B->misc = take(4 * (size_t)BM_STRIDE * F);
   B->counter = take(64);
@@ -278,20 +280,22 @@ k_b_render_persistent(BatchRaster a) {
     fa.tile_start = a.tile_start + d.tile_off + f;
     fa.rgb = a.rgb + 3 * d.g_off;
     const float gs = (float)(2.0 / (3.0 * (double)d.W * (double)d.H));
-    fused_tile<TILE, PPL>(S, acc, fa, t, a.targets + d.px_off, a.loss_part + d.tile_off + t, gs,
+    fused_tile<TILE, PPL>(S, acc, fa, t, a.targets + d.px_off,
+                          a.loss_part + (d.tile_off + t) * Cfg<TILE, PPL>::NW, gs,
                           a.g_xy + 2 * d.g_off, a.g_chol + 3 * d.g_off, a.g_rgb + 3 * d.g_off);
   }
 }
 
 // One block per frame: loss of this iteration into trace[(t-1) * F + f].
 __global__ void __launch_bounds__(256)
-k_b_loss(const BFrame *__restrict__ D, int F, const float *__restrict__ loss_part,
+k_b_loss(const BFrame *__restrict__ D, int F, int nw, const float *__restrict__ loss_part,
          const int *__restrict__ step, float *__restrict__ trace, int trace_rows) {
   __shared__ double red[4];
   const int f = blockIdx.x;
   const BFrame d = D[f];
   double s = 0.0;
-  for (int i = threadIdx.x; i < d.n_tiles; i += 256) s += (double)loss_part[d.tile_off + i];
+  const float *lp = loss_part + d.tile_off * nw;
+  s = thread_sum_parts(lp, d.n_tiles * nw);
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -444,7 +448,7 @@ hipError_t enqueue_batch_iteration(const BatchLayout &B, void *ws, int grid, con
   if (e == hipSuccess) e = enqueue_batch_raster(B, ws, grid, rgb, targets, g_xy, g_chol, g_rgb, st);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_b_loss, dim3(B.F), dim3(256), 0, st, at<const BFrame>(ws, B.desc), B.F,
-                       at<const float>(ws, B.loss_part), step, trace, trace_rows);
+                       B.nw, at<const float>(ws, B.loss_part), step, trace, trace_rows);
     e = hipGetLastError();
   }
   if (e == hipSuccess)
@@ -630,7 +634,7 @@ extern "C" int gs2d_batch_render_grads(int32_t n_frames, const gs2d_frame *frame
       e = hipMemcpyAsync(one, &h_one, sizeof(int32_t), hipMemcpyHostToDevice, st);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(k_b_loss, dim3(B.F), dim3(256), 0, st, at<const BFrame>(ws, B.desc), B.F,
-                           at<const float>(ws, B.loss_part), one, loss_per_frame, 1);
+                           B.nw, at<const float>(ws, B.loss_part), one, loss_per_frame, 1);
         e = hipGetLastError();
       }
       if (e == hipSuccess) e = hipStreamSynchronize(st);  // h_one leaves scope

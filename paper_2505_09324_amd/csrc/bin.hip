@@ -102,7 +102,7 @@ k_adam_project_wide(int N, int TX, int TY, float inv_tile, PendingAdam a,
   __syncthreads();
   if (blockIdx.x == gridDim.x - 1) {  // the loss of the previous iteration
     double s = 0.0;
-    for (int i = threadIdx.x; i < a.n_part; i += WIDE_PROJ) s += (double)a.loss_part[i];
+    s = thread_sum_parts(a.loss_part, a.n_part);
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();

@@ -34,6 +34,7 @@ struct Layout {
   int W, H, N, T, max_pairs;
   int ppl;             // pixels per lane of the raster kernels (1, 2, 4)
   int TX, TY, n_tiles;
+  int loss_parts;   // loss partials: one per raster wavefront (n_tiles * waves per tile)
   int sort_blocks;  // G: fixed chunks of the key array in the second pass
   int sort_passes;  // radix passes over the tile bits (1 or 2)
   bool wide;        // single pass whose digit is the whole tile index
@@ -65,6 +66,31 @@ __device__ inline float adam_update(float theta, float g, float *__restrict__ m,
 __device__ inline void adam_bias(int t, float b1, float b2, float *bc1, float *bc2) {
   *bc1 = (float)(1.0 - pow((double)b1, (double)t));
   *bc2 = (float)(1.0 - pow((double)b2, (double)t));
+}
+
+// One thread's share of a block-wide FP64 sum of n floats (element i goes
+// to thread i mod blockDim.x in 16-byte groups when p is 16-byte aligned):
+// eight independent loads are in flight per thread.  The caller reduces the
+// per-thread values across the block.
+__device__ inline double thread_sum_parts(const float *__restrict__ p, int n) {
+  const int nt = blockDim.x, t = threadIdx.x;
+  double s = 0.0;
+  int done = 0;
+  if ((reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+    const float4 *p4 = reinterpret_cast<const float4 *>(p);
+    const int n4 = n >> 2;
+    for (int i0 = t; i0 < n4; i0 += 8 * nt) {
+      float4 v[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v[j] = p4[min(i0 + j * nt, n4 - 1)];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (i0 + j * nt < n4) s += ((double)v[j].x + (double)v[j].y) + ((double)v[j].z + (double)v[j].w);
+    }
+    done = 4 * n4;
+  }
+  for (int i = done + t; i < n; i += nt) s += (double)p[i];
+  return s;
 }
 
 // The optimiser step of the previous iteration, applied by the first

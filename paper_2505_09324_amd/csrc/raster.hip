@@ -69,11 +69,7 @@ k_render_fwd(FrameArgs f, const float *__restrict__ target, float *__restrict__ 
       }
     }
   }
-  if (loss_part) {
-    __syncthreads();
-    const float s = block_sum<C::NW>(S, l);
-    if (threadIdx.x == 0) loss_part[tile] = s;
-  }
+  if (loss_part) wave_loss(l, loss_part + tile * C::NW + (threadIdx.x >> 6));
 }
 
 // ---------------------------------------------------------------- backward --
@@ -127,8 +123,8 @@ k_render_fused(FrameArgs f, const float *__restrict__ target, float *__restrict_
   using C = Cfg<TILE, PPL>;
   __shared__ Smem<C::NW> S;
   __shared__ float acc[CH * 8];
-  fused_tile<TILE, PPL>(S, acc, f, (int)blockIdx.x, target, loss_part + blockIdx.x, grad_scale,
-                        g_xy, g_chol, g_rgb);
+  fused_tile<TILE, PPL>(S, acc, f, (int)blockIdx.x, target, loss_part + blockIdx.x * C::NW,
+                        grad_scale, g_xy, g_chol, g_rgb);
 }
 
 // ------------------------------------------------- in-cutoff pair counting --
@@ -172,7 +168,7 @@ __global__ void __launch_bounds__(1024)
 k_loss_reduce(const float *__restrict__ part, int n, float scale, float *__restrict__ out) {
   __shared__ double red[16];
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 1024) s += (double)part[i];
+  s = thread_sum_parts(part, n);
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -263,7 +259,7 @@ hipError_t launch_count_pairs(const Layout &L, void *ws, unsigned long long *out
 
 hipError_t launch_loss_reduce(const Layout &L, void *ws, float *loss, hipStream_t st) {
   hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(1024), 0, st, at<const float>(ws, L.loss_part),
-                     L.n_tiles, (float)(1.0 / (3.0 * L.W * (double)L.H)), loss);
+                     L.loss_parts, (float)(1.0 / (3.0 * L.W * (double)L.H)), loss);
   return hipGetLastError();
 }
 

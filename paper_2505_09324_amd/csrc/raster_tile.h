@@ -41,7 +41,6 @@ struct Smem {
   uint16_t mask[CH];      // bit w: box meets sub-block w (at most 16)
   int id[CH];
   uint16_t list[NW][CH];
-  float red[NW];
 };
 
 struct FrameArgs {
@@ -261,16 +260,12 @@ __device__ inline void flush_grads(const Smem<NW> &S, const float *acc, int cnt,
   }
 }
 
-// Block sum of one float per thread; the result is valid in thread 0.
-template <int NW>
-__device__ inline float block_sum(Smem<NW> &S, float v) {
+// Wavefront sum of one float per lane; lane 0 writes it to *slot.  Loss
+// partials are kept per wavefront (tile t, wavefront w at t * NW + w), so a
+// wavefront never waits for the rest of its tile to record its loss.
+__device__ inline void wave_loss(float v, float *__restrict__ slot) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  if ((threadIdx.x & 63) == 0) S.red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  float s = 0.f;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < NW; ++w) s += S.red[w];
-  return s;
+  if ((threadIdx.x & 63) == 0) *slot = v;
 }
 
 // Bit r set: pixel row r of this lane lies inside the frame.
@@ -288,21 +283,47 @@ __device__ inline unsigned inside_mask(const FrameArgs &f, int px, int py0) {
 // pixel's tile list, so a tile can finish its forward pass, form
 // dL/dC = 2 (C - target) / (3HW) in registers and run its backward pass
 // without dL/dC ever reaching memory.  One call processes one tile with the
-// whole workgroup; the block sum of its squared residuals goes to *loss_slot.
+// whole workgroup; each wavefront's sum of squared residuals goes to
+// loss_slots[w].
+//
+// A list that fits one LDS chunk (the common case) is staged once; after
+// one barrier every wavefront compacts it to its sub-block, runs its
+// forward pass (keeping the Gaussians that reach its pixels), its residuals
+// and its backward pass on its own, and a second barrier precedes the flush
+// of the tile's gradient accumulators.  Longer lists are staged chunk by
+// chunk, twice.
+template <int TILE, int PPL>
+__device__ inline void residuals(const float (&a)[PPL][3], const float (&tg)[PPL][3],
+                                 unsigned inside, float grad_scale, float (&g)[PPL][3], float *l) {
+  float s = 0.f;
+#pragma unroll
+  for (int r = 0; r < PPL; ++r) {
+    g[r][0] = g[r][1] = g[r][2] = 0.f;
+    if ((inside >> r) & 1u) {
+      const float r0 = a[r][0] - tg[r][0], r1 = a[r][1] - tg[r][1], r2 = a[r][2] - tg[r][2];
+      s += r0 * r0 + r1 * r1 + r2 * r2;
+      g[r][0] = r0 * grad_scale;
+      g[r][1] = r1 * grad_scale;
+      g[r][2] = r2 * grad_scale;
+    }
+  }
+  *l = s;
+}
+
 template <int TILE, int PPL>
 __device__ inline void fused_tile(Smem<Cfg<TILE, PPL>::NW> &S, float *acc, const FrameArgs &f,
                                   int tile, const float *__restrict__ target,
-                                  float *__restrict__ loss_slot, float grad_scale,
+                                  float *__restrict__ loss_slots, float grad_scale,
                                   float *__restrict__ g_xy, float *__restrict__ g_chol,
                                   float *__restrict__ g_rgb) {
   using C = Cfg<TILE, PPL>;
+  const int w = threadIdx.x >> 6;
   const int tx = tile % f.TX, ty = tile / f.TX;
   const int beg = f.tile_start[tile], end = f.tile_start[tile + 1];
   int px, py0;
   pixel_of_thread<TILE, PPL>(tx, ty, &px, &py0);
   const float pxc = (float)px + 0.5f, pyc0 = (float)py0 + 0.5f;
   const unsigned inside = inside_mask<PPL>(f, px, py0);
-  const bool single = (end - beg) <= CH;  // the whole list fits one LDS chunk
   // the target pixels are loaded first, their latency hidden by the staging
   const size_t HW = (size_t)f.W * f.H;
   float tg[PPL][3];
@@ -314,55 +335,44 @@ __device__ inline void fused_tile(Smem<Cfg<TILE, PPL>::NW> &S, float *acc, const
     tg[r][2] = target[2 * HW + p];
   }
   float a[PPL][3] = {};
-  int len = 0;
+  float g[PPL][3];
+  float l;
+  if (end - beg <= CH) {
+    const int cnt = end - beg;
+    __syncthreads();  // LDS of a previous tile (persistent callers) is free
+    stage_chunk<TILE, PPL>(S, f.keys, beg, cnt, tx, ty, f.geom, f.rgb);
+    for (int i = threadIdx.x; i < cnt * 8; i += C::NT) acc[i] = 0.f;
+    __syncthreads();
+    int len = compact_chunk<C::NW>(S, cnt);
+    len = fwd_chunk<C::NW, PPL, true>(S, len, pxc, pyc0, inside, a);
+    residuals<TILE, PPL>(a, tg, inside, grad_scale, g, &l);
+    wave_loss(l, loss_slots + w);
+    bwd_chunk<C::NW, PPL, false>(S, acc, len, pxc, pyc0, g);
+    __syncthreads();
+    flush_grads<C::NT, C::NW>(S, acc, cnt, g_xy, g_chol, g_rgb);
+    return;
+  }
   for (int c = beg; c < end; c += CH) {
     const int cnt = min(CH, end - c);
     __syncthreads();
     stage_chunk<TILE, PPL>(S, f.keys, c, cnt, tx, ty, f.geom, f.rgb);
     __syncthreads();
-    len = compact_chunk<C::NW>(S, cnt);
-    __syncthreads();
-    // a single chunk stays in LDS for the backward pass: keep only the
-    // Gaussians that reach this wavefront's pixels
-    if (single)
-      len = fwd_chunk<C::NW, PPL, true>(S, len, pxc, pyc0, inside, a);
-    else
-      fwd_chunk<C::NW, PPL, false>(S, len, pxc, pyc0, inside, a);
+    const int len = compact_chunk<C::NW>(S, cnt);
+    fwd_chunk<C::NW, PPL, false>(S, len, pxc, pyc0, inside, a);
   }
-  float g[PPL][3];
-  float l = 0.f;
-#pragma unroll
-  for (int r = 0; r < PPL; ++r) {
-    g[r][0] = g[r][1] = g[r][2] = 0.f;
-    if ((inside >> r) & 1u) {
-      const float r0 = a[r][0] - tg[r][0], r1 = a[r][1] - tg[r][1], r2 = a[r][2] - tg[r][2];
-      l += r0 * r0 + r1 * r1 + r2 * r2;
-      g[r][0] = r0 * grad_scale;
-      g[r][1] = r1 * grad_scale;
-      g[r][2] = r2 * grad_scale;
-    }
-  }
-  __syncthreads();
-  const float s = block_sum<C::NW>(S, l);
-  if (threadIdx.x == 0) *loss_slot = s;
-  if (beg >= end) return;
+  residuals<TILE, PPL>(a, tg, inside, grad_scale, g, &l);
+  wave_loss(l, loss_slots + w);
   for (int c = beg; c < end; c += CH) {
     const int cnt = min(CH, end - c);
     __syncthreads();
-    if (!single) stage_chunk<TILE, PPL>(S, f.keys, c, cnt, tx, ty, f.geom, f.rgb);
-    for (int i = threadIdx.x; i < CH * 8; i += C::NT) acc[i] = 0.f;
+    stage_chunk<TILE, PPL>(S, f.keys, c, cnt, tx, ty, f.geom, f.rgb);
+    for (int i = threadIdx.x; i < cnt * 8; i += C::NT) acc[i] = 0.f;
     __syncthreads();
-    if (!single) {
-      len = compact_chunk<C::NW>(S, cnt);
-      __syncthreads();
-      bwd_chunk<C::NW, PPL, true>(S, acc, len, pxc, pyc0, g);
-    } else {
-      bwd_chunk<C::NW, PPL, false>(S, acc, len, pxc, pyc0, g);
-    }
+    const int len = compact_chunk<C::NW>(S, cnt);
+    bwd_chunk<C::NW, PPL, true>(S, acc, len, pxc, pyc0, g);
     __syncthreads();
     flush_grads<C::NT, C::NW>(S, acc, cnt, g_xy, g_chol, g_rgb);
   }
 }
-
 
 }  // namespace gs2d
