@@ -2,16 +2,18 @@
 """Fitting-iteration throughput on one MI355X: one 1920x1080 synthetic frame,
 30,000 Gaussians from the content-aware ROI initialisation, Adam.
 
-A step is one fitting iteration: projection + tile binning + radix sort,
+A step is one fitting iteration: projection + tile binning + tile sort,
 fused forward render / MSE / backward render, Adam.  Prints one JSON line.
 
     python bench.py [--steps 1950] [--warmup 50] [--no-cpu-baseline]
 
 Besides the throughput the line carries
-  roofline      the dominant kernel (fused per-tile forward+backward) timed
-                with HIP events on the stream it is launched on, against the
-                FP32 vector peak, with its algorithmic FLOPs = 52 per
-                (pixel, Gaussian) pair inside the 3-sigma cutoff;
+  roofline      the dominant kernel (fused per-tile forward+backward): back
+                to back launches on the torch stream captured in a graph, as
+                the fitting loop replays them, timed with HIP events around
+                the replay; against the FP32 vector peak, with its
+                algorithmic FLOPs = 52 per (pixel, Gaussian) pair inside the
+                3-sigma cutoff; traffic from the committed counter record;
   cpu_baseline  the FP64 oracle timed on this host's cores on a bounded
                 sample (a few full iterations of the same workload).
 """
@@ -138,6 +140,24 @@ def kernel_digest():
     return h.hexdigest()
 
 
+def time_graph(fn, reps):
+    """Mean seconds per call of `fn` (library launches on the current
+    stream), the calls captured back to back in one graph as the fitting
+    loop replays them, timed with HIP events around the replay."""
+    import torch
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(reps):
+            fn()
+    graph.replay()  # warm
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,29 +227,14 @@ def main():
     n_pairs = int(_lib.read_bins(shape, ws)["n_pairs"])
     g = [torch.zeros(N, d, device=dev) for d in (2, 3, 3)]
     _lib.render_fused(shape, ws, rgb, T, *g)          # warm
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.kernel_reps):
-        _lib.render_fused(shape, ws, rgb, T, *g)
-    e1.record()
-    torch.cuda.synchronize()
-    t_fused = e0.elapsed_time(e1) / args.kernel_reps * 1e-3
+    t_fused = time_graph(lambda: _lib.render_fused(shape, ws, rgb, T, *g), args.kernel_reps)
     # other stages, same way
-    e0.record()
-    for _ in range(args.kernel_reps):
-        _lib.project_bin(shape, xy, chol, ws)
-    e1.record()
-    torch.cuda.synchronize()
-    t_bin = e0.elapsed_time(e1) / args.kernel_reps * 1e-3
+    t_bin = time_graph(lambda: _lib.project_bin(shape, xy, chol, ws), args.kernel_reps)
     step2 = torch.zeros(1, dtype=torch.int32, device=dev)
     mm, vv = m.clone(), v.clone()
     xs, cs, rs = xy.clone(), chol.clone(), rgb.clone()
-    e0.record()
-    for _ in range(args.kernel_reps):
-        _lib.adam_step(xs, cs, rs, *g, mm, vv, step2, cfg)
-    e1.record()
-    torch.cuda.synchronize()
-    t_adam = e0.elapsed_time(e1) / args.kernel_reps * 1e-3
+    t_adam = time_graph(lambda: _lib.adam_step(xs, cs, rs, *g, mm, vv, step2, cfg), args.kernel_reps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     if args.sweep:
         for tt, pp in ((8, 1), (16, 1), (16, 2), (32, 1), (32, 2), (32, 4)):
