@@ -337,7 +337,10 @@ int gs2d_cnn_read_targets(int32_t H, int32_t W, const void *ws, size_t ws_bytes,
 int gs2d_cnn_backward(int32_t H, int32_t W, const float *master, const uint16_t *wbf16,
                       float *grad, float *loss3, void *ws, size_t ws_bytes, void *stream);
 /* Adam on the master weights (step: device int32 counter, incremented),
- * decoupled weight decay, clears grad, refreshes the BF16 copies. */
+ * decoupled weight decay, clears grad, and writes each updated weight to its
+ * BF16 copies in the same pass.  wbf16 must have been filled once by
+ * gs2d_cnn_sync_weights: the zero padding of the transposed copies is not
+ * rewritten here. */
 int gs2d_cnn_adam(int32_t H, int32_t W, float *master, float *grad, float *m, float *v,
                   int32_t *step, float lr, float weight_decay, uint16_t *wbf16, void *stream);
 /* Decode the last forward pass into N Gaussians: per tile argmax count and

@@ -9,17 +9,29 @@
 // (v_mfma_f32_16x16x32_bf16).
 //
 // Every convolution pass is an implicit GEMM C[M x N] = A[M x K] B[K x N]
-// with a 64 x 64 workgroup tile, K in steps of 32, both operand tiles
-// staged in LDS as [row][k] (k contiguous) so that each lane reads its 8
-// BF16 MFMA operands with one 16-byte LDS load:
+// whose operand tiles are staged in LDS as [row][k] (k contiguous, row pitch
+// padded so that the 16-byte reads of one MFMA step hit distinct banks) and
+// whose next stage is loaded into registers while the current one is
+// multiplied:
 //   forward      M = Cout, N = output pixels, K = (tap, Cin)
-//                A = W[co][tap][ci], B = input gathered per tap (im2col)
-//   grad input   M = Cin,  N = input pixels,  K = (tap, Cout)
-//                A = W^T[ci][tap][co], B = dZ gathered from the output
-//                pixel each tap maps back to (stride-parity rule)
-//   grad weight  M = Cout, N = (tap, Cin),    K = output pixels (split over
-//                workgroups, FP32 atomics into dW)
-// with dZ = dL/d(layer output) masked by ReLU'.
+//                A = W[co][tap][ci], B = input gathered per tap (im2col);
+//                bias, ReLU and the BF16 rounding run in the epilogue
+//   grad input   M = Cin, N = input pixels of one stride-parity class,
+//                K = (the class's taps, Cout).  With stride 2 an input pixel
+//                (y, x) receives output gradients only through the taps
+//                with ty = y + 1 (mod 2) and tx = x + 1 (mod 2): 1, 2, 2 or 4
+//                of the 9, so the four parity classes are separate GEMMs and
+//                no multiply-by-zero is issued.  The epilogue applies the
+//                previous layer's ReLU' and writes its BF16 dZ directly.
+//   grad weight  M = Cout, N = (tap, Cin), K = output pixels, split over
+//                workgroups whose partial tiles a second kernel sums (plain
+//                stores: FP32 atomics from every workgroup cost more than the
+//                GEMM).  Both
+//                operands are channels-last in memory and pixel-contiguous in
+//                LDS: each thread loads an 8 pixel x 8 channel block and
+//                transposes it in registers.  The blocks of the first N tile
+//                also sum dZ over their pixels: the bias gradient.
+// dZ = dL/d(layer output) masked by ReLU', held as BF16 [pixels][CoutS].
 #include <cmath>
 
 #include "gs2d_internal.h"
@@ -31,10 +43,15 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 32, LDK = BK + 8;  // LDS row pitch (elements)
 constexpr int NLAYER = 5;
 constexpr int HEAD_CH = 73;
 constexpr int NSLOT = 8, NPAR = 8;
+constexpr int KPAD = 32;     // K of the weight matrices is padded to one MFMA step
+constexpr int KS = 64;       // k per LDS stage (forward, grad input)
+constexpr int LP = KS + 8;   // its row pitch in halves (144 B = 9 x 16 B)
+constexpr int PS = 128;      // output pixels per LDS stage (grad weight)
+constexpr int LPW = PS + 8;  // its row pitch in halves (272 B = 17 x 16 B)
+constexpr int GW_MIN_PIX = 4 * PS;  // smallest pixel range of a grad-weight block
 
 __device__ inline uint16_t f2bf(float x) {  // round to nearest even
   const uint32_t u = __float_as_uint(x);
@@ -45,211 +62,441 @@ __device__ inline float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b <<
 struct ConvDims {
   int Hin, Win, Cin, Hout, Wout, Cout, stride, relu;
   int Mpad;   // rows of the weight matrix (Cout rounded up to 64)
-  int Kf;     // forward K = 9 * Cin, padded to a multiple of BK
-  int CoutS;  // channel stride of dZ / output gradients (Cout rounded up to 8)
-  int Kb;     // grad-input K = 9 * CoutS, padded to BK
+  int Kf;     // forward K = 9 * Cin, padded to a multiple of KPAD
+  int CoutS;  // channel stride of dZ (Cout rounded up to 8)
+  int Kb;     // row length of the transposed weights = 9 * CoutS, padded to KPAD
 };
-
-// ------------------------------------------------------------------ GEMM --
-enum { MODE_FWD = 0, MODE_BWD_DATA = 1, MODE_BWD_WEIGHT = 2 };
 
 struct ConvArgs {
   ConvDims d;
-  const uint16_t *x;       // layer input [Hin*Win][Cin] bf16
-  const uint16_t *w;       // [Mpad][Kf] bf16 (forward / grad-weight output layout)
-  const uint16_t *wt;      // [Cin][Kb] bf16 (grad input)
-  const float *bias;       // [Mpad]
-  uint16_t *y;             // forward output [Hout*Wout][Cout] bf16 (hidden layers)
-  float *y_planar;         // forward output [Cout][Hout*Wout] fp32 (head)
-  const float *dy;         // dL/d(output) [Hout*Wout][CoutS] fp32
-  const uint16_t *yact;    // forward output of this layer (ReLU mask), bf16 [..][Cout]
-  float *dx;               // dL/d(input) [Hin*Win][Cin] fp32
-  float *dw;               // dL/dW [Mpad][Kf] fp32 (atomic adds)
-  int ksplit;              // grad-weight: pixels per workgroup (multiple of BK)
+  const uint16_t *x;     // layer input [Hin*Win][Cin] bf16 (grad input: its ReLU mask)
+  const uint16_t *w;     // [Mpad][Kf] bf16, k = tap * Cin + ci
+  const uint16_t *wt;    // [Cin][Kb] bf16, k = tap * CoutS + co (grad input)
+  const float *bias;     // [Mpad]
+  uint16_t *y;           // forward output [Hout*Wout][Cout] bf16 (hidden layers)
+  float *y_planar;       // forward output [Cout][Hout*Wout] fp32 (head)
+  const uint16_t *dz;    // dZ of this layer [Hout*Wout][CoutS] bf16
+  uint16_t *dz_prev;     // grad input: dZ of the previous layer [Hin*Win][Cin] bf16
+  float *gpart;          // grad weight: partial tiles [work][64 col][64 row] fp32
+  float *bpart;          // grad weight: bias partials [split][M tile][64] fp32
+  int ksplit;            // grad weight: output pixels per workgroup (multiple of PS)
+  int ntile_n, nwork;    // grad weight: N tiles, real workgroups (grid rounded up to 8)
+  int ncls;              // grad input: parity classes (4 for stride 2, else 1)
+  int cls_tile0[5];      // grad input: first workgroup of each class, then the total
 };
 
-// dZ = dy (masked by ReLU' when the layer has one), as bf16
-__device__ inline void load_dz8(const ConvArgs &a, long long p, int co, uint16_t out[8]) {
-  const float *src = a.dy + p * a.d.CoutS + co;
-  const float4 u0 = *reinterpret_cast<const float4 *>(src);
-  const float4 u1 = *reinterpret_cast<const float4 *>(src + 4);
-  float v[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-  if (a.d.relu) {
-    // yact has stride Cout (= 64 for every ReLU layer)
-    const uint4 m = *reinterpret_cast<const uint4 *>(a.yact + p * a.d.Cout + co);
-    const uint16_t *mb = reinterpret_cast<const uint16_t *>(&m);
+// One 32-deep MFMA step of a wave's (16 MI) x (16 NJ) tile.  As / Bs point at
+// the wave's first A / B row in LDS ([row][k] with pitch PITCH); lane l reads
+// row l & 15 of every 16-row block at k + 8 (l >> 4) as one 16-byte load.
+template <int MI, int NJ, int PITCH>
+__device__ __forceinline__ void mfma_step(const uint16_t *As, const uint16_t *Bs, int k, int lane,
+                                          floatx4 (&acc)[MI][NJ]) {
+  const int r = lane & 15, kk = k + (lane >> 4) * 8;
+  bf16x8 av[MI], bv[NJ];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = (bf2f(mb[j]) > 0.f) ? v[j] : 0.f;
-  }
+  for (int i = 0; i < MI; ++i)
+    av[i] = __builtin_bit_cast(bf16x8,
+                               *reinterpret_cast<const uint4 *>(As + (16 * i + r) * PITCH + kk));
 #pragma unroll
-  for (int j = 0; j < 8; ++j) out[j] = (co + j < a.d.Cout) ? f2bf(v[j]) : (uint16_t)0;
+  for (int j = 0; j < NJ; ++j)
+    bv[j] = __builtin_bit_cast(bf16x8,
+                               *reinterpret_cast<const uint4 *>(Bs + (16 * j + r) * PITCH + kk));
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(256) k_conv_gemm(ConvArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDK];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][LDK];
+// --------------------------------------------------------------- forward --
+// Workgroup tile 64 (Cout) x 32 WN (pixels); waves 2 x 2, each 32 x 16 WN.
+// Staging: A row t >> 2, k chunks (t & 3) * 8 and +32; B pixel rows
+// (t >> 3) + 32 j, k chunk (t & 7) * 8 (one tap and 8 channels: Cin % 8 == 0).
+template <int WN>
+__global__ void __launch_bounds__(256) k_conv_fwd(ConvArgs a) {
+  constexpr int BN = 32 * WN;
+  __shared__ __attribute__((aligned(16))) uint16_t As[64 * LP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LP];
   const ConvDims &d = a.d;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int m0 = blockIdx.y * BM;
-  const int n0 = blockIdx.x * BN;
-  int K, kbeg, kend;
-  if (MODE == MODE_FWD) {
-    K = d.Kf;
-    kbeg = 0;
-    kend = K;
-  } else if (MODE == MODE_BWD_DATA) {
-    K = d.Kb;
-    kbeg = 0;
-    kend = K;
-  } else {
-    K = d.Hout * d.Wout;
-    kbeg = blockIdx.z * a.ksplit;
-    kend = min(K, kbeg + a.ksplit);
+  const int m0 = blockIdx.y * 64;
+  const long long P = (long long)d.Hout * d.Wout;
+  const long long n0 = (long long)blockIdx.x * BN;
+  const int K = d.Kf;
+  const int ar = tid >> 2, ak = (tid & 3) * 8;
+  const uint16_t *wrow = a.w + (size_t)(m0 + ar) * K;
+  const int br = tid >> 3, bk = (tid & 7) * 8;
+  int iy0[WN], ix0[WN];
+  bool pv[WN];
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const long long p = n0 + br + 32 * j;
+    pv[j] = p < P;
+    const int oy = pv[j] ? (int)(p / d.Wout) : 0, ox = pv[j] ? (int)(p - (long long)oy * d.Wout) : 0;
+    iy0[j] = oy * d.stride - 1;
+    ix0[j] = ox * d.stride - 1;
   }
-  floatx4 acc[4];
+  uint4 ra[2], rb[WN];
+  auto load = [&](int k0) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i) acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    __syncthreads();
-    if (MODE == MODE_FWD || MODE == MODE_BWD_DATA) {
-      // thread -> (row r, 8 consecutive k at kc)
-      const int r = tid >> 2, kc = (tid & 3) * 8;
-      const int k = k0 + kc;
-      // A tile
-      {
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (MODE == MODE_FWD) {
-          v = *reinterpret_cast<const uint4 *>(a.w + (size_t)(m0 + r) * d.Kf + k);
-        } else if (m0 + r < d.Cin) {
-          v = *reinterpret_cast<const uint4 *>(a.wt + (size_t)(m0 + r) * d.Kb + k);
-        }
-        *reinterpret_cast<uint4 *>(&As[r][kc]) = v;
-      }
-      // B tile
-      {
-        uint16_t val[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        const long long p = (long long)n0 + r;
-        if (MODE == MODE_FWD) {
-          const int tap = k / d.Cin, ci = k % d.Cin;
-          if (p < (long long)d.Hout * d.Wout && tap < 9) {
-            const int oy = (int)(p / d.Wout), ox = (int)(p % d.Wout);
-            const int iy = oy * d.stride + tap / 3 - 1, ix = ox * d.stride + tap % 3 - 1;
-            if (iy >= 0 && iy < d.Hin && ix >= 0 && ix < d.Win) {
-              const uint4 u = *reinterpret_cast<const uint4 *>(
-                  a.x + ((size_t)iy * d.Win + ix) * d.Cin + ci);
-              *reinterpret_cast<uint4 *>(val) = u;
-            }
-          }
-        } else {
-          const int tap = k / d.CoutS, co = k % d.CoutS;
-          if (p < (long long)d.Hin * d.Win && tap < 9) {
-            const int y = (int)(p / d.Win), x = (int)(p % d.Win);
-            const int oy2 = y + 1 - tap / 3, ox2 = x + 1 - tap % 3;
-            if (oy2 >= 0 && ox2 >= 0 && oy2 % d.stride == 0 && ox2 % d.stride == 0) {
-              const int oy = oy2 / d.stride, ox = ox2 / d.stride;
-              if (oy < d.Hout && ox < d.Wout) load_dz8(a, (long long)oy * d.Wout + ox, co, val);
-            }
-          }
-        }
-        *reinterpret_cast<uint4 *>(&Bs[r][kc]) = *reinterpret_cast<uint4 *>(val);
-      }
-    } else {
-      // grad weight: k = output pixel. thread -> (pixel t>>3, 8 rows at (t&7)*8)
-      const int pk = tid >> 3, rc = (tid & 7) * 8;
-      const long long p = (long long)k0 + pk;
-      uint16_t av[8] = {0, 0, 0, 0, 0, 0, 0, 0}, bv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (p < kend) {
-        if (m0 + rc < d.CoutS) load_dz8(a, p, m0 + rc, av);
-        const int n = n0 + rc;  // (tap, ci) column of dW
-        const int tap = n / d.Cin, ci = n % d.Cin;
-        if (tap < 9) {
-          const int oy = (int)(p / d.Wout), ox = (int)(p % d.Wout);
-          const int iy = oy * d.stride + tap / 3 - 1, ix = ox * d.stride + tap % 3 - 1;
-          if (iy >= 0 && iy < d.Hin && ix >= 0 && ix < d.Win) {
-            const uint4 u =
-                *reinterpret_cast<const uint4 *>(a.x + ((size_t)iy * d.Win + ix) * d.Cin + ci);
-            *reinterpret_cast<uint4 *>(bv) = u;
-          }
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        As[rc + j][pk] = av[j];
-        Bs[rc + j][pk] = bv[j];
-      }
+    for (int h = 0; h < 2; ++h) {
+      const int k = k0 + ak + 32 * h;
+      ra[h] = (k < K) ? *reinterpret_cast<const uint4 *>(wrow + k) : make_uint4(0, 0, 0, 0);
     }
-    __syncthreads();
-    const int r16 = lane & 15, kq = (lane >> 4) * 8;
-    const bf16x8 A = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&As[16 * w + r16][kq]));
+    const int k = k0 + bk;
+    const int tap = k / d.Cin, ci = k - tap * d.Cin;
+    const int ty = tap / 3, tx = tap - 3 * ty;
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-      const bf16x8 B =
-          __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(&Bs[16 * nb + r16][kq]));
-      acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[nb], 0, 0, 0);
+    for (int j = 0; j < WN; ++j) {
+      rb[j] = make_uint4(0, 0, 0, 0);
+      const int iy = iy0[j] + ty, ix = ix0[j] + tx;
+      if (pv[j] && k < K && tap < 9 && iy >= 0 && iy < d.Hin && ix >= 0 && ix < d.Win)
+        rb[j] = *reinterpret_cast<const uint4 *>(a.x + ((size_t)iy * d.Win + ix) * d.Cin + ci);
     }
+  };
+  floatx4 acc[2][WN];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int wm = w & 1, wn = w >> 1;
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += KS) {
+    __syncthreads();
+    *reinterpret_cast<uint4 *>(As + ar * LP + ak) = ra[0];
+    *reinterpret_cast<uint4 *>(As + ar * LP + ak + 32) = ra[1];
+#pragma unroll
+    for (int j = 0; j < WN; ++j) *reinterpret_cast<uint4 *>(Bs + (br + 32 * j) * LP + bk) = rb[j];
+    __syncthreads();
+    if (k0 + KS < K) load(k0 + KS);
+    mfma_step<2, WN, LP>(As + 32 * wm * LP, Bs + 16 * WN * wn * LP, 0, lane, acc);
+    if (k0 + 32 < K) mfma_step<2, WN, LP>(As + 32 * wm * LP, Bs + 16 * WN * wn * LP, 32, lane, acc);
   }
-
-  // epilogue: lane holds D[4*(lane>>4) + r][lane & 15] of each 16x16 block
-  const int mrow = m0 + 16 * w + 4 * (lane >> 4);
+  // lane holds D[4 (lane >> 4) + r][lane & 15] of each 16 x 16 block
 #pragma unroll
-  for (int nb = 0; nb < 4; ++nb) {
-    const long long col = (long long)n0 + 16 * nb + (lane & 15);
-    if (MODE == MODE_FWD) {
-      if (col >= (long long)d.Hout * d.Wout) continue;
+  for (int i = 0; i < 2; ++i) {
+    const int row = m0 + 32 * wm + 16 * i + 4 * (lane >> 4);
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      const long long col = n0 + 16 * WN * wn + 16 * j + (lane & 15);
+      if (col >= P) continue;
       if (a.y) {
-        uint16_t o[4];
+        if (row < d.Cout) {  // Cout is a multiple of 4 for the hidden layers
+          uint16_t o[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          float v = acc[nb][r] + a.bias[mrow + r];
-          if (d.relu) v = fmaxf(v, 0.f);
-          o[r] = f2bf(v);
+          for (int r = 0; r < 4; ++r) {
+            float v = acc[i][j][r] + a.bias[row + r];
+            if (d.relu) v = fmaxf(v, 0.f);
+            o[r] = f2bf(v);
+          }
+          *reinterpret_cast<uint2 *>(a.y + col * d.Cout + row) = *reinterpret_cast<uint2 *>(o);
         }
-        if (mrow < d.Cout)  // Cout is a multiple of 4 for hidden layers
-          *reinterpret_cast<uint2 *>(a.y + col * d.Cout + mrow) = *reinterpret_cast<uint2 *>(o);
       } else {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          if (mrow + r < d.Cout)
-            a.y_planar[(size_t)(mrow + r) * d.Hout * d.Wout + col] = acc[nb][r] + a.bias[mrow + r];
+          if (row + r < d.Cout) a.y_planar[(size_t)(row + r) * P + col] = acc[i][j][r] + a.bias[row + r];
       }
-    } else if (MODE == MODE_BWD_DATA) {
-      if (col >= (long long)d.Hin * d.Win || mrow >= d.Cin) continue;
-      *reinterpret_cast<float4 *>(a.dx + col * d.Cin + mrow) =
-          make_float4(acc[nb][0], acc[nb][1], acc[nb][2], acc[nb][3]);
-    } else {
-      if (col >= d.Kf) continue;
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (mrow + r < d.Cout && acc[nb][r] != 0.f)
-          atomicAdd(&a.dw[(size_t)(mrow + r) * d.Kf + col], acc[nb][r]);
     }
   }
 }
 
-// dL/dbias[co] = sum over output pixels of dZ[p][co]; grid (pixel slices,
-// 64-channel blocks), atomics across slices
-__global__ void __launch_bounds__(256)
-k_bias_grad(ConvDims d, const float *__restrict__ dy, const uint16_t *__restrict__ yact,
-            float *__restrict__ db) {
-  __shared__ float red[4][64];
-  const int cl = threadIdx.x & 63, part = threadIdx.x >> 6;
-  const int co = blockIdx.y * 64 + cl;
-  const long long P = (long long)d.Hout * d.Wout;
-  float s = 0.f;
-  if (co < d.Cout) {
-    for (long long p = blockIdx.x * 4 + part; p < P; p += (long long)gridDim.x * 4) {
-      float v = dy[p * d.CoutS + co];
-      if (d.relu && !(bf2f(yact[p * d.Cout + co]) > 0.f)) v = 0.f;
-      s += v;
+// ------------------------------------------------------------ grad input --
+// Parity class c of a stride-2 layer: (py, px) = pixel parities, in order of
+// decreasing K: (1,1) 4 taps, (1,0) 2, (0,1) 2, (0,0) 1.  Stride 1: one class
+// with all 9 taps.  Class pixel (yy, xx) is input pixel (s yy + py, s xx + px);
+// its j-th tap is (ty, tx) with ty = py ? 2 jy : 1 (stride 2) or jy (stride 1).
+struct ParityClass {
+  int py, px, nty, ntx, Hc, Wc;
+};
+__device__ __forceinline__ ParityClass parity_class(const ConvDims &d, int c) {
+  ParityClass k;
+  if (d.stride == 1) {
+    k.py = k.px = 0;
+    k.nty = k.ntx = 3;
+    k.Hc = d.Hin;
+    k.Wc = d.Win;
+  } else {
+    k.py = (c < 2) ? 1 : 0;
+    k.px = (c == 0 || c == 2) ? 1 : 0;
+    k.nty = k.py ? 2 : 1;
+    k.ntx = k.px ? 2 : 1;
+    k.Hc = (d.Hin - k.py + 1) / 2;
+    k.Wc = (d.Win - k.px + 1) / 2;
+  }
+  return k;
+}
+
+// Workgroup tile 64 (Cin) x 32 WN (class pixels), staging as the forward.
+template <int WN>
+__global__ void __launch_bounds__(256) k_conv_bwd_data(ConvArgs a) {
+  constexpr int BN = 32 * WN;
+  __shared__ __attribute__((aligned(16))) uint16_t As[64 * LP];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[BN * LP];
+  const ConvDims &d = a.d;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  int c = 0;
+  while (c + 1 < a.ncls && (int)blockIdx.x >= a.cls_tile0[c + 1]) ++c;
+  const ParityClass pc = parity_class(d, c);
+  const long long Pc = (long long)pc.Hc * pc.Wc;
+  const long long n0 = (long long)(blockIdx.x - a.cls_tile0[c]) * BN;
+  const int m0 = blockIdx.y * 64;
+  const int K = pc.nty * pc.ntx * d.CoutS;
+  const int ar = tid >> 2, ak = (tid & 3) * 8;
+  const bool arow_ok = m0 + ar < d.Cin;
+  const uint16_t *wrow = a.wt + (size_t)(arow_ok ? m0 + ar : 0) * d.Kb;
+  const int br = tid >> 3, bk = (tid & 7) * 8;
+  int yb[WN], xb[WN];
+  bool pv[WN];
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const long long q = n0 + br + 32 * j;
+    pv[j] = q < Pc;
+    const int yy = pv[j] ? (int)(q / pc.Wc) : 0, xx = pv[j] ? (int)(q - (long long)yy * pc.Wc) : 0;
+    yb[j] = yy * d.stride + pc.py + 1;  // y + 1
+    xb[j] = xx * d.stride + pc.px + 1;
+  }
+  auto tap_of = [&](int jt, int &ty, int &tx) {
+    const int jy = jt / pc.ntx, jx = jt - jy * pc.ntx;
+    ty = (d.stride == 1) ? jy : (pc.py ? 2 * jy : 1);
+    tx = (d.stride == 1) ? jx : (pc.px ? 2 * jx : 1);
+  };
+  uint4 ra[2], rb[WN];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int k = k0 + ak + 32 * h;
+      ra[h] = make_uint4(0, 0, 0, 0);
+      if (arow_ok && k < K) {
+        const int jt = k / d.CoutS, co = k - jt * d.CoutS;
+        int ty, tx;
+        tap_of(jt, ty, tx);
+        ra[h] = *reinterpret_cast<const uint4 *>(wrow + (ty * 3 + tx) * d.CoutS + co);
+      }
+    }
+    const int k = k0 + bk;
+    const int jt = k / d.CoutS, co = k - jt * d.CoutS;
+    int ty, tx;
+    tap_of(jt, ty, tx);
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      rb[j] = make_uint4(0, 0, 0, 0);
+      // output pixel (oy, ox) with s oy = y + 1 - ty (exact by the class choice)
+      const int oy2 = yb[j] - ty, ox2 = xb[j] - tx;
+      if (pv[j] && k < K && oy2 >= 0 && ox2 >= 0) {
+        const int oy = oy2 / d.stride, ox = ox2 / d.stride;
+        if (oy < d.Hout && ox < d.Wout)
+          rb[j] = *reinterpret_cast<const uint4 *>(a.dz + ((size_t)oy * d.Wout + ox) * d.CoutS + co);
+      }
+    }
+  };
+  floatx4 acc[2][WN];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int wm = w & 1, wn = w >> 1;
+  load(0);
+  // the epilogue's output pixels and their ReLU masks (the previous layer's
+  // output), fetched now so that the loads overlap the K loop
+  size_t po[WN];
+  uint2 mask[2][WN];
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const long long q = n0 + 16 * WN * wn + 16 * j + (lane & 15);
+    po[j] = ~(size_t)0;
+    if (q < Pc) {
+      const int yy = (int)(q / pc.Wc), xx = (int)(q - (long long)yy * pc.Wc);
+      po[j] = (size_t)(yy * d.stride + pc.py) * d.Win + (xx * d.stride + pc.px);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int ci = m0 + 32 * wm + 16 * i + 4 * (lane >> 4);
+      mask[i][j] = (po[j] != ~(size_t)0 && ci < d.Cin)
+                       ? *reinterpret_cast<const uint2 *>(a.x + po[j] * d.Cin + ci)
+                       : make_uint2(0, 0);
     }
   }
-  red[part][cl] = s;
-  __syncthreads();
-  if (part == 0 && co < d.Cout) {
-    const float t = red[0][cl] + red[1][cl] + red[2][cl] + red[3][cl];
-    if (t != 0.f) atomicAdd(&db[co], t);
+  for (int k0 = 0; k0 < K; k0 += KS) {
+    __syncthreads();
+    *reinterpret_cast<uint4 *>(As + ar * LP + ak) = ra[0];
+    *reinterpret_cast<uint4 *>(As + ar * LP + ak + 32) = ra[1];
+#pragma unroll
+    for (int j = 0; j < WN; ++j) *reinterpret_cast<uint4 *>(Bs + (br + 32 * j) * LP + bk) = rb[j];
+    __syncthreads();
+    if (k0 + KS < K) load(k0 + KS);
+    mfma_step<2, WN, LP>(As + 32 * wm * LP, Bs + 16 * WN * wn * LP, 0, lane, acc);
+    if (k0 + 32 < K) mfma_step<2, WN, LP>(As + 32 * wm * LP, Bs + 16 * WN * wn * LP, 32, lane, acc);
+  }
+  // dZ of the previous layer = dL/dx masked by its ReLU' (x > 0), as BF16
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int ci = m0 + 32 * wm + 16 * i + 4 * (lane >> 4);
+    if (ci >= d.Cin) continue;
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      if (po[j] == ~(size_t)0) continue;
+      const uint16_t *mb = reinterpret_cast<const uint16_t *>(&mask[i][j]);
+      uint16_t o[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) o[r] = f2bf(bf2f(mb[r]) > 0.f ? acc[i][j][r] : 0.f);
+      *reinterpret_cast<uint2 *>(a.dz_prev + po[j] * d.Cin + ci) = *reinterpret_cast<uint2 *>(o);
+    }
+  }
+}
+
+// ----------------------------------------------------------- grad weight --
+__device__ __forceinline__ uint32_t u4_at(const uint4 &u, int i) {
+  return i == 0 ? u.x : i == 1 ? u.y : i == 2 ? u.z : u.w;
+}
+
+// Workgroup tile 64 (Cout) x 64 (tap, Cin) over a range of ksplit output
+// pixels, PS per stage; waves 2 x 2, each 32 x 32; the tile goes to gpart.  Threads 0..127 stage A
+// (dZ), 128..255 stage B (the input gathered at the tile's tap); thread
+// chunk: 8 channels (group g = c >> 4) x 8 pixels (group q = c & 15).  The
+// 1D grid is ordered so that the N tiles of one pixel range are consecutive
+// work items on one XCD (workgroup b runs on XCD b % 8): dZ of that range is
+// fetched into one L2.
+__global__ void __launch_bounds__(256) k_conv_bwd_weight(ConvArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[64 * LPW];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * LPW];
+  const ConvDims &d = a.d;
+  const int per_xcd = (int)(gridDim.x >> 3);
+  const int work = (int)(blockIdx.x & 7) * per_xcd + (int)(blockIdx.x >> 3);
+  if (work >= a.nwork) return;
+  const int ntm = d.Mpad / 64;
+  const int nt = work % a.ntile_n, mt = (work / a.ntile_n) % ntm, split = work / (a.ntile_n * ntm);
+  const int m0 = mt * 64, n0 = nt * 64;
+  const long long P = (long long)d.Hout * d.Wout;
+  const long long kbeg = (long long)split * a.ksplit, kend = min(P, kbeg + a.ksplit);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const bool isA = tid < 128;
+  const int ch = tid & 127, q = ch & 15, g = ch >> 4;
+  // A: channels co0 .. co0 + 7 of dZ; B: columns n .. n + 7 = one tap, 8 channels
+  const int co0 = m0 + 8 * g;
+  const int n = n0 + 8 * g, tap = n / d.Cin, ci = n - tap * d.Cin;
+  const int ty = tap / 3, tx = tap - 3 * ty;
+  const bool colok = isA ? (co0 < d.CoutS) : (n < d.Kf && tap < 9);
+  const bool do_bias = isA && nt == 0;
+  uint4 v[8];
+  auto load = [&](long long k0) {
+    const long long p0 = k0 + 8 * q;
+    if (isA) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const long long p = p0 + j;
+        v[j] = (colok && p < kend)
+                   ? *reinterpret_cast<const uint4 *>(a.dz + p * d.CoutS + co0)
+                   : make_uint4(0, 0, 0, 0);
+      }
+    } else {
+      int oy = (int)(min(p0, P - 1) / d.Wout);
+      int ox = (int)(min(p0, P - 1) - (long long)oy * d.Wout);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        v[j] = make_uint4(0, 0, 0, 0);
+        const int iy = oy * d.stride + ty - 1, ix = ox * d.stride + tx - 1;
+        if (colok && p0 + j < kend && iy >= 0 && iy < d.Hin && ix >= 0 && ix < d.Win)
+          v[j] = *reinterpret_cast<const uint4 *>(a.x + ((size_t)iy * d.Win + ix) * d.Cin + ci);
+        if (++ox == d.Wout) {
+          ox = 0;
+          ++oy;
+        }
+      }
+    }
+  };
+  float bsum[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) bsum[r] = 0.f;
+  floatx4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int wm = w & 1, wn = w >> 1;
+  uint16_t *dst = (isA ? As : Bs) + 8 * g * LPW + 8 * q;
+  load(kbeg);
+  for (long long k0 = kbeg; k0 < kend; k0 += PS) {
+    __syncthreads();
+    // 8 x 8 transpose: row 2i + (0|1) of channel pair i = the even / odd
+    // halves of dword i of the 8 pixels
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      uint32_t lo[4], hi[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t e = u4_at(v[2 * j], i), o = u4_at(v[2 * j + 1], i);
+        lo[j] = (e & 0xFFFFu) | (o << 16);
+        hi[j] = (e >> 16) | (o & 0xFFFF0000u);
+      }
+      *reinterpret_cast<uint4 *>(dst + (2 * i) * LPW) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+      *reinterpret_cast<uint4 *>(dst + (2 * i + 1) * LPW) = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+      if (do_bias) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          bsum[2 * i] += __uint_as_float(lo[j] << 16) + __uint_as_float(lo[j] & 0xFFFF0000u);
+          bsum[2 * i + 1] += __uint_as_float(hi[j] << 16) + __uint_as_float(hi[j] & 0xFFFF0000u);
+        }
+      }
+    }
+    __syncthreads();
+    if (k0 + PS < kend) load(k0 + PS);
+    const int nsub = (int)min((long long)(PS / 32), (kend - k0 + 31) / 32);
+#pragma unroll
+    for (int s = 0; s < PS / 32; ++s)
+      if (s < nsub) mfma_step<2, 2, LPW>(As + 32 * wm * LPW, Bs + 32 * wn * LPW, 32 * s, lane, acc);
+  }
+  if (do_bias) {  // lanes 16 k .. 16 k + 15 share the channel group
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      float s = bsum[r];
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      s += __shfl_xor(s, 4, 64);
+      s += __shfl_xor(s, 8, 64);
+      if (q == 0) a.bpart[((size_t)split * ntm + mt) * 64 + 8 * g + r] = s;
+    }
+  }
+  // partial tile, column-major: the 4 rows a lane holds are contiguous
+  float *pt = a.gpart + (size_t)work * 4096;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int row = 32 * wm + 16 * i + 4 * (lane >> 4);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = 32 * wn + 16 * j + (lane & 15);
+      *reinterpret_cast<float4 *>(pt + col * 64 + row) =
+          make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+    }
+  }
+}
+
+// Sum of the grad-weight partial tiles over the pixel splits, added into dW
+// (and the bias partials into dbias).  Grid x: 16 workgroups per 64 x 64
+// tile (one element per thread), then one per M tile for the bias; grid y:
+// chunks of GW_CHUNK splits, combined with FP32 atomics.
+constexpr int GW_CHUNK = 32;
+__global__ void __launch_bounds__(256)
+k_gw_reduce(ConvDims d, int splits, int ntile_n, const float *__restrict__ gpart,
+            const float *__restrict__ bpart, float *__restrict__ dw, float *__restrict__ db) {
+  const int ntm = d.Mpad / 64, tiles = ntile_n * ntm;
+  const int s0 = blockIdx.y * GW_CHUNK, s1 = min(splits, s0 + GW_CHUNK);
+  const int tid = threadIdx.x;
+  if ((int)blockIdx.x < 16 * tiles) {
+    const int tile = blockIdx.x >> 4, e = (blockIdx.x & 15) * 256 + tid;
+    const int row = (tile / ntile_n) * 64 + (e & 63), col = (tile % ntile_n) * 64 + (e >> 6);
+    if (row >= d.Cout || col >= d.Kf) return;
+    const float *src = gpart + (size_t)tile * 4096 + e;
+    float sum = 0.f;
+#pragma unroll 8
+    for (int sp = s0; sp < s1; ++sp) sum += src[(size_t)sp * tiles * 4096];
+    if (sum != 0.f) atomicAdd(&dw[(size_t)row * d.Kf + col], sum);
+  } else {
+    const int mt = blockIdx.x - 16 * tiles, co = mt * 64 + tid;
+    if (tid >= 64 || co >= d.Cout) return;
+    float sum = 0.f;
+#pragma unroll 8
+    for (int sp = s0; sp < s1; ++sp) sum += bpart[((size_t)sp * ntm + mt) * 64 + tid];
+    if (sum != 0.f) atomicAdd(&db[co], sum);
   }
 }
 
@@ -274,81 +521,106 @@ k_cnn_input(int H, int W, const float *__restrict__ frame, const float *__restri
 __device__ inline float sigm(float z) { return 1.f / (1.f + __expf(-z)); }
 
 // Per-tile loss: CE over the 9 count logits + Chamfer between the first k
-// slots and the k targets (8-vectors); gradients into dhead, channels-last
-// [n_tiles][CoutS].  Partial loss sums per tile go to tile_loss (CE, CD).
+// slots and the k targets (8-vectors).  16 lanes per tile: lane c < 9 holds
+// count logit c, lane s < 8 holds prediction slot s and target s.  The head
+// gradient goes out as dZ of the head (BF16 [n_tiles][CoutS]); per-tile loss
+// sums to tile_loss (CE, CD).
 __global__ void __launch_bounds__(256)
 k_head_loss(int n_tiles, int CoutS, const float *__restrict__ head, const int *__restrict__ tcount,
-            const float *__restrict__ tvec, const int *__restrict__ n_cd_dev, float *__restrict__ dhead,
-            float *__restrict__ tile_loss) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_tiles) return;
+            const float *__restrict__ tvec, const int *__restrict__ n_cd_dev,
+            uint16_t *__restrict__ dz, float *__restrict__ tile_loss) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = gid >> 4, l = gid & 15, base = threadIdx.x & 48;  // group's first lane in the wave
+  const bool live = t < n_tiles;
+  const int tt = live ? t : 0;
   const float inv_tiles = 1.f / (float)n_tiles;
   const int n_cd = max(1, *n_cd_dev);
-  float z[9], g[HEAD_CH];
-  for (int c = 0; c < HEAD_CH; ++c) g[c] = 0.f;
-  float mx = -INFINITY;
-  for (int c = 0; c < 9; ++c) {
-    z[c] = head[(size_t)c * n_tiles + t];
-    mx = fmaxf(mx, z[c]);
-  }
-  float se = 0.f;
-  for (int c = 0; c < 9; ++c) se += __expf(z[c] - mx);
-  const int k = min(max(tcount[t], 0), NSLOT);
+  const int k = min(max(tcount[tt], 0), NSLOT);
+  // cross entropy of the count logits
+  const float z = (l < 9) ? head[(size_t)l * n_tiles + tt] : -INFINITY;
+  float mx = z;
+  for (int o = 1; o < 16; o <<= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+  float se = (l < 9) ? __expf(z - mx) : 0.f;
+  for (int o = 1; o < 16; o <<= 1) se += __shfl_xor(se, o, 64);
   const float lse = mx + __logf(se);
-  const float ce = lse - z[k];
-  for (int c = 0; c < 9; ++c) g[c] = (__expf(z[c] - lse) - (c == k ? 1.f : 0.f)) * inv_tiles;
-  float cd = 0.f;
-  if (k > 0) {
-    float P[NSLOT][NPAR], Q[NSLOT][NPAR], raw01[NSLOT][2];
-    for (int s = 0; s < k; ++s)
-      for (int j = 0; j < NPAR; ++j) {
-        const float r = head[(size_t)(9 + s * NPAR + j) * n_tiles + t];
-        if (j < 2) raw01[s][j] = r;
-        P[s][j] = (j < 2) ? sigm(r) : r;
-        Q[s][j] = tvec[((size_t)t * NSLOT + s) * NPAR + j];
-      }
-    float gp[NSLOT][NPAR];
-    for (int s = 0; s < k; ++s)
-      for (int j = 0; j < NPAR; ++j) gp[s][j] = 0.f;
-    const float inv_k = 1.f / (float)k;
-    // predictions -> nearest target; targets -> nearest prediction
-    for (int s = 0; s < k; ++s) {
-      int best = 0;
-      float bd = INFINITY;
-      for (int q = 0; q < k; ++q) {
-        float dd = 0.f;
-        for (int j = 0; j < NPAR; ++j) dd += (P[s][j] - Q[q][j]) * (P[s][j] - Q[q][j]);
-        if (dd < bd) bd = dd, best = q;
-      }
-      cd += bd * inv_k;
-      for (int j = 0; j < NPAR; ++j) gp[s][j] += 2.f * (P[s][j] - Q[best][j]) * inv_k;
-    }
-    for (int q = 0; q < k; ++q) {
-      int best = 0;
-      float bd = INFINITY;
-      for (int s = 0; s < k; ++s) {
-        float dd = 0.f;
-        for (int j = 0; j < NPAR; ++j) dd += (P[s][j] - Q[q][j]) * (P[s][j] - Q[q][j]);
-        if (dd < bd) bd = dd, best = s;
-      }
-      cd += bd * inv_k;
-      for (int j = 0; j < NPAR; ++j) gp[best][j] += 2.f * (P[best][j] - Q[q][j]) * inv_k;
-    }
-    const float sc = 1.f / (float)n_cd;
-    for (int s = 0; s < k; ++s)
-      for (int j = 0; j < NPAR; ++j) {
-        float v = gp[s][j] * sc;
-        if (j < 2) {
-          const float sg = sigm(raw01[s][j]);
-          v *= sg * (1.f - sg);
-        }
-        g[9 + s * NPAR + j] = v;
-      }
+  const float zk = __shfl(z, base + k, 64);
+  const float ce = lse - zk;
+  const float gce = (l < 9) ? (__expf(z - lse) - (l == k ? 1.f : 0.f)) * inv_tiles : 0.f;
+  // Chamfer: predictions P (sigmoid on the two offsets), targets Q
+  const int s = l & 7;
+  float Pv[NPAR], Qv[NPAR], raw[2];
+#pragma unroll
+  for (int j = 0; j < NPAR; ++j) {
+    const float r = head[(size_t)(9 + s * NPAR + j) * n_tiles + tt];
+    if (j < 2) raw[j] = r;
+    Pv[j] = (j < 2) ? sigm(r) : r;
+    Qv[j] = tvec[((size_t)tt * NSLOT + s) * NPAR + j];
   }
-  for (int c = 0; c < HEAD_CH; ++c) dhead[(size_t)t * CoutS + c] = g[c];
-  for (int c = HEAD_CH; c < CoutS; ++c) dhead[(size_t)t * CoutS + c] = 0.f;
-  tile_loss[2 * t] = ce;
-  tile_loss[2 * t + 1] = cd;
+  const float inv_k = k > 0 ? 1.f / (float)k : 0.f;
+  // prediction s -> nearest target (first minimum)
+  float bd = INFINITY, Qb[NPAR];
+#pragma unroll
+  for (int j = 0; j < NPAR; ++j) Qb[j] = 0.f;
+  for (int qq = 0; qq < NSLOT; ++qq) {
+    float Qq[NPAR], dd = 0.f;
+#pragma unroll
+    for (int j = 0; j < NPAR; ++j) {
+      Qq[j] = __shfl(Qv[j], base + qq, 64);
+      dd += (Pv[j] - Qq[j]) * (Pv[j] - Qq[j]);
+    }
+    if (qq < k && dd < bd) {
+      bd = dd;
+#pragma unroll
+      for (int j = 0; j < NPAR; ++j) Qb[j] = Qq[j];
+    }
+  }
+  // target s -> nearest prediction (first minimum)
+  float bd2 = INFINITY;
+  int best2 = 0;
+  for (int ss = 0; ss < NSLOT; ++ss) {
+    float dd = 0.f;
+#pragma unroll
+    for (int j = 0; j < NPAR; ++j) {
+      const float Ps = __shfl(Pv[j], base + ss, 64);
+      dd += (Ps - Qv[j]) * (Ps - Qv[j]);
+    }
+    if (ss < k && dd < bd2) bd2 = dd, best2 = ss;
+  }
+  const bool own = l < 8 && s < k;
+  float cd = own ? (bd + bd2) * inv_k : 0.f;
+  for (int o = 1; o < 16; o <<= 1) cd += __shfl_xor(cd, o, 64);
+  float gp[NPAR];
+#pragma unroll
+  for (int j = 0; j < NPAR; ++j) gp[j] = 2.f * (Pv[j] - Qb[j]) * inv_k;
+  for (int qq = 0; qq < NSLOT; ++qq) {  // targets whose nearest prediction is s
+    const int b = __shfl(best2, base + qq, 64);
+#pragma unroll
+    for (int j = 0; j < NPAR; ++j) {
+      const float Qq = __shfl(Qv[j], base + qq, 64);
+      if (qq < k && b == s) gp[j] += 2.f * (Pv[j] - Qq) * inv_k;
+    }
+  }
+  if (!live) return;
+  uint16_t *out = dz + (size_t)t * CoutS;
+  if (l < 9) out[l] = f2bf(gce);
+  if (l < 8) {
+    const float sc = 1.f / (float)n_cd;
+#pragma unroll
+    for (int j = 0; j < NPAR; ++j) {
+      float v = own ? gp[j] * sc : 0.f;
+      if (j < 2) {
+        const float sg = sigm(raw[j]);
+        v *= sg * (1.f - sg);
+      }
+      out[9 + s * NPAR + j] = f2bf(v);
+    }
+  }
+  if (l == 15)
+    for (int c = HEAD_CH; c < CoutS; ++c) out[c] = 0;
+  if (l == 0) {
+    tile_loss[2 * t] = ce;
+    tile_loss[2 * t + 1] = cd;
+  }
 }
 
 __global__ void __launch_bounds__(256)
@@ -362,14 +634,15 @@ k_count_target_tiles(int n_tiles, const int *__restrict__ tcount, int *__restric
   if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
 }
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
 k_loss_sum(int n_tiles, const float *__restrict__ tile_loss, const int *__restrict__ n_cd_dev,
            float *__restrict__ out) {
-  __shared__ double red[2][4];
+  __shared__ double red[2][16];
   double ce = 0.0, cd = 0.0;
-  for (int t = threadIdx.x; t < n_tiles; t += 256) {
-    ce += tile_loss[2 * t];
-    cd += tile_loss[2 * t + 1];
+  for (int t = threadIdx.x; t < n_tiles; t += 1024) {
+    const float2 v = *reinterpret_cast<const float2 *>(tile_loss + 2 * t);
+    ce += v.x;
+    cd += v.y;
   }
   for (int o = 32; o > 0; o >>= 1) {
     ce += __shfl_xor(ce, o, 64);
@@ -381,8 +654,11 @@ k_loss_sum(int n_tiles, const float *__restrict__ tile_loss, const int *__restri
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double c1 = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    const double c2 = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    double c1 = 0.0, c2 = 0.0;
+    for (int w = 0; w < 16; ++w) {
+      c1 += red[0][w];
+      c2 += red[1][w];
+    }
     const int n_cd = *n_cd_dev;
     out[0] = (float)(c1 / n_tiles + (n_cd > 0 ? c2 / n_cd : 0.0));
     out[1] = (float)(c1 / n_tiles);
@@ -393,6 +669,24 @@ k_loss_sum(int n_tiles, const float *__restrict__ tile_loss, const int *__restri
 }  // namespace
 
 // ------------------------------------------------------------ layout ----
+// Grad-weight work split: about 1024 workgroups (split x tile), each over a
+// multiple of PS and at least GW_MIN_PIX output pixels.
+struct GwSplit {
+  int ntile_n, tiles, ksplit, splits;
+};
+static GwSplit gw_split(const ConvDims &d) {
+  GwSplit g;
+  const long long P = (long long)d.Hout * d.Wout;
+  g.ntile_n = (d.Kf + 63) / 64;
+  g.tiles = g.ntile_n * (d.Mpad / 64);
+  const long long want = std::max(1, 1024 / g.tiles);
+  long long ks = (P + want - 1) / want;
+  ks = std::max<long long>(GW_MIN_PIX, (ks + PS - 1) / PS * PS);
+  g.ksplit = (int)ks;
+  g.splits = (int)((P + ks - 1) / ks);
+  return g;
+}
+
 struct CnnLayout {
   int H, W;
   ConvDims L[NLAYER];
@@ -400,7 +694,7 @@ struct CnnLayout {
   size_t wb_off[NLAYER], n_wb;                    // bf16 weight offsets (elements)
   size_t wt_off[NLAYER], n_wt;                    // bf16 transposed weights (elements)
   // workspace (bytes)
-  size_t x_in, act[NLAYER], head, dhead, dact[NLAYER], tcount, tvec, tile_loss, ncd, total;
+  size_t x_in, act[NLAYER], head, dz[NLAYER], gpart, bpart, tcount, tvec, tile_loss, ncd, total;
   int TX, TY, n_tiles;
 };
 
@@ -423,10 +717,10 @@ static bool cnn_layout(int H, int W, CnnLayout *C) {
     d.Wout = (w + 2 - 3) / d.stride + 1;
     d.Cout = head ? HEAD_CH : 64;
     d.relu = head ? 0 : 1;
-    d.Mpad = (d.Cout + BM - 1) / BM * BM;
-    d.Kf = (9 * d.Cin + BK - 1) / BK * BK;
+    d.Mpad = (d.Cout + 63) / 64 * 64;
+    d.Kf = (9 * d.Cin + KPAD - 1) / KPAD * KPAD;
     d.CoutS = (d.Cout + 7) / 8 * 8;
-    d.Kb = (9 * d.CoutS + BK - 1) / BK * BK;
+    d.Kb = (9 * d.CoutS + KPAD - 1) / KPAD * KPAD;
     C->w_off[i] = pw;
     pw += (size_t)d.Mpad * d.Kf;
     C->b_off[i] = pw;
@@ -458,12 +752,16 @@ static bool cnn_layout(int H, int W, CnnLayout *C) {
     C->act[i] = (i < NLAYER - 1) ? take((size_t)d.Hout * d.Wout * d.Cout * 2) : 0;
   }
   C->head = take((size_t)HEAD_CH * C->n_tiles * 4);
-  C->dhead = take((size_t)C->n_tiles * hd.CoutS * 4);
-  for (int i = 0; i < NLAYER; ++i) {
+  size_t gp = 0, bp = 0;
+  for (int i = 0; i < NLAYER; ++i) {  // dZ of every layer's output, BF16
     const ConvDims &d = C->L[i];
-    // gradient w.r.t. the input of layer i (not needed for layer 0)
-    C->dact[i] = (i > 0) ? take((size_t)d.Hin * d.Win * d.Cin * 4) : 0;
+    C->dz[i] = take((size_t)d.Hout * d.Wout * d.CoutS * 2);
+    const GwSplit g = gw_split(d);
+    gp = std::max(gp, (size_t)g.splits * g.tiles * 4096 * 4);
+    bp = std::max(bp, (size_t)g.splits * (d.Mpad / 64) * 64 * 4);
   }
+  C->gpart = take(gp);
+  C->bpart = take(bp);
   C->tcount = take((size_t)C->n_tiles * 4);
   C->tvec = take((size_t)C->n_tiles * NSLOT * NPAR * 4);
   C->tile_loss = take((size_t)C->n_tiles * 2 * 4);
@@ -472,20 +770,66 @@ static bool cnn_layout(int H, int W, CnnLayout *C) {
   return true;
 }
 
-static hipError_t conv_launch(int mode, const ConvArgs &a, hipStream_t st) {
+// Pixel tile 32 WN: the widest that still gives >= min_blocks workgroups.
+static int pick_wn(long long pixels, int mtiles, long long min_blocks) {
+  for (int wn = 4; wn > 1; wn >>= 1)
+    if ((pixels + 32 * wn - 1) / (32 * wn) * mtiles >= min_blocks) return wn;
+  return 1;
+}
+
+// Forward: 64-pixel tiles where they still give >= 2000 workgroups, else
+// 32 (measured at 1080p: 128-pixel tiles are slower on every layer).
+static hipError_t launch_conv_fwd(const ConvArgs &a, hipStream_t st) {
   const ConvDims &d = a.d;
-  if (mode == MODE_FWD) {
-    dim3 g((unsigned)((d.Hout * (long long)d.Wout + BN - 1) / BN), (unsigned)(d.Mpad / BM));
-    hipLaunchKernelGGL(k_conv_gemm<MODE_FWD>, g, dim3(256), 0, st, a);
-  } else if (mode == MODE_BWD_DATA) {
-    dim3 g((unsigned)((d.Hin * (long long)d.Win + BN - 1) / BN), (unsigned)((d.Cin + BM - 1) / BM));
-    hipLaunchKernelGGL(k_conv_gemm<MODE_BWD_DATA>, g, dim3(256), 0, st, a);
-  } else {
-    const long long P = (long long)d.Hout * d.Wout;
-    const int splits = (int)((P + a.ksplit - 1) / a.ksplit);
-    dim3 g((unsigned)((d.Kf + BN - 1) / BN), (unsigned)((d.CoutS + BM - 1) / BM), (unsigned)splits);
-    hipLaunchKernelGGL(k_conv_gemm<MODE_BWD_WEIGHT>, g, dim3(256), 0, st, a);
+  const long long P = (long long)d.Hout * d.Wout;
+  const int mt = d.Mpad / 64, wn = std::min(2, pick_wn(P, mt, 2000));
+  const dim3 g((unsigned)((P + 32 * wn - 1) / (32 * wn)), (unsigned)mt);
+  if (wn == 4) hipLaunchKernelGGL(k_conv_fwd<4>, g, dim3(256), 0, st, a);
+  else if (wn == 2) hipLaunchKernelGGL(k_conv_fwd<2>, g, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(k_conv_fwd<1>, g, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// Grad input: the parity classes' tiles are concatenated along grid x in
+// the class order of parity_class (largest K first).
+static hipError_t launch_conv_bwd_data(ConvArgs a, hipStream_t st) {
+  const ConvDims &d = a.d;
+  const int mt = (d.Cin + 63) / 64, wn = pick_wn((long long)d.Hin * d.Win, mt, 1000);
+  const long long bn = 32 * wn;
+  a.ncls = d.stride == 2 ? 4 : 1;
+  long long tiles = 0;
+  for (int c = 0; c < a.ncls; ++c) {
+    long long px;
+    if (d.stride == 2) {
+      const int py = c < 2 ? 1 : 0, pxp = (c == 0 || c == 2) ? 1 : 0;
+      px = (long long)((d.Hin - py + 1) / 2) * ((d.Win - pxp + 1) / 2);
+    } else {
+      px = (long long)d.Hin * d.Win;
+    }
+    a.cls_tile0[c] = (int)tiles;
+    tiles += (px + bn - 1) / bn;
   }
+  a.cls_tile0[a.ncls] = (int)tiles;
+  if (tiles == 0) return hipSuccess;
+  const dim3 g((unsigned)tiles, (unsigned)mt);
+  if (wn == 4) hipLaunchKernelGGL(k_conv_bwd_data<4>, g, dim3(256), 0, st, a);
+  else if (wn == 2) hipLaunchKernelGGL(k_conv_bwd_data<2>, g, dim3(256), 0, st, a);
+  else hipLaunchKernelGGL(k_conv_bwd_data<1>, g, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// Grad weight: partial tiles (gw_split), then their sum into dw / db.
+static hipError_t launch_conv_bwd_weight(ConvArgs a, float *dw, float *db, hipStream_t st) {
+  const ConvDims &d = a.d;
+  const GwSplit g = gw_split(d);
+  a.ntile_n = g.ntile_n;
+  a.ksplit = g.ksplit;
+  a.nwork = g.splits * g.tiles;
+  const unsigned grid = (unsigned)((a.nwork + 7) / 8 * 8);
+  hipLaunchKernelGGL(k_conv_bwd_weight, dim3(grid), dim3(256), 0, st, a);
+  const dim3 rg((unsigned)(16 * g.tiles + d.Mpad / 64), (unsigned)((g.splits + GW_CHUNK - 1) / GW_CHUNK));
+  hipLaunchKernelGGL(k_gw_reduce, rg, dim3(256), 0, st, d, g.splits, g.ntile_n, a.gpart, a.bpart,
+                     dw, db);
   return hipGetLastError();
 }
 
@@ -508,10 +852,22 @@ k_cnn_weights_to_bf16(ConvDims d, const float *__restrict__ wm, uint16_t *__rest
   }
 }
 
+// Where each layer's parameters live: FP32 master / gradient offsets
+// (weights [Mpad][Kf] then bias [Mpad]) and the BF16 copies.
+struct CnnParamMap {
+  ConvDims d[NLAYER];
+  long long w_off[NLAYER], b_off[NLAYER], wb_off[NLAYER], wt_off[NLAYER];
+};
+
+// Adam with decoupled weight decay on the FP32 master weights; each updated
+// weight is written to its BF16 copies in the same pass (forward layout, and
+// for the layers whose input gradient is needed the transposed one, whose
+// padding keeps the zeros of the last full conversion).
 __global__ void __launch_bounds__(256)
-k_cnn_adam(size_t n, float *__restrict__ p, float *__restrict__ g, float *__restrict__ m,
-           float *__restrict__ v, const int32_t *__restrict__ step, float lr, float b1, float b2,
-           float eps, float wd) {
+k_cnn_adam(size_t n, CnnParamMap map, float *__restrict__ p, float *__restrict__ g,
+           float *__restrict__ m, float *__restrict__ v, const int32_t *__restrict__ step,
+           float lr, float b1, float b2, float eps, float wd, uint16_t *__restrict__ wb,
+           uint16_t *__restrict__ wt) {
   __shared__ float s_bc1, s_bc2;
   if (threadIdx.x == 0) {
     const int t = step[0];
@@ -528,7 +884,22 @@ k_cnn_adam(size_t n, float *__restrict__ p, float *__restrict__ g, float *__rest
     const float vv = b2 * v[i] + (1.f - b2) * gr * gr;
     m[i] = mm;
     v[i] = vv;
-    p[i] -= lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+    const float pn = p[i] - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+    p[i] = pn;
+    int l = 0;
+#pragma unroll
+    for (int j = 1; j < NLAYER; ++j)
+      if ((long long)i >= map.w_off[j]) l = j;
+    if ((long long)i >= map.b_off[l]) continue;  // a bias
+    const ConvDims &d = map.d[l];
+    const long long e = (long long)i - map.w_off[l];
+    const int co = (int)(e / d.Kf), k = (int)(e - (long long)co * d.Kf);
+    const uint16_t b = f2bf(pn);
+    wb[map.wb_off[l] + e] = b;
+    if (l > 0 && co < d.Cout && k < 9 * d.Cin) {
+      const int tap = k / d.Cin, ci = k - tap * d.Cin;
+      wt[map.wt_off[l] + (long long)ci * d.Kb + tap * d.CoutS + co] = b;
+    }
   }
 }
 
@@ -819,7 +1190,7 @@ int gs2d_cnn_forward(int32_t H, int32_t W, const float *frame, const float *prev
     } else {
       a.y_planar = at<float>(ws, C.head);
     }
-    if (conv_launch(MODE_FWD, a, st) != hipSuccess) return GS2D_EHIP;
+    if (launch_conv_fwd(a, st) != hipSuccess) return GS2D_EHIP;
   }
   if (head_out &&
       hipMemcpyAsync(head_out, at<float>(ws, C.head), sizeof(float) * HEAD_CH * C.n_tiles,
@@ -894,35 +1265,28 @@ int gs2d_cnn_backward(int32_t H, int32_t W, const float *master, const uint16_t 
   if (ws_bytes < C.total) return GS2D_ENOSPACE;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const ConvDims &hd = C.L[NLAYER - 1];
-  hipLaunchKernelGGL(k_head_loss, dim3((C.n_tiles + 255) / 256), dim3(256), 0, st, C.n_tiles,
-                     hd.CoutS, at<const float>(ws, C.head), at<const int>(ws, C.tcount),
-                     at<const float>(ws, C.tvec), at<const int>(ws, C.ncd), at<float>(ws, C.dhead),
+  hipLaunchKernelGGL(k_head_loss, dim3((unsigned)((16LL * C.n_tiles + 255) / 256)), dim3(256), 0,
+                     st, C.n_tiles, hd.CoutS, at<const float>(ws, C.head),
+                     at<const int>(ws, C.tcount), at<const float>(ws, C.tvec),
+                     at<const int>(ws, C.ncd), at<uint16_t>(ws, C.dz[NLAYER - 1]),
                      at<float>(ws, C.tile_loss));
   if (loss3)
-    hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(256), 0, st, C.n_tiles,
+    hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(1024), 0, st, C.n_tiles,
                        at<const float>(ws, C.tile_loss), at<const int>(ws, C.ncd), loss3);
   const uint16_t *wt = wbf16 + C.n_wb;
-  const float *dy = at<const float>(ws, C.dhead);
   for (int i = NLAYER - 1; i >= 0; --i) {
-    const ConvDims &d = C.L[i];
     ConvArgs a = {};
-    a.d = d;
+    a.d = C.L[i];
     a.x = (i == 0) ? at<const uint16_t>(ws, C.x_in) : at<const uint16_t>(ws, C.act[i - 1]);
-    a.dy = dy;
-    a.yact = d.relu ? at<const uint16_t>(ws, C.act[i]) : nullptr;
-    a.dw = grad + C.w_off[i];
-    a.ksplit = 2048;
-    if (conv_launch(MODE_BWD_WEIGHT, a, st) != hipSuccess) return GS2D_EHIP;
-    const long long P = (long long)d.Hout * d.Wout;
-    hipLaunchKernelGGL(k_bias_grad,
-                       dim3((unsigned)std::min<long long>((P + 1023) / 1024, 1024),
-                            (unsigned)((d.Cout + 63) / 64)),
-                       dim3(256), 0, st, d, dy, a.yact, grad + C.b_off[i]);
+    a.dz = at<const uint16_t>(ws, C.dz[i]);
+    a.gpart = at<float>(ws, C.gpart);
+    a.bpart = at<float>(ws, C.bpart);
+    if (launch_conv_bwd_weight(a, grad + C.w_off[i], grad + C.b_off[i], st) != hipSuccess)
+      return GS2D_EHIP;
     if (i > 0) {
       a.wt = wt + C.wt_off[i];
-      a.dx = at<float>(ws, C.dact[i]);
-      if (conv_launch(MODE_BWD_DATA, a, st) != hipSuccess) return GS2D_EHIP;
-      dy = a.dx;
+      a.dz_prev = at<uint16_t>(ws, C.dz[i - 1]);
+      if (launch_conv_bwd_data(a, st) != hipSuccess) return GS2D_EHIP;
     }
   }
   return hipGetLastError() == hipSuccess ? GS2D_OK : GS2D_EHIP;
@@ -935,11 +1299,18 @@ int gs2d_cnn_adam(int32_t H, int32_t W, float *master, float *grad, float *m, fl
     return GS2D_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (launch_step_tick(step, st) != hipSuccess) return GS2D_EHIP;
+  CnnParamMap map;
+  for (int i = 0; i < NLAYER; ++i) {
+    map.d[i] = C.L[i];
+    map.w_off[i] = (long long)C.w_off[i];
+    map.b_off[i] = (long long)C.b_off[i];
+    map.wb_off[i] = (long long)C.wb_off[i];
+    map.wt_off[i] = (long long)C.wt_off[i];
+  }
   hipLaunchKernelGGL(k_cnn_adam, dim3((unsigned)std::min<size_t>((C.n_params + 255) / 256, 2048)),
-                     dim3(256), 0, st, C.n_params, master, grad, m, v, step, lr, 0.9f, 0.999f,
-                     1e-8f, weight_decay);
-  if (hipGetLastError() != hipSuccess) return GS2D_EHIP;
-  return gs2d_cnn_sync_weights(H, W, master, wbf16, stream);
+                     dim3(256), 0, st, C.n_params, map, master, grad, m, v, step, lr, 0.9f, 0.999f,
+                     1e-8f, weight_decay, wbf16, wbf16 + C.n_wb);
+  return hipGetLastError() == hipSuccess ? GS2D_OK : GS2D_EHIP;
 }
 
 int gs2d_cnn_decode(int32_t H, int32_t W, int32_t N, const float *plain_xy,

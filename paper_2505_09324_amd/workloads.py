@@ -352,9 +352,60 @@ def run_learned(train_seqs=34, frames_per_seq=60, max_samples=2000, epochs=6, ev
     }
 
 
+def cnn_conv_flops(H, W):
+    """Multiply-add FLOPs of the initialiser's convolutions for one H x W
+    frame, counting real channels only (6 input channels, 73 head outputs):
+    per layer 2 * Hout * Wout * Cout * 9 * Cin."""
+    out, h, w, cin = [], H, W, 6
+    for i in range(5):
+        s = 2 if i < 4 else 1
+        h, w = (h - 1) // s + 1, (w - 1) // s + 1
+        cout = 64 if i < 4 else 73
+        out.append(2.0 * h * w * cout * 9 * cin)
+        cin = cout
+    return out
+
+
+def run_cnn_step(steps=20, warmup=3, W=1920, H=1080, N=30000, seed=900, device="cuda"):
+    """Training steps of the initialiser on one synthetic frame pair and a
+    synthetic fitted-Gaussian target set: forward, loss + backward, Adam.
+    Times each phase with events on the stream the library launches on."""
+    f0, _ = synth.make_frame_torch(W, H, seed, 0, device)
+    f1, _ = synth.make_frame_torch(W, H, seed, 1, device)
+    xy, chol, rgb = (torch.from_numpy(a).to(device) for a in
+                     synth.random_gaussians(N, W, H, seed=seed + 1, scale_lo=0.6, scale_hi=3.0))
+    net = _lib.CNNInit(H, W, seed=seed + 2, device=device)
+    net.set_targets(xy, chol, rgb)
+    for _ in range(warmup):
+        net.forward(f1, f0)
+        net.backward()
+        net.step(lr=1e-4)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e in ev:
+        e[0].record()
+        net.forward(f1, f0)
+        e[1].record()
+        net.backward()
+        e[2].record()
+        net.step(lr=1e-4)
+        e[3].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    fwd = sum(e[0].elapsed_time(e[1]) for e in ev) / steps
+    bwd = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+    adam = sum(e[2].elapsed_time(e[3]) for e in ev) / steps
+    fl = cnn_conv_flops(H, W)
+    return {"workload": "cnn_train_step", "size": [W, H], "steps": steps,
+            "ms_forward": fwd, "ms_backward": bwd, "ms_adam": adam, "ms_step_wall": wall * 1e3,
+            "conv_gflop_forward": sum(fl) / 1e9, "conv_gflop_step": 3 * sum(fl) / 1e9,
+            "loss": float(net.loss3[0])}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["batch", "video", "learned"])
+    ap.add_argument("which", choices=["batch", "video", "learned", "cnn-step"])
     ap.add_argument("--frames", type=int, default=None)
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--train-seqs", type=int, default=34)
@@ -368,6 +419,9 @@ def main(argv=None):
         out = run_batch(n_frames=args.frames or 48, iters=args.iters or 300)
     elif args.which == "video":
         out = run_video(n_frames=args.frames or 60, iters_rest=args.iters or 200)
+    elif args.which == "cnn-step":
+        W, H = (int(x) for x in args.size.split("x"))
+        out = run_cnn_step(steps=args.iters or 20, W=W, H=H, N=args.N)
     else:
         W, H = (int(x) for x in args.size.split("x"))
         out = run_learned(train_seqs=args.train_seqs, frames_per_seq=args.frames or 60,

@@ -11,11 +11,16 @@ from gpu_util import DEV, dev, host
 pytestmark = pytest.mark.gpu
 
 H, W = 96, 128          # 6 x 8 tiles of 16 px
+# a frame whose sides are no multiple of 16, nor even at every layer (70 ->
+# 35 -> 18 -> 9 -> 5, 117 -> 59 -> 30 -> 15 -> 8): ragged tiles and every
+# stride-parity class of the grad-input kernels with odd extents
+SIZES = [(96, 128), (70, 117)]
 
 
-def _frames(seed):
-    f0, _ = synth.make_frame(W, H, seed=seed, t=0)
-    f1, _ = synth.make_frame(W, H, seed=seed, t=3)
+def _frames(seed, hw=(H, W)):
+    h, w = hw
+    f0, _ = synth.make_frame(w, h, seed=seed, t=0)
+    f1, _ = synth.make_frame(w, h, seed=seed, t=3)
     return f0, f1
 
 
@@ -23,18 +28,56 @@ def _x(f1, f0):
     return np.concatenate([f1, f1 - f0]).astype(np.float64)
 
 
-def test_forward_matches_oracle():
-    print("cnn forward", flush=True)
-    f0, f1 = _frames(41)
-    net = _lib.CNNInit(H, W, seed=5)
+@pytest.mark.parametrize("hw", SIZES)
+def test_forward_matches_oracle(hw):
+    h, w = hw
+    print("cnn forward", hw, flush=True)
+    f0, f1 = _frames(41, hw)
+    net = _lib.CNNInit(h, w, seed=5)
     head = torch.empty(73, net.TY, net.TX, device=DEV)
     net.forward(dev(f1), dev(f0), head_out=head)
     torch.cuda.synchronize()
     ref, _ = ocnn.forward(_x(f1, f0), net.oracle_params(), bf16=True)
     got = host(head)
-    assert got.shape == ref.shape == (73, 6, 8)
+    assert got.shape == ref.shape == (73, (h + 15) // 16, (w + 15) // 16)
     scale = np.abs(ref).mean()
     assert np.abs(got - ref).max() <= 2e-2 * scale, np.abs(got - ref).max() / scale
+
+
+def test_forward_1080p_matches_oracle_on_crops():
+    """Full 1920 x 1080 frame, the launch shapes training and inference use.
+    A head output depends on input pixels within 31 px of its tile (four
+    stride-2 layers and the 3x3 head), so on a 256-px crop whose origin is a
+    multiple of 16 the oracle reproduces every tile at least 32 px inside
+    the crop, and every tile along a crop edge that is also the frame's edge."""
+    print("cnn forward 1080p", flush=True)
+    Hf, Wf = 1080, 1920
+    f0, _ = synth.make_frame(Wf, Hf, seed=47, t=0)
+    f1, _ = synth.make_frame(Wf, Hf, seed=47, t=2)
+    net = _lib.CNNInit(Hf, Wf, seed=12)
+    head = torch.empty(73, net.TY, net.TX, device=DEV)
+    net.forward(dev(f1), dev(f0), head_out=head)
+    torch.cuda.synchronize()
+    got = host(head)
+    assert got.shape == (73, 68, 120)
+    params = net.oracle_params()
+    x = _x(f1, f0)
+    checked = 0
+    # crop origins (pixels): top-left corner, interior, bottom-right corner
+    for y0, x0 in [(0, 0), (400, 912), (Hf - 248, Wf - 256)]:
+        ch, cw = min(256, Hf - y0), min(256, Wf - x0)
+        ref, _ = ocnn.forward(x[:, y0:y0 + ch, x0:x0 + cw], params, bf16=True)
+        ty0, tx0 = y0 // 16, x0 // 16
+        lo_y = 0 if y0 == 0 else 2
+        lo_x = 0 if x0 == 0 else 2
+        hi_y = ref.shape[1] if y0 + ch == Hf else 15
+        hi_x = ref.shape[2] if x0 + cw == Wf else 15
+        g = got[:, ty0 + lo_y:ty0 + hi_y, tx0 + lo_x:tx0 + hi_x]
+        r = ref[:, lo_y:hi_y, lo_x:hi_x]
+        scale = np.abs(r).mean()
+        assert np.abs(g - r).max() <= 2e-2 * scale, (y0, x0, np.abs(g - r).max() / scale)
+        checked += r.shape[1] * r.shape[2]
+    assert checked >= 3 * 13 * 13
 
 
 def test_targets_match_oracle():
@@ -57,9 +100,11 @@ def test_targets_match_oracle():
     assert counts.max() == 8 and counts.sum() > 300
 
 
-def test_backward_matches_oracle():
-    print("cnn backward", flush=True)
-    f0, f1 = _frames(43)
+@pytest.mark.parametrize("hw", SIZES)
+def test_backward_matches_oracle(hw):
+    H, W = hw
+    print("cnn backward", hw, flush=True)
+    f0, f1 = _frames(43, hw)
     xy, chol, rgb = synth.random_gaussians(700, W, H, seed=7, scale_lo=0.6, scale_hi=3.0)
     net = _lib.CNNInit(H, W, seed=8)
     net.set_targets(dev(xy), dev(chol), dev(rgb))
