@@ -218,10 +218,11 @@ def psnr_curve(shape, ws, target, params, budget, points, cfg):
 
 
 def make_training_set(seqs, n_frames, W, H, N, iters_first, iters_rest, device, lr=LR_DEFAULT,
-                      log=print):
+                      log=print, frames=None):
     """Fitted Gaussians of every frame of the training sequences (frame 0
     from the content-aware init, later frames warm-started), the targets the
-    learned initialiser is trained on."""
+    learned initialiser is trained on.  `frames` (a dict, optional) receives
+    every frame keyed by (seed, t) for reuse while training."""
     shape = _lib.make_shape(W, H, N, 32, px_per_lane=2)
     ws = _lib.alloc_workspace(shape, device)
     cfg = _lib.adam_cfg(lr)
@@ -230,6 +231,8 @@ def make_training_set(seqs, n_frames, W, H, N, iters_first, iters_rest, device, 
         params = None
         for t in range(n_frames):
             f, m = synth.make_frame_torch(W, H, seed, t, device)
+            if frames is not None:
+                frames[(seed, t)] = f
             if params is None:
                 params = [p.contiguous() for p in plain_init_dev(f, m, N, seed + 7919)]
                 iters = iters_first
@@ -247,16 +250,24 @@ def make_training_set(seqs, n_frames, W, H, N, iters_first, iters_rest, device, 
     return samples
 
 
-def train_initialiser(net, samples, W, H, epochs, lr, device, log=print, seed=0):
+def train_initialiser(net, samples, W, H, epochs, lr, device, log=print, seed=0, frames=None):
+    """Epochs over the samples in a seeded random order; frames come from
+    `frames` (keyed by (seed, t)) when given, else are synthesised again."""
     rng = np.random.default_rng(seed)
     hist = []
+
+    def frame(sd, t):
+        if frames is not None and (sd, t) in frames:
+            return frames[(sd, t)]
+        return synth.make_frame_torch(W, H, sd, t, device)[0]
+
     for ep in range(epochs):
         order = rng.permutation(len(samples))
         tot = 0.0
         for i, k in enumerate(order):
             sd, t, params = samples[k]
-            f, _ = synth.make_frame_torch(W, H, sd, t, device)
-            prev = synth.make_frame_torch(W, H, sd, t - 1, device)[0] if t > 0 else None
+            f = frame(sd, t)
+            prev = frame(sd, t - 1) if t > 0 else None
             net.forward(f, prev)
             net.set_targets(*params)
             loss = net.backward()
@@ -276,15 +287,21 @@ def run_learned(train_seqs=34, frames_per_seq=60, max_samples=2000, epochs=6, ev
     frame 0 then warm start, C learned init on frame 0 then warm start."""
     t_all = time.perf_counter()
     seqs = [5000 + i for i in range(train_seqs)]
+    # every training frame stays resident in HBM (34 x 60 1080p frames are
+    # ~51 GB) when the device has room for it with a wide margin
+    free, _ = torch.cuda.mem_get_info()
+    frame_bytes = 3 * W * H * 4 * len(seqs) * frames_per_seq
+    cache = {} if frame_bytes < 0.5 * free else None
     samples = make_training_set(seqs, frames_per_seq, W, H, N, iters_first, iters_rest, device,
-                                log=log)[:max_samples]
+                                log=log, frames=cache)[:max_samples]
     t_data = time.perf_counter() - t_all
     net = _lib.CNNInit(H, W, seed=11, device=device)
     t0 = time.perf_counter()
-    hist = train_initialiser(net, samples, W, H, epochs, lr_cnn, device, log=log)
+    hist = train_initialiser(net, samples, W, H, epochs, lr_cnn, device, log=log, frames=cache)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    del samples
+    resident = cache is not None
+    del samples, cache
     # held-out evaluation
     shape = _lib.make_shape(W, H, N, 32, px_per_lane=2)
     ws = _lib.alloc_workspace(shape, device)
@@ -349,6 +366,7 @@ def run_learned(train_seqs=34, frames_per_seq=60, max_samples=2000, epochs=6, ev
         "psnr_at_budget_cold": budget_mean,
         "learned_predicted_per_frame": [npred_log[t] for t in sorted(npred_log)],
         "train_loss_per_epoch": hist, "data_seconds": t_data, "train_seconds": t_train,
+        "train_frames_resident": resident,
     }
 
 
