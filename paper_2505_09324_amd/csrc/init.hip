@@ -117,18 +117,38 @@ k_init_chunk_sums(size_t HW, const long long *__restrict__ qm, const long long *
   }
 }
 
-// Exclusive scan of the chunk sums in place (one thread: few thousand chunks);
-// the totals go to part[3*n .. 3*n+2].
-__global__ void k_init_scan_parts(int n, long long *__restrict__ part) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Exclusive scan of the chunk sums in place by one workgroup of SCAN_T
+// threads (a few thousand chunks: each thread scans a contiguous run, then
+// the run totals are scanned across the workgroup); the totals go to
+// part[3*n .. 3*n+2].  Integer sums: the order does not matter.
+constexpr int SCAN_T = 1024;
+__global__ void __launch_bounds__(SCAN_T) k_init_scan_parts(int n, long long *__restrict__ part) {
+  __shared__ long long run[3][SCAN_T];
+  const int t = threadIdx.x;
+  const int per = (n + SCAN_T - 1) / SCAN_T;
+  const int beg = min(n, t * per), end = min(n, beg + per);
   long long s[3] = {0, 0, 0};
-  for (int c = 0; c < n; ++c)
+  for (int c = beg; c < end; ++c)
+    for (int k = 0; k < 3; ++k) s[k] += part[3 * (size_t)c + k];
+  for (int k = 0; k < 3; ++k) run[k][t] = s[k];
+  __syncthreads();
+  for (int o = 1; o < SCAN_T; o <<= 1) {  // inclusive Hillis-Steele scan of the run totals
+    long long x[3];
+    for (int k = 0; k < 3; ++k) x[k] = t >= o ? run[k][t - o] : 0;
+    __syncthreads();
+    for (int k = 0; k < 3; ++k) run[k][t] += x[k];
+    __syncthreads();
+  }
+  long long acc[3];
+  for (int k = 0; k < 3; ++k) acc[k] = run[k][t] - s[k];
+  for (int c = beg; c < end; ++c)
     for (int k = 0; k < 3; ++k) {
       const long long v = part[3 * (size_t)c + k];
-      part[3 * (size_t)c + k] = s[k];
-      s[k] += v;
+      part[3 * (size_t)c + k] = acc[k];
+      acc[k] += v;
     }
-  for (int k = 0; k < 3; ++k) part[3 * (size_t)n + k] = s[k];
+  if (t == SCAN_T - 1)
+    for (int k = 0; k < 3; ++k) part[3 * (size_t)n + k] = run[k][t];
 }
 
 // Inclusive scan inside each chunk plus the chunk's offset, in place.
@@ -289,7 +309,7 @@ extern "C" int gs2d_init_plain(int32_t W, int32_t H, const float *target, const 
                        dim3(256), 0, st, W, H, target, roi_mask, qm, qa, r);
     hipLaunchKernelGGL(k_init_chunk_sums, dim3(L.n_chunks), dim3(INIT_BLOCK), 0, st, HW, qm, qa, r,
                        part);
-    hipLaunchKernelGGL(k_init_scan_parts, dim3(1), dim3(64), 0, st, L.n_chunks, part);
+    hipLaunchKernelGGL(k_init_scan_parts, dim3(1), dim3(SCAN_T), 0, st, L.n_chunks, part);
     hipLaunchKernelGGL(k_init_chunk_scan, dim3(L.n_chunks), dim3(INIT_BLOCK), 0, st, HW, qm, qa, r,
                        part);
     // region totals decide the sampling regions: read them back (3 int64)
