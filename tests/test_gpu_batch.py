@@ -65,6 +65,36 @@ def test_batch_render_matches_oracle_per_frame(T, ppl):
         assert_grads_close({"xy": gx[f], "chol": gc[f], "rgb": gr[f]}, ref)
 
 
+def test_batch_two_pass_sort_when_a_frame_has_many_tiles():
+    """A batch mixing small frames with one of more than 2048 tiles (400 x
+    330 at T = 8: 50 x 42, 12-bit tile ids, so both 8-bit radix passes
+    carry keys across the whole tile range): lists, loss and gradients of
+    every frame against the oracle."""
+    print("batch two-pass sort", flush=True)
+    sizes = SMALL[:2] + [(400, 330, 1200)]
+    frames, params, targets, cat = _batch_inputs(sizes, 700)
+    Nt = sum(n for _, _, n in sizes)
+    ws = torch.empty(_lib.batch_workspace_bytes(sizes, 8, 1), dtype=torch.uint8, device=DEV)
+    g = [torch.zeros(Nt, d, device=DEV) for d in (2, 3, 3)]
+    loss = torch.zeros(len(sizes), device=DEV)
+    _lib.batch_render_grads(sizes, 8, 1, dev(targets), dev(cat[0]), dev(cat[1]), dev(cat[2]),
+                            *g, ws, loss_per_frame=loss)
+    torch.cuda.synchronize()
+    gx = _split(host(g[0]).ravel(), sizes, 2)
+    gc = _split(host(g[1]).ravel(), sizes, 3)
+    gr = _split(host(g[2]).ravel(), sizes, 3)
+    for f, ((w, h, n), frame, (xy, chol, rgb)) in enumerate(zip(sizes, frames, params)):
+        b = _lib.read_batch_bins(sizes, 8, 1, f, ws)
+        ob = bin_gaussians(xy, chol, w, h, 8)
+        np.testing.assert_array_equal(b["keys"].astype(np.int64),
+                                      ob["pair_tiles"] * 65536 + ob["pair_ids"])
+        np.testing.assert_array_equal(b["tile_start"], ob["tile_start"])
+        img = render_box(xy, chol, rgb, h, w, want_bounds=False)["img"]
+        assert float(loss[f]) == pytest.approx(mse(img, frame), rel=1e-4)
+        ref = gradients(xy, chol, rgb, dloss_dimg(img, frame), h, w)
+        assert_grads_close({"xy": gx[f], "chol": gc[f], "rgb": gr[f]}, ref)
+
+
 def test_fit_batch_trajectories_match_oracle():
     """10 lockstep Adam steps: every frame's loss trace vs the oracle loop
     run on that frame alone (1e-3 relative)."""
