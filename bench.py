@@ -234,6 +234,13 @@ def main():
     mm, vv = m.clone(), v.clone()
     xs, cs, rs = xy.clone(), chol.clone(), rgb.clone()
     t_adam = time_graph(lambda: _lib.adam_step(xs, cs, rs, *g, mm, vv, step2, cfg), args.kernel_reps)
+    # the unfused raster entry points (the autograd path): forward with the
+    # loss and dL/dC, and the backward from dL/dC (which first clears g)
+    dl = torch.empty(3, H, W, device=dev)
+    loss_d = torch.zeros((), device=dev)
+    t_fwd = time_graph(lambda: _lib.render_fwd(shape, ws, rgb, target=T, dl_dimg=dl, loss=loss_d),
+                       args.kernel_reps)
+    t_bwd = time_graph(lambda: _lib.render_bwd(shape, ws, rgb, dl, *g), args.kernel_reps)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     if args.sweep:
@@ -280,7 +287,8 @@ def main():
                      "launch_us": round(t_fused * 1e6, 2), "pairs_in_cutoff": p_in,
                      "flops_per_launch": flops},
         "stages_us": {"project_bin": round(t_bin * 1e6, 2), "render_fused": round(t_fused * 1e6, 2),
-                      "adam": round(t_adam * 1e6, 2)},
+                      "adam": round(t_adam * 1e6, 2), "render_fwd_loss": round(t_fwd * 1e6, 2),
+                      "render_bwd": round(t_bwd * 1e6, 2)},
         "n_pairs": n_pairs,
         "autotune_us_per_round": tune,
         "cpu_baseline": cpu,
