@@ -16,7 +16,7 @@ import time
 import numpy as np
 import torch
 
-from . import _lib, synth
+from . import _lib, autotune, synth
 
 LR_DEFAULT = (2e-2, 5e-3, 5e-3)   # mean, Cholesky vector, colour
 
@@ -58,10 +58,13 @@ def batch_inputs(n_frames=48, seed=400, device="cuda"):
     return sizes, targets, xy, chol, rgb, frames
 
 
-def autotuned(sizes, targets, xy, chol, rgb, reps=3):
-    cands = [(8, 1), (16, 1), (16, 2), (32, 1), (32, 2), (32, 4)]
-    best, ms = _lib.autotune_batch(sizes, targets, xy, chol, rgb, cands, reps=reps)
-    return cands[best], dict(zip([f"{t}/{p}" for t, p in cands], ms))
+def autotuned(sizes, targets, xy, chol, rgb, reps=3, cache_path=None):
+    """(tile, px_per_lane) for the batch and the candidates' ms per round;
+    with cache_path None every candidate is timed (the workload reports the
+    timings)."""
+    cfg, ms, _ = autotune.tuned_batch_config(sizes, targets, xy, chol, rgb, reps=reps,
+                                             cache_path=cache_path)
+    return cfg, ms
 
 
 def run_batch(n_frames=48, iters=300, seed=400, check_every=50, device="cuda", lr=LR_DEFAULT):

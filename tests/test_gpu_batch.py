@@ -152,3 +152,20 @@ def test_autotuner_and_full_batch_workload():
     b = _lib.read_batch_bins(sizes, T, ppl, f, ws)
     ob = bin_gaussians(host(xy)[off:off + n], host(chol)[off:off + n], w, h, T)
     np.testing.assert_array_equal(b["keys"].astype(np.int64), ob["pair_tiles"] * 65536 + ob["pair_ids"])
+
+
+def test_autotune_cache_on_device(tmp_path):
+    """The first call times the candidates on the GPU and stores the choice;
+    the second call with the same batch returns it from the JSON file."""
+    print("autotune cache", flush=True)
+    from paper_2505_09324_amd import autotune
+    frames, params, targets, cat = _batch_inputs(SMALL, 900)
+    path = str(tmp_path / "autotune.json")
+    args = (SMALL, dev(targets), dev(cat[0]), dev(cat[1]), dev(cat[2]))
+    cands = [(16, 1), (32, 2)]
+    cfg, ms, cached = autotune.tuned_batch_config(*args, candidates=cands, reps=2, cache_path=path)
+    assert not cached and cfg in cands and all(v > 0 for v in ms.values())
+    cfg2, ms2, cached2 = autotune.tuned_batch_config(*args, candidates=cands, reps=2,
+                                                     cache_path=path)
+    assert cached2 and cfg2 == cfg and ms2 == {}
+
