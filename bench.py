@@ -170,6 +170,8 @@ def main():
                     help="pixels per lane of the raster kernels (1/2/4); 0 = autotuner")
     ap.add_argument("--sweep", action="store_true",
                     help="also time the fused kernel for every (tile, ppl) variant (stderr)")
+    ap.add_argument("--launch", choices=("graph", "eager"), default="graph",
+                    help="fitting chunks replayed as captured hipGraphs, or launched directly")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -211,11 +213,13 @@ def main():
 
     if args.warmup > 0:
         _lib.fit_frame(shape, T, xy, chol, rgb, m, v, step, trace, ws,
-                       _lib.fit_opts(args.warmup, min(args.check_every, args.warmup), cfg=cfg))
+                       _lib.fit_opts(args.warmup, min(args.check_every, args.warmup),
+                                     use_graph=args.launch == "graph", cfg=cfg))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = _lib.fit_frame(shape, T, xy, chol, rgb, m, v, step, trace, ws,
-                        _lib.fit_opts(args.steps, args.check_every, cfg=cfg))
+                        _lib.fit_opts(args.steps, args.check_every,
+                                      use_graph=args.launch == "graph", cfg=cfg))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     tr = trace[:args.warmup + args.steps].cpu().numpy()
@@ -279,7 +283,7 @@ def main():
                                f"{args.warmup}..{args.warmup + args.steps}",
                    "W": W, "H": H, "N": N, "tile": args.tile, "px_per_lane": args.ppl,
                    "lr": list(LR),
-                   "graph_chunk": args.check_every},
+                   "launch": args.launch, "chunk": args.check_every},
         "psnr_final_db": round(psnr_final, 3),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32, 4),

@@ -125,13 +125,17 @@ def run_batch(n_frames=48, iters=300, seed=400, check_every=50, device="cuda", l
 
 
 # ------------------------------------------------------------------ video --
-def fit_sequence(frames, masks, N, iters_first, iters_rest, init_seed, tile=16, ppl=1,
-                 lr=LR_DEFAULT, psnr_target=0.0, check_every=10, device="cuda",
+def fit_sequence(frames, masks, N, iters_first, iters_rest, init_seed, tile=32, ppl=2,
+                 lr=LR_DEFAULT, psnr_target=0.0, check_every=None, device="cuda",
                  warm_start=True, init_fn=None):
     """Fit a sequence frame by frame.  Frame 0 starts from `init_fn` (default
     the content-aware init); with warm_start each later frame starts from the
     previous frame's fitted Gaussians with the Adam state reset, otherwise
-    from its own init.  Returns per-frame records."""
+    from its own init.  Tile 32 / 2 px per lane is what the autotuner picks
+    at 1080p; without a PSNR target the loss is read back every 50
+    iterations, with one every 10.  Returns per-frame records."""
+    if check_every is None:
+        check_every = 10 if psnr_target > 0 else 50
     H, W = frames[0].shape[1:]
     shape = _lib.make_shape(W, H, N, tile, px_per_lane=ppl)
     ws = _lib.alloc_workspace(shape, device)
