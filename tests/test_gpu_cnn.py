@@ -15,6 +15,9 @@ H, W = 96, 128          # 6 x 8 tiles of 16 px
 # 35 -> 18 -> 9 -> 5, 117 -> 59 -> 30 -> 15 -> 8): ragged tiles and every
 # stride-parity class of the grad-input kernels with odd extents
 SIZES = [(96, 128), (70, 117)]
+# the smallest frames the network accepts: a 1 x 1 and a 2 x 3 tile head,
+# parity classes of extent 1 and layers whose input is a single pixel row
+TINY = [(16, 16), (17, 33)]
 
 
 def _frames(seed, hw=(H, W)):
@@ -28,7 +31,7 @@ def _x(f1, f0):
     return np.concatenate([f1, f1 - f0]).astype(np.float64)
 
 
-@pytest.mark.parametrize("hw", SIZES)
+@pytest.mark.parametrize("hw", SIZES + TINY)
 def test_forward_matches_oracle(hw):
     h, w = hw
     print("cnn forward", hw, flush=True)
@@ -103,7 +106,7 @@ def test_targets_match_oracle():
 # 288 x 352: layer 0's 144 x 176 outputs make 50 pixel splits of the grad-
 # weight GEMM, so its partial tiles are summed in two chunks (combined with
 # atomics), as at full resolution
-@pytest.mark.parametrize("hw", SIZES + [(288, 352)])
+@pytest.mark.parametrize("hw", SIZES + TINY + [(288, 352)])
 def test_backward_matches_oracle(hw):
     H, W = hw
     print("cnn backward", hw, flush=True)
