@@ -257,9 +257,13 @@ def make_training_set(seqs, n_frames, W, H, N, iters_first, iters_rest, device, 
     return samples
 
 
-def train_initialiser(net, samples, W, H, epochs, lr, device, log=print, seed=0, frames=None):
+def train_initialiser(net, samples, W, H, epochs, lr, device, log=print, seed=0, frames=None,
+                      iframe_rate=0.1):
     """Epochs over the samples in a seeded random order; frames come from
-    `frames` (keyed by (seed, t)) when given, else are synthesised again."""
+    `frames` (keyed by (seed, t)) when given, else are synthesised again.
+    A fraction `iframe_rate` of the P-frame samples is presented as an
+    I-frame (no previous frame, zero residual input), so that the I-frame
+    case is not limited to the first frame of each sequence."""
     rng = np.random.default_rng(seed)
     hist = []
 
@@ -274,7 +278,8 @@ def train_initialiser(net, samples, W, H, epochs, lr, device, log=print, seed=0,
         for i, k in enumerate(order):
             sd, t, params = samples[k]
             f = frame(sd, t)
-            prev = frame(sd, t - 1) if t > 0 else None
+            as_iframe = t == 0 or rng.random() < iframe_rate
+            prev = None if as_iframe else frame(sd, t - 1)
             net.forward(f, prev)
             net.set_targets(*params)
             loss = net.backward()
