@@ -382,6 +382,48 @@ def run_learned(train_seqs=34, frames_per_seq=60, max_samples=2000, epochs=6, ev
     }
 
 
+def run_fit(W=640, H=360, N=1000, iters=1000, psnr_target=30.0, seed=950, device="cuda"):
+    """One synthetic frame fitted from the content-aware init: iterations and
+    seconds (init included) to `psnr_target`, and the iteration rate of an
+    `iters`-iteration fit without a stop rule.  (tile, px per lane) from the
+    autotuner on this frame."""
+    f, m = synth.make_frame_torch(W, H, seed, 0, device)
+    plain_init_dev(f, m, N, seed + 2)  # first use loads the library's code objects
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    params = [p.contiguous() for p in plain_init_dev(f, m, N, seed + 1)]
+    torch.cuda.synchronize()
+    t_init = time.perf_counter() - t0
+    (T, ppl), _ = autotuned([(W, H, N)], f.reshape(-1), *params)
+    shape = _lib.make_shape(W, H, N, T, px_per_lane=ppl)
+    ws = _lib.alloc_workspace(shape, device)
+    cfg = _lib.adam_cfg(LR_DEFAULT)
+    # time to the target (read-backs every 10 iterations), from the same init
+    p1 = [q.clone() for q in params]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hit, run = fit_to_target(shape, ws, f, p1, psnr_target, 10000, 10, cfg)
+    torch.cuda.synchronize()
+    t_target = time.perf_counter() - t0
+    # iteration rate over a fixed budget
+    p2 = [q.clone() for q in params]
+    mm = torch.zeros(8 * N, device=device)
+    vv = torch.zeros(8 * N, device=device)
+    step = torch.zeros(1, dtype=torch.int32, device=device)
+    trace = torch.zeros(iters + 8, device=device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _lib.fit_frame(shape, f, *p2, mm, vv, step, trace, ws, _lib.fit_opts(iters, 50, cfg=cfg))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": f"one {W}x{H} synthetic frame, {N} Gaussians from the content-aware init",
+            "tile": T, "px_per_lane": ppl, "init_seconds": t_init,
+            "iters_to_target": hit, "target_psnr_db": psnr_target,
+            "seconds_to_target_incl_init": (t_init + t_target) if hit is not None else None,
+            "iters_per_s": iters / dt, "ms_per_iter": dt / iters * 1e3,
+            "psnr_after_iters": psnr(float(trace[iters - 1])), "iters": iters}
+
+
 def cnn_conv_flops(H, W):
     """Multiply-add FLOPs of the initialiser's convolutions for one H x W
     frame, counting real channels only (6 input channels, 73 head outputs):
@@ -435,7 +477,7 @@ def run_cnn_step(steps=20, warmup=3, W=1920, H=1080, N=30000, seed=900, device="
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["batch", "video", "learned", "cnn-step"])
+    ap.add_argument("which", choices=["batch", "video", "learned", "cnn-step", "fit"])
     ap.add_argument("--frames", type=int, default=None)
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--train-seqs", type=int, default=34)
@@ -449,6 +491,9 @@ def main(argv=None):
         out = run_batch(n_frames=args.frames or 48, iters=args.iters or 300)
     elif args.which == "video":
         out = run_video(n_frames=args.frames or 60, iters_rest=args.iters or 200)
+    elif args.which == "fit":
+        W, H = (int(x) for x in (args.size if args.size != "1920x1080" else "640x360").split("x"))
+        out = run_fit(W=W, H=H, N=args.N if args.N != 30000 else 1000, iters=args.iters or 1000)
     elif args.which == "cnn-step":
         W, H = (int(x) for x in args.size.split("x"))
         out = run_cnn_step(steps=args.iters or 20, W=W, H=H, N=args.N)
