@@ -301,7 +301,9 @@ int gs2d_autotune_batch(int32_t n_frames, const gs2d_frame *frames, const float 
  * Buffers (caller-owned, device): master FP32 weights [param_count]; BF16
  * weight copies [bf16_weight_count] (uint16); workspace
  * [cnn_workspace_bytes] holding activations, the head output, the current
- * training targets and gradients of activations.  H, W >= 16. */
+ * training targets, each layer's BF16 output gradient (ReLU applied) and
+ * the grad-weight partial sums.  H, W >= 16, H * W <= 2^26.  One workspace
+ * serves one call at a time (calls on one stream are ordered). */
 size_t gs2d_cnn_param_count(int32_t H, int32_t W);
 size_t gs2d_cnn_workspace_bytes(int32_t H, int32_t W);
 size_t gs2d_cnn_bf16_weight_count(int32_t H, int32_t W);
