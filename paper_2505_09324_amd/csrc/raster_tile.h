@@ -170,9 +170,9 @@ __device__ inline int fwd_chunk(Smem<NW> &S, int len, float pxc, float pyc0, uns
     const float u1s = u1 * u1;
     const float base = (pyc0 - A.y) - A.w * u1;
     bool any = false;
+    float u2 = base * B.x;  // the next pixel row adds 1/l3 (staged units)
 #pragma unroll
-    for (int r = 0; r < PPL; ++r) {
-      const float u2 = (base + (float)r) * B.x;
+    for (int r = 0; r < PPL; ++r, u2 += B.x) {
       const float q = u1s + u2 * u2;
       const float e = __builtin_amdgcn_exp2f(-q);
       const bool in_cut = q <= CUTOFF_QS;
@@ -209,7 +209,7 @@ __device__ inline void bwd_chunk(const Smem<NW> &S, float *acc, int len, float p
     bool any = false;
 #pragma unroll
     for (int r = 0; r < PPL; ++r) {
-      u2[r] = (base + (float)r) * B.x;
+      u2[r] = r == 0 ? base * B.x : u2[r - 1] + B.x;  // the next pixel row adds 1/l3
       q[r] = u1s + u2[r] * u2[r];
       any |= q[r] <= CUTOFF_QS;
     }
