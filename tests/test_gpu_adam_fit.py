@@ -181,3 +181,54 @@ def test_fit_frame_stops_at_psnr_and_flags_overflow():
     st2 = _lib.fit_frame(small.shape, dev(frame), P["xy"], P["chol"], P["rgb"], M, V, step, trace,
                          small.ws, _lib.fit_opts(20, 5, cfg=_lib.adam_cfg(LR)), check=False)
     assert st2.code == _lib.GS2D_EOVERFLOW and st2.status & _lib.STATUS_OVERFLOW
+
+
+def test_fit_frame_1080p_matches_separate_calls():
+    """1920x1080 / 30k Gaussians from the content-aware init, in the launch
+    configuration the fitting benchmark times (tile 32, 2 px per lane, one
+    graph-replayed chunk in which each Adam step runs inside the next
+    iteration's projection kernel): 4 iterations of gs2d_fit_frame against
+    the same 4 iterations as separate gs2d_project_bin, gs2d_render_fused and
+    gs2d_adam_step calls (each pinned to the oracle by the tests above).
+    Loss trace, parameters and moments agree up to the order of the float
+    atomics that accumulate the gradients."""
+    print("fit_frame 1080p vs separate calls", flush=True)
+    from paper_2505_09324_amd import workloads
+    W, H, N, K = 1920, 1080, 30000, 4
+    f, m = synth.make_frame_torch(W, H, 61, 0, DEV)
+    p0 = [p.contiguous() for p in workloads.plain_init_dev(f, m, N, 62)]
+    shape = _lib.make_shape(W, H, N, 32, px_per_lane=2)
+    lr = (2e-2, 5e-3, 5e-3)
+    cfg = _lib.adam_cfg(lr)
+    # the fitting loop
+    pa = [q.clone() for q in p0]
+    ma, va = torch.zeros(8 * N, device=DEV), torch.zeros(8 * N, device=DEV)
+    sa = torch.zeros(1, dtype=torch.int32, device=DEV)
+    tra = torch.zeros(K + 8, device=DEV)
+    st = _lib.fit_frame(shape, f, *pa, ma, va, sa, tra, _lib.alloc_workspace(shape),
+                        _lib.fit_opts(K, K, cfg=cfg))
+    assert st.iters_run == K and st.status == 0
+    # the same steps through the separate entry points
+    ws = _lib.alloc_workspace(shape)
+    pb = [q.clone() for q in p0]
+    mb, vb = torch.zeros(8 * N, device=DEV), torch.zeros(8 * N, device=DEV)
+    sb = torch.zeros(1, dtype=torch.int32, device=DEV)
+    g = [torch.zeros(N, d, device=DEV) for d in (2, 3, 3)]
+    losses = []
+    for _ in range(K):
+        _lib.project_bin(shape, pb[0], pb[1], ws)
+        loss = torch.zeros((), device=DEV)
+        _lib.render_fused(shape, ws, pb[2], f, *g, loss=loss)
+        losses.append(float(loss))
+        _lib.adam_step(*pb, *g, mb, vb, sb, cfg, zero_grads=True)
+    torch.cuda.synchronize()
+    assert int(sa.item()) == int(sb.item()) == K
+    np.testing.assert_allclose(host(tra)[:K], losses, rtol=1e-5)
+    for (name, a, b), step in zip((("xy", pa[0], pb[0]), ("chol", pa[1], pb[1]),
+                                   ("rgb", pa[2], pb[2])), lr):
+        a, b = host(a), host(b)
+        err = np.abs(a - b)
+        assert np.all(err <= 1e-3 * step + 1e-6 * np.abs(b)), (name, err.max())
+    for a, b in ((ma, mb), (va, vb)):
+        a, b = host(a), host(b)
+        assert np.abs(a - b).max() <= 1e-4 * np.abs(b).max() + 1e-12
