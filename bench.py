@@ -177,8 +177,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(frames or groups of pictures would be sharded across GPUs, see DESIGN.md); "
+        print("bench.py measures one GPU: there is no multi-GPU path (independent frames or "
+              "groups of pictures would be sharded across GPUs, one process each); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
