@@ -325,7 +325,8 @@ int gs2d_cnn_forward(int32_t H, int32_t W, const float *frame, const float *prev
 /* Per-tile training targets from N fitted Gaussians (stored in ws): the
  * Gaussians whose centre lies in the tile, at most 8, the heaviest by
  * |l1 l3| |c'|^2 (ties to the lower index).  scratch: >= 2*4N + 4*256*G +
- * 4*(tiles+1) + 256 bytes, 256-aligned.  Synchronises `stream`. */
+ * 4*(tiles+1) + 256 bytes, 256-aligned, in use until the stream reaches the
+ * end of the call's work (stream-ordered, no host synchronisation). */
 int gs2d_cnn_targets(int32_t H, int32_t W, int32_t N, const float *xy, const float *chol,
                      const float *rgb, void *ws, size_t ws_bytes, void *scratch,
                      size_t scratch_bytes, void *stream);

@@ -1068,8 +1068,10 @@ k_cnn_targets(int n_tiles, int TX, int T, const uint32_t *__restrict__ keys,
 // outside the frame or the Gaussian is degenerate (sorts last).
 __global__ void __launch_bounds__(256)
 k_centre_keys(int N, int W, int H, int TX, int T, const float *__restrict__ xy,
-              const float *__restrict__ chol, uint32_t *__restrict__ keys, int *__restrict__ n_valid) {
+              const float *__restrict__ chol, uint32_t *__restrict__ keys, int *__restrict__ n_keys,
+              int *__restrict__ n_valid) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n == 0) *n_keys = N;  // the sort's key count (all N keys are sorted)
   if (n >= N) return;
   const float x = xy[2 * n], y = xy[2 * n + 1];
   const float l1 = chol[3 * n], l3 = chol[3 * n + 2];
@@ -1224,12 +1226,9 @@ int gs2d_cnn_targets(int32_t H, int32_t W, int32_t N, const float *xy, const flo
   int *misc = at<int>(scratch, o);  // [0] n keys, [1] n valid
   hipError_t e = launch_fill_zero_u32(reinterpret_cast<uint32_t *>(misc), 16, st);
   if (e != hipSuccess) return GS2D_EHIP;
-  hipLaunchKernelGGL(k_centre_keys, dim3((N + 255) / 256), dim3(256), 0, st, N, W, H, C.TX, 16, xy,
-                     chol, ka, misc + 1);
   // all N keys are sorted (invalid ones carry tile 0xFFFF and sort last)
-  const int32_t hN = N;
-  if (hipMemcpyAsync(misc, &hN, sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess)
-    return GS2D_EHIP;
+  hipLaunchKernelGGL(k_centre_keys, dim3((N + 255) / 256), dim3(256), 0, st, N, W, H, C.TX, 16, xy,
+                     chol, ka, misc, misc + 1);
   const uint32_t *sorted = nullptr;
   e = launch_radix_sort_tiles(ka, kb, misc, G, hist, 2, st, &sorted);
   if (e == hipSuccess) e = launch_tile_ranges(sorted, misc + 1, C.n_tiles, tstart, st);
@@ -1239,7 +1238,6 @@ int gs2d_cnn_targets(int32_t H, int32_t W, int32_t N, const float *xy, const flo
                      at<float>(ws, C.tvec));
   hipLaunchKernelGGL(k_count_target_tiles, dim3(1), dim3(256), 0, st, C.n_tiles,
                      at<const int>(ws, C.tcount), at<int>(ws, C.ncd));
-  if (hipStreamSynchronize(st) != hipSuccess) return GS2D_EHIP;  // hN leaves scope
   return hipGetLastError() == hipSuccess ? GS2D_OK : GS2D_EHIP;
 }
 

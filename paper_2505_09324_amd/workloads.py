@@ -274,7 +274,7 @@ def train_initialiser(net, samples, W, H, epochs, lr, device, log=print, seed=0,
 
     for ep in range(epochs):
         order = rng.permutation(len(samples))
-        tot = 0.0
+        tot = torch.zeros((), device=device)  # summed on the device: no per-step read-back
         for i, k in enumerate(order):
             sd, t, params = samples[k]
             f = frame(sd, t)
@@ -284,8 +284,8 @@ def train_initialiser(net, samples, W, H, epochs, lr, device, log=print, seed=0,
             net.set_targets(*params)
             loss = net.backward()
             net.step(lr=lr)
-            tot += float(loss[0])
-        hist.append(tot / len(samples))
+            tot += loss[0]
+        hist.append(float(tot) / len(samples))
         log(f"epoch {ep + 1}/{epochs}: mean loss {hist[-1]:.4f}")
     return hist
 
