@@ -54,6 +54,12 @@ def test_workspace_bytes_validation(lib):
                 _lib.Shape(64, 64, 5, 8, 100, 2), _lib.Shape(64, 64, 5, 16, 100, 3),
                 _lib.Shape(64, 64, 5, 32, 100, 8)):
         assert lib.gs2d_workspace_bytes(ctypes.byref(bad)) == 0
+    # the limits themselves: N = 65536 and 256 x 256 tiles are accepted, one
+    # Gaussian or one tile row / column more is not
+    assert lib.gs2d_workspace_bytes(ctypes.byref(_lib.make_shape(2048, 2048, 65536, 8))) > 0
+    for bad in (_lib.make_shape(2048, 2048, 65537, 8), _lib.make_shape(2049, 2048, 100, 8),
+                _lib.make_shape(2048, 2049, 100, 8)):
+        assert lib.gs2d_workspace_bytes(ctypes.byref(bad)) == 0
 
 
 def test_bins_view_checks_space_and_alignment(lib):

@@ -86,6 +86,21 @@ def test_bins_repeatable_and_1080p():
     _compare(a, bin_gaussians(xy, chol, W, H, 16), N)
 
 
+def test_bins_maximum_sizes():
+    """N = 65536 on 2048x2048 at T = 8, i.e. 65536 tiles: both 16-bit key
+    fields at their top value.  The last Gaussian sits in the last tile, so
+    the last key is 2^32 - 1."""
+    print("bins maximum sizes", flush=True)
+    W = H = 2048
+    N = 65536
+    xy, chol, _ = synth.random_gaussians(N, W, H, seed=301, scale_lo=0.3, scale_hi=2.0)
+    xy[-1] = [W - 2.75, H - 1.5]
+    f = GpuFrame(W, H, N, 8)
+    out = f.bin(dev(xy), dev(chol))
+    _compare(out, bin_gaussians(xy, chol, W, H, 8), N)
+    assert int(out["keys"][out["n_pairs"] - 1]) == 0xFFFFFFFF
+
+
 def test_bins_all_culled_and_empty_lists():
     print("bins all culled", flush=True)
     xy = np.full((10, 2), np.nan, np.float32)

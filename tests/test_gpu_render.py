@@ -10,7 +10,7 @@ import torch
 from oracle.grads import gradients
 from oracle.loss import dloss_dimg, mse
 from oracle.render import render_box, render_bruteforce, render_pixels
-from paper_2505_09324_amd import synth
+from paper_2505_09324_amd import _lib, synth
 from gpu_util import VARIANTS, GpuFrame, assert_grads_close, assert_pixels_close, dev, host
 
 pytestmark = pytest.mark.gpu
@@ -117,7 +117,15 @@ def test_full_hd_sampled_pixels_and_gaussians():
     # gradients of sampled Gaussians: oracle image on each window, then the
     # oracle gradient of that Gaussian with dL/dC from the oracle image
     gx, gc, gr = f.backward(dev(rgb), dl)
-    sel = rng.choice(N, 24, replace=False)
+    _check_window_grads(xy, chol, rgb, frame, (gx, gc, gr), rng.choice(N, 24, replace=False))
+
+
+def _check_window_grads(xy, chol, rgb, frame, grads, sel):
+    """Gradients of Gaussians `sel` against the oracle: the oracle image on a
+    window round each one's 3-sigma box, dL/dC of the whole-frame MSE there,
+    and the oracle gradient of that one Gaussian."""
+    H, W = frame.shape[1:]
+    gx, gc, gr = (host(g) for g in grads)
     for n in sel:
         l1, l2, l3 = chol[n].astype(np.float64)
         rx, ry = 3 * abs(l1), 3 * math.hypot(l2, l3)
@@ -127,12 +135,43 @@ def test_full_hd_sampled_pixels_and_gaussians():
             continue
         ys, xs = np.mgrid[y0:y1, x0:x1]
         win = render_pixels(xy, chol, rgb, xs.ravel(), ys.ravel())["img"].reshape(3, y1 - y0, x1 - x0)
-        full_dl = np.zeros((3, y1 - y0, x1 - x0))
-        full_dl[:] = 2.0 * (win - frame[:, y0:y1, x0:x1]) / (3.0 * W * H)
+        full_dl = 2.0 * (win - frame[:, y0:y1, x0:x1]) / (3.0 * W * H)
         sub_xy = xy[n:n + 1] - np.array([x0, y0], np.float32)
         r = gradients(sub_xy, chol[n:n + 1], rgb[n:n + 1], full_dl, y1 - y0, x1 - x0)
-        got = {"xy": host(gx)[n:n + 1], "chol": host(gc)[n:n + 1], "rgb": host(gr)[n:n + 1]}
-        assert_grads_close(got, r)
+        assert_grads_close({"xy": gx[n:n + 1], "chol": gc[n:n + 1], "rgb": gr[n:n + 1]}, r)
+
+
+def test_maximum_sizes_forward_backward_fused():
+    """The largest shape the 16-bit tile and id key fields hold: N = 65536
+    Gaussians on 2048x2048 at T = 8 (256 x 256 = 65536 tiles), with the last
+    Gaussian in the last tile.  Sampled pixels (and the last tile's) against
+    the per-pixel oracle; render_bwd and the fused pass against the oracle's
+    gradients of sampled Gaussians, the last one included; the fused loss
+    against the oracle's MSE."""
+    print("maximum sizes render", flush=True)
+    W = H = 2048
+    N = 65536
+    frame, _ = synth.make_frame(W, H, seed=303)
+    xy, chol, rgb = synth.random_gaussians(N, W, H, seed=301, scale_lo=0.3, scale_hi=2.0)
+    xy[-1] = [W - 2.75, H - 1.5]
+    f = GpuFrame(W, H, N, 8)
+    P = [dev(xy), dev(chol), dev(rgb)]
+    img, dl, loss = f.forward(*P, dev(frame))
+    rng = np.random.default_rng(304)
+    ys, xs = np.mgrid[H - 8:H, W - 8:W]
+    px = np.concatenate([rng.integers(0, W, 300), xs.ravel()])
+    py = np.concatenate([rng.integers(0, H, 300), ys.ravel()])
+    assert_pixels_close(host(img)[:, py, px], render_pixels(xy, chol, rgb, px, py))
+    full = render_box(xy, chol, rgb, W, H, want_bounds=False)["img"]
+    assert float(loss) == pytest.approx(mse(full, frame), rel=1e-4)
+    sel = np.concatenate([rng.choice(N - 1, 12, replace=False), [N - 1]])
+    _check_window_grads(xy, chol, rgb, frame, f.backward(P[2], dl), sel)
+    g = [torch.zeros(N, d, device="cuda") for d in (2, 3, 3)]
+    floss = torch.empty((), device="cuda")
+    _lib.render_fused(f.shape, f.ws, P[2], dev(frame), *g, loss=floss)
+    torch.cuda.synchronize()
+    assert float(floss) == pytest.approx(mse(full, frame), rel=1e-4)
+    _check_window_grads(xy, chol, rgb, frame, g, sel)
 
 
 @pytest.mark.parametrize("T,ppl", VARIANTS)
@@ -141,7 +180,6 @@ def test_fused_render_matches_oracle_and_counts_pairs(T, ppl):
     oracle; the in-cutoff pair count vs the oracle's count."""
     print(f"fused T={T} ppl={ppl}", flush=True)
     from oracle.render import count_pairs_in_cutoff
-    from paper_2505_09324_amd import _lib
     frame, xy, chol, rgb = _c1()
     chol[:, 1] = np.random.default_rng(4).uniform(-1, 1, 500).astype(np.float32)
     f = GpuFrame(128, 128, 500, T, ppl=ppl)
