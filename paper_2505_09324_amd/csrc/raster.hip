@@ -6,8 +6,9 @@
 // handles the PPL vertically adjacent pixels (x0 + lx, y0 + ly*PPL + k),
 // which share d_x, u1 = d_x / l1 and u1^2.  The tile's Gaussian list is
 // staged through LDS in chunks; while staging, each Gaussian's 3-sigma box
-// is tested against every sub-block, and each wavefront compacts the chunk
-// into its own list of Gaussians whose box meets its sub-block.
+// and then its cutoff ellipse are tested against every sub-block, and each
+// wavefront compacts the chunk into its own list of the Gaussians that can
+// reach its sub-block's pixels.
 //
 // Per (pixel, Gaussian), with d = (x+1/2, y+1/2) - mu and u = L^-1 d:
 //   u1 = d1 / l1;  u2 = (d2 - l2 u1) / l3;  q = u1^2 + u2^2
@@ -41,7 +42,7 @@ k_render_fwd(FrameArgs f, const float *__restrict__ target, float *__restrict__ 
   for (int c = beg; c < end; c += CH) {
     const int cnt = min(CH, end - c);
     __syncthreads();
-    stage_chunk<TILE, PPL>(S, f.keys, c, cnt, tx, ty, f.geom, f.rgb);
+    stage_chunk<TILE, PPL>(S, f.keys, c, cnt, tx, ty, f.W, f.H, f.geom, f.rgb);
     __syncthreads();
     const int len = compact_chunk<C::NW>(S, cnt);
     __syncthreads();
@@ -103,12 +104,12 @@ k_render_bwd(FrameArgs f, const float *__restrict__ dl_dimg, float *__restrict__
   for (int c = beg; c < end; c += CH) {
     const int cnt = min(CH, end - c);
     __syncthreads();
-    stage_chunk<TILE, PPL>(S, f.keys, c, cnt, tx, ty, f.geom, f.rgb);
+    stage_chunk<TILE, PPL>(S, f.keys, c, cnt, tx, ty, f.W, f.H, f.geom, f.rgb);
     for (int i = threadIdx.x; i < CH * 8; i += C::NT) acc[i] = 0.f;
     __syncthreads();
     const int len = compact_chunk<C::NW>(S, cnt);
     __syncthreads();
-    bwd_chunk<C::NW, PPL, true>(S, acc, len, pxc, pyc0, g);
+    bwd_chunk<C::NW, PPL, false>(S, acc, len, pxc, pyc0, g);
     __syncthreads();
     flush_grads<C::NT, C::NW>(S, acc, cnt, g_xy, g_chol, g_rgb);
   }
@@ -147,7 +148,7 @@ k_count_pairs(FrameArgs f, unsigned long long *__restrict__ out) {
   for (int c = beg; c < end; c += CH) {
     const int cnt = min(CH, end - c);
     __syncthreads();
-    stage_chunk<TILE, 1>(S, f.keys, c, cnt, tx, ty, f.geom, nullptr);
+    stage_chunk<TILE, 1>(S, f.keys, c, cnt, tx, ty, f.W, f.H, f.geom, nullptr);
     __syncthreads();
     const int len = compact_chunk<C::NW>(S, cnt);
     __syncthreads();

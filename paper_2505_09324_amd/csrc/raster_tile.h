@@ -51,13 +51,56 @@ struct FrameArgs {
   const float *rgb;
 };
 
-// Stage keys[beg, beg+cnt) into LDS with their sub-block masks.
-template <int TILE, int PPL>
+// Whether the ellipse q' <= qmax (staged units: u1 = dx a, u2 = (dy - l2s u1)
+// r3s) reaches the rectangle [X0, X1] x [Y0, Y1].  q' is a convex quadratic,
+// so outside its centre its minimum over the rectangle lies on an edge that
+// faces the centre: on the edge x = Xe the minimum sits where u2 = 0 (dy =
+// l2s u1), clamped to the edge; on the edge y = Ye, q' = (a dx)^2 +
+// (e - c dx)^2 with c = l2s a r3s and e = dy r3s, minimised at dx = c e /
+// (a^2 + c^2), clamped.  A NaN anywhere counts as a hit.
+__device__ inline bool ellipse_meets_rect(float mx, float my, float a, float l2s, float r3s,
+                                          float X0, float X1, float Y0, float Y1, float qmax) {
+  const bool left = mx < X0, right = mx > X1, below = my < Y0, above = my > Y1;
+  if (!(left || right || below || above)) return true;
+  float best = INFINITY;
+  if (left || right) {
+    const float u1 = ((left ? X0 : X1) - mx) * a;
+    const float t = l2s * u1;
+    const float dy = fminf(fmaxf(t, Y0 - my), Y1 - my);
+    const float u2 = (dy - t) * r3s;
+    best = u1 * u1 + u2 * u2;
+  }
+  if (below || above) {
+    const float dy = (below ? Y0 : Y1) - my;
+    const float c = l2s * a * r3s, e = dy * r3s;
+    // an approximate reciprocal only moves the evaluated point off the
+    // minimiser, which raises q' by a second-order amount
+    const float dx = fminf(fmaxf(c * e * __builtin_amdgcn_rcpf(a * a + c * c), X0 - mx), X1 - mx);
+    const float u1 = dx * a;
+    const float u2 = (dy - l2s * u1) * r3s;
+    best = fminf(best, u1 * u1 + u2 * u2);
+  }
+  return !(best > qmax);
+}
+
+// Stage keys[beg, beg+cnt) into LDS with their sub-block masks: bit w is set
+// when the Gaussian's 3-sigma box meets sub-block w and, with EXACT, its
+// cutoff ellipse also comes within a rounding margin of one of the
+// sub-block's in-frame pixel centres (on fitted frames about one box-met
+// sub-block in six fails the ellipse test).  The margin, 0.01 (1 + |l2 /
+// l3|) in staged q units, bounds the rounding of both this test and the
+// per-pixel evaluation (each about 1e-5 (1 + |l2 / l3|)), so no sub-block
+// with a pixel the raster counts inside the cutoff is dropped.  Exact masks
+// leave few Gaussians without a pixel in the cutoff, so their users skip
+// the per-Gaussian hit checks; the persistent batched kernel, whose
+// register budget the test's live values overrun, keeps box masks.
+template <int TILE, int PPL, bool EXACT = true>
 __device__ inline void stage_chunk(Smem<Cfg<TILE, PPL>::NW> &S, const uint32_t *__restrict__ keys,
-                                   int beg, int cnt, int tx, int ty,
+                                   int beg, int cnt, int tx, int ty, int W, int H,
                                    const float4 *__restrict__ geom, const float *__restrict__ rgb) {
   using C = Cfg<TILE, PPL>;
   constexpr float inv_w = 0.125f, inv_h = 1.0f / (float)C::SBH;
+  const float xlast = (float)W - 0.5f, ylast = (float)H - 0.5f;  // last pixel centres
   for (int j = threadIdx.x; j < cnt; j += C::NT) {
     const int id = (int)(keys[beg + j] & 0xFFFFu);
     const float4 g0 = geom[2 * id], g1 = geom[2 * id + 1];
@@ -67,8 +110,9 @@ __device__ inline void stage_chunk(Smem<Cfg<TILE, PPL>::NW> &S, const uint32_t *
       c1 = rgb[3 * id + 1];
       c2 = rgb[3 * id + 2];
     }
-    S.A[j] = make_float4(g0.x, g0.y, g0.z * EXP_SCALE, g0.w * (1.0f / EXP_SCALE));
-    S.B[j] = make_float4(g1.x * EXP_SCALE, c0, c1, c2);
+    const float a = g0.z * EXP_SCALE, l2s = g0.w * (1.0f / EXP_SCALE), r3s = g1.x * EXP_SCALE;
+    S.A[j] = make_float4(g0.x, g0.y, a, l2s);
+    S.B[j] = make_float4(r3s, c0, c1, c2);
     S.id[j] = id;
     const float xlo = __fsub_rn(g0.x, g1.y), xhi = __fadd_rn(g0.x, g1.y);
     const float ylo = __fsub_rn(g0.y, g1.z), yhi = __fadd_rn(g0.y, g1.z);
@@ -79,9 +123,19 @@ __device__ inline void stage_chunk(Smem<Cfg<TILE, PPL>::NW> &S, const uint32_t *
     const float by1f = floorf(yhi * inv_h) - (float)(ty * C::SBY);
     const int bx0 = (int)fmaxf(bx0f, 0.f), bx1 = (int)fminf(bx1f, (float)(C::SBX - 1));
     const int by0 = (int)fmaxf(by0f, 0.f), by1 = (int)fminf(by1f, (float)(C::SBY - 1));
+    const float qmax = CUTOFF_QS + 0.01f * (1.0f + fabsf(l2s * r3s));
     uint32_t m = 0;
-    for (int by = by0; by <= by1; ++by)
-      for (int bx = bx0; bx <= bx1; ++bx) m |= 1u << (by * C::SBX + bx);
+    for (int by = by0; by <= by1; ++by) {
+      const float Y0 = (float)(ty * TILE + by * C::SBH) + 0.5f;
+      const float Y1 = fminf(Y0 + (float)(C::SBH - 1), ylast);
+      for (int bx = bx0; bx <= bx1; ++bx) {
+        const float X0 = (float)(tx * TILE + bx * 8) + 0.5f;
+        const float X1 = fminf(X0 + 7.0f, xlast);
+        if (!EXACT ||
+            (X0 <= X1 && Y0 <= Y1 && ellipse_meets_rect(g0.x, g0.y, a, l2s, r3s, X0, X1, Y0, Y1, qmax)))
+          m |= 1u << (by * C::SBX + bx);
+      }
+    }
     S.mask[j] = (uint16_t)m;
   }
 }
@@ -288,8 +342,9 @@ __device__ inline unsigned inside_mask(const FrameArgs &f, int px, int py0) {
 //
 // A list that fits one LDS chunk (the common case) is staged once; after
 // one barrier every wavefront compacts it to its sub-block, runs its
-// forward pass (keeping the Gaussians that reach its pixels), its residuals
-// and its backward pass on its own, and a second barrier precedes the flush
+// forward pass (with box masks also keeping only the Gaussians that reach
+// its pixels), its residuals and its backward pass on its own, and a second
+// barrier precedes the flush
 // of the tile's gradient accumulators.  Longer lists are staged chunk by
 // chunk, twice.
 template <int TILE, int PPL>
@@ -310,7 +365,7 @@ __device__ inline void residuals(const float (&a)[PPL][3], const float (&tg)[PPL
   *l = s;
 }
 
-template <int TILE, int PPL>
+template <int TILE, int PPL, bool EXACT = true>
 __device__ inline void fused_tile(Smem<Cfg<TILE, PPL>::NW> &S, float *acc, const FrameArgs &f,
                                   int tile, const float *__restrict__ target,
                                   float *__restrict__ loss_slots, float grad_scale,
@@ -340,11 +395,11 @@ __device__ inline void fused_tile(Smem<Cfg<TILE, PPL>::NW> &S, float *acc, const
   if (end - beg <= CH) {
     const int cnt = end - beg;
     __syncthreads();  // LDS of a previous tile (persistent callers) is free
-    stage_chunk<TILE, PPL>(S, f.keys, beg, cnt, tx, ty, f.geom, f.rgb);
+    stage_chunk<TILE, PPL, EXACT>(S, f.keys, beg, cnt, tx, ty, f.W, f.H, f.geom, f.rgb);
     for (int i = threadIdx.x; i < cnt * 8; i += C::NT) acc[i] = 0.f;
     __syncthreads();
     int len = compact_chunk<C::NW>(S, cnt);
-    len = fwd_chunk<C::NW, PPL, true>(S, len, pxc, pyc0, inside, a);
+    len = fwd_chunk<C::NW, PPL, !EXACT>(S, len, pxc, pyc0, inside, a);
     residuals<TILE, PPL>(a, tg, inside, grad_scale, g, &l);
     wave_loss(l, loss_slots + w);
     bwd_chunk<C::NW, PPL, false>(S, acc, len, pxc, pyc0, g);
@@ -355,7 +410,7 @@ __device__ inline void fused_tile(Smem<Cfg<TILE, PPL>::NW> &S, float *acc, const
   for (int c = beg; c < end; c += CH) {
     const int cnt = min(CH, end - c);
     __syncthreads();
-    stage_chunk<TILE, PPL>(S, f.keys, c, cnt, tx, ty, f.geom, f.rgb);
+    stage_chunk<TILE, PPL, EXACT>(S, f.keys, c, cnt, tx, ty, f.W, f.H, f.geom, f.rgb);
     __syncthreads();
     const int len = compact_chunk<C::NW>(S, cnt);
     fwd_chunk<C::NW, PPL, false>(S, len, pxc, pyc0, inside, a);
@@ -365,11 +420,11 @@ __device__ inline void fused_tile(Smem<Cfg<TILE, PPL>::NW> &S, float *acc, const
   for (int c = beg; c < end; c += CH) {
     const int cnt = min(CH, end - c);
     __syncthreads();
-    stage_chunk<TILE, PPL>(S, f.keys, c, cnt, tx, ty, f.geom, f.rgb);
+    stage_chunk<TILE, PPL, EXACT>(S, f.keys, c, cnt, tx, ty, f.W, f.H, f.geom, f.rgb);
     for (int i = threadIdx.x; i < cnt * 8; i += C::NT) acc[i] = 0.f;
     __syncthreads();
     const int len = compact_chunk<C::NW>(S, cnt);
-    bwd_chunk<C::NW, PPL, true>(S, acc, len, pxc, pyc0, g);
+    bwd_chunk<C::NW, PPL, !EXACT>(S, acc, len, pxc, pyc0, g);
     __syncthreads();
     flush_grads<C::NT, C::NW>(S, acc, cnt, g_xy, g_chol, g_rgb);
   }
