@@ -9,6 +9,7 @@ import torch
 
 from oracle.grads import gradients
 from oracle.loss import dloss_dimg, mse
+from oracle.gauss import mahalanobis_sq
 from oracle.render import render_box, render_bruteforce, render_pixels
 from paper_2505_09324_amd import _lib, synth
 from gpu_util import VARIANTS, GpuFrame, assert_grads_close, assert_pixels_close, dev, host
@@ -172,6 +173,66 @@ def test_maximum_sizes_forward_backward_fused():
     torch.cuda.synchronize()
     assert float(floss) == pytest.approx(mse(full, frame), rel=1e-4)
     _check_window_grads(xy, chol, rgb, frame, g, sel)
+
+
+def _marginal_gaussians(W, H, sbh, n, seed):
+    """n sheared Gaussians of mixed orientation, each with its mean outside
+    one 8 x sbh pixel block and its cutoff ellipse reaching that block only
+    just: the smallest q over the block's in-frame pixel centres lies 5e-4
+    to 4e-3 below 9 (FP64, on the FP32 parameters)."""
+    rng = np.random.default_rng(seed)
+    xy = np.zeros((n, 2), np.float32)
+    chol = np.zeros((n, 3), np.float32)
+    k = 0
+    while k < n:
+        bx, by = int(rng.integers(0, -(-W // 8))), int(rng.integers(0, -(-H // sbh)))
+        xs = np.arange(bx * 8, min(W, bx * 8 + 8)) + 0.5
+        ys = np.arange(by * sbh, min(H, by * sbh + sbh)) + 0.5
+        l = np.array([rng.uniform(0.4, 3.0) * rng.choice([-1.0, 1.0]), rng.uniform(-4.0, 4.0),
+                      rng.uniform(0.4, 3.0)])
+        side = [xs[0] - rng.uniform(0.2, 6.0), xs[-1] + rng.uniform(0.2, 6.0),
+                rng.uniform(xs[0], xs[-1])]
+        cx = side[rng.integers(0, 3)]
+        side = [ys[0] - rng.uniform(0.2, 6.0), ys[-1] + rng.uniform(0.2, 6.0),
+                rng.uniform(ys[0], ys[-1])]
+        cy = side[rng.integers(0, 3)]
+        if xs[0] <= cx <= xs[-1] and ys[0] <= cy <= ys[-1]:
+            continue
+        X, Y = np.meshgrid(xs, ys)
+        qmin = mahalanobis_sq(X - cx, Y - cy, *l).min()
+        l *= math.sqrt(qmin / rng.uniform(9.0 - 3e-3, 9.0 - 1e-3))  # q scales as 1 / s^2
+        mu, lf = np.array([cx, cy], np.float32), l.astype(np.float32)
+        q32 = mahalanobis_sq(X - float(mu[0]), Y - float(mu[1]), *lf.astype(np.float64)).min()
+        if not 9.0 - 4e-3 <= q32 <= 9.0 - 5e-4:
+            continue
+        xy[k], chol[k] = mu, lf
+        k += 1
+    return xy, chol
+
+
+@pytest.mark.parametrize("T,ppl", VARIANTS)
+def test_block_masks_keep_marginal_pixels(T, ppl):
+    """Gaussians whose cutoff ellipse reaches a neighbouring 8 x 8P pixel
+    block only just, on a ragged 123 x 90 frame: pixels and fused-pass
+    gradients against the oracle.  A block dropped by the staging's
+    ellipse test would lose an exp(-4.5) c' contribution, far above the
+    pixel tolerance (the marginal q lie outside the oracle's ambiguity
+    band)."""
+    print(f"marginal blocks T={T} ppl={ppl}", flush=True)
+    W, H, N = 123, 90, 300
+    xy, chol = _marginal_gaussians(W, H, 8 * ppl, N, seed=400 + 10 * T + ppl)
+    rgb = np.random.default_rng(401).uniform(0.2, 1.0, (N, 3)).astype(np.float32)
+    frame, _ = synth.make_frame(W, H, seed=402)
+    f = GpuFrame(W, H, N, T, ppl=ppl)
+    P = [dev(xy), dev(chol), dev(rgb)]
+    img, _, _ = f.forward(*P, dev(frame))
+    ref = render_bruteforce(xy, chol, rgb, H, W)
+    assert_pixels_close(host(img), ref)
+    g = [torch.zeros(N, d, device="cuda") for d in (2, 3, 3)]
+    _lib.render_fused(f.shape, f.ws, P[2], dev(frame), *g)
+    torch.cuda.synchronize()
+    want = gradients(xy, chol, rgb, dloss_dimg(ref["img"], frame), H, W)
+    assert_grads_close({"xy": host(g[0]), "chol": host(g[1]), "rgb": host(g[2])}, want)
 
 
 @pytest.mark.parametrize("T,ppl", VARIANTS)
