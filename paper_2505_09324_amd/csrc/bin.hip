@@ -87,19 +87,15 @@ k_project_wide(int N, int TX, int TY, float inv_tile, const float *__restrict__ 
 // thread per Gaussian applies Adam to its 8 parameters (gradients cleared)
 // and projects the updated Gaussian from its registers.  One extra block
 // (blockIdx.x == gridDim.x - 1) reduces the previous iteration's loss
-// partials into the trace.
+// partials into the trace.  Every thread reads the step (written only by
+// the later emission kernel) and derives the bias corrections itself, so
+// its parameter, gradient and moment loads wait for no barrier.
 __global__ void __launch_bounds__(WIDE_PROJ)
 k_adam_project_wide(int N, int TX, int TY, float inv_tile, PendingAdam a,
                     float4 *__restrict__ geom, int4 *__restrict__ rect, int *__restrict__ counts,
                     int *__restrict__ bsum, int *__restrict__ bcull) {
-  __shared__ float s_bc1, s_bc2;
-  __shared__ int s_t;
   __shared__ double red[WIDE_PROJ / 64];
-  if (threadIdx.x == 0) {
-    s_t = a.step[0];
-    adam_bias(s_t, a.cfg.beta1, a.cfg.beta2, &s_bc1, &s_bc2);
-  }
-  __syncthreads();
+  const int s_t = a.step[0];
   if (blockIdx.x == gridDim.x - 1) {  // the loss of the previous iteration
     double s = 0.0;
     s = thread_sum_parts(a.loss_part, a.n_part);
@@ -113,7 +109,9 @@ k_adam_project_wide(int N, int TX, int TY, float inv_tile, PendingAdam a,
     }
     return;
   }
-  const float bc1 = s_bc1, bc2 = s_bc2, b1 = a.cfg.beta1, b2 = a.cfg.beta2, eps = a.cfg.eps;
+  const float b1 = a.cfg.beta1, b2 = a.cfg.beta2, eps = a.cfg.eps;
+  float bc1, bc2;
+  adam_bias(s_t, b1, b2, &bc1, &bc2);
   const int n = blockIdx.x * WIDE_PROJ + threadIdx.x;
   int v = 0;
   if (n < N) {
