@@ -23,17 +23,12 @@ k_adam(int N, float *__restrict__ xy, float *__restrict__ chol, float *__restric
        float lr1, float lr2, float b1, float b2, float eps, const uint8_t *__restrict__ active,
        int zero_grads, const float *__restrict__ loss_part, int n_part, float loss_scale,
        float *__restrict__ loss_trace, int trace_len) {
-  __shared__ float s_bc1, s_bc2;
-  __shared__ int s_t;
   __shared__ double red[4];
-  if (threadIdx.x == 0) {
-    const int t = step[0];
-    s_t = t;
-    adam_bias(t, b1, b2, &s_bc1, &s_bc2);
-  }
-  __syncthreads();
-  const int t = s_t;
-  const float bc1 = s_bc1, bc2 = s_bc2;
+  // every thread reads the step (advanced only by a separate kernel) and
+  // derives the bias corrections itself: no barrier before the loads
+  const int t = step[0];
+  float bc1, bc2;
+  adam_bias(t, b1, b2, &bc1, &bc2);
   const int total = 8 * N;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
     float *p, *g;
