@@ -6,6 +6,7 @@
 #include <new>
 #include <vector>
 
+#include "bin_common.h"
 #include "gs2d_internal.h"
 
 namespace gs2d {
@@ -58,7 +59,7 @@ bool make_layout(const gs2d_shape &s, Layout *L) {
   // radix histogram rows: one per emission block (<= 256 rows of 256 words,
   // or <= 64 rows of up to 2048 words on the single-pass path), then one
   // per sort chunk of the second pass (<= 128 rows of 256 words)
-  L->hist = take((size_t)RADIX * 256 * 4 * 2);
+  L->hist = take(HIST_BYTES);
   L->tile_start = take(((size_t)L->n_tiles + 1) * 4);
   L->loss_parts = L->n_tiles * (s.tile / 8) * (s.tile / (8 * ppl));
   L->loss_part = take((size_t)L->loss_parts * 4);

@@ -167,8 +167,9 @@ k_emit_wide(int N, int TX, int nbp, int max_pairs, int D, const int4 *__restrict
     misc[MISC_STICKY] |= (int)st;
     if (tick) tick[0] += 1;
   }
-  emit_block_wide(blockIdx.x * WIDE_BLOCK, N, TX, pre, np, D, rect, counts, offsets, keys,
-                  hist + (size_t)blockIdx.x * D);
+  emit_block_wide(blockIdx.x * WIDE_BLOCK, N, TX, pre, end_keys, np, D, rect, counts, offsets,
+                  keys, hist + (size_t)blockIdx.x * D,
+                  hist + WIDE_PART_ROWS + (size_t)blockIdx.x * (WIDE_SPLIT - 1) * D);
 }
 
 __global__ void __launch_bounds__(WIDE_SCATTER)

@@ -19,6 +19,17 @@ constexpr int WIDE_MAX_TILES = 2048;  // largest digit range (11 bits)
 constexpr int WIDE_SCATTER = 512;     // threads of its scatter blocks
 constexpr int WIDE_SPLIT = 4;         // scatter blocks per emission chunk
 static_assert(WIDE_BLOCK * 64 >= 65536, "at most 64 emission blocks per frame");
+// Histogram area of the single-pass path (words): the chunk rows (chunk b at
+// b * D), then from WIDE_PART_ROWS the cumulative part rows (chunk b, row r
+// at WIDE_PART_ROWS + (b * (WIDE_SPLIT - 1) + r) * D).
+constexpr size_t WIDE_PART_ROWS = (size_t)64 * WIDE_MAX_TILES;
+constexpr size_t WIDE_HIST_WORDS = (size_t)64 * WIDE_MAX_TILES * WIDE_SPLIT;
+// Workspace bytes of the binning histograms: the radix path's per-block
+// rows or the single-pass path's chunk and cumulative part rows, whichever
+// is larger.
+constexpr size_t RADIX_HIST_BYTES = (size_t)RADIX * 256 * 4 * 2;
+constexpr size_t HIST_BYTES =
+    WIDE_HIST_WORDS * 4 > RADIX_HIST_BYTES ? WIDE_HIST_WORDS * 4 : RADIX_HIST_BYTES;
 
 // Projection of Gaussian n (index into xy/chol and the outputs).
 // counts[n] = number of tiles met, or -1 for a culled Gaussian (the scan
@@ -429,15 +440,29 @@ __device__ inline void tile_ranges(const uint32_t *__restrict__ keys, int n, int
 // ------------------------------------------------------ single-pass path --
 // Key emission as emit_block, by blocks of WIDE_BLOCK threads; the block's
 // keys are one chunk of the single radix pass whose digit is the whole tile
-// index: hist_row[t] (t < D) receives how many of them fall in tile t.
-__device__ inline void emit_block_wide(int base, int N, int TX, long long block_off, int n_keys,
-                                       int D, const int4 *__restrict__ rect,
+// index: hist_row[t] (t < D) receives how many of them fall in tile t, and
+// part_rows[r * D + t] how many of them fall in tile t within the chunk's
+// first r + 1 scatter parts (the split the scatter uses: WIDE_SPLIT parts
+// of q = ceil(keys / WIDE_SPLIT) keys), for r < WIDE_SPLIT - 1.
+__device__ inline void emit_block_wide(int base, int N, int TX, long long block_off,
+                                       long long block_end, int n_keys, int D,
+                                       const int4 *__restrict__ rect,
                                        const int *__restrict__ counts, int *__restrict__ offsets,
                                        uint32_t *__restrict__ keys,
-                                       uint32_t *__restrict__ hist_row) {
+                                       uint32_t *__restrict__ hist_row,
+                                       uint32_t *__restrict__ part_rows) {
+  constexpr int NP = WIDE_SPLIT - 1;
   __shared__ int lds[WIDE_BLOCK / 64];
   __shared__ uint32_t h[WIDE_MAX_TILES];
-  for (int d = threadIdx.x; d < D; d += WIDE_BLOCK) h[d] = 0;
+  __shared__ uint32_t hp[NP][WIDE_MAX_TILES];
+  for (int d = threadIdx.x; d < D; d += WIDE_BLOCK) {
+    h[d] = 0;
+#pragma unroll
+    for (int r = 0; r < NP; ++r) hp[r][d] = 0;
+  }
+  const int cbeg = (int)min(block_off, (long long)n_keys);
+  const int cend = (int)min(block_end, (long long)n_keys);
+  const int q = (cend - cbeg + WIDE_SPLIT - 1) / WIDE_SPLIT;  // >= 1 when a key exists
   const int n = base + (int)threadIdx.x;
   int c = 0;
   if (n < N) {
@@ -459,19 +484,29 @@ __device__ inline void emit_block_wide(int base, int N, int TX, long long block_
           const uint32_t tile = (uint32_t)(ty * TX + tx);
           keys[k] = (tile << 16) | (uint32_t)n;
           atomicAdd(&h[tile], 1u);
+          const int part = (k - cbeg) / q;
+          if (part < NP) atomicAdd(&hp[part][tile], 1u);
         }
     }
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < D; d += WIDE_BLOCK) hist_row[d] = h[d];
+  for (int d = threadIdx.x; d < D; d += WIDE_BLOCK) {
+    hist_row[d] = h[d];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int r = 0; r < NP; ++r) {
+      acc += hp[r][d];
+      part_rows[(size_t)r * D + d] = acc;
+    }
+  }
 }
 
 // Stable scatter of part `part` (of WIDE_SPLIT equal parts) of chunk b (the
 // keys emission block b wrote; its bounds from the nbp projection-block
 // sums) on the whole tile index (D = 2^bits >= n_tiles digits) by one block
 // of WIDE_SCATTER threads, from the `nb` histogram rows (row r = chunk r, D
-// words each); the chunk's earlier parts are counted into the offsets with
-// LDS atomics.
+// words each) and, for part > 0, the chunk's cumulative part row part - 1
+// (its earlier parts' keys per tile).
 // Each key goes to (keys of lower tiles in all chunks) + (keys of its tile
 // in earlier chunks) + (earlier keys of its tile in this chunk).  Block 0
 // also writes tile_start[0, n_tiles] (the per-tile totals' exclusive
@@ -510,6 +545,10 @@ __device__ inline void scatter_chunk_wide(const uint32_t *__restrict__ in,
   uint4 h[RB];
 #pragma unroll
   for (int j = 0; j < RB; ++j) h[j] = h4[(size_t)min(r0 + j * K, nb - 1) * C + cq];
+  uint4 early = make_uint4(0u, 0u, 0u, 0u);  // this chunk's earlier parts, per digit
+  if (part > 0 && r0 == 0)
+    early = reinterpret_cast<const uint4 *>(
+        hist + WIDE_PART_ROWS + ((size_t)b * (WIDE_SPLIT - 1) + part - 1) * D)[cq];
   long long pre_keys, end_keys, total;
   int culled;
   chunk_bounds<NT>(nbp, b, WIDE_GROUP, bsum, bcull, &pre_keys, &end_keys, &total, &culled);
@@ -571,10 +610,10 @@ __device__ inline void scatter_chunk_wide(const uint32_t *__restrict__ in,
   if (r0 == 0) {
     const uint32_t b0 = ex, b1 = b0 + tot.x, b2 = b1 + tot.y, b3 = b2 + tot.z;
     const int d = 4 * cq;
-    off[d + 0] = b0 + pre.x;
-    off[d + 1] = b1 + pre.y;
-    off[d + 2] = b2 + pre.z;
-    off[d + 3] = b3 + pre.w;
+    off[d + 0] = b0 + pre.x + early.x;
+    off[d + 1] = b1 + pre.y + early.y;
+    off[d + 2] = b2 + pre.z + early.z;
+    off[d + 3] = b3 + pre.w + early.w;
     if (first) {
       if (d + 0 < n_tiles) tile_start[d + 0] = (int)b0;
       if (d + 1 < n_tiles) tile_start[d + 1] = (int)b1;
@@ -584,13 +623,6 @@ __device__ inline void scatter_chunk_wide(const uint32_t *__restrict__ in,
   }
   if (first && tid == 0) tile_start[n_tiles] = n;
   __syncthreads();
-  // keys of this chunk's earlier parts precede this part's keys of the
-  // same tile
-  if (beg > cbeg) {
-#pragma unroll 4
-    for (int i = cbeg + tid; i < beg; i += NT) atomicAdd(&off[in[i] >> 16], 1u);
-    __syncthreads();
-  }
   const unsigned long long lt = lanemask_lt();
   const unsigned long long me = 1ull << lane;
   for (int gbase = beg; gbase < end; gbase += KPT * NT) {
