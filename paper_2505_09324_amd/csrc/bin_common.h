@@ -451,14 +451,13 @@ __device__ inline void emit_block_wide(int base, int N, int TX, long long block_
                                        uint32_t *__restrict__ keys,
                                        uint32_t *__restrict__ hist_row,
                                        uint32_t *__restrict__ part_rows) {
-  constexpr int NP = WIDE_SPLIT - 1;
+  // one LDS count per key, into its part's histogram; the chunk row is the
+  // sum of the parts
   __shared__ int lds[WIDE_BLOCK / 64];
-  __shared__ uint32_t h[WIDE_MAX_TILES];
-  __shared__ uint32_t hp[NP][WIDE_MAX_TILES];
+  __shared__ uint32_t hp[WIDE_SPLIT][WIDE_MAX_TILES];
   for (int d = threadIdx.x; d < D; d += WIDE_BLOCK) {
-    h[d] = 0;
 #pragma unroll
-    for (int r = 0; r < NP; ++r) hp[r][d] = 0;
+    for (int r = 0; r < WIDE_SPLIT; ++r) hp[r][d] = 0;
   }
   const int cbeg = (int)min(block_off, (long long)n_keys);
   const int cend = (int)min(block_end, (long long)n_keys);
@@ -483,21 +482,19 @@ __device__ inline void emit_block_wide(int base, int N, int TX, long long block_
         for (int tx = rc.x; tx <= rc.z && k < end; ++tx, ++k) {
           const uint32_t tile = (uint32_t)(ty * TX + tx);
           keys[k] = (tile << 16) | (uint32_t)n;
-          atomicAdd(&h[tile], 1u);
-          const int part = (k - cbeg) / q;
-          if (part < NP) atomicAdd(&hp[part][tile], 1u);
+          atomicAdd(&hp[(k - cbeg) / q][tile], 1u);  // part < WIDE_SPLIT: k < cbeg + WIDE_SPLIT q
         }
     }
   }
   __syncthreads();
   for (int d = threadIdx.x; d < D; d += WIDE_BLOCK) {
-    hist_row[d] = h[d];
     uint32_t acc = 0;
 #pragma unroll
-    for (int r = 0; r < NP; ++r) {
+    for (int r = 0; r < WIDE_SPLIT - 1; ++r) {
       acc += hp[r][d];
       part_rows[(size_t)r * D + d] = acc;
     }
+    hist_row[d] = acc + hp[WIDE_SPLIT - 1][d];
   }
 }
 
