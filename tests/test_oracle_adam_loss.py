@@ -92,3 +92,33 @@ def test_loss_gradient_is_derivative_of_mse():
     e[1, 2, 3] = 1e-6
     assert (mse(a + e, b) - mse(a - e, b)) / 2e-6 == pytest.approx(g[1, 2, 3], rel=1e-6)
     assert psnr_from_mse(0.0) == math.inf
+
+
+@pytest.mark.parametrize("wd", [0.0, 0.05])
+def test_adamw_matches_torch_adamw(wd):
+    """Decoupled decay: six steps against torch.optim.AdamW (FP64, CPU)."""
+    from oracle.adam import adamw_step
+    rng = np.random.default_rng(9)
+    p = rng.normal(size=257)
+    m = np.zeros(257)
+    v = np.zeros(257)
+    tp = torch.tensor(p.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.AdamW([tp], lr=3e-3, betas=(0.9, 0.999), eps=1e-8, weight_decay=wd)
+    t = 0
+    for _ in range(6):
+        g = rng.normal(size=257)
+        p, m, v, t = adamw_step(p, g, m, v, t, 3e-3, wd)
+        tp.grad = torch.tensor(g)
+        opt.step()
+    np.testing.assert_allclose(p, tp.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_adamw_decay_is_not_in_the_moments():
+    """With a zero gradient the moments stay zero and the parameters shrink
+    by exactly (1 - lr wd): the decay bypasses the adaptive scaling (an L2
+    term added to the gradient would instead move p by about lr per step)."""
+    from oracle.adam import adamw_step
+    p0 = np.array([2.0, -0.5, 1e-3])
+    p, m, v, t = adamw_step(p0, np.zeros(3), np.zeros(3), np.zeros(3), 0, 0.1, 0.2)
+    np.testing.assert_allclose(p, p0 * (1 - 0.1 * 0.2), rtol=1e-15)
+    assert not m.any() and not v.any() and t == 1

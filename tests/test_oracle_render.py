@@ -118,3 +118,55 @@ def test_pairs_in_cutoff_matches_ellipse_area():
     l = (4.0, 1.0, 3.0)
     n = count_pairs_in_cutoff(np.array([[50.3, 50.1]]), np.array([l]), 100, 100)
     assert abs(n - 9 * math.pi * 12.0) / (9 * math.pi * 12.0) < 0.02
+
+
+def test_render_pixels_equals_bruteforce_at_sampled_pixels():
+    """The per-pixel evaluator that checks large frames: at sampled pixels
+    (corners and edges included) it must give the brute-force image, the
+    absolute sum and the ambiguity-band mass, with culled Gaussians (NaN,
+    inf, |l1| or |l3| below 2^-14), off-frame means and huge, sheared and
+    negative-diagonal Gaussians in the set."""
+    from oracle.render import render_pixels
+    W, H, N = 57, 43, 160
+    xy, chol, rgb = synth.random_gaussians(N, W, H, seed=21, scale_lo=0.3, scale_hi=7.0)
+    rng = np.random.default_rng(22)
+    chol[:, 1] = rng.uniform(-4, 4, N)
+    chol[::9, 0] *= -1
+    chol[::11, 2] *= -1
+    xy[:12] = rng.uniform(-25, 80, size=(12, 2))
+    xy[12] = [np.nan, 3.0]
+    chol[13] = [np.inf, 0.0, 1.0]
+    chol[14] = [0.5 * 2.0 ** -14, 0.0, 2.0]
+    chol[15] = [2.0, 0.0, 0.0]
+    chol[16] = [60.0, -20.0, 45.0]
+    rgb[:] = rng.uniform(-1.0, 1.0, (N, 3))
+    full = render_bruteforce(xy, chol, rgb, H, W)
+    px = np.concatenate([rng.integers(0, W, 200), [0, W - 1, 0, W - 1]])
+    py = np.concatenate([rng.integers(0, H, 200), [0, 0, H - 1, H - 1]])
+    got = render_pixels(xy, chol, rgb, px, py)
+    for k in ("img", "abs", "amb"):
+        np.testing.assert_allclose(got[k], full[k][:, py, px], rtol=1e-12, atol=1e-14)
+    assert np.any(full["img"][:, py, px] != 0.0)
+
+
+def test_render_pixels_single_gaussian_matches_scipy_density():
+    """P1 at arbitrary pixels: one Gaussian's value is c' times the scipy
+    normal density scaled by 2 pi sqrt(det Sigma), cut at q <= 9 computed
+    from numpy's inverse of L L^T."""
+    from oracle.render import render_pixels
+    l = (2.3, -1.1, 1.4)
+    mu = np.array([31.7, 18.2])
+    c = np.array([0.6, -0.4, 1.2])
+    S = _sigma(l)
+    rv = multivariate_normal(mean=mu, cov=S)
+    rng = np.random.default_rng(23)
+    px = rng.integers(20, 44, 400)
+    py = rng.integers(10, 27, 400)
+    pts = np.stack([px + 0.5, py + 0.5], -1)
+    d = pts - mu
+    q = np.einsum("pi,ij,pj->p", d, np.linalg.inv(S), d)
+    w = np.where(q <= 9.0, rv.pdf(pts) * 2 * math.pi * math.sqrt(np.linalg.det(S)), 0.0)
+    got = render_pixels(mu[None], np.array([l]), c[None], px, py)["img"]
+    assert np.count_nonzero(w) > 50 and np.count_nonzero(w == 0.0) > 50
+    for k in range(3):
+        np.testing.assert_allclose(got[k], c[k] * w, rtol=1e-12, atol=1e-15)
