@@ -334,13 +334,26 @@ int gs2d_cnn_targets(int32_t H, int32_t W, int32_t N, const float *xy, const flo
  * (slot s < count: the target in loss units, else 0). */
 int gs2d_cnn_read_targets(int32_t H, int32_t W, const void *ws, size_t ws_bytes, int32_t *counts,
                           float *vectors, void *stream);
+/* Device view of a tensor the last forward / backward pass left in `ws`
+ * (read-only; valid until the next call on that workspace), for inspecting
+ * one layer at a time.  which = 0: the input activations of `layer`, BF16
+ * channels-last [Hin][Win][Cin] (layer 0: the 3 colour and 3 residual
+ * channels padded to 8 with zeros; layer l > 0: layer l-1's ReLU output);
+ * which = 1: the gradient of the loss w.r.t. the output of `layer` with the
+ * ReLU mask applied, BF16 [Hout][Wout][CoutS] (CoutS = Cout rounded up to
+ * 8; the head's entry holds the loss gradient of the 73 head channels).
+ * *ptr receives the device address, dims[3] = (rows, columns, channel
+ * stride).  Host-only. */
+int gs2d_cnn_tensor_view(int32_t H, int32_t W, int32_t layer, int32_t which, const void *ws,
+                         size_t ws_bytes, const void **ptr, int32_t *dims);
 /* Loss of the last forward pass against the stored targets and the backward
  * pass: weight and bias gradients are ADDED to grad [param_count];
  * loss3 (nullable) = {total, mean CE, mean Chamfer}. */
 int gs2d_cnn_backward(int32_t H, int32_t W, const float *master, const uint16_t *wbf16,
                       float *grad, float *loss3, void *ws, size_t ws_bytes, void *stream);
-/* Adam on the master weights (step: device int32 counter, incremented),
- * decoupled weight decay, clears grad, and writes each updated weight to its
+/* Adam on the master weights (step: device int32 counter, incremented) with
+ * decoupled weight decay, w <- w - lr (m_hat / (sqrt(v_hat) + 1e-8) + wd w),
+ * betas (0.9, 0.999); clears grad, and writes each updated weight to its
  * BF16 copies in the same pass.  wbf16 must have been filled once by
  * gs2d_cnn_sync_weights: the zero padding of the transposed copies is not
  * rewritten here. */

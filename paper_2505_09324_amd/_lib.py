@@ -103,6 +103,8 @@ _SIGS = {
                                    c_void_p, c_size_t, c_void_p, c_size_t, c_void_p]),
     "gs2d_cnn_read_targets": (c_int32, [c_int32, c_int32, c_void_p, c_size_t, c_void_p, c_void_p,
                                         c_void_p]),
+    "gs2d_cnn_tensor_view": (c_int32, [c_int32, c_int32, c_int32, c_int32, c_void_p, c_size_t,
+                                       POINTER(c_void_p), c_void_p]),
     "gs2d_cnn_backward": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_void_p, c_size_t, c_void_p]),
     "gs2d_cnn_adam": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -491,6 +493,22 @@ class CNNInit:
             self.H, self.W, _ptr(self.ws, "ws", torch.uint8), self.ws.numel(),
             _ptr(counts, "counts", torch.int32), _ptr(vec, "vec"), _stream()))
         return counts, vec
+
+    def tensor(self, layer, which):
+        """A copy of a layer tensor the last forward / backward pass left in
+        the workspace (which = 0: the layer's BF16 input activations, 1: the
+        BF16 gradient w.r.t. its output), as a float32 host array
+        [channels][rows][columns] (all stored channels, padding included)."""
+        import numpy as np
+        ptr = c_void_p()
+        dims = (c_int32 * 3)()
+        _check("gs2d_cnn_tensor_view", lib().gs2d_cnn_tensor_view(
+            self.H, self.W, int(layer), int(which), _ptr(self.ws, "ws", torch.uint8), self.ws.numel(),
+            ctypes.byref(ptr), dims))
+        rows, cols, ch = dims[0], dims[1], dims[2]
+        raw = _slice(self.ws, ptr.value, rows * cols * ch, torch.int16).cpu().numpy()
+        bits = raw.view(np.uint16).astype(np.uint32) << 16
+        return bits.view(np.float32).reshape(rows, cols, ch).transpose(2, 0, 1).copy()
 
     def backward(self):
         """Head loss + full backward; gradients ADDED to self.grad (cleared by step)."""

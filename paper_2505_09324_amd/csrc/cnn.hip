@@ -878,13 +878,14 @@ k_cnn_adam(size_t n, CnnParamMap map, float *__restrict__ p, float *__restrict__
   const float bc1 = s_bc1, bc2 = s_bc2;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
        i += (size_t)gridDim.x * blockDim.x) {
-    const float gr = g[i] + wd * p[i];
+    const float gr = g[i], p0 = p[i];
     g[i] = 0.f;
     const float mm = b1 * m[i] + (1.f - b1) * gr;
     const float vv = b2 * v[i] + (1.f - b2) * gr * gr;
     m[i] = mm;
     v[i] = vv;
-    const float pn = p[i] - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+    // the decay acts on the weight itself, outside the adaptive scaling
+    const float pn = p0 - lr * ((mm / bc1) / (sqrtf(vv / bc2) + eps) + wd * p0);
     p[i] = pn;
     int l = 0;
 #pragma unroll
@@ -1239,6 +1240,30 @@ int gs2d_cnn_targets(int32_t H, int32_t W, int32_t N, const float *xy, const flo
   hipLaunchKernelGGL(k_count_target_tiles, dim3(1), dim3(256), 0, st, C.n_tiles,
                      at<const int>(ws, C.tcount), at<int>(ws, C.ncd));
   return hipGetLastError() == hipSuccess ? GS2D_OK : GS2D_EHIP;
+}
+
+int gs2d_cnn_tensor_view(int32_t H, int32_t W, int32_t layer, int32_t which, const void *ws,
+                         size_t ws_bytes, const void **ptr, int32_t *dims) {
+  CnnLayout C;
+  if (!cnn_layout(H, W, &C) || layer < 0 || layer >= NLAYER || !ws || !ptr || !dims)
+    return GS2D_EINVAL;
+  if (ws_bytes < C.total) return GS2D_ENOSPACE;
+  const ConvDims &d = C.L[layer];
+  const char *b = static_cast<const char *>(ws);
+  if (which == 0) {  // the layer's input activations
+    *ptr = b + (layer == 0 ? C.x_in : C.act[layer - 1]);
+    dims[0] = d.Hin;
+    dims[1] = d.Win;
+    dims[2] = d.Cin;
+  } else if (which == 1) {  // dLoss / d(layer output), ReLU mask applied
+    *ptr = b + C.dz[layer];
+    dims[0] = d.Hout;
+    dims[1] = d.Wout;
+    dims[2] = d.CoutS;
+  } else {
+    return GS2D_EINVAL;
+  }
+  return GS2D_OK;
 }
 
 int gs2d_cnn_read_targets(int32_t H, int32_t W, const void *ws, size_t ws_bytes, int32_t *counts,

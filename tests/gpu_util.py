@@ -4,7 +4,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-from paper_2505_09324_amd import _lib
+from paper_2505_09324_amd import _lib, synth
 
 DEV = "cuda"
 
@@ -77,3 +77,25 @@ def assert_grads_close(gpu, ref, rel=1e-3):
 
 # every compiled raster variant: (tile, pixels per lane)
 VARIANTS = [(8, 1), (16, 1), (16, 2), (32, 1), (32, 2), (32, 4)]
+
+
+def dense_long_lists():
+    """A dense 90x70 frame of 3000 large, sheared, zero-mean-colour
+    Gaussians: tile lists reach 806 (tile 8), 1119 (16) and 1657 (32)
+    entries, i.e. up to seven LDS chunks of 256."""
+    W, H, N = 90, 70, 3000
+    xy, chol, rgb = synth.random_gaussians(N, W, H, seed=31, scale_lo=1.5, scale_hi=9.0)
+    chol[:, 1] = np.random.default_rng(32).uniform(-3, 3, N).astype(np.float32)
+    rgb -= 0.5
+    frame, _ = synth.make_frame(W, H, seed=33)
+    return W, H, N, frame, xy, chol, rgb
+
+
+def loss_bound(ref, frame):
+    """Largest |loss_gpu - loss_ref| that pixels within their own bar
+    (|dC| <= 1e-4 A + Amb) allow, plus FP32 summation slack."""
+    b = 1e-4 * ref["abs"] + ref["amb"]
+    r = np.abs(ref["img"] - frame)
+    lo = float(((ref["img"] - frame) ** 2).mean())
+    return float((2 * r * b + b * b).sum() / r.size) + 1e-6 * lo
+

@@ -10,7 +10,7 @@ from oracle.grads import gradients
 from oracle.loss import dloss_dimg, mse
 from oracle.render import render_box
 from paper_2505_09324_amd import _lib, synth
-from gpu_util import DEV, VARIANTS, assert_grads_close, dev, host
+from gpu_util import DEV, VARIANTS, assert_grads_close, dense_long_lists, dev, host, loss_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -169,3 +169,45 @@ def test_autotune_cache_on_device(tmp_path):
                                                      cache_path=path)
     assert cached2 and cfg2 == cfg and ms2 == {}
 
+
+
+def test_batch_long_lists_every_variant():
+    """The persistent batched kernel on a frame whose tile lists exceed 256
+    and 512 entries (up to seven LDS chunks), beside a sparse frame: lists
+    bit-exact, loss and every gradient element of both frames against the
+    oracle, for every (tile, pixels per lane) variant."""
+    W, H, N, frame, xy, chol, rgb = dense_long_lists()
+    f2, _ = synth.make_frame(64, 48, seed=34)
+    xy2, chol2, rgb2 = synth.random_gaussians(150, 64, 48, seed=35, scale_lo=0.8, scale_hi=4.0)
+    sizes = [(W, H, N), (64, 48, 150)]
+    frames = [frame, f2]
+    params = [(xy, chol, rgb), (xy2, chol2, rgb2)]
+    targets = np.concatenate([a.ravel() for a in frames])
+    cat = [np.concatenate([p[k] for p in params]) for k in range(3)]
+    refs = []
+    for (w, h, n), fr, (a, b, c) in zip(sizes, frames, params):
+        r = render_box(a, b, c, h, w)
+        refs.append((r, gradients(a, b, c, dloss_dimg(r["img"], fr), h, w)))
+    Nt = N + 150
+    for T, ppl in VARIANTS:
+        print(f"batch long lists T={T} ppl={ppl}", flush=True)
+        ws = torch.empty(_lib.batch_workspace_bytes(sizes, T, ppl), dtype=torch.uint8, device=DEV)
+        g = [torch.zeros(Nt, d, device=DEV) for d in (2, 3, 3)]
+        loss = torch.zeros(2, device=DEV)
+        _lib.batch_render_grads(sizes, T, ppl, dev(targets), dev(cat[0]), dev(cat[1]),
+                                dev(cat[2]), *g, ws, loss_per_frame=loss)
+        torch.cuda.synchronize()
+        gx = _split(host(g[0]).ravel(), sizes, 2)
+        gc = _split(host(g[1]).ravel(), sizes, 3)
+        gr = _split(host(g[2]).ravel(), sizes, 3)
+        for fi, ((w, h, n), fr, (a, b, c)) in enumerate(zip(sizes, frames, params)):
+            bb = _lib.read_batch_bins(sizes, T, ppl, fi, ws)
+            ob = bin_gaussians(a, b, w, h, T)
+            np.testing.assert_array_equal(bb["keys"].astype(np.int64),
+                                          ob["pair_tiles"] * 65536 + ob["pair_ids"])
+            np.testing.assert_array_equal(bb["tile_start"], ob["tile_start"])
+            if fi == 0:
+                assert np.diff(ob["tile_start"]).max() > 512
+            r, want = refs[fi]
+            assert abs(float(loss[fi]) - mse(r["img"], fr)) <= loss_bound(r, fr)
+            assert_grads_close({"xy": gx[fi], "chol": gc[fi], "rgb": gr[fi]}, want)

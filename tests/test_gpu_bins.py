@@ -109,3 +109,68 @@ def test_bins_all_culled_and_empty_lists():
     out = f.bin(dev(xy), dev(chol))
     assert out["n_pairs"] == 0 and out["n_culled"] == 10
     assert np.all(out["tile_start"] == 0)
+
+
+def _content_aware(W, H, N, frame_seed, init_seed):
+    from oracle.init import init_from_frame
+    frame, mask = synth.make_frame(W, H, seed=frame_seed)
+    xy, chol, rgb, _ = init_from_frame(frame, mask, synth.init_draws(N, seed=init_seed))
+    return xy, chol
+
+
+def test_bins_1080p_content_aware_single_pass_sort():
+    """The fitting workload's binning: 1920x1080, 30k Gaussians from the
+    content-aware ROI initialisation, tile 32 (2040 tiles, so the one-pass
+    sort over 30 emission chunks of 1024 Gaussians, each scattered by four
+    blocks).  Then the same set sheared and rescaled the way a fit moves it
+    (l2 != 0, mixed scales).  Keys, tile ranges, counts and offsets are
+    bit-identical to the oracle."""
+    print("bins 1080p content-aware T=32 single pass", flush=True)
+    W, H, N = 1920, 1080, 30000
+    xy, chol = _content_aware(W, H, N, 201, 202)
+    f = GpuFrame(W, H, N, 32, ppl=2)
+    _compare(f.bin(dev(xy), dev(chol)), bin_gaussians(xy, chol, W, H, 32), N)
+    rng = np.random.default_rng(205)
+    chol2 = chol * rng.uniform(0.5, 2.5, (N, 1)).astype(np.float32)
+    chol2[:, 1] = rng.uniform(-4, 4, N).astype(np.float32)
+    xy2 = xy + rng.normal(0, 3, (N, 2)).astype(np.float32)
+    _compare(f.bin(dev(xy2), dev(chol2)), bin_gaussians(xy2, chol2, W, H, 32), N)
+
+
+@pytest.mark.parametrize("T,W,H", [(8, 357, 355), (16, 701, 695), (32, 1401, 1397)])
+def test_bins_ragged_multi_chunk_single_pass(T, W, H):
+    """About 5000 Gaussians (five emission chunks, the last one partial) on
+    ragged frames just under the one-pass sort's 2048-tile limit (45 x 45 or
+    44 x 44 tiles), with off-frame, culled, sheared and large Gaussians."""
+    print(f"bins ragged multi-chunk T={T} {W}x{H}", flush=True)
+    N = 4999
+    xy, chol, _ = synth.random_gaussians(N, W, H, seed=600 + T, scale_lo=0.3, scale_hi=3.0 * T / 8)
+    rng = np.random.default_rng(610 + T)
+    chol[:, 1] = rng.uniform(-T / 4, T / 4, N).astype(np.float32)
+    chol[::13, 2] *= -1
+    xy[:50] = rng.uniform(-3 * T, W + 3 * T, size=(50, 2)).astype(np.float32)
+    xy[60:63] = np.nan
+    chol[70:73, 0] = 0.0
+    f = GpuFrame(W, H, N, T)
+    ref = bin_gaussians(xy, chol, W, H, T)
+    out = f.bin(dev(xy), dev(chol))
+    assert out["n_tiles"] <= 2048 and out["n_tiles"] > 1900
+    _compare(out, ref, N)
+    assert out["n_culled"] == 6
+
+
+def test_bins_single_pass_limits():
+    """The one-pass sort at its limits: exactly 2048 tiles (2048 x 1024 at
+    tile 32) with the maximum 65536 Gaussians (64 emission chunks), the last
+    Gaussian in the last tile."""
+    print("bins single-pass limits", flush=True)
+    W, H, N = 2048, 1024, 65536
+    xy, chol, _ = synth.random_gaussians(N, W, H, seed=620, scale_lo=0.5, scale_hi=12.0)
+    chol[:, 1] = np.random.default_rng(621).uniform(-3, 3, N).astype(np.float32)
+    xy[-1] = [W - 1.0, H - 1.0]
+    chol[-1] = [0.5, 0.0, 0.5]
+    f = GpuFrame(W, H, N, 32)
+    out = f.bin(dev(xy), dev(chol))
+    assert out["n_tiles"] == 2048
+    _compare(out, bin_gaussians(xy, chol, W, H, 32), N)
+    assert int(out["keys"][out["n_pairs"] - 1]) == (2047 << 16) | (N - 1)

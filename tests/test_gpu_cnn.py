@@ -200,3 +200,163 @@ def test_trained_initialiser_beats_plain_init_at_fixed_budget():
     print({k: [round(x, 2) for x in v] for k, v in gains.items()}, flush=True)
     assert np.mean(gains[50]) >= 1.5, gains
     assert np.mean(gains[100]) >= 1.0, gains
+
+
+def _half_ulp_bf16(x):
+    """Half a bfloat16 unit in the last place at magnitude |x| (normal
+    range): bfloat16 keeps 8 significant bits."""
+    a = np.maximum(np.abs(x), 2.0 ** -126)
+    return 0.5 * 2.0 ** (np.floor(np.log2(a)) - 7)
+
+
+def _close_bf16(got, want, acc, what):
+    """A BF16 output rounded once from an FP32 accumulation: within half a
+    BF16 ulp of (|want| + acc) plus the accumulation bound acc."""
+    bound = _half_ulp_bf16(np.abs(want) + acc) + acc + 1e-30
+    err = np.abs(got.astype(np.float64) - want)
+    bad = err > bound
+    assert not bad.any(), (what, int(bad.sum()), bad.size, float((err - bound)[bad].max()))
+
+
+def _chamfer_ties(head, targets, rel=1e-4):
+    """Slot rows of the head whose Chamfer gradient depends on a nearest-
+    neighbour choice that is within `rel` of a tie (FP32 and FP64 may pick
+    differently there): boolean [8, TY, TX]."""
+    _, TY, TX = head.shape
+    amb = np.zeros((8, TY, TX), bool)
+    for t, Q in targets.items():
+        ty, tx = divmod(t, TX)
+        k = len(Q)
+        if k == 0:
+            continue
+        _, P = ocnn.slot_vectors(head[:, ty, tx].astype(np.float64))
+        d = ((P[:k, None, :] - np.asarray(Q)[None]) ** 2).sum(-1)
+        for i in range(k):                     # nearest target of each slot
+            s = np.sort(d[i])
+            if k > 1 and s[1] - s[0] <= rel * max(s[1], 1e-30):
+                amb[i, ty, tx] = True
+        for j in range(k):                     # nearest slot of each target
+            s = np.argsort(d[:, j])
+            if k > 1 and d[s[1], j] - d[s[0], j] <= rel * max(d[s[1], j], 1e-30):
+                amb[s[0], ty, tx] = amb[s[1], ty, tx] = True
+    return amb
+
+
+@pytest.mark.parametrize("hw", SIZES + TINY + [(288, 352)])
+def test_layers_elementwise_against_oracle(hw):
+    """Every convolution pass checked element by element, one layer at a
+    time, on the GPU's own BF16 operands: each layer's input activations
+    and output gradient are read from the workspace and fed to the oracle's
+    direct convolution and its backward.
+      - forward: the next layer's BF16 input equals bf16(ReLU(conv)) and the
+        head equals conv, within half a BF16 ulp plus 1e-3 sum|w x|;
+      - head gradient: the loss gradient of every head channel (slots whose
+        Chamfer nearest neighbour is within 1e-4 of a tie excepted);
+      - grad input: each hidden layer's BF16 dZ equals bf16(mask * W^T dZ);
+      - grad weight and bias: every element within 1e-3 sum|dZ x|."""
+    H, W = hw
+    print("cnn layers element-wise", hw, flush=True)
+    f0, f1 = _frames(49, hw)
+    xy, chol, rgb = synth.random_gaussians(700, W, H, seed=50, scale_lo=0.6, scale_hi=3.0)
+    net = _lib.CNNInit(H, W, seed=51)
+    net.set_targets(dev(xy), dev(chol), dev(rgb))
+    head = torch.empty(73, net.TY, net.TX, device=DEV)
+    net.forward(dev(f1), dev(f0), head_out=head)
+    net.backward()
+    torch.cuda.synchronize()
+    params = net.oracle_params()
+    grads = net.oracle_grads()
+    hd = host(head).astype(np.float64)
+    # input of layer 0: the frame and the residual, BF16-rounded
+    X0 = net.tensor(0, 0)
+    assert X0.shape[0] == 8 and not X0[6:].any()
+    np.testing.assert_array_equal(X0[:6], ocnn.bf16_round(_x(f1, f0)))
+    X = [net.tensor(i, 0).astype(np.float64) for i in range(5)]
+    X[0] = X[0][:6]
+    for i, (w, b) in enumerate(params):
+        wq = ocnn.bf16_round(w).astype(np.float64)
+        stride = 2 if i < 4 else 1
+        y = ocnn.conv3x3(X[i], wq, b, stride)
+        acc = 1e-3 * ocnn.conv3x3(np.abs(X[i]), np.abs(wq), np.abs(b), stride)
+        if i < 4:
+            _close_bf16(X[i + 1], np.maximum(y, 0.0), acc, f"forward layer {i}")
+        else:
+            assert np.all(np.abs(hd - y) <= acc + 1e-30), "head"
+    # loss gradient of the head, from the GPU's head output
+    targets = ocnn.tile_targets(xy, chol, rgb, W, H, 16)
+    _, hg = ocnn.head_loss(hd, targets)
+    DZ4 = net.tensor(4, 1)[:73].astype(np.float64)
+    keep = np.ones_like(hg, bool)
+    amb = _chamfer_ties(hd, targets)
+    for s in range(8):
+        keep[9 + 8 * s:17 + 8 * s] &= ~amb[s][None]
+    _close_bf16(DZ4[keep], hg[keep], 1e-5 * np.abs(hg[keep]), "head dZ")
+    assert keep.mean() > 0.9
+    # backward, layer by layer, from the GPU's own dZ
+    for i in range(4, -1, -1):
+        w, _ = params[i]
+        wq = ocnn.bf16_round(w).astype(np.float64)
+        stride = 2 if i < 4 else 1
+        cout = 73 if i == 4 else 64
+        DZ = net.tensor(i, 1)[:cout].astype(np.float64)
+        dx, dw, db = ocnn.conv3x3_backward(X[i], wq, DZ, stride)
+        adx, adw, adb = ocnn.conv3x3_backward(np.abs(X[i]), np.abs(wq), np.abs(DZ), stride)
+        gw, gb = grads[i]
+        assert np.all(np.abs(gw - dw) <= 1e-3 * adw + 1e-30), f"grad weight {i}"
+        assert np.all(np.abs(gb - db) <= 1e-3 * adb + 1e-30), f"grad bias {i}"
+        if i > 0:
+            mask = X[i] > 0
+            got = net.tensor(i - 1, 1)[:64]
+            assert not got[~mask].any(), f"grad input {i}: masked entries not zero"
+            _close_bf16(got[mask], dx[mask], 1e-3 * adx[mask], f"grad input into layer {i}")
+
+
+def test_cnn_adam_matches_oracle_decoupled_decay():
+    """Three Adam steps on the FP32 master weights with decoupled weight
+    decay, each against the oracle fed the GPU's state (parameters within
+    1e-6 relative plus 1e-6 lr; moments relative to their two terms); the
+    gradient is cleared and both BF16 weight copies equal the rounded
+    master weights."""
+    print("cnn adam", flush=True)
+    from oracle.adam import adamw_step
+    net = _lib.CNNInit(H, W, seed=52)
+    rng = np.random.default_rng(53)
+    n = net.n_params
+    lr, wd = 2e-3, 0.05
+    t = 0
+    for k in range(3):
+        p0 = host(net.master).astype(np.float64)
+        m0 = host(net.m).astype(np.float64)
+        v0 = host(net.v).astype(np.float64)
+        g = rng.normal(size=n).astype(np.float32) * np.float32(10.0 ** rng.uniform(-3, 1))
+        net.grad.copy_(torch.from_numpy(g))
+        net.step(lr=lr, weight_decay=wd)
+        torch.cuda.synchronize()
+        lr32, wd32 = float(np.float32(lr)), float(np.float32(wd))
+        p1, m1, v1, t = adamw_step(p0, g, m0, v0, t, lr32, wd32, float(np.float32(0.9)),
+                                   float(np.float32(0.999)), float(np.float32(1e-8)))
+        assert int(net.step_count.item()) == t
+        assert np.all(np.abs(host(net.master) - p1) <= 1e-6 * np.abs(p1) + 1e-6 * lr), k
+        gd = g.astype(np.float64)
+        assert np.all(np.abs(host(net.m) - m1) <= 1e-6 * (0.9 * np.abs(m0) + 0.1 * np.abs(gd)))
+        assert np.all(np.abs(host(net.v) - v1) <= 1e-5 * (0.999 * v0 + 0.001 * gd * gd))
+        assert not host(net.grad).any()
+    master = host(net.master)
+    wb = host(net.wbf16).view(np.uint16)
+    bits = lambda a: (ocnn.bf16_round(a).view(np.uint32) >> 16).astype(np.uint16)
+    wb_off = wt_off = 0
+    n_wb = sum(net.layer_info(i)["Mpad"] * net.layer_info(i)["Kf"] for i in range(5))
+    for i in range(5):
+        d = net.layer_info(i)
+        M = master[d["w_off"]:d["w_off"] + d["Mpad"] * d["Kf"]]
+        np.testing.assert_array_equal(wb[wb_off:wb_off + M.size], bits(M))
+        cs = (d["Cout"] + 7) // 8 * 8
+        kb = (9 * cs + 31) // 32 * 32
+        if i > 0:
+            wt = wb[n_wb + wt_off:n_wb + wt_off + d["Cin"] * kb].reshape(d["Cin"], kb)
+            Mw = M.reshape(d["Mpad"], d["Kf"])
+            for tap in range(9):
+                want = bits(Mw[:d["Cout"], tap * d["Cin"]:(tap + 1) * d["Cin"]].T.copy())
+                np.testing.assert_array_equal(wt[:, tap * cs:tap * cs + d["Cout"]], want)
+        wb_off += M.size
+        wt_off += d["Cin"] * kb

@@ -12,7 +12,8 @@ from oracle.loss import dloss_dimg, mse
 from oracle.gauss import mahalanobis_sq
 from oracle.render import render_box, render_bruteforce, render_pixels
 from paper_2505_09324_amd import _lib, synth
-from gpu_util import VARIANTS, GpuFrame, assert_grads_close, assert_pixels_close, dev, host
+from gpu_util import (VARIANTS, GpuFrame, assert_grads_close, assert_pixels_close, dense_long_lists,
+                      dev, host, loss_bound)
 
 pytestmark = pytest.mark.gpu
 
@@ -261,3 +262,28 @@ def test_fused_render_matches_oracle_and_counts_pairs(T, ppl):
     # pairs whose q lies within 1e-4 of the cutoff may fall either way
     got, want = _lib.count_pairs(f.shape, f.ws), count_pairs_in_cutoff(xy, chol, 128, 128)
     assert abs(got - want) <= 2, (got, want)
+
+
+def test_fused_long_lists_every_variant():
+    """The fused pass on lists longer than 256 and 512 (the staged-twice
+    branch: forward over every chunk, residuals, then each chunk staged again
+    for the backward and flushed): loss and every gradient element against
+    the oracle, for every (tile, pixels per lane) variant."""
+    W, H, N, frame, xy, chol, rgb = dense_long_lists()
+    ref = render_box(xy, chol, rgb, H, W)
+    want_loss = mse(ref["img"], frame)
+    tol = loss_bound(ref, frame)
+    want = gradients(xy, chol, rgb, dloss_dimg(ref["img"], frame), H, W)
+    P = [dev(xy), dev(chol), dev(rgb)]
+    for T, ppl in VARIANTS:
+        print(f"fused long lists T={T} ppl={ppl}", flush=True)
+        f = GpuFrame(W, H, N, T, ppl=ppl)
+        b = f.bin(P[0], P[1])
+        lens = np.diff(b["tile_start"])
+        assert lens.max() > 512 and (lens > 256).sum() >= 9
+        g = [torch.zeros(N, d, device="cuda") for d in (2, 3, 3)]
+        loss = torch.empty((), device="cuda")
+        _lib.render_fused(f.shape, f.ws, P[2], dev(frame), *g, loss=loss)
+        torch.cuda.synchronize()
+        assert abs(float(loss) - want_loss) <= tol, (float(loss), want_loss, tol)
+        assert_grads_close({"xy": host(g[0]), "chol": host(g[1]), "rgb": host(g[2])}, want)
