@@ -200,7 +200,7 @@ def main():
     tune = None
     if args.tile == 0 or args.ppl == 0:
         cands = [(8, 1), (16, 1), (16, 2), (32, 1), (32, 2), (32, 4)]
-        best, ms = _lib.autotune_batch([(W, H, N)], T.reshape(-1), xy, chol, rgb, cands, reps=5)
+        best, ms = _lib.autotune_frame(W, H, N, T, xy, chol, rgb, cands, reps=5)
         args.tile, args.ppl = cands[best]
         tune = {f"{t}/{p}": round(x * 1e3, 1) for (t, p), x in zip(cands, ms)}
     shape = _lib.make_shape(W, H, N, args.tile, px_per_lane=args.ppl)
@@ -210,18 +210,22 @@ def main():
     step = torch.zeros(1, dtype=torch.int32, device=dev)
     trace = torch.zeros(args.warmup + args.steps + 8, device=dev)
     cfg = _lib.adam_cfg(LR)
+    ctx = _lib.Context()
+    use_graph = args.launch == "graph"
+    fit = lambda iters, chunk: (shape, T, xy, chol, rgb, m, v, step, trace, ws,
+                                _lib.fit_opts(iters, chunk, use_graph=use_graph, cfg=cfg))
 
     if args.warmup > 0:
-        _lib.fit_frame(shape, T, xy, chol, rgb, m, v, step, trace, ws,
-                       _lib.fit_opts(args.warmup, min(args.check_every, args.warmup),
-                                     use_graph=args.launch == "graph", cfg=cfg))
+        _lib.fit_frame(*fit(args.warmup, min(args.check_every, args.warmup)), ctx=ctx)
+    # the warm-up also instantiates the graphs the timed call replays
+    _lib.fit_prepare(*fit(args.steps, args.check_every), ctx=ctx)
+    captures0 = ctx.stats()[1]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = _lib.fit_frame(shape, T, xy, chol, rgb, m, v, step, trace, ws,
-                        _lib.fit_opts(args.steps, args.check_every,
-                                      use_graph=args.launch == "graph", cfg=cfg))
+    st = _lib.fit_frame(*fit(args.steps, args.check_every), ctx=ctx)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    assert ctx.stats()[1] == captures0, "the timed call captured a graph"
     tr = trace[:args.warmup + args.steps].cpu().numpy()
     psnr_final = float(10 * np.log10(1.0 / tr[-1]))
 
@@ -295,6 +299,7 @@ def main():
                       "render_bwd": round(t_bwd * 1e6, 2)},
         "n_pairs": n_pairs,
         "autotune_us_per_round": tune,
+        "autotune_kernels": "one-frame binning + k_render_fused per candidate (tile/px per lane)",
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

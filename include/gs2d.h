@@ -14,14 +14,16 @@
  * --------------------------------
  *  - All array arguments are DEVICE pointers to contiguous buffers owned by
  *    the caller; the library never allocates device memory for them and keeps
- *    no pointer after a call returns.  Scratch space is one caller-provided
- *    workspace of gs2d_workspace_bytes() bytes (256-byte aligned).
+ *    no pointer after a call returns (except inside a gs2d_ctx's cached
+ *    graphs, below).  Scratch space is one caller-provided workspace of
+ *    gs2d_workspace_bytes() bytes (256-byte aligned).
  *  - Parameter layout (structure of arrays, FP32): xy [N][2] (x, y in pixel
  *    units, origin at the top-left corner of the frame), chol [N][3]
  *    (l1, l2, l3), rgb [N][3].  Images are planar FP32 [3][H][W].
  *  - `stream` is a hipStream_t passed as void*; NULL means the default
- *    stream.  Every call except gs2d_fit_frame only enqueues work and
- *    returns; results are ready when the stream reaches them.
+ *    stream.  Calls only enqueue work on it and return (results are ready
+ *    when the stream reaches them) unless their comment says that they
+ *    synchronise it.
  *  - Every call returns a gs2d_status and never aborts.  Invalid arguments
  *    return GS2D_EINVAL before anything is enqueued.  Conditions found on the
  *    device are reported in the workspace status word (gs2d_bins.status):
@@ -179,10 +181,36 @@ int gs2d_adam_step(int32_t N, float *xy, float *chol, float *rgb, float *g_xy, f
                    float *g_rgb, float *m, float *v, int32_t *step, const gs2d_adam_cfg *cfg,
                    const uint8_t *active, int32_t zero_grads, void *stream);
 
-/* The whole fitting loop for one frame: repeat {project+bin, forward render
- * with fused loss and backward render in one pass per tile, Adam} for
- * opts->iters iterations or until the PSNR of an evaluated iteration reaches
- * opts->psnr_target (checked every opts->check_every iterations).
+/* --------------------------------------------------------------- context --
+ * Opaque host object holding the instantiated hipGraphs of fitting chunks
+ * (gs2d_fit_frame / gs2d_fit_batch with use_graph), keyed by every pointer,
+ * size, chunk length and Adam setting baked into them.  A video encoder fits
+ * every frame of a sequence with the same buffers (Sec. 3.2: I-frames from an
+ * initialisation, P-frames warm-started from the previous frame), so a chunk
+ * is captured and instantiated once per sequence, not once per frame.  The
+ * context belongs to one device and serves one host thread at a time; it
+ * keeps at most 16 graphs (least recently used dropped) and keeps the cached
+ * pointers until it is destroyed or the entry is dropped, so buffers freed
+ * and reallocated at the same address are re-used by a cached graph.
+ *   gs2d_ctx_create: *out = new context for `device` (GS2D_EINVAL for an
+ *   invalid device; the current device is left unchanged).
+ *   gs2d_ctx_destroy: frees it (NULL is ignored); no fitting call may be in
+ *   flight.
+ *   gs2d_ctx_stats: graphs cached now and graphs instantiated so far (each
+ *   output nullable). */
+typedef struct gs2d_ctx gs2d_ctx;
+int gs2d_ctx_create(gs2d_ctx **out, int32_t device);
+void gs2d_ctx_destroy(gs2d_ctx *ctx);
+int gs2d_ctx_stats(const gs2d_ctx *ctx, int32_t *cached, int64_t *captures);
+
+/* The whole fitting loop for one frame, the per-frame encoding of Sec. 3.2
+ * (optimisation steps of the Gaussians' attributes against an L2 loss, from
+ * an initialisation or the previous frame's Gaussians): repeat
+ * {project+bin, forward render with fused loss and backward render in one
+ * pass per tile, Adam} for opts->iters iterations or until the PSNR of an
+ * evaluated iteration reaches opts->psnr_target (checked every
+ * opts->check_every iterations).
+ *   ctx: graph cache (nullable: graphs are then captured for this call only).
  *   target [3][H][W]; xy/chol/rgb updated in place; m, v [8N] and step as
  *   for gs2d_adam_step (continue from their contents: zero them for a cold
  *   start);
@@ -190,13 +218,39 @@ int gs2d_adam_step(int32_t N, float *xy, float *chol, float *rgb, float *g_xy, f
  *   parameters before update k, k = step[0] at that iteration (entries the
  *   call does not reach are left untouched); trace_len must exceed
  *   step[0] + opts->iters.
- * Synchronises with `stream` on entry, runs on an internal stream, and
- * returns after the work is complete.  Returns GS2D_EOVERFLOW if the
- * tile-pair capacity was exceeded. */
-int gs2d_fit_frame(const gs2d_shape *shape, const float *target, float *xy, float *chol,
-                   float *rgb, float *m, float *v, int32_t *step, float *loss_trace,
+ * Work is enqueued on `stream` (NULL: the default stream) behind whatever the
+ * caller enqueued before; the call waits for the stream at each PSNR check
+ * and returns after the work is complete.  Returns GS2D_EOVERFLOW if the
+ * tile-pair capacity was exceeded, GS2D_EINVAL if ctx belongs to another
+ * device. */
+int gs2d_fit_frame(gs2d_ctx *ctx, const gs2d_shape *shape, const float *target, float *xy,
+                   float *chol, float *rgb, float *m, float *v, int32_t *step, float *loss_trace,
                    int32_t trace_len, void *ws, size_t ws_bytes, const gs2d_fit_opts *opts,
                    gs2d_fit_stats *stats, void *stream);
+
+/* Instantiate into ctx (required) the graphs that gs2d_fit_frame with the
+ * same arguments would replay (chunks of min(check_every, iters) and of the
+ * remainder iters % check_every), without launching anything, so that a
+ * latency-critical loop starts with its graphs ready.  No-op without
+ * use_graph. */
+int gs2d_fit_prepare(gs2d_ctx *ctx, const gs2d_shape *shape, const float *target, float *xy,
+                     float *chol, float *rgb, float *m, float *v, int32_t *step,
+                     float *loss_trace, int32_t trace_len, void *ws, size_t ws_bytes,
+                     const gs2d_fit_opts *opts);
+
+/* One-frame autotuner: for each candidate (cand_tile[i], cand_ppl[i]) times
+ * `reps` rounds of what gs2d_fit_frame runs per iteration apart from Adam
+ * (projection + binning with the default pair capacity max(65536, 16 N +
+ * 4 tiles), then the fused forward/loss/backward raster of Eq. 2) with HIP
+ * events after one untimed round; out_ms[i] = mean milliseconds per round,
+ * *best = index of the fastest.  ws must hold gs2d_workspace_bytes of every
+ * candidate; grad_scratch [8N] floats receives accumulated gradients
+ * (garbage).  Synchronises `stream`. */
+int gs2d_autotune_frame(int32_t W, int32_t H, int32_t N, const float *target, const float *xy,
+                        const float *chol, const float *rgb, int32_t n_cand,
+                        const int32_t *cand_tile, const int32_t *cand_ppl, int32_t reps,
+                        float *grad_scratch, void *ws, size_t ws_bytes, float *out_ms,
+                        int32_t *best, void *stream);
 
 /* Workspace bytes for gs2d_init_plain on a W x H frame (0 if invalid). */
 size_t gs2d_init_workspace_bytes(int32_t W, int32_t H);
@@ -250,14 +304,14 @@ size_t gs2d_batch_workspace_bytes(int32_t n_frames, const gs2d_frame *frames, in
                                   int32_t px_per_lane);
 
 /* Fit all frames of a batch for opts->iters iterations (same rules as
- * gs2d_fit_frame; one shared step counter).  loss_trace is [trace_rows]
- * [n_frames]: row k holds every frame's MSE at iteration k (= step value
- * before the update).  The PSNR stop triggers when every frame has reached
+ * gs2d_fit_frame, including ctx and stream; one shared step counter).
+ * loss_trace is [trace_rows][n_frames]: row k holds every frame's MSE at
+ * iteration k (= step value before the update).  The PSNR stop triggers when every frame has reached
  * opts->psnr_target.  `frames` is a host array. */
-int gs2d_fit_batch(int32_t n_frames, const gs2d_frame *frames, int32_t tile, int32_t px_per_lane,
-                   const float *targets, float *xy, float *chol, float *rgb, float *m, float *v,
-                   int32_t *step, float *loss_trace, int32_t trace_rows, void *ws,
-                   size_t ws_bytes, const gs2d_fit_opts *opts, gs2d_fit_stats *stats,
+int gs2d_fit_batch(gs2d_ctx *ctx, int32_t n_frames, const gs2d_frame *frames, int32_t tile,
+                   int32_t px_per_lane, const float *targets, float *xy, float *chol, float *rgb,
+                   float *m, float *v, int32_t *step, float *loss_trace, int32_t trace_rows,
+                   void *ws, size_t ws_bytes, const gs2d_fit_opts *opts, gs2d_fit_stats *stats,
                    void *stream);
 
 /* Binning and one persistent fused raster pass of a batch without an

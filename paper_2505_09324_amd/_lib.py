@@ -9,7 +9,8 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_float, c_int32, c_size_t, c_uint32, c_void_p, c_char_p, c_double
+from ctypes import (POINTER, c_char_p, c_double, c_float, c_int32, c_int64, c_size_t, c_uint32,
+                    c_void_p)
 
 import torch
 
@@ -72,14 +73,23 @@ _SIGS = {
     "gs2d_adam_step": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, POINTER(AdamCfg), c_void_p, c_int32,
                                  c_void_p]),
-    "gs2d_fit_frame": (c_int32, [POINTER(Shape), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                                 c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_size_t,
+    "gs2d_ctx_create": (c_int32, [POINTER(c_void_p), c_int32]),
+    "gs2d_ctx_destroy": (None, [c_void_p]),
+    "gs2d_ctx_stats": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int64)]),
+    "gs2d_fit_frame": (c_int32, [c_void_p, POINTER(Shape), c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_size_t,
                                  POINTER(FitOpts), POINTER(FitStats), c_void_p]),
+    "gs2d_fit_prepare": (c_int32, [c_void_p, POINTER(Shape), c_void_p, c_void_p, c_void_p,
+                                   c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                                   c_void_p, c_size_t, POINTER(FitOpts)]),
+    "gs2d_autotune_frame": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                      c_void_p, c_int32, c_void_p, c_void_p, c_int32, c_void_p,
+                                      c_void_p, c_size_t, c_void_p, c_void_p, c_void_p]),
     "gs2d_render_fused": (c_int32, [POINTER(Shape), c_void_p, c_size_t, c_void_p, c_void_p, c_void_p,
                                     c_void_p, c_void_p, c_void_p, c_void_p]),
     "gs2d_count_pairs": (c_int32, [POINTER(Shape), c_void_p, c_size_t, c_void_p, c_void_p]),
     "gs2d_batch_workspace_bytes": (c_size_t, [c_int32, POINTER(Frame), c_int32, c_int32]),
-    "gs2d_fit_batch": (c_int32, [c_int32, POINTER(Frame), c_int32, c_int32, c_void_p, c_void_p,
+    "gs2d_fit_batch": (c_int32, [c_void_p, c_int32, POINTER(Frame), c_int32, c_int32, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_int32, c_void_p, c_size_t, POINTER(FitOpts), POINTER(FitStats),
                                  c_void_p]),
@@ -293,21 +303,98 @@ def fit_opts(iters, check_every=50, psnr_target=0.0, use_graph=True, cfg=None) -
                    cfg if cfg is not None else adam_cfg())
 
 
-def fit_frame(shape: Shape, target, xy, chol, rgb, m, v, step, loss_trace, ws, opts: FitOpts,
-              check=True) -> FitStats:
+class Context:
+    """A gs2d_ctx: the device's cache of instantiated fitting-chunk graphs."""
+
+    def __init__(self, device=None):
+        dev = torch.cuda.current_device() if device is None else int(device)
+        h = c_void_p()
+        _check("gs2d_ctx_create", lib().gs2d_ctx_create(ctypes.byref(h), dev))
+        self.handle, self.device = h, dev
+
+    def stats(self):
+        """(graphs cached now, graphs instantiated so far)."""
+        n, c = c_int32(), c_int64()
+        _check("gs2d_ctx_stats", lib().gs2d_ctx_stats(self.handle, ctypes.byref(n), ctypes.byref(c)))
+        return int(n.value), int(c.value)
+
+    def close(self):
+        if self.handle:
+            lib().gs2d_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def default_context() -> Context:
+    """One context per device for callers that pass none."""
+    dev = torch.cuda.current_device()
+    if dev not in _default_ctx:
+        _default_ctx[dev] = Context(dev)
+    return _default_ctx[dev]
+
+
+def _fit_args(shape: Shape, target, xy, chol, rgb, m, v, step, loss_trace, ws):
     N, H, W = shape.N, shape.H, shape.W
+    return (ctypes.byref(shape), _ptr(target, "target", shape=(3, H, W)),
+            _ptr(xy, "xy", shape=(N, 2)), _ptr(chol, "chol", shape=(N, 3)),
+            _ptr(rgb, "rgb", shape=(N, 3)), _ptr(m, "m", shape=(8 * N,)), _ptr(v, "v", shape=(8 * N,)),
+            _ptr(step, "step", torch.int32, shape=(1,)), _ptr(loss_trace, "loss_trace"),
+            int(loss_trace.numel()), _ptr(ws, "ws", torch.uint8), ws.numel())
+
+
+def fit_frame(shape: Shape, target, xy, chol, rgb, m, v, step, loss_trace, ws, opts: FitOpts,
+              check=True, ctx: Context | None = None) -> FitStats:
+    """gs2d_fit_frame on the current stream; ctx defaults to the device's
+    shared context (pass ctx=False for none)."""
+    if ctx is None:
+        ctx = default_context()
     stats = FitStats()
     code = lib().gs2d_fit_frame(
-        ctypes.byref(shape), _ptr(target, "target", shape=(3, H, W)),
-        _ptr(xy, "xy", shape=(N, 2)), _ptr(chol, "chol", shape=(N, 3)),
-        _ptr(rgb, "rgb", shape=(N, 3)), _ptr(m, "m", shape=(8 * N,)), _ptr(v, "v", shape=(8 * N,)),
-        _ptr(step, "step", torch.int32, shape=(1,)), _ptr(loss_trace, "loss_trace"),
-        int(loss_trace.numel()), _ptr(ws, "ws", torch.uint8), ws.numel(), ctypes.byref(opts),
-        ctypes.byref(stats), _stream())
+        ctx.handle if ctx else None,
+        *_fit_args(shape, target, xy, chol, rgb, m, v, step, loss_trace, ws),
+        ctypes.byref(opts), ctypes.byref(stats), _stream())
     if check:
         _check("gs2d_fit_frame", code)
     stats.code = code
     return stats
+
+
+def fit_prepare(shape: Shape, target, xy, chol, rgb, m, v, step, loss_trace, ws, opts: FitOpts,
+                ctx: Context | None = None):
+    """Instantiate the graphs fit_frame with these arguments will replay."""
+    if ctx is None:
+        ctx = default_context()
+    _check("gs2d_fit_prepare", lib().gs2d_fit_prepare(
+        ctx.handle, *_fit_args(shape, target, xy, chol, rgb, m, v, step, loss_trace, ws),
+        ctypes.byref(opts)))
+
+
+def autotune_frame(W, H, N, target, xy, chol, rgb, candidates, reps=5):
+    """Time binning + fused raster for every (tile, px_per_lane) candidate on
+    one frame; returns (best_index, [ms per round])."""
+    shapes = [make_shape(W, H, N, t, px_per_lane=p) for t, p in candidates]
+    need = max(workspace_bytes(s) for s in shapes)
+    ws = torch.empty(need, dtype=torch.uint8, device=xy.device)
+    scratch = torch.zeros(8 * N, device=xy.device)
+    ct = (c_int32 * len(candidates))(*[int(t) for t, _ in candidates])
+    cp = (c_int32 * len(candidates))(*[int(p) for _, p in candidates])
+    out = (c_float * len(candidates))()
+    best = c_int32(-1)
+    _check("gs2d_autotune_frame", lib().gs2d_autotune_frame(
+        int(W), int(H), int(N), _ptr(target, "target", shape=(3, H, W)),
+        _ptr(xy, "xy", shape=(N, 2)), _ptr(chol, "chol", shape=(N, 3)),
+        _ptr(rgb, "rgb", shape=(N, 3)), len(candidates), ct, cp, int(reps),
+        _ptr(scratch, "scratch"), _ptr(ws, "ws", torch.uint8), ws.numel(), out,
+        ctypes.byref(best), _stream()))
+    return int(best.value), [float(x) for x in out]
 
 
 def init_plain(target, roi_mask, pick_roi, jit_roi, pick_out, jit_out, ws=None, picked=None):
@@ -358,14 +445,16 @@ def _batch_totals(sizes):
 
 
 def fit_batch(sizes, tile, px_per_lane, targets, xy, chol, rgb, m, v, step, loss_trace, ws,
-              opts: FitOpts, check=True) -> FitStats:
+              opts: FitOpts, check=True, ctx: Context | None = None) -> FitStats:
     F = len(sizes)
     Nt, Pt = _batch_totals(sizes)
     if loss_trace.dim() != 2 or loss_trace.shape[1] != F:
         raise ValueError("loss_trace must be [rows, n_frames]")
+    if ctx is None:
+        ctx = default_context()
     stats = FitStats()
     code = lib().gs2d_fit_batch(
-        F, frames_array(sizes), int(tile), int(px_per_lane), _ptr(targets, "targets", shape=(Pt,)),
+        ctx.handle if ctx else None, F, frames_array(sizes), int(tile), int(px_per_lane), _ptr(targets, "targets", shape=(Pt,)),
         _ptr(xy, "xy", shape=(Nt, 2)), _ptr(chol, "chol", shape=(Nt, 3)),
         _ptr(rgb, "rgb", shape=(Nt, 3)), _ptr(m, "m", shape=(8 * Nt,)), _ptr(v, "v", shape=(8 * Nt,)),
         _ptr(step, "step", torch.int32, shape=(1,)), _ptr(loss_trace, "loss_trace"),

@@ -1,6 +1,7 @@
 // C ABI of the frame fitter: argument validation, workspace carving and the
-// host side of the fitting loop (chunked, optionally replayed from a
-// captured hipGraph, with a PSNR stop rule checked between chunks).
+// host side of the fitting loop (chunked, optionally replayed from hipGraphs
+// cached in a gs2d_ctx, with a PSNR stop rule checked between chunks).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <new>
@@ -255,113 +256,235 @@ hipError_t enqueue_iterations(const Layout &L, void *ws, const float *target, fl
   return e;
 }
 
-struct StreamGuard {
-  hipStream_t s = nullptr;
-  hipGraph_t g = nullptr;
-  hipGraphExec_t x = nullptr;
-  ~StreamGuard() {
-    if (x) (void)hipGraphExecDestroy(x);
-    if (g) (void)hipGraphDestroy(g);
-    if (s) {
-      (void)hipStreamSynchronize(s);
-      (void)hipStreamDestroy(s);
-    }
+GraphKey frame_chunk_key(const Layout &L, const FitArgs &a, int k) {
+  GraphKey key{1,
+               (uint64_t)L.W,
+               (uint64_t)L.H,
+               (uint64_t)L.N,
+               (uint64_t)L.T,
+               (uint64_t)L.max_pairs,
+               (uint64_t)L.ppl,
+               key_word(a.target),
+               key_word(a.xy),
+               key_word(a.chol),
+               key_word(a.rgb),
+               key_word(a.m),
+               key_word(a.v),
+               key_word(a.step),
+               key_word(a.trace),
+               (uint64_t)a.trace_len,
+               key_word(a.ws),
+               (uint64_t)k};
+  for (float f : a.cfg.lr) key.push_back(key_word(f));
+  key.push_back(key_word(a.cfg.beta1));
+  key.push_back(key_word(a.cfg.beta2));
+  key.push_back(key_word(a.cfg.eps));
+  return key;
+}
+
+// Enqueue a chunk of k iterations on `st`: the context's cached graph when
+// graphs are used, else direct launches.
+int run_chunk(gs2d_ctx *ctx, bool use_graph, const Layout &L, const FitArgs &a, int k,
+              hipStream_t st, bool launch) {
+  if (!use_graph) {
+    if (!launch) return GS2D_OK;
+    return hip_status(enqueue_iterations(L, a.ws, a.target, a.xy, a.chol, a.rgb, a.m, a.v, a.step,
+                                         a.trace, a.trace_len, a.cfg, k, st));
   }
-};
+  hipGraphExec_t x = nullptr;
+  hipError_t e = ctx->graph_for(
+      frame_chunk_key(L, a, k),
+      [&](hipStream_t cs) {
+        return enqueue_iterations(L, a.ws, a.target, a.xy, a.chol, a.rgb, a.m, a.v, a.step,
+                                  a.trace, a.trace_len, a.cfg, k, cs);
+      },
+      &x);
+  if (e == hipSuccess && launch) e = hipGraphLaunch(x, st);
+  return hip_status(e);
+}
+
+int check_fit_args(gs2d_ctx *ctx, const gs2d_shape *shape, const float *target, float *xy,
+                   float *chol, float *rgb, float *m, float *v, int32_t *step, float *loss_trace,
+                   void *ws, size_t ws_bytes, const gs2d_fit_opts *opts, Layout *L) {
+  int rc = check_ws(shape, ws, ws_bytes, L);
+  if (rc != GS2D_OK) return rc;
+  if (!target || !xy || !chol || !rgb || !m || !v || !step || !loss_trace || !opts)
+    return GS2D_EINVAL;
+  if (opts->iters < 0 || opts->check_every < 1) return GS2D_EINVAL;
+  return gs2d_ctx_check(ctx);
+}
 
 }  // namespace
 
-extern "C" int gs2d_fit_frame(const gs2d_shape *shape, const float *target, float *xy,
-                              float *chol, float *rgb, float *m, float *v, int32_t *step,
-                              float *loss_trace, int32_t trace_len, void *ws, size_t ws_bytes,
-                              const gs2d_fit_opts *opts, gs2d_fit_stats *stats, void *stream) {
+extern "C" int gs2d_fit_prepare(gs2d_ctx *ctx, const gs2d_shape *shape, const float *target,
+                                float *xy, float *chol, float *rgb, float *m, float *v,
+                                int32_t *step, float *loss_trace, int32_t trace_len, void *ws,
+                                size_t ws_bytes, const gs2d_fit_opts *opts) {
   try {
-    const auto t0 = std::chrono::steady_clock::now();
     Layout L;
-    int rc = check_ws(shape, ws, ws_bytes, &L);
+    if (!ctx) return GS2D_EINVAL;
+    int rc = check_fit_args(ctx, shape, target, xy, chol, rgb, m, v, step, loss_trace, ws,
+                            ws_bytes, opts, &L);
     if (rc != GS2D_OK) return rc;
-    if (!target || !xy || !chol || !rgb || !m || !v || !step || !loss_trace || !opts)
-      return GS2D_EINVAL;
-    if (opts->iters < 0 || opts->check_every < 1) return GS2D_EINVAL;
-    if (stats) {
-      stats->iters_run = 0;
-      stats->iter_hit_target = -1;
-      stats->final_loss = NAN;
-      stats->final_psnr = NAN;
-      stats->seconds = 0.0;
-      stats->status = 0;
-      stats->n_culled = 0;
-    }
-    if (hipStreamSynchronize(as_stream(stream)) != hipSuccess) return GS2D_EHIP;
-    int32_t step0 = 0;
-    if (hipMemcpy(&step0, step, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    if (!opts->use_graph || opts->iters == 0) return GS2D_OK;
+    const FitArgs a{target, xy, chol, rgb, m, v, step, loss_trace, trace_len, ws, opts->adam};
+    const int k0 = std::min(opts->check_every, opts->iters);
+    rc = run_chunk(ctx, true, L, a, k0, nullptr, false);
+    const int rem = opts->iters % opts->check_every;
+    if (rc == GS2D_OK && opts->iters > opts->check_every && rem != 0)
+      rc = run_chunk(ctx, true, L, a, rem, nullptr, false);
+    return rc;
+  } catch (...) {
+    return GS2D_EHIP;
+  }
+}
+
+namespace gs2d {
+
+int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_fit_opts &opts,
+                  gs2d_fit_stats *stats, hipStream_t st) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (stats) {
+    stats->iters_run = 0;
+    stats->iter_hit_target = -1;
+    stats->final_loss = NAN;
+    stats->final_psnr = NAN;
+    stats->seconds = 0.0;
+    stats->status = 0;
+    stats->n_culled = 0;
+  }
+  int32_t step0 = 0;
+  if (hipMemcpyAsync(&step0, a.step, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return GS2D_EHIP;
+  if (step0 < 0 || (long long)step0 + opts.iters >= (long long)a.trace_len) return GS2D_EINVAL;
+
+  // without a context the call's graphs live until it returns
+  gs2d_ctx local;
+  gs2d_ctx *cx = ctx ? ctx : &local;
+  const bool use_graph = opts.use_graph != 0;
+  int32_t *misc = at<int32_t>(a.ws, L.misc);
+  hipError_t e = launch_fill_zero_u32(reinterpret_cast<uint32_t *>(misc), MISC_COUNT, st);
+  if (e == hipSuccess) e = launch_fill_zero(at<float>(a.ws, L.grads), 8 * (size_t)L.N, st);
+  if (e != hipSuccess) return GS2D_EHIP;
+
+  constexpr int TRACE_PIECE = 256;  // loss values read back per copy
+  float trace_host[TRACE_PIECE];
+  int32_t misc_host[4] = {0, 0, 0, 0};
+  int done = 0, hit = -1;
+  float last_loss = NAN;
+  uint32_t sticky = 0;
+  while (done < opts.iters) {
+    const int k = std::min(opts.check_every, opts.iters - done);
+    int rc = run_chunk(cx, use_graph, L, a, k, st, true);
+    if (rc != GS2D_OK) return rc;
+    if (hipMemcpyAsync(misc_host, misc, sizeof(misc_host), hipMemcpyDeviceToHost, st) !=
+        hipSuccess)
       return GS2D_EHIP;
-    if (step0 < 0 || (long long)step0 + opts->iters >= (long long)trace_len) return GS2D_EINVAL;
-
-    StreamGuard G;
-    if (hipStreamCreateWithFlags(&G.s, hipStreamNonBlocking) != hipSuccess) return GS2D_EHIP;
-    hipStream_t st = G.s;
-    int32_t *misc = at<int32_t>(ws, L.misc);
-    hipError_t e = launch_fill_zero_u32(reinterpret_cast<uint32_t *>(misc), MISC_COUNT, st);
-    if (e == hipSuccess) e = launch_fill_zero(at<float>(ws, L.grads), 8 * (size_t)L.N, st);
-    if (e != hipSuccess) return GS2D_EHIP;
-
-    std::vector<float> trace_host((size_t)opts->check_every);
-    int done = 0, graph_k = 0, hit = -1;
-    float last_loss = NAN;
-    uint32_t sticky = 0;
-    while (done < opts->iters) {
-      const int k = std::min(opts->check_every, opts->iters - done);
-      if (opts->use_graph) {
-        if (graph_k != k) {
-          if (G.x) (void)hipGraphExecDestroy(G.x), G.x = nullptr;
-          if (G.g) (void)hipGraphDestroy(G.g), G.g = nullptr;
-          if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
-            return GS2D_EHIP;
-          const hipError_t ce = enqueue_iterations(L, ws, target, xy, chol, rgb, m, v, step,
-                                                   loss_trace, trace_len, opts->adam, k, st);
-          hipError_t ee = hipStreamEndCapture(st, &G.g);
-          if (ce != hipSuccess || ee != hipSuccess) return GS2D_EHIP;
-          if (hipGraphInstantiate(&G.x, G.g, nullptr, nullptr, 0) != hipSuccess) return GS2D_EHIP;
-          graph_k = k;
-        }
-        if (hipGraphLaunch(G.x, st) != hipSuccess) return GS2D_EHIP;
-      } else {
-        if (enqueue_iterations(L, ws, target, xy, chol, rgb, m, v, step, loss_trace, trace_len,
-                               opts->adam, k, st) != hipSuccess)
-          return GS2D_EHIP;
-      }
-      if (hipMemcpyAsync(trace_host.data(), loss_trace + step0 + done, sizeof(float) * k,
-                         hipMemcpyDeviceToHost, st) != hipSuccess)
+    for (int i0 = 0; i0 < k; i0 += TRACE_PIECE) {
+      const int n = std::min(TRACE_PIECE, k - i0);
+      if (hipMemcpyAsync(trace_host, a.trace + step0 + done + i0, sizeof(float) * n,
+                         hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
         return GS2D_EHIP;
-      if (hipMemcpyAsync(&sticky, misc + MISC_STICKY, sizeof(uint32_t), hipMemcpyDeviceToHost,
-                         st) != hipSuccess)
-        return GS2D_EHIP;
-      if (hipStreamSynchronize(st) != hipSuccess) return GS2D_EHIP;
-      for (int i = 0; i < k; ++i) {
+      for (int i = 0; i < n; ++i) {
         last_loss = trace_host[i];
-        if (hit < 0 && opts->psnr_target > 0.f && last_loss > 0.f &&
-            10.0 * std::log10(1.0 / last_loss) >= opts->psnr_target)
-          hit = done + i;
+        if (hit < 0 && opts.psnr_target > 0.f && last_loss > 0.f &&
+            10.0 * std::log10(1.0 / last_loss) >= opts.psnr_target)
+          hit = done + i0 + i;
       }
-      done += k;
-      if (sticky & STATUS_OVERFLOW) break;
-      if (hit >= 0) break;
     }
-    int32_t n_culled = 0;
-    (void)hipMemcpy(&n_culled, misc + MISC_N_CULLED, sizeof(int32_t), hipMemcpyDeviceToHost);
-    if (stats) {
-      stats->iters_run = done;
-      stats->iter_hit_target = hit;
-      stats->final_loss = last_loss;
-      stats->final_psnr =
-          (last_loss > 0.f) ? (float)(10.0 * std::log10(1.0 / last_loss)) : INFINITY;
-      stats->status = sticky;
-      stats->n_culled = n_culled;
-      stats->seconds =
-          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    sticky = (uint32_t)misc_host[MISC_STICKY];
+    done += k;
+    if (sticky & STATUS_OVERFLOW) break;
+    if (hit >= 0) break;
+  }
+  if (stats) {
+    stats->iters_run = done;
+    stats->iter_hit_target = hit;
+    stats->final_loss = last_loss;
+    stats->final_psnr = (last_loss > 0.f) ? (float)(10.0 * std::log10(1.0 / last_loss)) : INFINITY;
+    stats->status = sticky;
+    stats->n_culled = misc_host[MISC_N_CULLED];
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return (sticky & STATUS_OVERFLOW) ? GS2D_EOVERFLOW : GS2D_OK;
+}
+
+}  // namespace gs2d
+
+extern "C" int gs2d_fit_frame(gs2d_ctx *ctx, const gs2d_shape *shape, const float *target,
+                              float *xy, float *chol, float *rgb, float *m, float *v,
+                              int32_t *step, float *loss_trace, int32_t trace_len, void *ws,
+                              size_t ws_bytes, const gs2d_fit_opts *opts, gs2d_fit_stats *stats,
+                              void *stream) {
+  try {
+    Layout L;
+    const int rc = check_fit_args(ctx, shape, target, xy, chol, rgb, m, v, step, loss_trace, ws,
+                                  ws_bytes, opts, &L);
+    if (rc != GS2D_OK) return rc;
+    const FitArgs a{target, xy, chol, rgb, m, v, step, loss_trace, trace_len, ws, opts->adam};
+    return fit_frame_run(ctx, L, a, *opts, stats, as_stream(stream));
+  } catch (...) {
+    return GS2D_EHIP;
+  }
+}
+
+// One-frame autotuner: for each candidate (tile, px_per_lane) the binning
+// and the fused raster that gs2d_fit_frame runs per iteration, timed with
+// HIP events over `reps` rounds after one untimed round.
+extern "C" int gs2d_autotune_frame(int32_t W, int32_t H, int32_t N, const float *target,
+                                   const float *xy, const float *chol, const float *rgb,
+                                   int32_t n_cand, const int32_t *cand_tile,
+                                   const int32_t *cand_ppl, int32_t reps, float *grad_scratch,
+                                   void *ws, size_t ws_bytes, float *out_ms, int32_t *best,
+                                   void *stream) {
+  struct Events {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Events() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
     }
-    return (sticky & STATUS_OVERFLOW) ? GS2D_EOVERFLOW : GS2D_OK;
+  };
+  try {
+    if (n_cand < 1 || !cand_tile || !cand_ppl || reps < 1 || !out_ms || !best || !grad_scratch ||
+        !target || !xy || !chol || !rgb)
+      return GS2D_EINVAL;
+    hipStream_t st = as_stream(stream);
+    Events E;
+    if (hipEventCreate(&E.e0) != hipSuccess || hipEventCreate(&E.e1) != hipSuccess)
+      return GS2D_EHIP;
+    float best_ms = INFINITY;
+    *best = -1;
+    for (int c = 0; c < n_cand; ++c) {
+      gs2d_shape s{W, H, N, cand_tile[c], 0, cand_ppl[c]};
+      if (s.tile != 8 && s.tile != 16 && s.tile != 32) return GS2D_EINVAL;
+      const long long tiles =
+          (long long)((W + s.tile - 1) / s.tile) * (long long)((H + s.tile - 1) / s.tile);
+      s.max_pairs = (int32_t)std::min<long long>(1LL << 30,
+                                                 std::max<long long>(65536, 16LL * N + 4 * tiles));
+      Layout L;
+      const int rc = check_ws(&s, ws, ws_bytes, &L);
+      if (rc != GS2D_OK) return rc;
+      float *g_xy = grad_scratch, *g_chol = g_xy + 2 * (size_t)N, *g_rgb = g_xy + 5 * (size_t)N;
+      hipError_t e = hipSuccess;
+      for (int r = 0; r <= reps && e == hipSuccess; ++r) {
+        if (r == 1) e = hipEventRecord(E.e0, st);
+        if (e == hipSuccess) e = launch_binning(L, xy, chol, ws, st);
+        if (e == hipSuccess) e = launch_render_fused(L, ws, rgb, target, g_xy, g_chol, g_rgb, st);
+      }
+      if (e == hipSuccess) e = hipEventRecord(E.e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(E.e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, E.e0, E.e1);
+      if (e != hipSuccess) return GS2D_EHIP;
+      out_ms[c] = ms / reps;
+      if (out_ms[c] < best_ms) {
+        best_ms = out_ms[c];
+        *best = c;
+      }
+    }
+    return GS2D_OK;
   } catch (...) {
     return GS2D_EHIP;
   }

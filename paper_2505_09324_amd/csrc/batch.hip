@@ -466,20 +466,11 @@ int check_batch_ws(int F, const gs2d_frame *frames, int tile, int ppl, void *ws,
   return GS2D_OK;
 }
 
-struct Owned {
-  hipStream_t s = nullptr;
-  hipGraph_t g = nullptr;
-  hipGraphExec_t x = nullptr;
+struct Events {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  ~Owned() {
-    if (x) (void)hipGraphExecDestroy(x);
-    if (g) (void)hipGraphDestroy(g);
+  ~Events() {
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (s) {
-      (void)hipStreamSynchronize(s);
-      (void)hipStreamDestroy(s);
-    }
   }
 };
 
@@ -499,10 +490,10 @@ extern "C" size_t gs2d_batch_workspace_bytes(int32_t n_frames, const gs2d_frame 
   }
 }
 
-extern "C" int gs2d_fit_batch(int32_t n_frames, const gs2d_frame *frames, int32_t tile,
-                              int32_t px_per_lane, const float *targets, float *xy, float *chol,
-                              float *rgb, float *m, float *v, int32_t *step, float *loss_trace,
-                              int32_t trace_rows, void *ws, size_t ws_bytes,
+extern "C" int gs2d_fit_batch(gs2d_ctx *ctx, int32_t n_frames, const gs2d_frame *frames,
+                              int32_t tile, int32_t px_per_lane, const float *targets, float *xy,
+                              float *chol, float *rgb, float *m, float *v, int32_t *step,
+                              float *loss_trace, int32_t trace_rows, void *ws, size_t ws_bytes,
                               const gs2d_fit_opts *opts, gs2d_fit_stats *stats, void *stream) {
   try {
     const auto t0 = std::chrono::steady_clock::now();
@@ -512,6 +503,8 @@ extern "C" int gs2d_fit_batch(int32_t n_frames, const gs2d_frame *frames, int32_
     if (!targets || !xy || !chol || !rgb || !m || !v || !step || !loss_trace || !opts)
       return GS2D_EINVAL;
     if (opts->iters < 0 || opts->check_every < 1) return GS2D_EINVAL;
+    rc = gs2d_ctx_check(ctx);
+    if (rc != GS2D_OK) return rc;
     if (stats) {
       stats->iters_run = 0;
       stats->iter_hit_target = -1;
@@ -521,14 +514,14 @@ extern "C" int gs2d_fit_batch(int32_t n_frames, const gs2d_frame *frames, int32_
       stats->status = 0;
       stats->n_culled = 0;
     }
-    if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return GS2D_EHIP;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     int32_t step0 = 0;
-    if (hipMemcpy(&step0, step, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpyAsync(&step0, step, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
       return GS2D_EHIP;
     if (step0 < 0 || (long long)step0 + opts->iters >= (long long)trace_rows) return GS2D_EINVAL;
-    Owned O;
-    if (hipStreamCreateWithFlags(&O.s, hipStreamNonBlocking) != hipSuccess) return GS2D_EHIP;
-    hipStream_t st = O.s;
+    gs2d_ctx local;  // without a context the call's graphs live until it returns
+    gs2d_ctx *cx = ctx ? ctx : &local;
     if (upload_tables(B, ws, st) != hipSuccess) return GS2D_EHIP;
     const int grid = batch_grid(B);
     if (grid < 1) return GS2D_EHIP;
@@ -539,32 +532,35 @@ extern "C" int gs2d_fit_batch(int32_t n_frames, const gs2d_frame *frames, int32_
     const int F = B.F;
     std::vector<float> rows((size_t)opts->check_every * F);
     std::vector<int> misc_host((size_t)BM_STRIDE * F);
-    int done = 0, graph_k = 0, hit = -1;
+    int done = 0, hit = -1;
     double last_mean = NAN;
     uint32_t sticky = 0;
     while (done < opts->iters) {
       const int k = std::min(opts->check_every, opts->iters - done);
+      auto enqueue = [&](hipStream_t s) {
+        hipError_t ce = hipSuccess;
+        for (int i = 0; i < k && ce == hipSuccess; ++i)
+          ce = enqueue_batch_iteration(B, ws, grid, targets, xy, chol, rgb, m, v, step,
+                                       loss_trace, trace_rows, opts->adam, s);
+        return ce;
+      };
       if (opts->use_graph) {
-        if (graph_k != k) {
-          if (O.x) (void)hipGraphExecDestroy(O.x), O.x = nullptr;
-          if (O.g) (void)hipGraphDestroy(O.g), O.g = nullptr;
-          if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
-            return GS2D_EHIP;
-          hipError_t ce = hipSuccess;
-          for (int i = 0; i < k && ce == hipSuccess; ++i)
-            ce = enqueue_batch_iteration(B, ws, grid, targets, xy, chol, rgb, m, v, step,
-                                         loss_trace, trace_rows, opts->adam, st);
-          hipError_t ee = hipStreamEndCapture(st, &O.g);
-          if (ce != hipSuccess || ee != hipSuccess) return GS2D_EHIP;
-          if (hipGraphInstantiate(&O.x, O.g, nullptr, nullptr, 0) != hipSuccess) return GS2D_EHIP;
-          graph_k = k;
-        }
-        if (hipGraphLaunch(O.x, st) != hipSuccess) return GS2D_EHIP;
-      } else {
-        for (int i = 0; i < k; ++i)
-          if (enqueue_batch_iteration(B, ws, grid, targets, xy, chol, rgb, m, v, step, loss_trace,
-                                      trace_rows, opts->adam, st) != hipSuccess)
-            return GS2D_EHIP;
+        GraphKey key{2, (uint64_t)F, (uint64_t)B.T, (uint64_t)B.ppl, (uint64_t)grid,
+                     key_word(targets), key_word(xy), key_word(chol), key_word(rgb),
+                     key_word(m), key_word(v), key_word(step), key_word(loss_trace),
+                     (uint64_t)trace_rows, key_word(ws), (uint64_t)k};
+        for (int f = 0; f < F; ++f)
+          key.push_back(((uint64_t)frames[f].W << 40) ^ ((uint64_t)frames[f].H << 20) ^
+                        (uint64_t)frames[f].N);
+        for (float x : opts->adam.lr) key.push_back(key_word(x));
+        key.push_back(key_word(opts->adam.beta1));
+        key.push_back(key_word(opts->adam.beta2));
+        key.push_back(key_word(opts->adam.eps));
+        hipGraphExec_t x = nullptr;
+        if (cx->graph_for(key, enqueue, &x) != hipSuccess || hipGraphLaunch(x, st) != hipSuccess)
+          return GS2D_EHIP;
+      } else if (enqueue(st) != hipSuccess) {
+        return GS2D_EHIP;
       }
       if (hipMemcpyAsync(rows.data(), loss_trace + (size_t)(step0 + done) * F,
                          sizeof(float) * (size_t)k * F, hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -689,7 +685,7 @@ extern "C" int gs2d_autotune_batch(int32_t n_frames, const gs2d_frame *frames,
     if (n_cand < 1 || !cand_tile || !cand_ppl || reps < 1 || !out_ms || !best || !grad_scratch)
       return GS2D_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    Owned O;
+    Events O;
     if (hipEventCreate(&O.e0) != hipSuccess || hipEventCreate(&O.e1) != hipSuccess)
       return GS2D_EHIP;
     float best_ms = INFINITY;

@@ -7,6 +7,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <functional>
+#include <vector>
+
 #include "gs2d.h"
 
 namespace gs2d {
@@ -112,6 +115,17 @@ struct PendingAdam {
 // Returns false if the shape is outside the supported limits.
 bool make_layout(const gs2d_shape &s, Layout *L);
 
+// The arguments of one fitting call that end up in its kernels.
+struct FitArgs {
+  const float *target;
+  float *xy, *chol, *rgb, *m, *v;
+  int32_t *step;
+  float *trace;
+  int trace_len;
+  void *ws;
+  gs2d_adam_cfg cfg;
+};
+
 template <typename T>
 inline T *at(void *ws, size_t off) {
   return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
@@ -167,4 +181,57 @@ __device__ inline unsigned long long lanemask_lt() {
   return (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
 }
 
+// ---- host-side graph cache (the opaque gs2d_ctx of the C ABI) ----
+
+// Words identifying one captured chunk of work: every pointer, size and
+// hyper-parameter baked into its kernel arguments.
+using GraphKey = std::vector<uint64_t>;
+
+inline uint64_t key_word(const void *p) { return (uint64_t)reinterpret_cast<uintptr_t>(p); }
+inline uint64_t key_word(float f) {
+  uint32_t u;
+  static_assert(sizeof(u) == sizeof(f), "float size");
+  __builtin_memcpy(&u, &f, sizeof(u));
+  return u;
+}
+
+}  // namespace gs2d
+
+// Instantiated graphs of fitting chunks, keyed by GraphKey, captured on a
+// stream of the context's own and launched on the caller's stream.  Host
+// only; one context serves one host thread at a time.
+struct gs2d_ctx {
+  static constexpr size_t MAX_GRAPHS = 16;
+  struct Entry {
+    gs2d::GraphKey key;
+    hipGraphExec_t exec;
+    uint64_t used;
+  };
+  int device = 0;
+  hipStream_t capture = nullptr;
+  std::vector<Entry> graphs;
+  uint64_t clock = 0;
+  uint64_t captures = 0;  // graphs instantiated over the context's life
+
+  // The executable for `key`: cached, or captured now by running `enqueue`
+  // on the capture stream (the least recently used entry is dropped when
+  // the cache is full; no cached graph is in flight then, since every
+  // fitting call waits for its work before returning).
+  hipError_t graph_for(const gs2d::GraphKey &key,
+                       const std::function<hipError_t(hipStream_t)> &enqueue,
+                       hipGraphExec_t *out);
+  ~gs2d_ctx();
+};
+
+// Checks that `ctx` (nullable) belongs to the current device.
+int gs2d_ctx_check(const gs2d_ctx *ctx);
+
+namespace gs2d {
+// The host side of gs2d_fit_frame on validated arguments (api.hip): chunks
+// of iterations on `st`, replayed from ctx's graphs when opts.use_graph
+// (ctx NULL: graphs kept for this call only), a read-back of the loss trace
+// and status after each chunk.  Allocates no host or device memory when
+// opts.use_graph is 0.
+int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_fit_opts &opts,
+                  gs2d_fit_stats *stats, hipStream_t st);
 }  // namespace gs2d

@@ -1,0 +1,140 @@
+"""The fitting context (cached chunk graphs launched on the caller's stream),
+gs2d_fit_prepare and the one-frame autotuner."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.fit import fit as oracle_fit
+from paper_2505_09324_amd import _lib, synth
+from gpu_util import DEV, GpuFrame, dev, host
+
+pytestmark = pytest.mark.gpu
+
+LR = (1e-2, 1e-2, 1e-2)
+
+
+def _state(xy, chol, rgb):
+    N = xy.shape[0]
+    return ({"xy": dev(xy), "chol": dev(chol), "rgb": dev(rgb)},
+            torch.zeros(8 * N, device=DEV), torch.zeros(8 * N, device=DEV),
+            torch.zeros(1, dtype=torch.int32, device=DEV))
+
+
+def test_context_caches_chunk_graphs_and_uses_the_callers_stream():
+    """Two fits of the 128x128 / 500-Gaussian case with the same buffers:
+    the second captures nothing; both run on a side stream right behind the
+    copy that fills the target there, and both trajectories equal the
+    oracle's (10 Adam steps, loss within 1e-3 relative at every step) and a
+    fit without a context."""
+    print("ctx cache + stream", flush=True)
+    frame, _ = synth.make_frame(128, 128, seed=101)
+    xy, chol, rgb = synth.random_gaussians(500, 128, 128, seed=102)
+    f = GpuFrame(128, 128, 500, 16)
+    _, ref = oracle_fit(xy, chol, rgb, frame, 10, lr=LR[0])
+    opts = _lib.fit_opts(10, check_every=4, cfg=_lib.adam_cfg(LR))
+    ctx = _lib.Context()
+    assert ctx.stats() == (0, 0)
+    src = dev(frame)
+    target = torch.zeros(3, 128, 128, device=DEV)
+    P, M, V, step = _state(xy, chol, rgb)
+    trace = torch.full((32,), -1.0, device=DEV)
+    side = torch.cuda.Stream()
+    traces = []
+    for rep in range(2):
+        torch.cuda.synchronize()
+        target.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            for k, a in zip(("xy", "chol", "rgb"), (xy, chol, rgb)):
+                P[k].copy_(dev(a))
+            M.zero_(), V.zero_(), step.zero_()
+            target.copy_(src)  # ordered before the fit only by the stream
+            st = _lib.fit_frame(f.shape, target, P["xy"], P["chol"], P["rgb"], M, V, step,
+                                trace, f.ws, opts, ctx=ctx)
+        assert st.iters_run == 10 and int(step.item()) == 10
+        traces.append(host(trace)[:10].copy())
+        # chunks of 4, 4 and 2 iterations: two graphs, captured by the first fit only
+        assert ctx.stats() == (2, 2), ctx.stats()
+    for tr in traces:
+        np.testing.assert_allclose(tr, ref, rtol=1e-3)
+    np.testing.assert_allclose(traces[1], traces[0], rtol=1e-5)
+    P2, M2, V2, s2 = _state(xy, chol, rgb)
+    tr2 = torch.full((32,), -1.0, device=DEV)
+    _lib.fit_frame(f.shape, src, P2["xy"], P2["chol"], P2["rgb"], M2, V2, s2, tr2, f.ws, opts,
+                   ctx=False)
+    np.testing.assert_allclose(host(tr2)[:10], traces[0], rtol=1e-5)
+    ctx.close()
+
+
+def test_prepare_instantiates_what_the_fit_replays():
+    print("ctx prepare", flush=True)
+    frame, _ = synth.make_frame(96, 64, seed=5)
+    xy, chol, rgb = synth.random_gaussians(200, 96, 64, seed=6)
+    f = GpuFrame(96, 64, 200, 16)
+    P, M, V, step = _state(xy, chol, rgb)
+    trace = torch.zeros(64, device=DEV)
+    ctx = _lib.Context()
+    args = (f.shape, dev(frame), P["xy"], P["chol"], P["rgb"], M, V, step, trace, f.ws)
+    opts = _lib.fit_opts(23, check_every=10, cfg=_lib.adam_cfg(LR))
+    _lib.fit_prepare(*args, opts, ctx=ctx)
+    assert ctx.stats() == (2, 2)  # chunks of 10 and of the remainder 3
+    torch.cuda.synchronize()
+    assert int(step.item()) == 0  # nothing ran
+    st = _lib.fit_frame(*args, opts, ctx=ctx)
+    assert st.iters_run == 23 and ctx.stats() == (2, 2)
+    # another chunk length is another graph
+    _lib.fit_frame(*args, _lib.fit_opts(5, check_every=5, cfg=_lib.adam_cfg(LR)), ctx=ctx)
+    assert ctx.stats() == (3, 3)
+    # a different learning rate is baked into the kernels: another graph
+    _lib.fit_frame(*args, _lib.fit_opts(5, check_every=5, cfg=_lib.adam_cfg(2e-2)), ctx=ctx)
+    assert ctx.stats() == (4, 4)
+    assert int(step.item()) == 33
+
+
+def test_context_rejects_a_device_that_does_not_exist():
+    h = ctypes.c_void_p()
+    n = torch.cuda.device_count()
+    assert _lib.lib().gs2d_ctx_create(ctypes.byref(h), n + 3) == _lib.GS2D_EINVAL
+    assert _lib.lib().gs2d_ctx_create(ctypes.byref(h), -1) == _lib.GS2D_EINVAL
+
+
+def test_batch_fit_reuses_its_graph():
+    print("ctx batch", flush=True)
+    sizes = [(64, 48, 150), (40, 40, 90)]
+    targets, xs, cs, rs = [], [], [], []
+    for i, (w, h, n) in enumerate(sizes):
+        fr, _ = synth.make_frame(w, h, seed=40 + i)
+        x, c, r = synth.random_gaussians(n, w, h, seed=50 + i)
+        targets.append(fr.ravel()), xs.append(x), cs.append(c), rs.append(r)
+    T = dev(np.concatenate(targets))
+    Nt = sum(n for _, _, n in sizes)
+    ws = torch.empty(_lib.batch_workspace_bytes(sizes, 16, 1), dtype=torch.uint8, device=DEV)
+    ctx = _lib.Context()
+    out = []
+    P = [torch.empty(Nt, d, device=DEV) for d in (2, 3, 3)]
+    m, v = torch.zeros(8 * Nt, device=DEV), torch.zeros(8 * Nt, device=DEV)
+    step = torch.zeros(1, dtype=torch.int32, device=DEV)
+    trace = torch.zeros(16, len(sizes), device=DEV)
+    for rep in range(2):
+        for p, a in zip(P, (xs, cs, rs)):  # same buffers, refilled
+            p.copy_(dev(np.concatenate(a)))
+        m.zero_(), v.zero_(), step.zero_()
+        _lib.fit_batch(sizes, 16, 1, T, *P, m, v, step, trace, ws,
+                       _lib.fit_opts(8, 4, cfg=_lib.adam_cfg(LR)), ctx=ctx)
+        out.append(host(trace)[:8].copy())
+        assert ctx.stats() == (1, 1)
+    np.testing.assert_allclose(out[1], out[0], rtol=1e-5)
+
+
+def test_one_frame_autotuner_times_every_candidate():
+    print("autotune frame", flush=True)
+    W, H, N = 200, 120, 800
+    frame, _ = synth.make_frame(W, H, seed=8)
+    xy, chol, rgb = synth.random_gaussians(N, W, H, seed=9)
+    cands = [(8, 1), (16, 1), (16, 2), (32, 1), (32, 2), (32, 4)]
+    best, ms = _lib.autotune_frame(W, H, N, dev(frame), dev(xy), dev(chol), dev(rgb), cands,
+                                   reps=3)
+    assert len(ms) == len(cands) and all(x > 0 for x in ms)
+    assert best == int(np.argmin(ms))
