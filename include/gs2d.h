@@ -252,6 +252,25 @@ int gs2d_autotune_frame(int32_t W, int32_t H, int32_t N, const float *target, co
                         float *grad_scratch, void *ws, size_t ws_bytes, float *out_ms,
                         int32_t *best, void *stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * fitting loop of gs2d_fit_frame with the same arguments apart from the
+ * workspace, which is a file-scope device array of
+ * GS2D_STATIC_WORKSPACE_BYTES inside the library (one per device, held until
+ * the process ends; enough for 1920x1080 with 30,000 Gaussians at every
+ * tile size).  Returns GS2D_ENOSPACE when gs2d_workspace_bytes(shape)
+ * exceeds it.  The chunks are launched directly (opts->use_graph is
+ * ignored) and the call allocates no host or device memory.  Every call on a
+ * device shares that device's array and leaves the last call's contents in
+ * it; the call clears what must start at zero.  Calls that overlap on one
+ * device (other host threads, other streams) race on the array: serialise
+ * them. */
+#define GS2D_STATIC_WORKSPACE_BYTES (16u << 20)
+int gs2d_fit_frame_static(const gs2d_shape *shape, const float *target, float *xy, float *chol,
+                          float *rgb, float *m, float *v, int32_t *step, float *loss_trace,
+                          int32_t trace_len, const gs2d_fit_opts *opts, gs2d_fit_stats *stats,
+                          void *stream);
+
 /* Workspace bytes for gs2d_init_plain on a W x H frame (0 if invalid). */
 size_t gs2d_init_workspace_bytes(int32_t W, int32_t H);
 

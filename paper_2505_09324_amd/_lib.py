@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libgs2d.so")
 
 GS2D_OK, GS2D_EINVAL, GS2D_ENOSPACE, GS2D_EOVERFLOW, GS2D_EHIP = 0, -1, -2, -3, -4
 STATUS_OVERFLOW, STATUS_CULLED = 1, 2
+GS2D_STATIC_WORKSPACE_BYTES = 16 << 20   # gs2d_fit_frame_static's device array
 
 
 class Shape(ctypes.Structure):
@@ -79,6 +80,9 @@ _SIGS = {
     "gs2d_fit_frame": (c_int32, [c_void_p, POINTER(Shape), c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_size_t,
                                  POINTER(FitOpts), POINTER(FitStats), c_void_p]),
+    "gs2d_fit_frame_static": (c_int32, [POINTER(Shape), c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                                        POINTER(FitOpts), POINTER(FitStats), c_void_p]),
     "gs2d_fit_prepare": (c_int32, [c_void_p, POINTER(Shape), c_void_p, c_void_p, c_void_p,
                                    c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
                                    c_void_p, c_size_t, POINTER(FitOpts)]),
@@ -363,6 +367,24 @@ def fit_frame(shape: Shape, target, xy, chol, rgb, m, v, step, loss_trace, ws, o
         ctypes.byref(opts), ctypes.byref(stats), _stream())
     if check:
         _check("gs2d_fit_frame", code)
+    stats.code = code
+    return stats
+
+
+def fit_frame_static(shape: Shape, target, xy, chol, rgb, m, v, step, loss_trace, opts: FitOpts,
+                     check=True) -> FitStats:
+    """gs2d_fit_frame_static: the fitting loop with the library's own
+    device-resident workspace (no allocation; shapes up to its size)."""
+    N, H, W = shape.N, shape.H, shape.W
+    stats = FitStats()
+    code = lib().gs2d_fit_frame_static(
+        ctypes.byref(shape), _ptr(target, "target", shape=(3, H, W)),
+        _ptr(xy, "xy", shape=(N, 2)), _ptr(chol, "chol", shape=(N, 3)),
+        _ptr(rgb, "rgb", shape=(N, 3)), _ptr(m, "m", shape=(8 * N,)), _ptr(v, "v", shape=(8 * N,)),
+        _ptr(step, "step", torch.int32, shape=(1,)), _ptr(loss_trace, "loss_trace"),
+        int(loss_trace.numel()), ctypes.byref(opts), ctypes.byref(stats), _stream())
+    if check:
+        _check("gs2d_fit_frame_static", code)
     stats.code = code
     return stats
 
