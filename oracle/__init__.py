@@ -24,8 +24,12 @@ What it computes, each function citing the passage it follows:
 * ``init``     - the content-aware ROI initialisation (Sec. 3.2.A), in the
                  gradient-magnitude-sampling form used for synthetic frames.
 * ``fit``      - the loop render -> loss -> gradients -> Adam.
+* ``select``   - the P-frame change mask and the reference Gaussians that
+                 influence a changed pixel (selective optimisation,
+                 Sec. 3.2.C), specified in FP32.
 
-Every function works in float64 unless it states otherwise; binning is the
-one deliberate FP32 part because a tile list is an integer decision that
-both sides must take in the same precision.
+Every function works in float64 unless it states otherwise; binning and the
+P-frame selection are the deliberate FP32 parts because a tile list and a
+selected set are integer decisions that both sides must take in the same
+precision.
 """

@@ -3,7 +3,9 @@
 This is the per-frame encoding loop of Sec. 3.2 ("optimization steps" that
 fit the Gaussians to the frame), run for a fixed number of steps.  The loss
 of step k is evaluated at the parameters before update k (so the first loss
-is that of the initialisation).
+is that of the initialisation).  With ``active`` only the Gaussians whose
+flag is set are updated (P-frame selective optimisation, Sec. 3.2.C); the
+loss and the rendering still use every Gaussian.
 """
 from __future__ import annotations
 
@@ -15,7 +17,7 @@ from .loss import dloss_dimg, mse
 from .render import render_box
 
 
-def fit(xy, chol, rgb, target, iters: int, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+def fit(xy, chol, rgb, target, iters: int, lr, beta1=0.9, beta2=0.999, eps=1e-8, active=None):
     """Returns (theta dict FP64, list of per-step losses)."""
     target = np.asarray(target, np.float64)
     H, W = target.shape[1:]
@@ -32,5 +34,5 @@ def fit(xy, chol, rgb, target, iters: int, lr, beta1=0.9, beta2=0.999, eps=1e-8)
         losses.append(mse(img, target))
         g = gradients(theta["xy"], theta["chol"], theta["rgb"], dloss_dimg(img, target), H, W)
         grad = {"xy": g["g_xy"], "chol": g["g_chol"], "rgb": g["g_rgb"]}
-        theta, m, v, t = adam_step(theta, grad, m, v, t, lr, beta1, beta2, eps)
+        theta, m, v, t = adam_step(theta, grad, m, v, t, lr, beta1, beta2, eps, active)
     return theta, losses
