@@ -9,8 +9,9 @@ the P-frame, the rest keep the reference frame's parameters.
 Readings (the paper gives no formula):
 
 * the residual of pixel p is taken between the two source frames, channel by
-  channel, and p has changed iff the largest absolute channel difference is
-  strictly above the threshold tau;
+  channel, and p has changed iff some channel's absolute difference is
+  strictly above the threshold tau (for finite values: the largest one is; a
+  channel whose difference is not a number never counts);
 * a Gaussian influences p iff p lies inside its 3-sigma cutoff (q <= 9), the
   same rule that decides which terms Eq. 2 sums; a Gaussian that the
   degenerate-covariance rule culls influences nothing.
@@ -19,7 +20,7 @@ Both are integer decisions taken from floating-point values, so they are
 specified in FP32 with a fixed operation order, round-to-nearest-even and no
 fused multiply-add (numpy float32 scalars and arrays evaluate exactly that):
 
-    d_k = I_t[k] - I_{t-1}[k];  m = max(|d_0|, |d_1|, |d_2|);  changed = m > tau
+    d_k = I_t[k] - I_{t-1}[k];  changed = |d_0| > tau or |d_1| > tau or |d_2| > tau
     dx = (x + 1/2) - mx;  dy = (y + 1/2) - my
     u1 = dx / l1;  t = l2 * u1;  e = dy - t;  u2 = e / l3
     q = u1 * u1 + u2 * u2;  influences = q <= 9
@@ -38,14 +39,13 @@ CUTOFF = F32(9.0)
 
 
 def changed_pixels(frame, prev, tau) -> np.ndarray:
-    """Boolean [H, W]: pixels whose largest absolute channel change between
+    """Boolean [H, W]: pixels where some channel's absolute change between
     prev and frame ([3, H, W] each, FP32) is strictly above tau."""
     a = np.asarray(frame, F32)
     b = np.asarray(prev, F32)
     with np.errstate(invalid="ignore"):
         d = np.abs(a - b)
-        m = np.maximum(np.maximum(d[0], d[1]), d[2])
-        return m > F32(tau)
+        return (d[0] > F32(tau)) | (d[1] > F32(tau)) | (d[2] > F32(tau))
 
 
 def influence_q(xy, chol, px, py) -> np.ndarray:

@@ -8,7 +8,7 @@ from oracle.select import changed_pixels, influence_q, select, selected_gaussian
 F32 = np.float32
 
 
-def test_change_is_strictly_above_threshold_on_the_largest_channel():
+def test_change_is_strictly_above_threshold_on_some_channel():
     prev = np.zeros((3, 2, 4), F32)
     cur = prev.copy()
     cur[0, 0, 0] = F32(0.25)                       # exactly tau: unchanged
@@ -16,9 +16,11 @@ def test_change_is_strictly_above_threshold_on_the_largest_channel():
     cur[2, 0, 2] = F32(-0.5)                       # |d| above, negative change
     cur[:, 0, 3] = F32(0.1)                        # every channel below
     cur[0, 1, 0] = np.nan                          # not comparable: unchanged
+    cur[1, 1, 2] = np.nan                          # a NaN channel does not veto another
+    cur[2, 1, 2] = F32(0.75)
     cur[:, 1, 1] = [F32(0.0), F32(0.3), F32(0.0)]  # one channel decides
     got = changed_pixels(cur, prev, 0.25)
-    want = np.array([[False, True, True, False], [False, True, False, False]])
+    want = np.array([[False, True, True, False], [False, True, True, False]])
     np.testing.assert_array_equal(got, want)
 
 
