@@ -89,6 +89,12 @@ typedef struct {
   float psnr_target;    /* stop at the first check with PSNR >= target; <=0 off */
   int32_t use_graph;    /* 1: capture each chunk in a hipGraph and replay    */
   gs2d_adam_cfg adam;
+  /* [N] device uint8 or NULL: only Gaussians with active[n] != 0 are
+   * updated; the others keep their parameters and moments bit for bit and
+   * their gradients are not accumulated (P-frame selective optimisation,
+   * Sec. 3.2.C).  The render and the loss always use every Gaussian.
+   * gs2d_fit_batch requires NULL. */
+  const uint8_t *active;
 } gs2d_fit_opts;
 
 typedef struct {
@@ -180,6 +186,26 @@ int gs2d_count_pairs(const gs2d_shape *shape, void *ws, size_t ws_bytes, uint64_
 int gs2d_adam_step(int32_t N, float *xy, float *chol, float *rgb, float *g_xy, float *g_chol,
                    float *g_rgb, float *m, float *v, int32_t *step, const gs2d_adam_cfg *cfg,
                    const uint8_t *active, int32_t zero_grads, void *stream);
+
+/* P-frame selective optimisation (Sec. 3.2.C): the pixels that changed since
+ * the reference frame by more than a user-defined threshold, and the
+ * reference Gaussians that influence one of them; a P-frame fits only those
+ * (pass `active` to gs2d_fit_frame through gs2d_fit_opts.active).  Both are
+ * integer decisions taken in FP32, in this order, without contraction:
+ *   pixel (x, y) changed  iff  |frame - prev| > tau on some channel;
+ *   Gaussian n influences it  iff  q <= 9, with dx = (x + 1/2) - mx,
+ *   dy = (y + 1/2) - my, u1 = dx / l1, u2 = (dy - l2 u1) / l3,
+ *   q = u1 u1 + u2 u2 (the Gaussian's 3-sigma cutoff, as in Eq. 2).
+ * xy, chol: the reference Gaussians [N][2], [N][3], which gs2d_project_bin
+ *   must have binned into ws (their tile lists are the pixel-to-Gaussian
+ *   mapping; culled Gaussians influence nothing).
+ * frame, prev: [3][H][W] FP32, the current and the reference source frame.
+ * active: [N] uint8 output, 1 for a selected Gaussian, else 0.
+ * counts: nullable device int32 [2] output = {changed pixels, selected
+ *   Gaussians}. */
+int gs2d_select_changed(const gs2d_shape *shape, void *ws, size_t ws_bytes, const float *xy,
+                        const float *chol, const float *frame, const float *prev, float tau,
+                        uint8_t *active, int32_t *counts, void *stream);
 
 /* --------------------------------------------------------------- context --
  * Opaque host object holding the instantiated hipGraphs of fitting chunks

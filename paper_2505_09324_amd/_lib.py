@@ -40,7 +40,7 @@ class AdamCfg(ctypes.Structure):
 
 class FitOpts(ctypes.Structure):
     _fields_ = [("iters", c_int32), ("check_every", c_int32), ("psnr_target", c_float),
-                ("use_graph", c_int32), ("adam", AdamCfg)]
+                ("use_graph", c_int32), ("adam", AdamCfg), ("active", c_void_p)]
 
 
 class FitStats(ctypes.Structure):
@@ -74,6 +74,8 @@ _SIGS = {
     "gs2d_adam_step": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_void_p, c_void_p, POINTER(AdamCfg), c_void_p, c_int32,
                                  c_void_p]),
+    "gs2d_select_changed": (c_int32, [POINTER(Shape), c_void_p, c_size_t, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_float, c_void_p, c_void_p, c_void_p]),
     "gs2d_ctx_create": (c_int32, [POINTER(c_void_p), c_int32]),
     "gs2d_ctx_destroy": (None, [c_void_p]),
     "gs2d_ctx_stats": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int64)]),
@@ -302,9 +304,16 @@ def adam_step(xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg: AdamCfg, acti
         _stream()))
 
 
-def fit_opts(iters, check_every=50, psnr_target=0.0, use_graph=True, cfg=None) -> FitOpts:
-    return FitOpts(int(iters), int(check_every), float(psnr_target), int(bool(use_graph)),
-                   cfg if cfg is not None else adam_cfg())
+def fit_opts(iters, check_every=50, psnr_target=0.0, use_graph=True, cfg=None,
+             active=None) -> FitOpts:
+    """Fitting options; active: [N] uint8 device tensor (only Gaussians with
+    a non-zero flag are optimised) or None."""
+    o = FitOpts(int(iters), int(check_every), float(psnr_target), int(bool(use_graph)),
+                cfg if cfg is not None else adam_cfg(), None)
+    if active is not None:
+        o.active = _ptr(active, "active", torch.uint8)
+        o._active_ref = active  # keep the tensor alive with the options
+    return o
 
 
 class Context:
@@ -369,6 +378,22 @@ def fit_frame(shape: Shape, target, xy, chol, rgb, m, v, step, loss_trace, ws, o
         _check("gs2d_fit_frame", code)
     stats.code = code
     return stats
+
+
+def select_changed(shape: Shape, ws, xy, chol, frame, prev, tau, active=None, counts=None):
+    """P-frame selection on the reference Gaussians binned in ws: fills
+    active [N] uint8 (allocated if None); counts (int32 [2], optional) gets
+    (changed pixels, selected Gaussians).  Returns active."""
+    N, H, W = shape.N, shape.H, shape.W
+    if active is None:
+        active = torch.empty(N, dtype=torch.uint8, device=xy.device)
+    _check("gs2d_select_changed", lib().gs2d_select_changed(
+        ctypes.byref(shape), _ptr(ws, "ws", torch.uint8), ws.numel(),
+        _ptr(xy, "xy", shape=(N, 2)), _ptr(chol, "chol", shape=(N, 3)),
+        _ptr(frame, "frame", shape=(3, H, W)), _ptr(prev, "prev", shape=(3, H, W)), float(tau),
+        _ptr(active, "active", torch.uint8, shape=(N,)),
+        _ptr(counts, "counts", torch.int32, shape=(2,), allow_none=True), _stream()))
+    return active
 
 
 def fit_frame_static(shape: Shape, target, xy, chol, rgb, m, v, step, loss_trace, opts: FitOpts,

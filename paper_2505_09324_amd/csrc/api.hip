@@ -236,21 +236,22 @@ namespace {
 // of k complete steps.
 hipError_t enqueue_iterations(const Layout &L, void *ws, const float *target, float *xy,
                               float *chol, float *rgb, float *m, float *v, int32_t *step,
-                              float *trace, int trace_len, const gs2d_adam_cfg &cfg, int k,
-                              hipStream_t st) {
+                              float *trace, int trace_len, const gs2d_adam_cfg &cfg,
+                              const uint8_t *active, int k, hipStream_t st) {
   float *g = at<float>(ws, L.grads);
   float *g_xy = g, *g_chol = g + 2 * (size_t)L.N, *g_rgb = g + 5 * (size_t)L.N;
   const float loss_scale = (float)(1.0 / (3.0 * L.W * (double)L.H));
   const PendingAdam pending{xy,    chol, rgb,  g_xy, g_chol, g_rgb, m,         v,
                             step,  cfg,  at<const float>(ws, L.loss_part), L.loss_parts,
-                            loss_scale, trace, trace_len};
+                            loss_scale, trace, trace_len, active};
   hipError_t e = hipSuccess;
   for (int i = 0; i < k && e == hipSuccess; ++i) {
     e = launch_binning(L, xy, chol, ws, st, step, i > 0 ? &pending : nullptr);
-    if (e == hipSuccess) e = launch_render_fused(L, ws, rgb, target, g_xy, g_chol, g_rgb, st);
+    if (e == hipSuccess)
+      e = launch_render_fused(L, ws, rgb, target, g_xy, g_chol, g_rgb, st, active);
   }
   if (e == hipSuccess && k > 0)
-    e = launch_adam(L.N, xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg, nullptr, 1,
+    e = launch_adam(L.N, xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg, active, 1,
                     at<const float>(ws, L.loss_part), L.loss_parts, loss_scale, trace, trace_len,
                     st);
   return e;
@@ -274,6 +275,7 @@ GraphKey frame_chunk_key(const Layout &L, const FitArgs &a, int k) {
                key_word(a.trace),
                (uint64_t)a.trace_len,
                key_word(a.ws),
+               key_word(a.active),
                (uint64_t)k};
   for (float f : a.cfg.lr) key.push_back(key_word(f));
   key.push_back(key_word(a.cfg.beta1));
@@ -289,14 +291,14 @@ int run_chunk(gs2d_ctx *ctx, bool use_graph, const Layout &L, const FitArgs &a, 
   if (!use_graph) {
     if (!launch) return GS2D_OK;
     return hip_status(enqueue_iterations(L, a.ws, a.target, a.xy, a.chol, a.rgb, a.m, a.v, a.step,
-                                         a.trace, a.trace_len, a.cfg, k, st));
+                                         a.trace, a.trace_len, a.cfg, a.active, k, st));
   }
   hipGraphExec_t x = nullptr;
   hipError_t e = ctx->graph_for(
       frame_chunk_key(L, a, k),
       [&](hipStream_t cs) {
         return enqueue_iterations(L, a.ws, a.target, a.xy, a.chol, a.rgb, a.m, a.v, a.step,
-                                  a.trace, a.trace_len, a.cfg, k, cs);
+                                  a.trace, a.trace_len, a.cfg, a.active, k, cs);
       },
       &x);
   if (e == hipSuccess && launch) e = hipGraphLaunch(x, st);
@@ -327,7 +329,8 @@ extern "C" int gs2d_fit_prepare(gs2d_ctx *ctx, const gs2d_shape *shape, const fl
                             ws_bytes, opts, &L);
     if (rc != GS2D_OK) return rc;
     if (!opts->use_graph || opts->iters == 0) return GS2D_OK;
-    const FitArgs a{target, xy, chol, rgb, m, v, step, loss_trace, trace_len, ws, opts->adam};
+    const FitArgs a{target, xy,        chol, rgb, m, v, step, loss_trace, trace_len, ws,
+                    opts->adam, opts->active};
     const int k0 = std::min(opts->check_every, opts->iters);
     rc = run_chunk(ctx, true, L, a, k0, nullptr, false);
     const int rem = opts->iters % opts->check_every;
@@ -423,7 +426,8 @@ extern "C" int gs2d_fit_frame(gs2d_ctx *ctx, const gs2d_shape *shape, const floa
     const int rc = check_fit_args(ctx, shape, target, xy, chol, rgb, m, v, step, loss_trace, ws,
                                   ws_bytes, opts, &L);
     if (rc != GS2D_OK) return rc;
-    const FitArgs a{target, xy, chol, rgb, m, v, step, loss_trace, trace_len, ws, opts->adam};
+    const FitArgs a{target, xy,        chol, rgb, m, v, step, loss_trace, trace_len, ws,
+                    opts->adam, opts->active};
     return fit_frame_run(ctx, L, a, *opts, stats, as_stream(stream));
   } catch (...) {
     return GS2D_EHIP;

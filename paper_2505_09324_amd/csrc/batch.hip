@@ -279,6 +279,7 @@ k_b_render_persistent(BatchRaster a) {
     fa.keys = a.keys + d.key_off;
     fa.tile_start = a.tile_start + d.tile_off + f;
     fa.rgb = a.rgb + 3 * d.g_off;
+    fa.active = nullptr;
     const float gs = (float)(2.0 / (3.0 * (double)d.W * (double)d.H));
     fused_tile<TILE, PPL, false>(S, acc, fa, t, a.targets + d.px_off,
                           a.loss_part + (d.tile_off + t) * Cfg<TILE, PPL>::NW, gs,
@@ -502,7 +503,7 @@ extern "C" int gs2d_fit_batch(gs2d_ctx *ctx, int32_t n_frames, const gs2d_frame 
     if (rc != GS2D_OK) return rc;
     if (!targets || !xy || !chol || !rgb || !m || !v || !step || !loss_trace || !opts)
       return GS2D_EINVAL;
-    if (opts->iters < 0 || opts->check_every < 1) return GS2D_EINVAL;
+    if (opts->iters < 0 || opts->check_every < 1 || opts->active) return GS2D_EINVAL;
     rc = gs2d_ctx_check(ctx);
     if (rc != GS2D_OK) return rc;
     if (stats) {

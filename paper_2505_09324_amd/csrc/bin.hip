@@ -116,31 +116,41 @@ k_adam_project_wide(int N, int TX, int TY, float inv_tile, PendingAdam a,
   int v = 0;
   if (n < N) {
     const size_t N2 = 2 * (size_t)N, N5 = 5 * (size_t)N;
+    // an inactive Gaussian keeps its parameters and moments (its gradient
+    // is still cleared)
+    const bool upd = !a.active || a.active[n];
     float p[8];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       const size_t i = 2 * (size_t)n + c;
       const float g = a.g_xy[i];
       a.g_xy[i] = 0.f;
-      p[c] = adam_update(a.xy[i], g, a.m + i, a.v + i, a.cfg.lr[0], b1, b2, eps, bc1, bc2);
-      a.xy[i] = p[c];
+      p[c] = a.xy[i];
+      if (upd) {
+        p[c] = adam_update(p[c], g, a.m + i, a.v + i, a.cfg.lr[0], b1, b2, eps, bc1, bc2);
+        a.xy[i] = p[c];
+      }
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const size_t i = 3 * (size_t)n + c;
       const float g = a.g_chol[i];
       a.g_chol[i] = 0.f;
-      p[2 + c] =
-          adam_update(a.chol[i], g, a.m + N2 + i, a.v + N2 + i, a.cfg.lr[1], b1, b2, eps, bc1, bc2);
-      a.chol[i] = p[2 + c];
+      p[2 + c] = a.chol[i];
+      if (upd) {
+        p[2 + c] = adam_update(p[2 + c], g, a.m + N2 + i, a.v + N2 + i, a.cfg.lr[1], b1, b2, eps,
+                               bc1, bc2);
+        a.chol[i] = p[2 + c];
+      }
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const size_t i = 3 * (size_t)n + c;
       const float g = a.g_rgb[i];
       a.g_rgb[i] = 0.f;
-      a.rgb[i] =
-          adam_update(a.rgb[i], g, a.m + N5 + i, a.v + N5 + i, a.cfg.lr[2], b1, b2, eps, bc1, bc2);
+      if (upd)
+        a.rgb[i] = adam_update(a.rgb[i], g, a.m + N5 + i, a.v + N5 + i, a.cfg.lr[2], b1, b2, eps,
+                               bc1, bc2);
     }
     v = project_values(n, TX, TY, inv_tile, p[0], p[1], p[2], p[3], p[4], geom, rect, counts);
   }
@@ -251,7 +261,7 @@ hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, v
   if (adam) {
     const PendingAdam &a = *adam;
     const hipError_t e = launch_adam(L.N, a.xy, a.chol, a.rgb, a.g_xy, a.g_chol, a.g_rgb, a.m, a.v,
-                                     const_cast<int32_t *>(a.step), a.cfg, nullptr, 1, a.loss_part,
+                                     const_cast<int32_t *>(a.step), a.cfg, a.active, 1, a.loss_part,
                                      a.n_part, a.loss_scale, a.trace, a.trace_len, st);
     if (e != hipSuccess) return e;
   }

@@ -110,6 +110,7 @@ struct PendingAdam {
   float loss_scale;
   float *trace;
   int trace_len;
+  const uint8_t *active;  // nullable: Gaussians with active[n] == 0 keep theta, m, v
 };
 
 // Returns false if the shape is outside the supported limits.
@@ -124,6 +125,7 @@ struct FitArgs {
   int trace_len;
   void *ws;
   gs2d_adam_cfg cfg;
+  const uint8_t *active;  // nullable: only flagged Gaussians are updated
 };
 
 template <typename T>
@@ -155,8 +157,10 @@ hipError_t launch_render_fwd(const Layout &L, void *ws, const float *rgb, const 
                              float *img, float *dl_dimg, hipStream_t st);
 hipError_t launch_render_bwd(const Layout &L, void *ws, const float *rgb, const float *dl_dimg,
                              float *g_xy, float *g_chol, float *g_rgb, hipStream_t st);
+// active (nullable): the backward skips Gaussians with active[n] == 0.
 hipError_t launch_render_fused(const Layout &L, void *ws, const float *rgb, const float *target,
-                               float *g_xy, float *g_chol, float *g_rgb, hipStream_t st);
+                               float *g_xy, float *g_chol, float *g_rgb, hipStream_t st,
+                               const uint8_t *active = nullptr);
 hipError_t launch_loss_reduce(const Layout &L, void *ws, float *loss, hipStream_t st);
 hipError_t launch_count_pairs(const Layout &L, void *ws, unsigned long long *out, hipStream_t st);
 

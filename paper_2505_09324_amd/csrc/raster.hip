@@ -190,6 +190,7 @@ static FrameArgs frame_args(const Layout &L, void *ws, const float *rgb) {
   f.keys = at<const uint32_t>(ws, L.keys_sorted());
   f.tile_start = at<const int>(ws, L.tile_start);
   f.rgb = rgb;
+  f.active = nullptr;
   return f;
 }
 
@@ -230,8 +231,10 @@ hipError_t launch_render_bwd(const Layout &L, void *ws, const float *rgb, const 
 }
 
 hipError_t launch_render_fused(const Layout &L, void *ws, const float *rgb, const float *target,
-                               float *g_xy, float *g_chol, float *g_rgb, hipStream_t st) {
+                               float *g_xy, float *g_chol, float *g_rgb, hipStream_t st,
+                               const uint8_t *active) {
   FrameArgs f = frame_args(L, ws, rgb);
+  f.active = active;
   float *lp = at<float>(ws, L.loss_part);
   bool done = false;
 #define CALL(TT, PP)                                                                           \

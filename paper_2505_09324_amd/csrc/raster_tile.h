@@ -41,6 +41,7 @@ struct Smem {
   uint16_t mask[CH];      // bit w: box meets sub-block w (at most 16)
   int id[CH];
   uint16_t list[NW][CH];
+  uint8_t act[CH];        // the Gaussian is optimised (FrameArgs::active)
 };
 
 struct FrameArgs {
@@ -49,6 +50,9 @@ struct FrameArgs {
   const uint32_t *keys;
   const int *tile_start;
   const float *rgb;
+  // nullable [N]: the fused backward skips Gaussians with active[n] == 0
+  // (they are not optimised, Sec. 3.2.C); the forward renders them all
+  const uint8_t *active;
 };
 
 // Whether the ellipse q' <= qmax (staged units: u1 = dx a, u2 = (dy - l2s u1)
@@ -97,7 +101,8 @@ __device__ inline bool ellipse_meets_rect(float mx, float my, float a, float l2s
 template <int TILE, int PPL, bool EXACT = true>
 __device__ inline void stage_chunk(Smem<Cfg<TILE, PPL>::NW> &S, const uint32_t *__restrict__ keys,
                                    int beg, int cnt, int tx, int ty, int W, int H,
-                                   const float4 *__restrict__ geom, const float *__restrict__ rgb) {
+                                   const float4 *__restrict__ geom, const float *__restrict__ rgb,
+                                   const uint8_t *__restrict__ active = nullptr) {
   using C = Cfg<TILE, PPL>;
   constexpr float inv_w = 0.125f, inv_h = 1.0f / (float)C::SBH;
   const float xlast = (float)W - 0.5f, ylast = (float)H - 0.5f;  // last pixel centres
@@ -114,6 +119,7 @@ __device__ inline void stage_chunk(Smem<Cfg<TILE, PPL>::NW> &S, const uint32_t *
     S.A[j] = make_float4(g0.x, g0.y, a, l2s);
     S.B[j] = make_float4(r3s, c0, c1, c2);
     S.id[j] = id;
+    if (active) S.act[j] = active[id];
     const float xlo = __fsub_rn(g0.x, g1.y), xhi = __fadd_rn(g0.x, g1.y);
     const float ylo = __fsub_rn(g0.y, g1.z), yhi = __fadd_rn(g0.y, g1.z);
     // sub-block columns/rows met by the box, tile-local
@@ -197,6 +203,23 @@ __device__ inline float reduce8_transpose(const float (&a)[8]) {
   d += dpp<DPP_QUAD_XOR2>(d);
   d += dpp<DPP_QUAD_XOR1>(d);
   return d;
+}
+
+// Drop the Gaussians whose staged active flag is 0 from this wavefront's
+// list (in place, order kept); returns the new length.
+template <int NW>
+__device__ inline int keep_active(Smem<NW> &S, int len) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const unsigned long long lt = lanemask_lt();
+  int kept = 0;
+  for (int k0 = 0; k0 < len; k0 += 64) {
+    const int j = (k0 + lane < len) ? S.list[w][k0 + lane] : 0;
+    const bool keep = (k0 + lane < len) && S.act[j];
+    const unsigned long long bal = __ballot(keep);
+    if (keep) S.list[w][kept + __popcll(bal & lt)] = (uint16_t)j;
+    kept += __popcll(bal);
+  }
+  return kept;
 }
 
 // Pixel column and first row of this thread.
@@ -395,13 +418,14 @@ __device__ inline void fused_tile(Smem<Cfg<TILE, PPL>::NW> &S, float *acc, const
   if (end - beg <= CH) {
     const int cnt = end - beg;
     __syncthreads();  // LDS of a previous tile (persistent callers) is free
-    stage_chunk<TILE, PPL, EXACT>(S, f.keys, beg, cnt, tx, ty, f.W, f.H, f.geom, f.rgb);
+    stage_chunk<TILE, PPL, EXACT>(S, f.keys, beg, cnt, tx, ty, f.W, f.H, f.geom, f.rgb, f.active);
     for (int i = threadIdx.x; i < cnt * 8; i += C::NT) acc[i] = 0.f;
     __syncthreads();
     int len = compact_chunk<C::NW>(S, cnt);
     len = fwd_chunk<C::NW, PPL, !EXACT>(S, len, pxc, pyc0, inside, a);
     residuals<TILE, PPL>(a, tg, inside, grad_scale, g, &l);
     wave_loss(l, loss_slots + w);
+    if (f.active) len = keep_active<C::NW>(S, len);
     bwd_chunk<C::NW, PPL, false>(S, acc, len, pxc, pyc0, g);
     __syncthreads();
     flush_grads<C::NT, C::NW>(S, acc, cnt, g_xy, g_chol, g_rgb);
@@ -420,10 +444,11 @@ __device__ inline void fused_tile(Smem<Cfg<TILE, PPL>::NW> &S, float *acc, const
   for (int c = beg; c < end; c += CH) {
     const int cnt = min(CH, end - c);
     __syncthreads();
-    stage_chunk<TILE, PPL, EXACT>(S, f.keys, c, cnt, tx, ty, f.W, f.H, f.geom, f.rgb);
+    stage_chunk<TILE, PPL, EXACT>(S, f.keys, c, cnt, tx, ty, f.W, f.H, f.geom, f.rgb, f.active);
     for (int i = threadIdx.x; i < cnt * 8; i += C::NT) acc[i] = 0.f;
     __syncthreads();
-    const int len = compact_chunk<C::NW>(S, cnt);
+    int len = compact_chunk<C::NW>(S, cnt);
+    if (f.active) len = keep_active<C::NW>(S, len);
     bwd_chunk<C::NW, PPL, !EXACT>(S, acc, len, pxc, pyc0, g);
     __syncthreads();
     flush_grads<C::NT, C::NW>(S, acc, cnt, g_xy, g_chol, g_rgb);

@@ -52,7 +52,8 @@ extern "C" int gs2d_fit_frame_static(const gs2d_shape *shape, const float *targe
     if (rc != GS2D_OK) return rc;
     gs2d_fit_opts eager = *opts;
     eager.use_graph = 0;  // instantiating a graph may allocate
-    const gs2d::FitArgs a{target, xy, chol, rgb, m, v, step, loss_trace, trace_len, ws, opts->adam};
+    const gs2d::FitArgs a{target, xy,         chol, rgb, m, v, step, loss_trace, trace_len, ws,
+                          opts->adam, opts->active};
     return gs2d::fit_frame_run(nullptr, L, a, eager, stats, reinterpret_cast<hipStream_t>(stream));
   } catch (...) {
     return GS2D_EHIP;
