@@ -220,3 +220,33 @@ def make_frame_torch(W: int, H: int, seed: int, t: int | None = None, device="cu
     alpha = torch.clamp(0.5 - (rho - 1.0) * min(a, b) / 1.5, 0.0, 1.0)
     img = alpha[None] * tex + (1.0 - alpha[None]) * bg
     return img.contiguous(), (rho <= 1.0)
+
+
+# "Mouth" of the local-change sequences: an ellipse inside the static
+# subject whose height oscillates, the only part of the frame that moves.
+MOUTH_AX = 0.045          # semi-axis along x, fraction of W
+MOUTH_AY = 0.012          # mean semi-axis along y, fraction of H
+MOUTH_DY = 0.22           # centre below the subject centre, fraction of b
+MOUTH_PERIOD = 9          # frames per open/close cycle
+
+
+def make_talking_frame_torch(W: int, H: int, seed: int, t: int, device="cuda"):
+    """A frame of a local-change sequence: the static scene of make_frame
+    (pose t=None) with a dark elliptical "mouth" inside the subject whose
+    height is MOUTH_AY H (1 + 0.9 sin(2 pi t / MOUTH_PERIOD)), edge
+    antialiased over 1.5 px; everything else is identical in every frame
+    (the mostly static content of a talking-head call).  FP32 on `device`.
+    Returns (frame [3,H,W], roi_mask [H,W] bool)."""
+    import torch
+    img, mask = make_frame_torch(W, H, seed, None, device)
+    sp = scene_params(seed)
+    ys = torch.arange(H, device=device, dtype=torch.float32)[:, None] + 0.5
+    xs = torch.arange(W, device=device, dtype=torch.float32)[None, :] + 0.5
+    ma = MOUTH_AX * W
+    mb = MOUTH_AY * H * (1.0 + 0.9 * math.sin(2.0 * math.pi * t / MOUTH_PERIOD))
+    mx, my = W / 2.0, H / 2.0 + MOUTH_DY * SUBJECT_AY * H
+    rho = torch.sqrt(((xs - mx) / ma) ** 2 + ((ys - my) / mb) ** 2)
+    alpha = torch.clamp(0.5 - (rho - 1.0) * min(ma, mb) / 1.5, 0.0, 1.0)
+    dark = torch.tensor(0.25 * sp.cs, device=device, dtype=torch.float32)[:, None, None]
+    out = alpha[None] * dark + (1.0 - alpha[None]) * img
+    return out.contiguous(), mask

@@ -5,6 +5,7 @@ of the fit runs in the HIP library.
 
     python -m paper_2505_09324_amd.workloads batch   # 48 uneven frames, one launch per stage
     python -m paper_2505_09324_amd.workloads video   # warm-started sequence
+    python -m paper_2505_09324_amd.workloads pframe [--sequence motion|local] [--tau 0.02]
 """
 from __future__ import annotations
 
@@ -182,6 +183,74 @@ def run_video(n_frames=60, W=1920, H=1080, N=30000, iters_first=2000, iters_rest
         "warm_mean_psnr_end": round(float(np.mean([r["psnr_last"] for r in rest])), 3) if rest else None,
         "per_frame": recs,
     }
+
+
+# ------------------------------------------- P-frame selective optimisation --
+def run_pframe(n_frames=30, W=1920, H=1080, N=30000, tau=0.02, psnr_target=35.0, cap=2000,
+               iters_first=2000, seed=301, sequence="motion", device="cuda", lr=LR_DEFAULT):
+    """P-frames fitted two ways from the same fitted I-frame (Sec. 3.2.C):
+    a full refit (every Gaussian warm-started and optimised) and the
+    selective optimisation (only the reference Gaussians influencing a pixel
+    whose change since the previous source frame exceeds tau).  Each arm
+    chains its own fitted frames.  Per P-frame the clock runs from the frame
+    being resident to the first PSNR check >= psnr_target (every 10
+    iterations), including the binning and selection.  sequence="motion":
+    the moving subject (+-40 px, +-10 degrees); "local": a static subject
+    whose mouth region alone changes."""
+    make = ((lambda t: synth.make_frame_torch(W, H, seed, t, device)) if sequence == "motion"
+            else (lambda t: synth.make_talking_frame_torch(W, H, seed, t, device)))
+    frames = [make(t)[0] for t in range(n_frames)]
+    f0, m0 = make(0)
+    shape = _lib.make_shape(W, H, N, 32, px_per_lane=2)
+    ws = _lib.alloc_workspace(shape, device)
+    cfg = _lib.adam_cfg(lr)
+    theta0 = [p.contiguous() for p in plain_init_dev(f0, m0, N, seed + 1)]
+    m = torch.zeros(8 * N, device=device)
+    v = torch.zeros(8 * N, device=device)
+    step = torch.zeros(1, dtype=torch.int32, device=device)
+    trace = torch.zeros(max(iters_first, cap) + 16, device=device)
+    _lib.fit_frame(shape, frames[0], *theta0, m, v, step, trace, ws,
+                   _lib.fit_opts(iters_first, 50, cfg=cfg))
+    psnr0 = psnr(float(trace[iters_first - 1]))
+    counts = torch.zeros(2, dtype=torch.int32, device=device)
+    active = torch.zeros(N, dtype=torch.uint8, device=device)
+    out = {"workload": f"{sequence} sequence, {n_frames} frames {W}x{H}, {N} Gaussians; I-frame "
+                       f"{iters_first} iterations ({psnr0:.2f} dB); P-frames to {psnr_target} dB "
+                       f"(cap {cap}), tau {tau}", "iframe_psnr": round(psnr0, 3)}
+    for arm in ("full", "selective"):
+        theta = [p.clone() for p in theta0]
+        recs = []
+        for t in range(1, n_frames):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sel = None
+            if arm == "selective":
+                _lib.project_bin(shape, theta[0], theta[1], ws)
+                _lib.select_changed(shape, ws, theta[0], theta[1], frames[t], frames[t - 1], tau,
+                                    active=active, counts=counts)
+                sel = active
+            m.zero_(), v.zero_(), step.zero_()
+            st = _lib.fit_frame(shape, frames[t], *theta, m, v, step, trace, ws,
+                                _lib.fit_opts(cap, 10, psnr_target, cfg=cfg, active=sel))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            c = counts.cpu().numpy() if arm == "selective" else (None, N)
+            recs.append({"frame": t, "seconds": dt, "iters": int(st.iters_run),
+                         "hit": int(st.iter_hit_target), "psnr_start": psnr(float(trace[0])),
+                         "psnr_end": float(st.final_psnr), "selected": int(c[1]),
+                         "changed_px": None if c[0] is None else int(c[0])})
+        hits = [r for r in recs if r["hit"] >= 0]
+        out[arm] = {
+            "mean_seconds": round(float(np.mean([r["seconds"] for r in recs])), 5),
+            "mean_iters": round(float(np.mean([r["iters"] for r in recs])), 2),
+            "frames_reaching_target": len(hits),
+            "mean_fraction_selected": round(float(np.mean([r["selected"] for r in recs])) / N, 4),
+            "mean_psnr_start": round(float(np.mean([r["psnr_start"] for r in recs])), 3),
+            "per_frame": recs,
+        }
+    out["selective_over_full_seconds"] = round(out["selective"]["mean_seconds"]
+                                               / out["full"]["mean_seconds"], 3)
+    return out
 
 
 # ------------------------------------------------------ learned initialiser --
@@ -477,7 +546,10 @@ def run_cnn_step(steps=20, warmup=3, W=1920, H=1080, N=30000, seed=900, device="
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["batch", "video", "learned", "cnn-step", "fit"])
+    ap.add_argument("which", choices=["batch", "video", "learned", "cnn-step", "fit", "pframe"])
+    ap.add_argument("--sequence", choices=["motion", "local"], default="motion")
+    ap.add_argument("--tau", type=float, default=0.02)
+    ap.add_argument("--target", type=float, default=35.0)
     ap.add_argument("--frames", type=int, default=None)
     ap.add_argument("--iters", type=int, default=None)
     ap.add_argument("--train-seqs", type=int, default=34)
@@ -494,6 +566,11 @@ def main(argv=None):
     elif args.which == "fit":
         W, H = (int(x) for x in (args.size if args.size != "1920x1080" else "640x360").split("x"))
         out = run_fit(W=W, H=H, N=args.N if args.N != 30000 else 1000, iters=args.iters or 1000)
+    elif args.which == "pframe":
+        out = run_pframe(n_frames=args.frames or 30, tau=args.tau, sequence=args.sequence,
+                         psnr_target=args.target)
+        for arm in ("full", "selective"):
+            out[arm].pop("per_frame")
     elif args.which == "cnn-step":
         W, H = (int(x) for x in args.size.split("x"))
         out = run_cnn_step(steps=args.iters or 20, W=W, H=H, N=args.N)
