@@ -24,12 +24,15 @@ What it computes, each function citing the passage it follows:
 * ``init``     - the content-aware ROI initialisation (Sec. 3.2.A), in the
                  gradient-magnitude-sampling form used for synthetic frames.
 * ``fit``      - the loop render -> loss -> gradients -> Adam.
+* ``quant``    - post-training quantisation of a fitted frame (binary16 means,
+                 uniform min-max Cholesky and colour codes), its entropy-coded
+                 bits and the bits-back saving of P-frames (Sec. 3.3, Eq. 3, 4).
 * ``select``   - the P-frame change mask and the reference Gaussians that
                  influence a changed pixel (selective optimisation,
                  Sec. 3.2.C), specified in FP32.
 
-Every function works in float64 unless it states otherwise; binning and the
-P-frame selection are the deliberate FP32 parts because a tile list and a
-selected set are integer decisions that both sides must take in the same
-precision.
+Every function works in float64 unless it states otherwise; binning, the
+P-frame selection and the quantiser codes are the deliberate FP32 parts
+because a tile list, a selected set and a code are integer decisions that
+both sides must take in the same precision.
 """

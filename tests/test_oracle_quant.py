@@ -1,0 +1,72 @@
+"""Pins of the post-training quantisation and bit-count oracle (Sec. 3.3,
+Eq. 3 and 4)."""
+import math
+
+import numpy as np
+
+from oracle.quant import bitsback_saving, entropy_bits, ptq, quantise_component, sequence_bits
+
+F32 = np.float32
+
+
+def test_uniform_quantiser_error_endpoints_and_order():
+    rng = np.random.default_rng(1)
+    x = rng.normal(0.3, 2.0, 5000).astype(F32)
+    for b in (1, 4, 6, 8, 12):
+        codes, xh, lo, hi = quantise_component(x, b)
+        L = 2 ** b - 1
+        step = (float(hi) - float(lo)) / L
+        assert codes.min() == 0 and codes.max() == L
+        assert codes[np.argmin(x)] == 0 and codes[np.argmax(x)] == L
+        assert xh[np.argmin(x)] == lo                     # lo + 0 * step
+        assert abs(float(xh[np.argmax(x)]) - float(hi)) <= 4e-7 * abs(float(hi))
+        err = np.abs(xh.astype(np.float64) - x)
+        assert err.max() <= step / 2 * (1 + 1e-5) + 1e-6  # half a step, FP32 slack
+        order = np.argsort(x, kind="stable")
+        assert np.all(np.diff(codes[order]) >= 0)         # monotone
+
+
+def test_constant_component_and_ties_to_even():
+    codes, xh, lo, hi = quantise_component(np.full(10, 2.5, F32), 6)
+    assert np.all(codes == 0) and np.all(xh == F32(2.5)) and lo == hi
+    assert entropy_bits(codes, 6) == 0.0
+    # 1 bit over [0, 1]: 0.5 lies exactly half-way and goes to the even code 0
+    codes, _, _, _ = quantise_component(np.array([0, 0.5, 0.75, 1], F32), 1)
+    np.testing.assert_array_equal(codes, [0, 0, 1, 1])
+    # 2 bits over [0, 3]: 1.5 and 2.5 are ties -> 2 and 2
+    codes, _, _, _ = quantise_component(np.array([0, 1.5, 2.5, 3], F32), 2)
+    np.testing.assert_array_equal(codes, [0, 2, 2, 3])
+
+
+def test_entropy_of_known_distributions():
+    b = 5
+    codes = np.tile(np.arange(32), 10)                    # uniform over all 32 levels
+    assert abs(entropy_bits(codes, b) - 320 * 5) < 1e-9
+    codes = np.array([0, 7] * 50)                         # two equiprobable symbols
+    assert abs(entropy_bits(codes, 3) - 100.0) < 1e-9
+    codes = np.array([0] * 75 + [1] * 25)                 # H(1/4) = 0.811278...
+    h = -(0.75 * math.log2(0.75) + 0.25 * math.log2(0.25))
+    assert abs(entropy_bits(codes, 1) - 100 * h) < 1e-9
+
+
+def test_half_precision_positions_and_frame_total():
+    xy = np.array([[1024.25, 1024.5], [1025.5, 3.0], [0.1, 1919.7]], F32)
+    chol = np.array([[1, 0, 1], [2, 0.5, 1], [3, -1, 2]], F32)
+    rgb = np.array([[0, 0.5, 1], [1, 0.5, 0], [0.5, 0.5, 0.5]], F32)
+    q = ptq(xy, chol, rgb, 4, 4)
+    # spacing of binary16 at 1024 is 1: 1024.25 -> 1024, 1024.5 ties -> 1024, 1025.5 -> 1026
+    np.testing.assert_array_equal(q["xy"][:2], [[1024, 1024], [1026, 3]])
+    assert abs(float(q["xy"][2, 1]) - 1919.7) <= 0.5 and float(q["xy"][2, 1]) % 1 == 0
+    # constant green channel: one symbol, zero bits
+    assert q["component_bits"][4] == 0.0
+    assert q["bits"] == 2 * 16 * 3 + q["component_bits"].sum() + 6 * 64
+
+
+def test_bitsback_saving_closed_forms():
+    assert abs(bitsback_saving(4) - math.log2(6)) < 1e-12    # log2 24 - log2 4
+    assert abs(bitsback_saving(1)) < 1e-12                   # log2 1 - log2 1
+    n = 1500.0                                               # N / 20 at N = 30000
+    stirling = n * math.log2(n) - n * math.log2(math.e) + 0.5 * math.log2(2 * math.pi * n)
+    assert abs(bitsback_saving(n) - (stirling - math.log2(n))) < 1e-3
+    total, s = sequence_bits(1000.0, 500.0, F=60, K=4, n_p=4)
+    assert abs(s - 45 * math.log2(6)) < 1e-9 and abs(total - (1500.0 - s)) < 1e-9
