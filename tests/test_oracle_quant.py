@@ -70,3 +70,24 @@ def test_bitsback_saving_closed_forms():
     assert abs(bitsback_saving(n) - (stirling - math.log2(n))) < 1e-3
     total, s = sequence_bits(1000.0, 500.0, F=60, K=4, n_p=4)
     assert abs(s - 45 * math.log2(6)) < 1e-9 and abs(total - (1500.0 - s)) < 1e-9
+
+
+def test_quantisation_aware_loop_uses_the_quantised_point():
+    """One quantisation-aware step's loss is the plain loss of the quantised
+    parameters; the parameters it moves are the unquantised ones."""
+    from oracle.fit import fit
+    from oracle.loss import mse
+    from oracle.render import render_box
+    from paper_2505_09324_amd import synth
+    frame, _ = synth.make_frame(32, 24, seed=8)
+    xy, chol, rgb = synth.random_gaussians(40, 32, 24, seed=9)
+    q = ptq(xy, chol, rgb, 3, 3)
+    img = render_box(q["xy"].astype(np.float64), q["chol"].astype(np.float64),
+                     q["rgb"].astype(np.float64), 24, 32, want_bounds=False)["img"]
+    th, losses = fit(xy, chol, rgb, frame, 1, lr=1e-2, quant_bits=(3, 3))
+    assert abs(losses[0] - mse(img, frame)) <= 1e-12 * losses[0]
+    plain, lp = fit(xy, chol, rgb, frame, 1, lr=1e-2)
+    assert losses[0] != lp[0]
+    # Adam's first step moves every parameter by about lr from where it was
+    step = np.abs(th["xy"] - np.asarray(xy, np.float64))
+    assert np.all(step <= 1e-2 * (1 + 1e-6)) and np.median(step) > 5e-3
