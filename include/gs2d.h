@@ -83,6 +83,12 @@ typedef struct {
   float beta1, beta2, eps;
 } gs2d_adam_cfg;
 
+/* Bit depths of the uniform quantisers of the Cholesky vector and the colour
+ * (gs2d_ptq, and quantisation-aware fitting through gs2d_fit_opts.qat). */
+typedef struct gs2d_quant_cfg_s {
+  int32_t bits_chol, bits_rgb;
+} gs2d_quant_cfg;
+
 typedef struct {
   int32_t iters;        /* maximum iterations                               */
   int32_t check_every;  /* iterations per launched chunk / PSNR check (>=1) */
@@ -95,6 +101,13 @@ typedef struct {
    * Sec. 3.2.C).  The render and the loss always use every Gaussian.
    * gs2d_fit_batch requires NULL. */
   const uint8_t *active;
+  /* Host pointer or NULL: quantisation-aware fitting (Sec. 3.3.A, QAT).
+   * Every iteration renders the parameters after the gs2d_ptq quantisers
+   * (ranges taken from the current parameters, so they follow the fit) and
+   * applies the gradients at the quantised point to the FP32 parameters
+   * (straight-through estimator).  The loss trace is the quantised
+   * render's.  gs2d_fit_batch and gs2d_fit_frame_static require NULL. */
+  const gs2d_quant_cfg *qat;
 } gs2d_fit_opts;
 
 typedef struct {
@@ -206,6 +219,28 @@ int gs2d_adam_step(int32_t N, float *xy, float *chol, float *rgb, float *g_xy, f
 int gs2d_select_changed(const gs2d_shape *shape, void *ws, size_t ws_bytes, const float *xy,
                         const float *chol, const float *frame, const float *prev, float tau,
                         uint8_t *active, int32_t *counts, void *stream);
+
+/* Post-training quantisation of a frame's Gaussians and its bit count
+ * (Sec. 3.3.A: distinct quantisers for mean, Cholesky vector and colour;
+ * Sec. 3.3.B: vanilla entropy coding of an I-frame).  Means: IEEE binary16
+ * (round to nearest even).  Cholesky components and colour channels: per
+ * component a uniform min-max quantiser with bits_chol / bits_rgb bits
+ * (1..12) over the frame's range, in FP32 in this order without
+ * contraction: lo = min, hi = max, L = 2^b - 1, inv = L / (hi - lo) (0 if
+ * hi == lo), step = (hi - lo) / L, code = clamp(rint((x - lo) inv), 0, L)
+ * (ties to even), dequantised x^ = lo + code step.  Inputs must be finite.
+ *   q_xy [N][2], q_chol [N][3], q_rgb [N][3]: dequantised parameters.
+ *   codes (nullable) [N][8] uint16: binary16 bits of x, y, then the six codes.
+ *   ranges (nullable) [6][2]: lo, hi of l1, l2, l3, r, g, b.
+ *   bits (nullable) [7] double: N * H (empirical entropy of the codes, the
+ *     size an ideal static entropy coder reaches) for each of the six
+ *     components, then the frame total 32 N + sum + 6 * 64 (side info).
+ *   ws: gs2d_ptq_workspace_bytes(N) bytes, 256-byte aligned. */
+size_t gs2d_ptq_workspace_bytes(int32_t N);
+int gs2d_ptq(int32_t N, const float *xy, const float *chol, const float *rgb,
+             const gs2d_quant_cfg *cfg, float *q_xy, float *q_chol, float *q_rgb,
+             uint16_t *codes, float *ranges, double *bits, void *ws, size_t ws_bytes,
+             void *stream);
 
 /* --------------------------------------------------------------- context --
  * Opaque host object holding the instantiated hipGraphs of fitting chunks

@@ -38,9 +38,14 @@ class AdamCfg(ctypes.Structure):
     _fields_ = [("lr", c_float * 3), ("beta1", c_float), ("beta2", c_float), ("eps", c_float)]
 
 
+class QuantCfg(ctypes.Structure):
+    _fields_ = [("bits_chol", c_int32), ("bits_rgb", c_int32)]
+
+
 class FitOpts(ctypes.Structure):
     _fields_ = [("iters", c_int32), ("check_every", c_int32), ("psnr_target", c_float),
-                ("use_graph", c_int32), ("adam", AdamCfg), ("active", c_void_p)]
+                ("use_graph", c_int32), ("adam", AdamCfg), ("active", c_void_p),
+                ("qat", POINTER(QuantCfg))]
 
 
 class FitStats(ctypes.Structure):
@@ -76,6 +81,10 @@ _SIGS = {
                                  c_void_p]),
     "gs2d_select_changed": (c_int32, [POINTER(Shape), c_void_p, c_size_t, c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_float, c_void_p, c_void_p, c_void_p]),
+    "gs2d_ptq_workspace_bytes": (c_size_t, [c_int32]),
+    "gs2d_ptq": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, POINTER(QuantCfg), c_void_p,
+                           c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
+                           c_void_p]),
     "gs2d_ctx_create": (c_int32, [POINTER(c_void_p), c_int32]),
     "gs2d_ctx_destroy": (None, [c_void_p]),
     "gs2d_ctx_stats": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int64)]),
@@ -305,14 +314,19 @@ def adam_step(xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg: AdamCfg, acti
 
 
 def fit_opts(iters, check_every=50, psnr_target=0.0, use_graph=True, cfg=None,
-             active=None) -> FitOpts:
+             active=None, qat=None) -> FitOpts:
     """Fitting options; active: [N] uint8 device tensor (only Gaussians with
-    a non-zero flag are optimised) or None."""
+    a non-zero flag are optimised) or None; qat: (bits_chol, bits_rgb) for
+    quantisation-aware fitting, or None."""
     o = FitOpts(int(iters), int(check_every), float(psnr_target), int(bool(use_graph)),
-                cfg if cfg is not None else adam_cfg(), None)
+                cfg if cfg is not None else adam_cfg(), None, None)
     if active is not None:
         o.active = _ptr(active, "active", torch.uint8)
         o._active_ref = active  # keep the tensor alive with the options
+    if qat is not None:
+        q = QuantCfg(int(qat[0]), int(qat[1]))
+        o.qat = ctypes.pointer(q)
+        o._qat_ref = q
     return o
 
 
@@ -378,6 +392,31 @@ def fit_frame(shape: Shape, target, xy, chol, rgb, m, v, step, loss_trace, ws, o
         _check("gs2d_fit_frame", code)
     stats.code = code
     return stats
+
+
+def ptq(xy, chol, rgb, bits_chol=6, bits_rgb=6, want_codes=False):
+    """Post-training quantisation on the GPU.  Returns a dict of device
+    tensors: xy, chol, rgb (dequantised), ranges [6, 2], bits [7] (float64:
+    six components' entropy-coded bits, then the frame total) and, with
+    want_codes, codes [N, 8] (int32 view of the uint16 codes)."""
+    N = xy.shape[0]
+    dev = xy.device
+    ws = torch.empty(int(lib().gs2d_ptq_workspace_bytes(N)), dtype=torch.uint8, device=dev)
+    out = {"xy": torch.empty(N, 2, device=dev), "chol": torch.empty(N, 3, device=dev),
+           "rgb": torch.empty(N, 3, device=dev), "ranges": torch.empty(6, 2, device=dev),
+           "bits": torch.empty(7, dtype=torch.float64, device=dev)}
+    codes = torch.empty(N, 8, dtype=torch.int16, device=dev) if want_codes else None
+    cfg = QuantCfg(int(bits_chol), int(bits_rgb))
+    _check("gs2d_ptq", lib().gs2d_ptq(
+        N, _ptr(xy, "xy", shape=(N, 2)), _ptr(chol, "chol", shape=(N, 3)),
+        _ptr(rgb, "rgb", shape=(N, 3)), ctypes.byref(cfg), _ptr(out["xy"], "q_xy"),
+        _ptr(out["chol"], "q_chol"), _ptr(out["rgb"], "q_rgb"),
+        _ptr(codes, "codes", torch.int16, allow_none=True), _ptr(out["ranges"], "ranges"),
+        _ptr(out["bits"], "bits", torch.float64), _ptr(ws, "ws", torch.uint8), ws.numel(),
+        _stream()))
+    if codes is not None:
+        out["codes"] = codes.to(torch.int32) & 0xFFFF
+    return out
 
 
 def select_changed(shape: Shape, ws, xy, chol, frame, prev, tau, active=None, counts=None):

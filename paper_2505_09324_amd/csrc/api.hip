@@ -65,6 +65,8 @@ bool make_layout(const gs2d_shape &s, Layout *L) {
   L->loss_parts = L->n_tiles * (s.tile / 8) * (s.tile / (8 * ppl));
   L->loss_part = take((size_t)L->loss_parts * 4);
   L->grads = take(N * 8 * 4);
+  L->qparams = take(N * 8 * 4);               // quantised xy | chol | rgb (QAT)
+  L->qws = take(quantise_workspace_bytes(s.N));
   L->misc = take(MISC_COUNT * 4);
   L->total = o;
   return true;
@@ -237,10 +239,30 @@ namespace {
 hipError_t enqueue_iterations(const Layout &L, void *ws, const float *target, float *xy,
                               float *chol, float *rgb, float *m, float *v, int32_t *step,
                               float *trace, int trace_len, const gs2d_adam_cfg &cfg,
-                              const uint8_t *active, int k, hipStream_t st) {
+                              const uint8_t *active, int k, hipStream_t st, int qat_bits_chol = 0,
+                              int qat_bits_rgb = 0) {
   float *g = at<float>(ws, L.grads);
   float *g_xy = g, *g_chol = g + 2 * (size_t)L.N, *g_rgb = g + 5 * (size_t)L.N;
   const float loss_scale = (float)(1.0 / (3.0 * L.W * (double)L.H));
+  if (qat_bits_chol > 0) {
+    // quantisation-aware: quantise, bin and render the quantised copy, then
+    // Adam on the FP32 parameters with its gradients (straight through)
+    float *q = at<float>(ws, L.qparams);
+    float *q_xy = q, *q_chol = q + 2 * (size_t)L.N, *q_rgb = q + 5 * (size_t)L.N;
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < k && e == hipSuccess; ++i) {
+      e = launch_quantise(L.N, xy, chol, rgb, qat_bits_chol, qat_bits_rgb, q_xy, q_chol, q_rgb,
+                          nullptr, nullptr, nullptr, at<void>(ws, L.qws), st);
+      if (e == hipSuccess) e = launch_binning(L, q_xy, q_chol, ws, st, step, nullptr);
+      if (e == hipSuccess)
+        e = launch_render_fused(L, ws, q_rgb, target, g_xy, g_chol, g_rgb, st, active);
+      if (e == hipSuccess)
+        e = launch_adam(L.N, xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg, active, 1,
+                        at<const float>(ws, L.loss_part), L.loss_parts, loss_scale, trace,
+                        trace_len, st);
+    }
+    return e;
+  }
   const PendingAdam pending{xy,    chol, rgb,  g_xy, g_chol, g_rgb, m,         v,
                             step,  cfg,  at<const float>(ws, L.loss_part), L.loss_parts,
                             loss_scale, trace, trace_len, active};
@@ -276,6 +298,8 @@ GraphKey frame_chunk_key(const Layout &L, const FitArgs &a, int k) {
                (uint64_t)a.trace_len,
                key_word(a.ws),
                key_word(a.active),
+               (uint64_t)a.qat_bits_chol,
+               (uint64_t)a.qat_bits_rgb,
                (uint64_t)k};
   for (float f : a.cfg.lr) key.push_back(key_word(f));
   key.push_back(key_word(a.cfg.beta1));
@@ -291,14 +315,16 @@ int run_chunk(gs2d_ctx *ctx, bool use_graph, const Layout &L, const FitArgs &a, 
   if (!use_graph) {
     if (!launch) return GS2D_OK;
     return hip_status(enqueue_iterations(L, a.ws, a.target, a.xy, a.chol, a.rgb, a.m, a.v, a.step,
-                                         a.trace, a.trace_len, a.cfg, a.active, k, st));
+                                         a.trace, a.trace_len, a.cfg, a.active, k, st,
+                                         a.qat_bits_chol, a.qat_bits_rgb));
   }
   hipGraphExec_t x = nullptr;
   hipError_t e = ctx->graph_for(
       frame_chunk_key(L, a, k),
       [&](hipStream_t cs) {
         return enqueue_iterations(L, a.ws, a.target, a.xy, a.chol, a.rgb, a.m, a.v, a.step,
-                                  a.trace, a.trace_len, a.cfg, a.active, k, cs);
+                                  a.trace, a.trace_len, a.cfg, a.active, k, cs, a.qat_bits_chol,
+                                  a.qat_bits_rgb);
       },
       &x);
   if (e == hipSuccess && launch) e = hipGraphLaunch(x, st);
@@ -313,6 +339,9 @@ int check_fit_args(gs2d_ctx *ctx, const gs2d_shape *shape, const float *target, 
   if (!target || !xy || !chol || !rgb || !m || !v || !step || !loss_trace || !opts)
     return GS2D_EINVAL;
   if (opts->iters < 0 || opts->check_every < 1) return GS2D_EINVAL;
+  if (opts->qat && (opts->qat->bits_chol < 1 || opts->qat->bits_chol > 12 ||
+                    opts->qat->bits_rgb < 1 || opts->qat->bits_rgb > 12))
+    return GS2D_EINVAL;
   return gs2d_ctx_check(ctx);
 }
 
@@ -329,8 +358,9 @@ extern "C" int gs2d_fit_prepare(gs2d_ctx *ctx, const gs2d_shape *shape, const fl
                             ws_bytes, opts, &L);
     if (rc != GS2D_OK) return rc;
     if (!opts->use_graph || opts->iters == 0) return GS2D_OK;
-    const FitArgs a{target, xy,        chol, rgb, m, v, step, loss_trace, trace_len, ws,
-                    opts->adam, opts->active};
+    const FitArgs a{target, xy, chol, rgb, m, v, step, loss_trace, trace_len, ws, opts->adam,
+                    opts->active, opts->qat ? opts->qat->bits_chol : 0,
+                    opts->qat ? opts->qat->bits_rgb : 0};
     const int k0 = std::min(opts->check_every, opts->iters);
     rc = run_chunk(ctx, true, L, a, k0, nullptr, false);
     const int rem = opts->iters % opts->check_every;
@@ -426,8 +456,9 @@ extern "C" int gs2d_fit_frame(gs2d_ctx *ctx, const gs2d_shape *shape, const floa
     const int rc = check_fit_args(ctx, shape, target, xy, chol, rgb, m, v, step, loss_trace, ws,
                                   ws_bytes, opts, &L);
     if (rc != GS2D_OK) return rc;
-    const FitArgs a{target, xy,        chol, rgb, m, v, step, loss_trace, trace_len, ws,
-                    opts->adam, opts->active};
+    const FitArgs a{target, xy, chol, rgb, m, v, step, loss_trace, trace_len, ws, opts->adam,
+                    opts->active, opts->qat ? opts->qat->bits_chol : 0,
+                    opts->qat ? opts->qat->bits_rgb : 0};
     return fit_frame_run(ctx, L, a, *opts, stats, as_stream(stream));
   } catch (...) {
     return GS2D_EHIP;

@@ -503,7 +503,7 @@ extern "C" int gs2d_fit_batch(gs2d_ctx *ctx, int32_t n_frames, const gs2d_frame 
     if (rc != GS2D_OK) return rc;
     if (!targets || !xy || !chol || !rgb || !m || !v || !step || !loss_trace || !opts)
       return GS2D_EINVAL;
-    if (opts->iters < 0 || opts->check_every < 1 || opts->active) return GS2D_EINVAL;
+    if (opts->iters < 0 || opts->check_every < 1 || opts->active || opts->qat) return GS2D_EINVAL;
     rc = gs2d_ctx_check(ctx);
     if (rc != GS2D_OK) return rc;
     if (stats) {

@@ -26,9 +26,9 @@
 // Gaussian order and the sort is stable on the tile bits, so the result is
 // ascending in (tile, index): unique, hence bit-exact between runs.
 //
-// The box/rectangle arithmetic uses the _rn intrinsics so that no multiply
-// and add are contracted: the tile decision must match its FP32
-// specification exactly.
+// The box/rectangle arithmetic uses the contraction-free f32_* operations
+// (each rounded once, no fused multiply-add): the tile decision must match
+// its FP32 specification exactly.
 #include "bin_common.h"
 
 namespace gs2d {

@@ -35,8 +35,8 @@ constexpr size_t HIST_BYTES =
 // counts[n] = number of tiles met, or -1 for a culled Gaussian (the scan
 // turns -1 into 0 and counts the culls).  geom[n] = {mx, my, 1/l1, l2, 1/l3,
 // rx, ry, 0}; rect[n] = {tx0, ty0, tx1, ty1}.  The box/rectangle arithmetic
-// uses the _rn intrinsics so that no multiply and add are contracted: the
-// tile decision must match its FP32 specification exactly.
+// uses the contraction-free f32_* operations (each rounded once, no fused
+// multiply-add): the tile decision must match its FP32 specification exactly.
 __device__ inline int project_values(int n, int TX, int TY, float inv_tile, float mx, float my,
                                      float l1, float l2, float l3, float4 *__restrict__ geom,
                                      int4 *__restrict__ rect, int *__restrict__ counts) {
@@ -49,17 +49,17 @@ __device__ inline int project_values(int n, int TX, int TY, float inv_tile, floa
     geom[2 * n + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
     return -1;
   }
-  const float a = __fmul_rn(l2, l2);
-  const float b = __fmul_rn(l3, l3);
-  const float s = __fadd_rn(a, b);
-  const float r = __fsqrt_rn(s);
-  const float ry = __fmul_rn(3.0f, r);
-  const float rx = __fmul_rn(3.0f, fabsf(l1));
-  const float xlo = __fsub_rn(mx, rx), xhi = __fadd_rn(mx, rx);
-  const float ylo = __fsub_rn(my, ry), yhi = __fadd_rn(my, ry);
+  const float a = f32_mul(l2, l2);
+  const float b = f32_mul(l3, l3);
+  const float s = f32_add(a, b);
+  const float r = f32_sqrt(s);
+  const float ry = f32_mul(3.0f, r);
+  const float rx = f32_mul(3.0f, fabsf(l1));
+  const float xlo = f32_sub(mx, rx), xhi = f32_add(mx, rx);
+  const float ylo = f32_sub(my, ry), yhi = f32_add(my, ry);
   // division by a power of two == multiplication by its exact reciprocal
-  const float fx0 = floorf(__fmul_rn(xlo, inv_tile)), fx1 = floorf(__fmul_rn(xhi, inv_tile));
-  const float fy0 = floorf(__fmul_rn(ylo, inv_tile)), fy1 = floorf(__fmul_rn(yhi, inv_tile));
+  const float fx0 = floorf(f32_mul(xlo, inv_tile)), fx1 = floorf(f32_mul(xhi, inv_tile));
+  const float fy0 = floorf(f32_mul(ylo, inv_tile)), fy1 = floorf(f32_mul(yhi, inv_tile));
   const float lastx = (float)(TX - 1), lasty = (float)(TY - 1);
   int cnt = 0;
   int4 rc = make_int4(0, 0, -1, -1);

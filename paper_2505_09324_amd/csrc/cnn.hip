@@ -1017,10 +1017,10 @@ k_cnn_targets(int n_tiles, int TX, int T, const uint32_t *__restrict__ keys,
   int k = 0;
   for (int i = tile_start[t]; i < tile_start[t + 1]; ++i) {
     const int n = (int)(keys[i] & 0xFFFFu);
-    const float a = fabsf(__fmul_rn(chol[3 * n], chol[3 * n + 2]));
+    const float a = fabsf(f32_mul(chol[3 * n], chol[3 * n + 2]));
     const float c0 = rgb[3 * n], c1 = rgb[3 * n + 1], c2 = rgb[3 * n + 2];
-    const float s = __fadd_rn(__fadd_rn(__fmul_rn(c0, c0), __fmul_rn(c1, c1)), __fmul_rn(c2, c2));
-    const float m = __fmul_rn(a, s);
+    const float s = f32_add(f32_add(f32_mul(c0, c0), f32_mul(c1, c1)), f32_mul(c2, c2));
+    const float m = f32_mul(a, s);
     if (k < NSLOT) {
       sel[k] = n;
       sm[k] = m;

@@ -44,7 +44,7 @@ struct Layout {
   int digit_bits;   // bits of that digit (8..11), D = 2^digit_bits
   int D;
   size_t geom, rect, counts, offsets, blocks, keys_a, keys_b, hist, tile_start, loss_part, grads,
-      misc, total;
+      qparams, qws, misc, total;
   // the buffer holding the sorted keys after all passes
   size_t keys_sorted() const { return (sort_passes & 1) ? keys_b : keys_a; }
 };
@@ -126,6 +126,7 @@ struct FitArgs {
   void *ws;
   gs2d_adam_cfg cfg;
   const uint8_t *active;  // nullable: only flagged Gaussians are updated
+  int qat_bits_chol, qat_bits_rgb;  // 0: plain fitting, else quantisation-aware
 };
 
 template <typename T>
@@ -176,9 +177,41 @@ hipError_t launch_adam(int N, float *xy, float *chol, float *rgb, float *g_xy, f
                        hipStream_t st);
 
 hipError_t launch_fill_zero(float *p, size_t n, hipStream_t st);
+
+// Quantisation (quant.hip): binary16 means, uniform min-max codes of the
+// Cholesky vector and colour; codes, ranges and bits nullable; qws holds
+// quantise_workspace_bytes(N).
+hipError_t launch_quantise(int N, const float *xy, const float *chol, const float *rgb,
+                           int bits_chol, int bits_rgb, float *q_xy, float *q_chol, float *q_rgb,
+                           uint16_t *codes, float *ranges, double *bits, void *qws,
+                           hipStream_t st);
+size_t quantise_workspace_bytes(int N);
 hipError_t launch_fill_zero_u32(uint32_t *p, size_t n, hipStream_t st);
 
 // ---- device helpers ----
+
+// FP32 operations evaluated exactly as written: each rounds once to nearest
+// even and is never fused with a neighbouring operation into a multiply-add
+// (these bodies are compiled with contraction off; the HIP _rn intrinsics
+// alone do not stop a product from being contracted into a following sum).
+// Every specified FP32 order whose result decides an integer (tile
+// rectangles, gradient levels, selection and quantiser tests, target ranks)
+// is written with them.
+__device__ inline float f32_mul(float a, float b) {
+#pragma clang fp contract(off)
+  return a * b;
+}
+__device__ inline float f32_add(float a, float b) {
+#pragma clang fp contract(off)
+  return a + b;
+}
+__device__ inline float f32_sub(float a, float b) {
+#pragma clang fp contract(off)
+  return a - b;
+}
+// Correctly rounded square root (the library's sqrtf lowering, which
+// corrects the hardware estimate; __fsqrt_rn is the uncorrected estimate).
+__device__ inline float f32_sqrt(float a) { return __builtin_sqrtf(a); }
 
 __device__ inline unsigned long long lanemask_lt() {
   const unsigned lane = __lane_id();

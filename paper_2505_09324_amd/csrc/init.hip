@@ -48,7 +48,7 @@ bool init_layout(int W, int H, InitLayout *L) {
 }
 
 __device__ inline float luma_sum(const float *__restrict__ T, size_t HW, size_t p) {
-  return __fadd_rn(__fadd_rn(T[p], T[HW + p]), T[2 * HW + p]);
+  return f32_add(f32_add(T[p], T[HW + p]), T[2 * HW + p]);
 }
 
 __global__ void __launch_bounds__(INIT_BLOCK)
@@ -61,22 +61,22 @@ k_init_levels(int W, int H, const float *__restrict__ T, const uint8_t *__restri
     float gx = 0.f, gy = 0.f;
     if (W > 1) {
       if (x == 0)
-        gx = __fmul_rn(__fsub_rn(luma_sum(T, HW, p + 1), luma_sum(T, HW, p)), 2.0f);
+        gx = f32_mul(f32_sub(luma_sum(T, HW, p + 1), luma_sum(T, HW, p)), 2.0f);
       else if (x == W - 1)
-        gx = __fmul_rn(__fsub_rn(luma_sum(T, HW, p), luma_sum(T, HW, p - 1)), 2.0f);
+        gx = f32_mul(f32_sub(luma_sum(T, HW, p), luma_sum(T, HW, p - 1)), 2.0f);
       else
-        gx = __fsub_rn(luma_sum(T, HW, p + 1), luma_sum(T, HW, p - 1));
+        gx = f32_sub(luma_sum(T, HW, p + 1), luma_sum(T, HW, p - 1));
     }
     if (H > 1) {
       if (y == 0)
-        gy = __fmul_rn(__fsub_rn(luma_sum(T, HW, p + W), luma_sum(T, HW, p)), 2.0f);
+        gy = f32_mul(f32_sub(luma_sum(T, HW, p + W), luma_sum(T, HW, p)), 2.0f);
       else if (y == H - 1)
-        gy = __fmul_rn(__fsub_rn(luma_sum(T, HW, p), luma_sum(T, HW, p - W)), 2.0f);
+        gy = f32_mul(f32_sub(luma_sum(T, HW, p), luma_sum(T, HW, p - W)), 2.0f);
       else
-        gy = __fsub_rn(luma_sum(T, HW, p + W), luma_sum(T, HW, p - W));
+        gy = f32_sub(luma_sum(T, HW, p + W), luma_sum(T, HW, p - W));
     }
-    const float mag = __fsqrt_rn(__fadd_rn(__fmul_rn(gx, gx), __fmul_rn(gy, gy)));
-    const long long q = (long long)floorf(__fmul_rn(mag, 1024.0f));
+    const float mag = f32_sqrt(f32_add(f32_mul(gx, gx), f32_mul(gy, gy)));
+    const long long q = (long long)floorf(f32_mul(mag, 1024.0f));
     const int in = mask[p] != 0;
     qm[p] = in ? q : 0;
     qa[p] = q;
@@ -265,8 +265,8 @@ k_init_draw(DrawArgs a, const int64_t *__restrict__ pick_roi, const float *__res
     jy = jit_out[2 * j + 1];
   }
   const int y = (int)(p / a.W), x = (int)(p % a.W);
-  xy[2 * i] = __fadd_rn(__fadd_rn((float)x, 0.5f), jx);
-  xy[2 * i + 1] = __fadd_rn(__fadd_rn((float)y, 0.5f), jy);
+  xy[2 * i] = f32_add(f32_add((float)x, 0.5f), jx);
+  xy[2 * i + 1] = f32_add(f32_add((float)y, 0.5f), jy);
   chol[3 * i] = s;
   chol[3 * i + 1] = 0.f;
   chol[3 * i + 2] = s;

@@ -35,9 +35,9 @@ struct SelSmem {
 
 __device__ inline bool changed_px(const float *__restrict__ a, const float *__restrict__ b,
                                   size_t p, size_t HW, float tau) {
-  const float d0 = __fsub_rn(a[p], b[p]);
-  const float d1 = __fsub_rn(a[HW + p], b[HW + p]);
-  const float d2 = __fsub_rn(a[2 * HW + p], b[2 * HW + p]);
+  const float d0 = f32_sub(a[p], b[p]);
+  const float d1 = f32_sub(a[HW + p], b[HW + p]);
+  const float d2 = f32_sub(a[2 * HW + p], b[2 * HW + p]);
   return fabsf(d0) > tau || fabsf(d1) > tau || fabsf(d2) > tau;
 }
 
@@ -109,15 +109,15 @@ k_select(int W, int H, int TX, const uint32_t *__restrict__ keys,
       const int j = S.list[w][k];
       const float4 A = S.A[j];
       const float l3 = S.l3[j];
-      const float u1 = __fdiv_rn(__fsub_rn(pxc, A.x), A.z);
-      const float t = __fmul_rn(A.w, u1);
-      const float u1s = __fmul_rn(u1, u1);
+      const float u1 = __fdiv_rn(f32_sub(pxc, A.x), A.z);
+      const float t = f32_mul(A.w, u1);
+      const float u1s = f32_mul(u1, u1);
       bool hit = false;
 #pragma unroll
       for (int r = 0; r < PPL; ++r) {
-        const float dy = __fsub_rn(pyc0 + (float)r, A.y);
-        const float u2 = __fdiv_rn(__fsub_rn(dy, t), l3);
-        const float q = __fadd_rn(u1s, __fmul_rn(u2, u2));
+        const float dy = f32_sub(pyc0 + (float)r, A.y);
+        const float u2 = __fdiv_rn(f32_sub(dy, t), l3);
+        const float q = f32_add(u1s, f32_mul(u2, u2));
         hit |= ((ch >> r) & 1u) && q <= 9.0f;
       }
       if (__ballot(hit) && lane == 0) active[S.id[j]] = 1;

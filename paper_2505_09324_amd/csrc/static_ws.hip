@@ -46,14 +46,14 @@ extern "C" int gs2d_fit_frame_static(const gs2d_shape *shape, const float *targe
     if (L.total > STATIC_BYTES) return GS2D_ENOSPACE;
     if (!target || !xy || !chol || !rgb || !m || !v || !step || !loss_trace || !opts)
       return GS2D_EINVAL;
-    if (opts->iters < 0 || opts->check_every < 1) return GS2D_EINVAL;
+    if (opts->iters < 0 || opts->check_every < 1 || opts->qat) return GS2D_EINVAL;
     void *ws = nullptr;
     const int rc = scratch_address(&ws);
     if (rc != GS2D_OK) return rc;
     gs2d_fit_opts eager = *opts;
     eager.use_graph = 0;  // instantiating a graph may allocate
-    const gs2d::FitArgs a{target, xy,         chol, rgb, m, v, step, loss_trace, trace_len, ws,
-                          opts->adam, opts->active};
+    const gs2d::FitArgs a{target, xy, chol, rgb, m, v, step, loss_trace, trace_len, ws,
+                          opts->adam, opts->active, 0, 0};
     return gs2d::fit_frame_run(nullptr, L, a, eager, stats, reinterpret_cast<hipStream_t>(stream));
   } catch (...) {
     return GS2D_EHIP;

@@ -174,3 +174,50 @@ def test_bins_single_pass_limits():
     assert out["n_tiles"] == 2048
     _compare(out, bin_gaussians(xy, chol, W, H, 32), N)
     assert int(out["keys"][out["n_pairs"] - 1]) == (2047 << 16) | (N - 1)
+
+
+def _rounding_edge_gaussians(n, T, seed):
+    """Gaussians whose box edge mx + 3|l1| or my + 3 sqrt(l2^2 + l3^2) lands
+    within rounding of a tile boundary, chosen (seeded search) where the
+    specified FP32 order (every operation rounded, correctly rounded sqrt)
+    and a fused multiply-add or an uncorrected sqrt would put the edge on
+    different sides of the boundary."""
+    f32, f64 = np.float32, np.float64
+    rng = np.random.default_rng(seed)
+    out_xy, out_l = [], []
+    while len(out_xy) < n:
+        l1 = f32(rng.uniform(0.5, 6.0))
+        l2 = f32(rng.uniform(-4.0, 4.0))
+        l3 = f32(rng.uniform(0.5, 6.0))
+        B = f32(T * rng.integers(2, 6))
+        # y edge: ry from separate roundings and from s = fma(l2, l2, l3*l3)
+        s_spec = f32(f32(l2 * l2) + f32(l3 * l3))
+        s_fma = f32(f64(l2) * f64(l2) + f64(f32(l3 * l3)))
+        r_exact = np.sqrt(f64(s_spec))
+        r_lo, r_hi = f32(np.float32(r_exact)), np.nextafter(f32(r_exact), f32(np.inf))
+        cands = {f32(f32(3) * f32(np.sqrt(s_spec))), f32(f32(3) * f32(np.sqrt(s_fma))),
+                 f32(f32(3) * r_lo), f32(f32(3) * r_hi)}
+        ry = f32(f32(3) * f32(np.sqrt(s_spec)))
+        my = f32(B - ry)
+        edges = {int(np.floor(f32(my + c) / f32(T))) for c in cands}
+        # x edge: rx = 3|l1| rounded vs mx + 3|l1| fused
+        rx = f32(f32(3) * abs(l1))
+        mx = f32(B - rx)
+        xe_spec = int(np.floor(f32(mx + rx) / f32(T)))
+        xe_fma = int(np.floor(f32(f64(mx) + f64(3) * f64(abs(l1))) / f32(T)))
+        if len(edges) > 1 or xe_spec != xe_fma:
+            out_xy.append([mx, my])
+            out_l.append([l1, l2, l3])
+    return np.array(out_xy, np.float32), np.array(out_l, np.float32)
+
+
+@pytest.mark.parametrize("T", [8, 16, 32])
+def test_bins_at_fp32_rounding_edges(T):
+    """Box edges within rounding of a tile boundary: the GPU's rectangles
+    follow the specified FP32 order (no contraction, correctly rounded
+    sqrt) bit for bit."""
+    print(f"bins rounding edges T={T}", flush=True)
+    xy, chol = _rounding_edge_gaussians(400, T, seed=T)
+    W = H = 6 * T + 7
+    f = GpuFrame(W, H, len(xy), T)
+    _compare(f.bin(dev(xy), dev(chol)), bin_gaussians(xy, chol, W, H, T), len(xy))
