@@ -6,6 +6,7 @@ of the fit runs in the HIP library.
     python -m paper_2505_09324_amd.workloads batch   # 48 uneven frames, one launch per stage
     python -m paper_2505_09324_amd.workloads video   # warm-started sequence
     python -m paper_2505_09324_amd.workloads pframe [--sequence motion|local] [--tau 0.02]
+    python -m paper_2505_09324_amd.workloads compress   # PTQ, QAT, Eq. 3-4 bit count
 """
 from __future__ import annotations
 
@@ -250,6 +251,99 @@ def run_pframe(n_frames=30, W=1920, H=1080, N=30000, tau=0.02, psnr_target=35.0,
         }
     out["selective_over_full_seconds"] = round(out["selective"]["mean_seconds"]
                                                / out["full"]["mean_seconds"], 3)
+    return out
+
+
+# ------------------------------------------------------------- compression --
+def frame_psnr(shape, ws, target, xy, chol, rgb):
+    """PSNR of the render of (xy, chol, rgb) against target (library calls)."""
+    _lib.project_bin(shape, xy, chol, ws)
+    loss = torch.zeros((), device=target.device)
+    _lib.render_fwd(shape, ws, rgb, target=target, loss=loss)
+    return psnr(float(loss))
+
+
+def run_compress(W=1920, H=1080, N=30000, iters=1000, seed=201,
+                 bit_pairs=((4, 4), (6, 6), (8, 8), (10, 10)), qat_bits=(6, 6), frames=60, gop=10,
+                 device="cuda", lr=LR_DEFAULT):
+    """Sec. 3.3: post-training quantisation of a fitted 1080p frame at several
+    bit depths (PSNR after quantisation, entropy-coded bits, bpp, latency),
+    quantisation-aware fitting against fitting + PTQ for the same iterations
+    (time and PSNR after quantisation, the comparison of Table 3), and the
+    sequence bit count of Eq. 3-4 for `frames` frames with an I-frame every
+    `gop`, N/20 Gaussians per P-frame as in the paper."""
+    import math
+    f, m = synth.make_frame_torch(W, H, seed, None, device)
+    shape = _lib.make_shape(W, H, N, 32, px_per_lane=2)
+    ws = _lib.alloc_workspace(shape, device)
+    cfg = _lib.adam_cfg(lr)
+    theta0 = [p.contiguous() for p in plain_init_dev(f, m, N, seed + 1)]
+    ctx = _lib.Context()
+
+    def fit(qat, qat_iters=None):
+        """Fit from theta0; with qat, the last qat_iters iterations (all when
+        None) are quantisation-aware, the Adam state carried across."""
+        th = [p.clone() for p in theta0]
+        mm = torch.zeros(8 * N, device=device)
+        vv = torch.zeros(8 * N, device=device)
+        step = torch.zeros(1, dtype=torch.int32, device=device)
+        trace = torch.zeros(iters + 8, device=device)
+        k_q = 0 if qat is None else (iters if qat_iters is None else qat_iters)
+        parts = [o for o in (_lib.fit_opts(iters - k_q, 50, cfg=cfg) if iters > k_q else None,
+                             _lib.fit_opts(k_q, 50, cfg=cfg, qat=qat) if k_q else None) if o]
+        for o in parts:
+            _lib.fit_prepare(shape, f, *th, mm, vv, step, trace, ws, o, ctx=ctx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for o in parts:
+            _lib.fit_frame(shape, f, *th, mm, vv, step, trace, ws, o, ctx=ctx)
+        torch.cuda.synchronize()
+        return th, time.perf_counter() - t0
+
+    fit(None)                                   # warm: graphs, clocks
+    theta, t_plain = fit(None)
+    out = {"workload": f"{W}x{H}, {N} Gaussians fitted {iters} iterations from the content-aware "
+                       f"init", "fit_psnr": round(frame_psnr(shape, ws, f, *theta), 3),
+           "fit_seconds": round(t_plain, 4), "ptq": []}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for bc, br in bit_pairs:
+        q = _lib.ptq(*theta, bc, br)
+        e0.record()
+        for _ in range(20):
+            q = _lib.ptq(*theta, bc, br)
+        e1.record()
+        torch.cuda.synchronize()
+        bits = q["bits"].cpu().numpy()
+        out["ptq"].append({"bits_chol": bc, "bits_rgb": br,
+                           "psnr": round(frame_psnr(shape, ws, f, q["xy"], q["chol"], q["rgb"]), 3),
+                           "bits": round(float(bits[6])), "bits_per_gaussian": round(float(bits[6]) / N, 3),
+                           "bpp": round(float(bits[6]) / (W * H), 5),
+                           "latency_ms": round(e0.elapsed_time(e1) / 20, 4)})
+    qp = _lib.ptq(*theta, *qat_bits)
+    out["qat"] = {"bits": list(qat_bits),
+                  "ptq_psnr_after_quantisation": round(frame_psnr(shape, ws, f, qp["xy"], qp["chol"], qp["rgb"]), 3)}
+    for name, k_q in (("whole_fit", None), ("last_20pct", iters // 5)):
+        fit(qat_bits, k_q)                      # warm the quantisation-aware graphs
+        theta_q, t_qat = fit(qat_bits, k_q)
+        qq = _lib.ptq(*theta_q, *qat_bits)
+        out["qat"][name] = {
+            "seconds": round(t_qat, 4),
+            "psnr_after_quantisation": round(frame_psnr(shape, ws, f, qq["xy"], qq["chol"], qq["rgb"]), 3),
+            "fp32_psnr": round(frame_psnr(shape, ws, f, *theta_q), 3),
+            "overhead_seconds_per_1000_iterations": round((t_qat - t_plain) * 1000 / iters, 4)}
+    # Eq. 3-4 for a sequence, the frame's quantised size standing for every frame
+    i_bits = float(qp["bits"][6].item())
+    n_p = N / 20
+    p_bits = n_p * i_bits / N
+    n_i = math.ceil(frames / gop)
+    s_p = (math.lgamma(n_p + 1) - math.log(n_p)) / math.log(2)
+    s_total = (frames - frames / gop) * s_p
+    total = n_i * i_bits + (frames - n_i) * p_bits - s_total
+    out["sequence"] = {"frames": frames, "gop": gop, "gaussians_per_p_frame": n_p,
+                       "i_frame_bits": round(i_bits), "p_frame_bits": round(p_bits),
+                       "bitsback_saving_per_p_frame": round(s_p, 1), "total_bits": round(total),
+                       "bpp": round(total / (frames * W * H), 5),
+                       "bpp_all_i_frames": round(i_bits / (W * H), 5)}
     return out
 
 
@@ -546,7 +640,8 @@ def run_cnn_step(steps=20, warmup=3, W=1920, H=1080, N=30000, seed=900, device="
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["batch", "video", "learned", "cnn-step", "fit", "pframe"])
+    ap.add_argument("which", choices=["batch", "video", "learned", "cnn-step", "fit", "pframe",
+                                      "compress"])
     ap.add_argument("--sequence", choices=["motion", "local"], default="motion")
     ap.add_argument("--tau", type=float, default=0.02)
     ap.add_argument("--target", type=float, default=35.0)
@@ -571,6 +666,8 @@ def main(argv=None):
                          psnr_target=args.target)
         for arm in ("full", "selective"):
             out[arm].pop("per_frame")
+    elif args.which == "compress":
+        out = run_compress(iters=args.iters or 1000)
     elif args.which == "cnn-step":
         W, H = (int(x) for x in args.size.split("x"))
         out = run_cnn_step(steps=args.iters or 20, W=W, H=H, N=args.N)
