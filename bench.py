@@ -110,7 +110,15 @@ def cpu_baseline(iters: int):
         for s in shm:
             s.close()
             s.unlink()
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                             None)
+    except OSError:
+        pass
     return {"value": iters / dt, "unit": "iters/s", "cores": P, "kind": "oracle",
+            "cpu_model": cpu_model, "os_cpu_count": os.cpu_count(),
             "sample": f"{iters} full FP64 iterations (render, MSE, gradients, Adam) of the "
                       f"1920x1080 / 30k-Gaussian workload from its initialisation, "
                       f"{P} processes", "seconds": round(dt, 3)}

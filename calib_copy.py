@@ -2,7 +2,7 @@
 a few times with a plain device copy, so that a counter profile of this
 script gives the counter's reading per byte actually moved.
 
-    rocprofv3 --pmc FETCH_SIZE -- python -m paper_2505_09324_amd.calib_copy
+    rocprofv3 --pmc FETCH_SIZE -- python calib_copy.py
 """
 import sys
 
