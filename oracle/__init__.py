@@ -30,9 +30,14 @@ What it computes, each function citing the passage it follows:
 * ``select``   - the P-frame change mask and the reference Gaussians that
                  influence a changed pixel (selective optimisation,
                  Sec. 3.2.C), specified in FP32.
+* ``superpixel`` - the superpixel ROI initialisation (Sec. 3.2.A, Fig. 2):
+                 SLIC-style K-means in (x, y, colour) from the content-aware
+                 seeds, exact integer segment moments, one Gaussian per
+                 segment from its centre, covariance and mean colour.
 
 Every function works in float64 unless it states otherwise; binning, the
-P-frame selection and the quantiser codes are the deliberate FP32 parts
+P-frame selection, the quantiser codes and the superpixel assignment are the
+deliberate FP32 parts
 because a tile list, a selected set and a code are integer decisions that
 both sides must take in the same precision.
 """
