@@ -7,8 +7,9 @@ colour from the segment's average colour.  Readings (the paper gives no
 parameters):
 
 * K = the number of ROI Gaussians; the K seeds are the ROI pixels the
-  content-aware sampler picks (A20), so both initialisations share their
-  seeds and their Gaussians outside the ROI;
+  content-aware sampler picks, so both initialisations share their seeds
+  and their Gaussians outside the ROI; as there, an empty ROI mask stands
+  for the whole frame;
 * K-means in (x, y, colour) in the manner of SLIC: with S = max(1,
   round(sqrt(R / K))) (R ROI pixels) and compactness m, the distance of ROI
   pixel p to centre k is D = ((dr^2 + dg^2) + db^2) + w (dx^2 + dy^2),
@@ -138,6 +139,8 @@ def kmeans(frame, roi, seeds_xy, iters: int, m: float):
     x, y).  Returns (labels of the last assignment, centres before it,
     centres after it, S)."""
     roi = np.asarray(roi, bool)
+    if not roi.any():
+        roi = np.ones_like(roi)
     K = len(seeds_xy)
     S = grid_step(int(roi.sum()), K)
     w = compactness_weight(m, S)

@@ -124,3 +124,11 @@ def test_assignment_is_the_argmin_of_the_slic_distance():
                 checked += 1
     assert checked > 0.9 * H * W
     assert grid_step(1000, 10) == 10 and grid_step(5, 10) == 1 and grid_step(1000, 7) == 12
+
+
+def test_empty_roi_is_the_whole_frame():
+    frame = np.random.default_rng(3).uniform(0, 1, (3, 10, 12)).astype(F32)
+    a = kmeans(frame, np.zeros((10, 12), bool), [[2, 2], [9, 7]], iters=2, m=0.3)
+    b = kmeans(frame, np.ones((10, 12), bool), [[2, 2], [9, 7]], iters=2, m=0.3)
+    np.testing.assert_array_equal(a[0], b[0])
+    assert np.all(a[0] >= 0) and a[3] == b[3] == 8
