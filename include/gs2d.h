@@ -360,6 +360,47 @@ int gs2d_init_plain(int32_t W, int32_t H, const float *target, const uint8_t *ro
                     const int64_t *pick_out, const float *jit_out, float *xy, float *chol,
                     float *rgb, int32_t *picked, void *ws, size_t ws_bytes, void *stream);
 
+/* Workspace bytes for gs2d_init_superpixel (0 if invalid: 1 <= K <= 65536,
+ * W * H <= 2^28). */
+size_t gs2d_superpixel_workspace_bytes(int32_t W, int32_t H, int32_t K);
+
+/* Superpixel ROI initialisation (Sec. 3.2.A, Fig. 2: the ROI is segmented by
+ * K-means superpixels, one Gaussian per segment with the segment's centre,
+ * covariance and average colour).  K-means in (x, y, colour) from K seed
+ * pixels, SLIC-style:
+ *   S = max(1, rint(sqrt(R / K))) with R the ROI pixel count (FP64, ties to
+ *   even), w = (m / S)^2 (FP32); ROI pixel p joins the centre k minimising
+ *   D = ((dr^2 + dg^2) + db^2) + w (dx^2 + dy^2)   (FP32, this order, no
+ *   contraction; d = pixel - centre; pixel position = its centre)
+ *   among the centres whose cell (floor(centre / S), FP32 division) is within
+ *   one cell of the pixel's (x // S, y // S) on both axes, ties to the lowest
+ *   k; a ROI pixel with no such centre gets label -1.  The new centres are
+ *   the exact means of their pixels (FP64 from int64 sums of the pixel
+ *   indices, plus 1/2, and of the colours in 1/65536 units), rounded to FP32;
+ *   an empty segment keeps its centre.  Seed k starts at the centre of pixel
+ *   seeds[k] with that pixel's colour rounded to 1/65536.
+ * After `iters` rounds, each non-empty segment k writes
+ *   xy[k] = mean + 1/2,  chol[k] = Cholesky factor of (covariance + I/12),
+ *   rgb[k] = colour sum / (2 pi l1 l3 (1 - e^-4.5)),
+ * evaluated in FP64 from the exact integer moments and rounded once, so the
+ * Gaussian's rendered mass under the q <= 9 cutoff equals the segment's
+ * colour total; an empty segment leaves xy/chol/rgb[k] as passed in.
+ *   target [3][H][W] FP32 (device); roi_mask [H][W] uint8 (device, non-zero =
+ *   ROI; an all-zero mask means the whole frame);
+ *   seeds [K] int32 pixel indices y*W+x (device; values outside [0, W*H) are
+ *   clamped into it); 1 <= iters <= 100; compactness m > 0 (finite);
+ *   xy [K][2], chol [K][3], rgb [K][3] FP32 (device, in: the Gaussians empty
+ *   segments keep, out: the segment Gaussians);
+ *   labels [H][W] int32 (device, nullable): the last assignment, -1 outside
+ *   the ROI;
+ *   centres [2][5][K] FP32 (device, nullable): x, y, r, g, b of every centre
+ *   before the last assignment, then after the last update.
+ * Enqueued on `stream` without synchronising (no host reads). */
+int gs2d_init_superpixel(int32_t W, int32_t H, const float *target, const uint8_t *roi_mask,
+                         int32_t K, const int32_t *seeds, int32_t iters, float compactness,
+                         float *xy, float *chol, float *rgb, int32_t *labels, float *centres,
+                         void *ws, size_t ws_bytes, void *stream);
+
 /* ---------------------------------------------------------------- batches --
  * Many frames of different sizes and Gaussian counts fitted in lockstep (the
  * per-frame encoding loop of Sec. 3.2 applied to independent frames or ROI

@@ -141,6 +141,10 @@ _SIGS = {
     "gs2d_init_plain": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
                                   c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gs2d_superpixel_workspace_bytes": (c_size_t, [c_int32, c_int32, c_int32]),
+    "gs2d_init_superpixel": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p,
+                                       c_int32, c_float, c_void_p, c_void_p, c_void_p, c_void_p,
+                                       c_void_p, c_void_p, c_size_t, c_void_p]),
 }
 
 
@@ -505,6 +509,31 @@ def init_plain(target, roi_mask, pick_roi, jit_roi, pick_out, jit_out, ws=None, 
         _ptr(jit_out, "jit_out", shape=(n_out, 2), allow_none=n_out == 0),
         _ptr(xy, "xy"), _ptr(chol, "chol"), _ptr(rgb, "rgb"),
         _ptr(picked, "picked", torch.int32, shape=(N,), allow_none=True),
+        _ptr(ws, "ws", torch.uint8), ws.numel(), _stream()))
+    return xy, chol, rgb
+
+
+def init_superpixel(target, roi_mask, seeds, xy, chol, rgb, iters=10, compactness=0.1,
+                    ws=None, labels=None, centres=None):
+    """Superpixel ROI initialisation on the GPU, in place: xy/chol/rgb [K]
+    hold the Gaussians empty segments keep and receive the segment Gaussians.
+    seeds [K] int32 pixel indices; labels [H, W] int32 and centres [2, 5, K]
+    FP32 are optional outputs."""
+    H, W = int(target.shape[1]), int(target.shape[2])
+    K = int(seeds.shape[0])
+    need = int(lib().gs2d_superpixel_workspace_bytes(W, H, K))
+    if need == 0:
+        raise GS2DError("gs2d_superpixel_workspace_bytes", GS2D_EINVAL)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=target.device)
+    _check("gs2d_init_superpixel", lib().gs2d_init_superpixel(
+        W, H, _ptr(target, "target", shape=(3, H, W)),
+        _ptr(roi_mask, "roi_mask", torch.uint8, shape=(H, W)), K,
+        _ptr(seeds, "seeds", torch.int32, shape=(K,)), int(iters), float(compactness),
+        _ptr(xy, "xy", shape=(K, 2)), _ptr(chol, "chol", shape=(K, 3)),
+        _ptr(rgb, "rgb", shape=(K, 3)),
+        _ptr(labels, "labels", torch.int32, shape=(H, W), allow_none=True),
+        _ptr(centres, "centres", shape=(2, 5, K), allow_none=True),
         _ptr(ws, "ws", torch.uint8), ws.numel(), _stream()))
     return xy, chol, rgb
 

@@ -7,6 +7,7 @@ of the fit runs in the HIP library.
     python -m paper_2505_09324_amd.workloads video   # warm-started sequence
     python -m paper_2505_09324_amd.workloads pframe [--sequence motion|local] [--tau 0.02]
     python -m paper_2505_09324_amd.workloads compress   # PTQ, QAT, Eq. 3-4 bit count
+    python -m paper_2505_09324_amd.workloads superpixel # superpixel vs content-aware ROI init
 """
 from __future__ import annotations
 
@@ -251,6 +252,82 @@ def run_pframe(n_frames=30, W=1920, H=1080, N=30000, tau=0.02, psnr_target=35.0,
         }
     out["selective_over_full_seconds"] = round(out["selective"]["mean_seconds"]
                                                / out["full"]["mean_seconds"], 3)
+    return out
+
+
+# ------------------------------------------------ superpixel initialisation --
+def run_superpixel(n_frames=3, W=1920, H=1080, N=30000, psnr_target=35.0, cap=3000, sp_iters=10,
+                   compactness=0.1, sweep=(0.03, 0.3), seed=201, device="cuda", lr=LR_DEFAULT):
+    """Initialisations of Sec. 3.2.A and Table 1 on the same frames: random
+    (uniform positions, scales in [0.5, 3], uniform colours: the
+    initialisation of the image codec the paper starts from), the
+    content-aware draws alone, and the superpixel segmentation seeded by the
+    same ROI draws (one Gaussian per K-means segment; the Gaussians outside
+    the ROI are shared).  Per frame and arm: initialisation time, PSNR of
+    the initial render, PSNR after 50/100/200/500/1000 iterations, and
+    iterations and seconds (initialisation + fit) to psnr_target, checked
+    every 10 iterations.  The compactness sweep runs on the first frame."""
+    shape = _lib.make_shape(W, H, N, 32, px_per_lane=2)
+    ws = _lib.alloc_workspace(shape, device)
+    cfg = _lib.adam_cfg(lr)
+    points = (50, 100, 200, 500, 1000)
+    out = {"workload": f"{n_frames} frames {W}x{H}, {N} Gaussians (70 % in the ROI); superpixel "
+                       f"{sp_iters} rounds, m {compactness}; fit to {psnr_target} dB (cap {cap})",
+           "frames": []}
+
+    def init(frame, mask, d, m_sp, rseed=0):
+        n_roi = d.pick_roi.shape[0]
+        picked = torch.empty(N, dtype=torch.int32, device=device)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if m_sp == "random":
+            xy, chol, rgb = (_dev(a, device) for a in synth.random_gaussians(N, W, H, rseed))
+            torch.cuda.synchronize()
+            return (xy, chol, rgb), time.perf_counter() - t0
+        xy, chol, rgb = _lib.init_plain(frame, mask, _dev(d.pick_roi, device),
+                                        _dev(d.jit_roi, device), _dev(d.pick_out, device),
+                                        _dev(d.jit_out, device), picked=picked)
+        if m_sp is not None:
+            _lib.init_superpixel(frame, mask, picked[:n_roi], xy[:n_roi], chol[:n_roi],
+                                 rgb[:n_roi], iters=sp_iters, compactness=m_sp)
+        torch.cuda.synchronize()
+        return (xy, chol, rgb), time.perf_counter() - t0
+
+    def arm(frame, mask, d, m_sp, rseed=0):
+        params, t_init = init(frame, mask, d, m_sp, rseed)
+        rec = {"init_ms": round(t_init * 1e3, 3),
+               "psnr_init": round(frame_psnr(shape, ws, frame, *params), 3)}
+        curve = psnr_curve(shape, ws, frame, params, max(points), points, cfg)
+        rec["psnr_at"] = {k: round(v, 3) for k, v in curve.items()}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hit, ran = fit_to_target(shape, ws, frame, params, psnr_target, cap, 10, cfg)
+        torch.cuda.synchronize()
+        rec["iters_to_target"] = hit
+        rec["seconds_to_target"] = (round(t_init + time.perf_counter() - t0, 4)
+                                    if hit is not None else None)
+        return rec
+
+    for f in range(n_frames):
+        frame, mask = synth.make_frame_torch(W, H, seed + 2 * f, None, device)
+        mask = mask.to(torch.uint8).contiguous()
+        d = synth.init_draws(N, seed=seed + 2 * f + 1)
+        if f == 0:                      # untimed warm-up of every initialiser
+            for m_sp in ("random", None, compactness):
+                init(frame, mask, d, m_sp)
+        rec = {"frame_seed": seed + 2 * f, "random": arm(frame, mask, d, "random", seed + 2 * f + 1),
+               "content_aware": arm(frame, mask, d, None),
+               "superpixel": arm(frame, mask, d, compactness)}
+        if f == 0:
+            rec["sweep"] = {str(m): arm(frame, mask, d, m) for m in sweep}
+        out["frames"].append(rec)
+    for name in ("random", "content_aware", "superpixel"):
+        recs = [r[name] for r in out["frames"]]
+        hits = [r["iters_to_target"] for r in recs if r["iters_to_target"] is not None]
+        out[name] = {"mean_init_ms": round(float(np.mean([r["init_ms"] for r in recs])), 3),
+                     "mean_psnr_init": round(float(np.mean([r["psnr_init"] for r in recs])), 3),
+                     "mean_iters_to_target": round(float(np.mean(hits)), 1) if hits else None,
+                     "frames_reaching_target": len(hits)}
     return out
 
 
@@ -641,7 +718,7 @@ def run_cnn_step(steps=20, warmup=3, W=1920, H=1080, N=30000, seed=900, device="
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("which", choices=["batch", "video", "learned", "cnn-step", "fit", "pframe",
-                                      "compress"])
+                                      "compress", "superpixel"])
     ap.add_argument("--sequence", choices=["motion", "local"], default="motion")
     ap.add_argument("--tau", type=float, default=0.02)
     ap.add_argument("--target", type=float, default=35.0)
@@ -668,6 +745,10 @@ def main(argv=None):
             out[arm].pop("per_frame")
     elif args.which == "compress":
         out = run_compress(iters=args.iters or 1000)
+    elif args.which == "superpixel":
+        W, H = (int(x) for x in args.size.split("x"))
+        out = run_superpixel(n_frames=args.frames or 3, W=W, H=H, N=args.N,
+                             psnr_target=args.target, cap=args.iters or 3000)
     elif args.which == "cnn-step":
         W, H = (int(x) for x in args.size.split("x"))
         out = run_cnn_step(steps=args.iters or 20, W=W, H=H, N=args.N)
