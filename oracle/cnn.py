@@ -239,6 +239,14 @@ def tile_targets(xy, chol, rgb, W, H, T=16):
     return res
 
 
+def decode_slot(q, tx, ty, T=16):
+    """Gaussian (mu_x, mu_y, l1, l2, l3, c0, c1, c2) of the slot parameters
+    q [8] of tile (tx, ty)."""
+    return (tx * T + T * sigmoid(q[0]), ty * T + T * sigmoid(q[1]),
+            math.exp(min(max(q[2], -4.0), 4.0)), q[3], math.exp(min(max(q[4], -4.0), 4.0)),
+            q[5], q[6], q[7])
+
+
 def decode(head, N, plain, T=16):
     """Predicted Gaussians from the head output [73, TY, TX]: per tile
     k = argmax of the count logits (first maximum) and slots 0..k-1, in tile
@@ -255,10 +263,7 @@ def decode(head, N, plain, T=16):
         k = int(np.argmax(z))
         p = head[9:, ty, tx].reshape(N_SLOTS, N_PARAM)
         for s in range(k):
-            q = p[s]
-            out.append((tx * T + T * sigmoid(q[0]), ty * T + T * sigmoid(q[1]),
-                        math.exp(min(max(q[2], -4.0), 4.0)), q[3],
-                        math.exp(min(max(q[4], -4.0), 4.0)), q[5], q[6], q[7]))
+            out.append(decode_slot(p[s], tx, ty, T))
     out = np.array(out, np.float64).reshape(-1, 8)
     pxy, pch, prgb = (np.asarray(a, np.float64) for a in plain)
     npred = min(len(out), N)
@@ -268,3 +273,72 @@ def decode(head, N, plain, T=16):
     chol = np.concatenate([out[:npred, 2:5], pch[:N - npred]])
     rgb = np.concatenate([out[:npred, 5:8], prgb[:N - npred]])
     return xy, chol, rgb, npred
+
+
+def tile_residual_energy(frame, prev, T=16):
+    """Mean squared residual of every T x T tile [TY, TX], specified in FP32
+    because it decides which tiles a P-frame re-initialises: per pixel
+    e = (dr*dr + dg*dg) + db*db with d = frame - prev, each operation
+    rounded once; a tile's sum adds its in-frame pixels one at a time in
+    row-major order starting from 0, and is divided by their count."""
+    f = np.asarray(frame, np.float32)
+    p = np.asarray(prev, np.float32)
+    d = f - p
+    e = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]
+    _, H, W = f.shape
+    TX, TY = (W + T - 1) // T, (H + T - 1) // T
+    ep = np.zeros((TY * T, TX * T), np.float32)     # out-of-frame pixels add +0 exactly
+    ep[:H, :W] = e
+    acc = np.zeros((TY, TX), np.float32)
+    for ry in range(T):
+        for rx in range(T):
+            acc = acc + ep[ry::T, rx::T]
+    ys = np.minimum(T, H - np.arange(TY) * T)
+    xs = np.minimum(T, W - np.arange(TX) * T)
+    cnt = (ys[:, None] * xs[None, :]).astype(np.float32)
+    return acc / cnt
+
+
+def pframe_replace(frame, prev, head, xy, chol, rgb, tau, T=16):
+    """Learned re-initialisation of a warm-started P-frame (Sec. 3.2.B used
+    at P-frames, Sec. 3.2.C): tiles whose mean squared residual against the
+    previous frame exceeds tau (FP32, strictly) are re-initialised.  The
+    warm-started Gaussians centred in such a tile (floor(mu / T) in FP32)
+    are freed, in increasing index order; the selected tiles' decoded
+    predictions (argmax count, slots 0..k-1; tiles in raster order) fill the
+    freed slots in that order.  Freed slots left over keep their Gaussians,
+    predictions left over are dropped, so N is unchanged; if any raw slot
+    parameter of a used prediction is not finite nothing is replaced.
+    Returns (xy, chol, rgb) in FP64 and a dict of the integer decisions."""
+    sel = tile_residual_energy(frame, prev, T) > np.float32(tau)
+    TY, TX = sel.shape
+    head = np.asarray(head, np.float64)
+    xy64 = np.array(xy, np.float64)
+    chol64 = np.array(chol, np.float64)
+    rgb64 = np.array(rgb, np.float64)
+    x32 = np.asarray(xy, np.float32)
+    with np.errstate(invalid="ignore"):
+        gx = np.floor(x32[:, 0] / np.float32(T))
+        gy = np.floor(x32[:, 1] / np.float32(T))
+        inside = (gx >= 0) & (gx < TX) & (gy >= 0) & (gy < TY)
+    freed = [n for n in np.nonzero(inside)[0] if sel[int(gy[n]), int(gx[n])]]
+    preds, raw_ok = [], True
+    for t in range(TY * TX):
+        ty, tx = divmod(t, TX)
+        if not sel[ty, tx]:
+            continue
+        k = int(np.argmax(head[:9, ty, tx]))
+        p = head[9:, ty, tx].reshape(N_SLOTS, N_PARAM)
+        for s in range(k):
+            raw_ok = raw_ok and bool(np.all(np.isfinite(p[s])))
+            preds.append(decode_slot(p[s], tx, ty, T))
+    m = min(len(freed), len(preds)) if raw_ok else 0
+    for i in range(m):
+        n = freed[i]
+        q = preds[i]
+        xy64[n] = q[0:2]
+        chol64[n] = q[2:5]
+        rgb64[n] = q[5:8]
+    info = {"selected": sel, "freed": np.array(freed, np.int64), "n_predicted": len(preds),
+            "replaced": m}
+    return xy64, chol64, rgb64, info
