@@ -15,7 +15,15 @@ Besides the throughput the line carries
                 algorithmic FLOPs = 52 per (pixel, Gaussian) pair inside the
                 3-sigma cutoff; traffic from the committed counter record;
   cpu_baseline  the FP64 oracle timed on this host's cores on a bounded
-                sample (a few full iterations of the same workload).
+                sample (a few full iterations of the same workload);
+  m2            seconds per frame to 35 dB on held-out 1080p frames for the
+                initialisation arms (A plain init every frame, L learned
+                init every frame, B plain init then warm start, C the
+                network on every frame: learned init, then learned
+                re-initialisation of the changed tiles of each warm-started
+                frame; C0 learned init then warm start), with the network
+                trained on a reduced set of fitter outputs stated in its
+                config (outside the timed region).
 """
 from __future__ import annotations
 
@@ -183,6 +191,10 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-m2", action="store_true")
+    ap.add_argument("--m2-seqs", type=int, default=8, help="training sequences of the M2 network")
+    ap.add_argument("--m2-frames", type=int, default=30, help="frames per training sequence")
+    ap.add_argument("--m2-eval", type=int, default=30, help="held-out evaluation frames")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: there is no multi-GPU path (independent frames or "
@@ -310,7 +322,43 @@ def main():
         "autotune_kernels": "one-frame binning + k_render_fused per candidate (tile/px per lane)",
         "cpu_baseline": cpu,
     }
+    if not args.no_m2:
+        out["m2"] = m2_record(args)
     print(json.dumps(out), flush=True)
+
+
+def m2_record(args):
+    """s/frame to 35 dB per initialisation arm (learned vs plain init), from
+    the learned-initialiser workload on a reduced training set."""
+    from paper_2505_09324_amd import workloads
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    r = workloads.run_learned(train_seqs=args.m2_seqs, frames_per_seq=args.m2_frames,
+                              max_samples=args.m2_seqs * args.m2_frames, epochs=6,
+                              eval_frames=args.m2_eval, W=W, H=H, N=N, psnr_target=35.0,
+                              tau_sweep=(), log=log)
+    arms = r["arms"]
+    return {
+        "metric": "s/frame to 35 dB, learned vs plain init",
+        "unit": "s/frame",
+        "higher_is_better": False,
+        "config": {"workload": f"per-tile initialiser trained on {args.m2_seqs * args.m2_frames} "
+                               f"fitter outputs ({args.m2_seqs} synthetic sequences x "
+                               f"{args.m2_frames} frames, seeds 5000..{5000 + args.m2_seqs - 1}; "
+                               "frame 0 fitted 2000 iterations, the rest warm-started 200), "
+                               f"6 epochs; evaluated on {args.m2_eval} held-out frames (seed "
+                               "5999), 1920x1080, 30000 Gaussians, PSNR checked every 10 "
+                               "iterations, clock from the frame resident to the first check "
+                               ">= 35 dB including the initialisation",
+                   "tau_reinit": r["tau_pframe"]},
+        "s_per_frame": {a: round(v["mean_seconds"], 5) for a, v in arms.items()},
+        "iters_to_target": {a: v["mean_iters_to_target"] for a, v in arms.items()},
+        "frames_reaching_target": {a: v["frames_reaching_target"] for a, v in arms.items()},
+        "C_over_A": round(r["C_over_A_seconds"], 4), "C_over_B": round(r["C_over_B_seconds"], 4),
+        "L_over_A": round(r["L_over_A_seconds"], 4), "C0_over_B": round(r["C0_over_B_seconds"], 4),
+        "reinit_per_frame": r["pframe_reinit_mean"].get("C"),
+        "seconds_total": round(time.perf_counter() - t0, 1),
+    }
 
 
 if __name__ == "__main__":

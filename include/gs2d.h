@@ -544,6 +544,38 @@ int gs2d_cnn_decode(int32_t H, int32_t W, int32_t N, const float *plain_xy,
                     float *rgb, int32_t *n_predicted, void *ws, size_t ws_bytes, void *scratch,
                     size_t scratch_bytes, void *stream);
 
+/* Scratch bytes of gs2d_cnn_pframe_replace (0 if invalid: 1 <= N <= 65536). */
+size_t gs2d_cnn_pframe_scratch_bytes(int32_t H, int32_t W, int32_t N);
+
+/* Learned re-initialisation of a warm-started P-frame (the regressor of
+ * Sec. 3.2.B used at the P-frames of Sec. 3.2.C): the 16 x 16 tiles whose
+ * mean squared residual against the previous frame exceeds tau get the
+ * network's predictions in place of the warm-started Gaussians centred in
+ * them.  Per tile, e = (dr*dr + dg*dg) + db*db per pixel (d = frame - prev),
+ * summed over its in-frame pixels in row-major order and divided by their
+ * count, in FP32 with every operation rounded once; selected iff e > tau.
+ * The Gaussians whose centre lies in a selected tile (floor(mu / 16), FP32)
+ * are freed, in increasing index order; the selected tiles' predictions
+ * (argmax of the count logits, first maximum; slots 0..k-1; tiles in raster
+ * order; decoded as gs2d_cnn_decode does) fill the freed slots in that
+ * order.  Freed slots beyond the predictions keep their Gaussians and
+ * predictions beyond the freed slots are dropped, so N is unchanged; if a
+ * raw parameter of any used slot is not finite nothing is replaced.
+ *   frame, prev [3][H][W] FP32 (device); tau >= 0 (finite);
+ *   head [73][TY][TX] FP32 (device), or NULL for the head the last
+ *   gs2d_cnn_forward on `ws` left there (then ws, ws_bytes are required);
+ *   xy [N][2], chol [N][3], rgb [N][3] (device, in/out: the warm-started
+ *   Gaussians);
+ *   stats [4] int32 (device): selected tiles, freed Gaussians, predicted
+ *   Gaussians, replaced Gaussians;
+ *   tile_sel [TY][TX] uint8 (device, nullable): 1 for a selected tile;
+ *   scratch [gs2d_cnn_pframe_scratch_bytes] (device, 256-byte aligned).
+ * Enqueued on `stream` without synchronising. */
+int gs2d_cnn_pframe_replace(int32_t H, int32_t W, int32_t N, const float *frame,
+                            const float *prev, float tau, const float *head, float *xy,
+                            float *chol, float *rgb, int32_t *stats, uint8_t *tile_sel, void *ws,
+                            size_t ws_bytes, void *scratch, size_t scratch_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

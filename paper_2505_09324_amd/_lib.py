@@ -141,6 +141,11 @@ _SIGS = {
     "gs2d_init_plain": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
                                   c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_size_t, c_void_p]),
+    "gs2d_cnn_pframe_scratch_bytes": (c_size_t, [c_int32, c_int32, c_int32]),
+    "gs2d_cnn_pframe_replace": (c_int32, [c_int32, c_int32, c_int32, c_void_p, c_void_p, c_float,
+                                          c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                          c_void_p, c_void_p, c_size_t, c_void_p, c_size_t,
+                                          c_void_p]),
     "gs2d_superpixel_workspace_bytes": (c_size_t, [c_int32, c_int32, c_int32]),
     "gs2d_init_superpixel": (c_int32, [c_int32, c_int32, c_void_p, c_void_p, c_int32, c_void_p,
                                        c_int32, c_float, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -741,6 +746,32 @@ class CNNInit:
             _ptr(self.ws, "ws", torch.uint8), self.ws.numel(),
             _ptr(self.scratch, "scratch", torch.uint8), self.scratch.numel(), _stream()))
         return xy, chol, rgb, npred
+
+    def pframe_replace(self, frame, prev, tau, xy, chol, rgb, head=None, tile_sel=None,
+                       stats=None):
+        """Replace, in place, the warm-started Gaussians of the tiles whose
+        mean squared residual exceeds tau by the predictions of `head` (None:
+        the last forward's).  Returns the device int32 stats [4] (selected
+        tiles, freed, predicted, replaced)."""
+        N = int(xy.shape[0])
+        dev = xy.device
+        need = int(lib().gs2d_cnn_pframe_scratch_bytes(self.H, self.W, N))
+        if need == 0:
+            raise GS2DError("gs2d_cnn_pframe_scratch_bytes", GS2D_EINVAL)
+        if self.scratch.numel() < need:
+            self.scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+        if stats is None:
+            stats = torch.zeros(4, dtype=torch.int32, device=dev)
+        _check("gs2d_cnn_pframe_replace", lib().gs2d_cnn_pframe_replace(
+            self.H, self.W, N, _ptr(frame, "frame", shape=(3, self.H, self.W)),
+            _ptr(prev, "prev", shape=(3, self.H, self.W)), float(tau),
+            _ptr(head, "head", shape=(73, self.TY, self.TX), allow_none=True),
+            _ptr(xy, "xy", shape=(N, 2)), _ptr(chol, "chol", shape=(N, 3)),
+            _ptr(rgb, "rgb", shape=(N, 3)), _ptr(stats, "stats", torch.int32, shape=(4,)),
+            _ptr(tile_sel, "tile_sel", torch.uint8, shape=(self.TY, self.TX), allow_none=True),
+            _ptr(self.ws, "ws", torch.uint8), self.ws.numel(),
+            _ptr(self.scratch, "scratch", torch.uint8), self.scratch.numel(), _stream()))
+        return stats
 
     def oracle_params(self):
         """Master weights as a list of (w [Cout, Cin, 3, 3], b [Cout]) numpy

@@ -945,6 +945,30 @@ k_decode_scan(int n_tiles, const int *__restrict__ counts, int *__restrict__ off
   if (threadIdx.x == 1023) offsets[n_tiles] = part[1023];
 }
 
+// Slot s of tile t (column tx, row ty) of the head [73][n_tiles] as a
+// Gaussian: mu = tile origin + T sigmoid(p0, p1), l1 = exp(clamp(p2, +-4)),
+// l2 = p3, l3 = exp(clamp(p4, +-4)), colour (p5, p6, p7); returns whether
+// the eight raw parameters are finite.
+__device__ inline bool decode_slot(const float *__restrict__ head, int n_tiles, int t, int s,
+                                   int tx, int ty, int T, float *__restrict__ xy,
+                                   float *__restrict__ chol, float *__restrict__ rgb) {
+  float p[NPAR];
+  bool ok = true;
+  for (int j = 0; j < NPAR; ++j) {
+    p[j] = head[(size_t)(9 + s * NPAR + j) * n_tiles + t];
+    ok = ok && isfinite(p[j]);
+  }
+  xy[0] = (float)(tx * T) + (float)T * sigm(p[0]);
+  xy[1] = (float)(ty * T) + (float)T * sigm(p[1]);
+  chol[0] = __expf(fminf(fmaxf(p[2], -4.f), 4.f));
+  chol[1] = p[3];
+  chol[2] = __expf(fminf(fmaxf(p[4], -4.f), 4.f));
+  rgb[0] = p[5];
+  rgb[1] = p[6];
+  rgb[2] = p[7];
+  return ok;
+}
+
 __global__ void __launch_bounds__(256)
 k_decode_write(int n_tiles, int TX, int T, const float *__restrict__ head,
                const int *__restrict__ counts, const int *__restrict__ offsets, int N_out,
@@ -957,22 +981,9 @@ k_decode_write(int n_tiles, int TX, int T, const float *__restrict__ head,
   for (int s = 0; s < k; ++s) {
     const int n = o + s;
     if (n >= N_out) break;
-    float p[NPAR];
-    for (int j = 0; j < NPAR; ++j) p[j] = head[(size_t)(9 + s * NPAR + j) * n_tiles + t];
-    const float mx = (float)(tx * T) + (float)T * sigm(p[0]);
-    const float my = (float)(ty * T) + (float)T * sigm(p[1]);
-    const float l1 = __expf(fminf(fmaxf(p[2], -4.f), 4.f));
-    const float l3 = __expf(fminf(fmaxf(p[4], -4.f), 4.f));
-    xy[2 * n] = mx;
-    xy[2 * n + 1] = my;
-    chol[3 * n] = l1;
-    chol[3 * n + 1] = p[3];
-    chol[3 * n + 2] = l3;
-    rgb[3 * n] = p[5];
-    rgb[3 * n + 1] = p[6];
-    rgb[3 * n + 2] = p[7];
-    bool ok = isfinite(mx) && isfinite(my) && isfinite(p[3]);
-    for (int j = 5; j < 8; ++j) ok = ok && isfinite(p[j]);
+    decode_slot(head, n_tiles, t, s, tx, ty, T, xy + 2 * n, chol + 3 * n, rgb + 3 * n);
+    bool ok = isfinite(xy[2 * n]) && isfinite(xy[2 * n + 1]) && isfinite(chol[3 * n + 1]);
+    for (int j = 0; j < 3; ++j) ok = ok && isfinite(rgb[3 * n + j]);
     if (!ok) atomicOr(bad, 1);
   }
 }
@@ -998,6 +1009,109 @@ k_decode_merge(int N, const int *__restrict__ total, const int *__restrict__ bad
     chol[3 * n + j] = pchol[3 * src + j];
     rgb[3 * n + j] = prgb[3 * src + j];
   }
+}
+
+// ------------------------------------------- P-frame re-initialisation ----
+// Tiles of a P-frame whose mean squared residual against the previous frame
+// exceeds tau are re-initialised from the network's predictions.  One
+// thread per T x T tile: e = (dr*dr + dg*dg) + db*db per pixel, the tile's
+// in-frame pixels summed one at a time in row-major order, divided by their
+// count (FP32, each operation rounded once: the selection is a decision).
+// A selected tile's prediction count is the argmax of its count logits
+// (first maximum); a non-finite raw parameter of a used slot sets *bad.
+__global__ void __launch_bounds__(256)
+k_pf_tiles(int H, int W, int TX, int n_tiles, int T, const float *__restrict__ frame,
+           const float *__restrict__ prev, float tau, const float *__restrict__ head,
+           uint8_t *__restrict__ sel, int *__restrict__ pcount, int *__restrict__ stats,
+           int *__restrict__ bad) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const size_t HW = (size_t)H * W;
+  const int tx = t % TX, ty = t / TX;
+  const int x0 = tx * T, y0 = ty * T, x1 = min(x0 + T, W), y1 = min(y0 + T, H);
+  float acc = 0.f;
+  for (int y = y0; y < y1; ++y)
+    for (int x = x0; x < x1; ++x) {
+      const size_t p = (size_t)y * W + x;
+      const float dr = f32_sub(frame[p], prev[p]);
+      const float dg = f32_sub(frame[HW + p], prev[HW + p]);
+      const float db = f32_sub(frame[2 * HW + p], prev[2 * HW + p]);
+      acc = f32_add(acc, f32_add(f32_add(f32_mul(dr, dr), f32_mul(dg, dg)), f32_mul(db, db)));
+    }
+  const bool on = __fdiv_rn(acc, (float)((x1 - x0) * (y1 - y0))) > tau;
+  sel[t] = on ? 1 : 0;
+  int k = 0;
+  if (on) {
+    atomicAdd(&stats[0], 1);
+    float bv = head[t];
+    for (int c = 1; c < 9; ++c) {
+      const float z = head[(size_t)c * n_tiles + t];
+      if (z > bv) bv = z, k = c;
+    }
+    bool ok = true;
+    for (int sl = 0; sl < k; ++sl)
+      for (int j = 0; j < NPAR; ++j) ok = ok && isfinite(head[(size_t)(9 + sl * NPAR + j) * n_tiles + t]);
+    if (!ok) atomicOr(bad, 1);
+  }
+  pcount[t] = k;
+}
+
+// One block: the warm-started Gaussians centred in a selected tile
+// (floor(mu / T) in FP32) get their rank among those, in index order
+// (frank[n], -1 for the others); stats = {selected tiles, freed,
+// predicted, replaced = bad ? 0 : min(freed, predicted)}.
+__global__ void __launch_bounds__(1024)
+k_pf_freed(int N, int TX, int TY, int T, const float *__restrict__ xy,
+           const uint8_t *__restrict__ sel, const int *__restrict__ pred_total,
+           const int *__restrict__ bad, int *__restrict__ frank, int *__restrict__ stats) {
+  __shared__ int part[1024];
+  const int per = (N + 1023) / 1024;
+  const int beg = min(N, (int)threadIdx.x * per), end = min(N, beg + per);
+  const float fT = (float)T;
+  auto freed = [&](int n) {
+    const float gx = floorf(__fdiv_rn(xy[2 * n], fT)), gy = floorf(__fdiv_rn(xy[2 * n + 1], fT));
+    if (!(gx >= 0.f && gx < (float)TX && gy >= 0.f && gy < (float)TY)) return false;
+    return sel[(int)gy * TX + (int)gx] != 0;
+  };
+  int c = 0;
+  for (int n = beg; n < end; ++n) c += freed(n) ? 1 : 0;
+  part[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int x = (int)threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += x;
+    __syncthreads();
+  }
+  int r = part[threadIdx.x] - c;
+  for (int n = beg; n < end; ++n) frank[n] = freed(n) ? r++ : -1;
+  if (threadIdx.x == 1023) {
+    const int f = part[1023], np = *pred_total;
+    stats[1] = f;
+    stats[2] = np;
+    stats[3] = *bad ? 0 : min(f, np);
+  }
+}
+
+// Freed Gaussian of rank r < replaced takes prediction r: the tile t with
+// poff[t] <= r < poff[t + 1] (binary search), slot r - poff[t].
+__global__ void __launch_bounds__(256)
+k_pf_replace(int N, int n_tiles, int TX, int T, const int *__restrict__ frank,
+             const int *__restrict__ stats, const int *__restrict__ poff,
+             const float *__restrict__ head, float *__restrict__ xy, float *__restrict__ chol,
+             float *__restrict__ rgb) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  const int r = frank[n];
+  if (r < 0 || r >= stats[3]) return;
+  int lo = 0, hi = n_tiles;  // largest t with poff[t] <= r
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (poff[mid] <= r) lo = mid;
+    else hi = mid;
+  }
+  decode_slot(head, n_tiles, lo, r - poff[lo], lo % TX, lo / TX, T, xy + 2 * n, chol + 3 * n,
+              rgb + 3 * n);
 }
 
 // Per-tile targets from fitted Gaussians: the Gaussians whose centre lies
@@ -1362,6 +1476,63 @@ int gs2d_cnn_decode(int32_t H, int32_t W, int32_t N, const float *plain_xy,
   hipLaunchKernelGGL(k_decode_merge, dim3((N + 255) / 256), dim3(256), 0, st, N,
                      offsets + C.n_tiles, flags, plain_xy, plain_chol, plain_rgb, xy, chol, rgb,
                      n_predicted);
+  return hipGetLastError() == hipSuccess ? GS2D_OK : GS2D_EHIP;
+}
+
+static size_t pf_scratch_layout(int n_tiles, int N, size_t *sel, size_t *pcount, size_t *poff,
+                                size_t *frank, size_t *flags) {
+  size_t o = 0;
+  *sel = o;
+  o += al256((size_t)n_tiles);
+  *pcount = o;
+  o += al256(4 * ((size_t)n_tiles + 1));
+  *poff = o;
+  o += al256(4 * ((size_t)n_tiles + 1));
+  *frank = o;
+  o += al256(4 * (size_t)N);
+  *flags = o;
+  o += 256;
+  return o;
+}
+
+size_t gs2d_cnn_pframe_scratch_bytes(int32_t H, int32_t W, int32_t N) {
+  CnnLayout C;
+  if (!cnn_layout(H, W, &C) || N < 1 || N > 65536) return 0;
+  size_t a, b, c, d, e;
+  return pf_scratch_layout(C.n_tiles, N, &a, &b, &c, &d, &e);
+}
+
+int gs2d_cnn_pframe_replace(int32_t H, int32_t W, int32_t N, const float *frame,
+                            const float *prev, float tau, const float *head, float *xy,
+                            float *chol, float *rgb, int32_t *stats, uint8_t *tile_sel, void *ws,
+                            size_t ws_bytes, void *scratch, size_t scratch_bytes, void *stream) {
+  CnnLayout C;
+  if (!cnn_layout(H, W, &C) || N < 1 || N > 65536 || !frame || !prev || !xy || !chol || !rgb ||
+      !stats || !scratch || !(tau >= 0.f) || !std::isfinite(tau))
+    return GS2D_EINVAL;
+  if (!head) {
+    if (!ws) return GS2D_EINVAL;
+    if (ws_bytes < C.total) return GS2D_ENOSPACE;
+    head = at<const float>(ws, C.head);
+  }
+  size_t o_sel, o_pc, o_po, o_fr, o_fl;
+  const size_t need = pf_scratch_layout(C.n_tiles, N, &o_sel, &o_pc, &o_po, &o_fr, &o_fl);
+  if (scratch_bytes < need || (reinterpret_cast<uintptr_t>(scratch) & 255)) return GS2D_ENOSPACE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  uint8_t *sel = tile_sel ? tile_sel : at<uint8_t>(scratch, o_sel);
+  int *pcount = at<int>(scratch, o_pc), *poff = at<int>(scratch, o_po);
+  int *frank = at<int>(scratch, o_fr), *flags = at<int>(scratch, o_fl);
+  if (launch_fill_zero_u32(reinterpret_cast<uint32_t *>(flags), 4, st) != hipSuccess ||
+      launch_fill_zero_u32(reinterpret_cast<uint32_t *>(stats), 4, st) != hipSuccess)
+    return GS2D_EHIP;
+  const unsigned nb = (C.n_tiles + 255) / 256;
+  hipLaunchKernelGGL(k_pf_tiles, dim3(nb), dim3(256), 0, st, H, W, C.TX, C.n_tiles, 16, frame,
+                     prev, tau, head, sel, pcount, stats, flags);
+  hipLaunchKernelGGL(k_decode_scan, dim3(1), dim3(1024), 0, st, C.n_tiles, pcount, poff);
+  hipLaunchKernelGGL(k_pf_freed, dim3(1), dim3(1024), 0, st, N, C.TX, C.TY, 16, xy, sel,
+                     poff + C.n_tiles, flags, frank, stats);
+  hipLaunchKernelGGL(k_pf_replace, dim3((N + 255) / 256), dim3(256), 0, st, N, C.n_tiles, C.TX, 16,
+                     frank, stats, poff, head, xy, chol, rgb);
   return hipGetLastError() == hipSuccess ? GS2D_OK : GS2D_EHIP;
 }
 

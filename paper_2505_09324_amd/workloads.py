@@ -532,11 +532,17 @@ def train_initialiser(net, samples, W, H, epochs, lr, device, log=print, seed=0,
 
 def run_learned(train_seqs=34, frames_per_seq=60, max_samples=2000, epochs=6, eval_frames=60,
                 W=1920, H=1080, N=30000, psnr_target=35.0, cap=10000, check_every=10,
-                iters_first=2000, iters_rest=200, lr_cnn=1e-3, device="cuda", log=print):
+                iters_first=2000, iters_rest=200, lr_cnn=1e-3, tau_pframe=1e-3,
+                tau_sweep=(1e-2, 3e-2, 1e-1), device="cuda", log=print):
     """Train the per-tile initialiser on fitter outputs, then compare time and
-    iterations to `psnr_target` on a held-out sequence for four arms:
+    iterations to `psnr_target` on a held-out sequence for five arms:
     A plain init every frame, L learned init every frame, B plain init on
-    frame 0 then warm start, C learned init on frame 0 then warm start."""
+    frame 0 then warm start, C0 learned init on frame 0 then warm start, and
+    C the network on every frame: learned init on frame 0, then each
+    warm-started frame has the tiles whose mean squared residual exceeds
+    tau_pframe re-initialised from the network's predictions (its forward
+    pass and the replacement are inside the frame's clock).  Arm C is also
+    run at each threshold of tau_sweep ("C@tau")."""
     t_all = time.perf_counter()
     seqs = [5000 + i for i in range(train_seqs)]
     # every training frame stays resident in HBM (34 x 60 1080p frames are
@@ -589,7 +595,11 @@ def run_learned(train_seqs=34, frames_per_seq=60, max_samples=2000, epochs=6, ev
         f"{[npred_log[t] for t in sorted(npred_log)]}")
 
     res = {}
-    for arm in ("A", "L", "B", "C"):
+    stats = torch.zeros(4, dtype=torch.int32, device=device)
+    replaced = {}
+    arms = ["A", "L", "B", "C0", "C"] + [f"C@{tau:g}" for tau in tau_sweep]
+    for arm in arms:
+        tau = tau_pframe if arm == "C" else (float(arm[2:]) if arm.startswith("C@") else None)
         recs = []
         params = None
         for t in range(eval_frames):
@@ -598,9 +608,15 @@ def run_learned(train_seqs=34, frames_per_seq=60, max_samples=2000, epochs=6, ev
             t0 = time.perf_counter()
             if arm in ("A", "L") or params is None:
                 params = init_for(arm, t)
+            elif tau is not None:
+                prev = frames[t - 1][0]
+                net.forward(f, prev)
+                net.pframe_replace(f, prev, tau, *params, stats=stats)
             hit, run = fit_to_target(shape, ws, f, params, psnr_target, cap, check_every, cfg)
             torch.cuda.synchronize()
             recs.append({"iters": hit, "seconds": time.perf_counter() - t0, "iters_run": run})
+            if tau is not None and t > 0:
+                replaced.setdefault(arm, []).append([int(x) for x in stats.cpu()])
         ok = [r for r in recs if r["iters"] is not None]
         res[arm] = {"frames_reaching_target": len(ok),
                     "mean_seconds": float(np.mean([r["seconds"] for r in recs])),
@@ -614,6 +630,11 @@ def run_learned(train_seqs=34, frames_per_seq=60, max_samples=2000, epochs=6, ev
                     f"N={N}), {epochs} epochs; evaluated on {eval_frames} held-out frames",
         "target_psnr_db": psnr_target, "arms": res,
         "C_over_A_seconds": ratio("C", "A"), "C_over_B_seconds": ratio("C", "B"),
+        "C0_over_B_seconds": ratio("C0", "B"), "tau_pframe": tau_pframe,
+        "pframe_reinit_mean": {a: {k: float(np.mean([r[i] for r in rs])) for i, k in
+                                   enumerate(("selected_tiles", "freed", "predicted", "replaced"))}
+                               for a, rs in replaced.items()},
+        "C_sweep_over_B_seconds": {a: ratio(a, "B") for a in arms if a.startswith("C@")},
         "L_over_A_seconds": ratio("L", "A"),
         "psnr_at_budget_cold": budget_mean,
         "learned_predicted_per_frame": [npred_log[t] for t in sorted(npred_log)],
@@ -721,6 +742,7 @@ def main(argv=None):
                                       "compress", "superpixel"])
     ap.add_argument("--sequence", choices=["motion", "local"], default="motion")
     ap.add_argument("--tau", type=float, default=0.02)
+    ap.add_argument("--tau-reinit", type=float, default=1e-3)
     ap.add_argument("--target", type=float, default=35.0)
     ap.add_argument("--frames", type=int, default=None)
     ap.add_argument("--iters", type=int, default=None)
@@ -756,7 +778,7 @@ def main(argv=None):
         W, H = (int(x) for x in args.size.split("x"))
         out = run_learned(train_seqs=args.train_seqs, frames_per_seq=args.frames or 60,
                           epochs=args.epochs, eval_frames=args.eval_frames, W=W, H=H, N=args.N,
-                          log=log)
+                          tau_pframe=args.tau_reinit, log=log)
     print(json.dumps(out), flush=True)
 
 
