@@ -108,6 +108,18 @@ typedef struct {
    * (straight-through estimator).  The loss trace is the quantised
    * render's.  gs2d_fit_batch and gs2d_fit_frame_static require NULL. */
   const gs2d_quant_cfg *qat;
+  /* Lazy tile binning, 0 <= bin_skin <= 64 pixels; 0: the tile lists are
+   * rebuilt every iteration.  With bin_skin > 0 (frames of at most 2048
+   * tiles, not with qat) each Gaussian is binned into the tiles its 3-sigma
+   * box grown by bin_skin pixels meets, and the lists are rebuilt only when
+   * some Gaussian's exact tile rectangle has left the one it was binned with
+   * (or it became culled), and at the start of every chunk; in between the
+   * projection still runs every iteration and the lists of the last rebuild
+   * are a superset of the exact ones in the same (tile, index) order.  Every
+   * pixel's sum tests each pair against the cutoff, so the render, the loss
+   * and the gradients are those of exact binning.  gs2d_fit_batch ignores
+   * it. */
+  float bin_skin;
 } gs2d_fit_opts;
 
 typedef struct {
@@ -118,6 +130,7 @@ typedef struct {
   double seconds;           /* host wall time of the call                   */
   uint32_t status;          /* workspace status word at return              */
   int32_t n_culled;
+  int32_t rebins;           /* tile-list rebuilds (lazy binning; else 0)    */
 } gs2d_fit_stats;
 
 /* Human-readable name of a status code (static string). */

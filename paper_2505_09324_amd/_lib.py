@@ -45,13 +45,13 @@ class QuantCfg(ctypes.Structure):
 class FitOpts(ctypes.Structure):
     _fields_ = [("iters", c_int32), ("check_every", c_int32), ("psnr_target", c_float),
                 ("use_graph", c_int32), ("adam", AdamCfg), ("active", c_void_p),
-                ("qat", POINTER(QuantCfg))]
+                ("qat", POINTER(QuantCfg)), ("bin_skin", c_float)]
 
 
 class FitStats(ctypes.Structure):
     _fields_ = [("iters_run", c_int32), ("iter_hit_target", c_int32), ("final_loss", c_float),
                 ("final_psnr", c_float), ("seconds", c_double), ("status", c_uint32),
-                ("n_culled", c_int32)]
+                ("n_culled", c_int32), ("rebins", c_int32)]
 
 
 class Frame(ctypes.Structure):
@@ -323,12 +323,13 @@ def adam_step(xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg: AdamCfg, acti
 
 
 def fit_opts(iters, check_every=50, psnr_target=0.0, use_graph=True, cfg=None,
-             active=None, qat=None) -> FitOpts:
+             active=None, qat=None, bin_skin=1.0) -> FitOpts:
     """Fitting options; active: [N] uint8 device tensor (only Gaussians with
     a non-zero flag are optimised) or None; qat: (bits_chol, bits_rgb) for
-    quantisation-aware fitting, or None."""
+    quantisation-aware fitting, or None; bin_skin: lazy tile binning margin
+    in pixels (0: rebuild the lists every iteration)."""
     o = FitOpts(int(iters), int(check_every), float(psnr_target), int(bool(use_graph)),
-                cfg if cfg is not None else adam_cfg(), None, None)
+                cfg if cfg is not None else adam_cfg(), None, None, float(bin_skin))
     if active is not None:
         o.active = _ptr(active, "active", torch.uint8)
         o._active_ref = active  # keep the tensor alive with the options

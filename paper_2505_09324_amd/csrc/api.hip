@@ -52,6 +52,7 @@ bool make_layout(const gs2d_shape &s, Layout *L) {
   const size_t N = (size_t)s.N;
   L->geom = take(N * 32);
   L->rect = take(N * 16);
+  L->brect = take(N * 16);  // lazy binning: the rectangles the lists were built from
   L->counts = take(N * 4);
   L->offsets = take((N + 1) * 4);
   L->blocks = take(2048);  // per-projection-block sums (<= 256 blocks): pairs, culled
@@ -240,7 +241,7 @@ hipError_t enqueue_iterations(const Layout &L, void *ws, const float *target, fl
                               float *chol, float *rgb, float *m, float *v, int32_t *step,
                               float *trace, int trace_len, const gs2d_adam_cfg &cfg,
                               const uint8_t *active, int k, hipStream_t st, int qat_bits_chol = 0,
-                              int qat_bits_rgb = 0) {
+                              int qat_bits_rgb = 0, float bin_skin = 0.f) {
   float *g = at<float>(ws, L.grads);
   float *g_xy = g, *g_chol = g + 2 * (size_t)L.N, *g_rgb = g + 5 * (size_t)L.N;
   const float loss_scale = (float)(1.0 / (3.0 * L.W * (double)L.H));
@@ -266,11 +267,14 @@ hipError_t enqueue_iterations(const Layout &L, void *ws, const float *target, fl
   const PendingAdam pending{xy,    chol, rgb,  g_xy, g_chol, g_rgb, m,         v,
                             step,  cfg,  at<const float>(ws, L.loss_part), L.loss_parts,
                             loss_scale, trace, trace_len, active};
-  hipError_t e = hipSuccess;
+  // lazy binning on the single-pass path: every chunk starts with a rebuild
+  // (the parameters or the workspace may have changed between chunks)
+  const float skin = (L.wide && bin_skin > 0.f) ? bin_skin : 0.f;
+  hipError_t e = skin > 0.f ? launch_mark_bins_stale(L, ws, st) : hipSuccess;
   for (int i = 0; i < k && e == hipSuccess; ++i) {
-    e = launch_binning(L, xy, chol, ws, st, step, i > 0 ? &pending : nullptr);
+    e = launch_binning(L, xy, chol, ws, st, step, i > 0 ? &pending : nullptr, skin);
     if (e == hipSuccess)
-      e = launch_render_fused(L, ws, rgb, target, g_xy, g_chol, g_rgb, st, active);
+      e = launch_render_fused(L, ws, rgb, target, g_xy, g_chol, g_rgb, st, active, skin > 0.f);
   }
   if (e == hipSuccess && k > 0)
     e = launch_adam(L.N, xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg, active, 1,
@@ -300,6 +304,7 @@ GraphKey frame_chunk_key(const Layout &L, const FitArgs &a, int k) {
                key_word(a.active),
                (uint64_t)a.qat_bits_chol,
                (uint64_t)a.qat_bits_rgb,
+               key_word(a.bin_skin),
                (uint64_t)k};
   for (float f : a.cfg.lr) key.push_back(key_word(f));
   key.push_back(key_word(a.cfg.beta1));
@@ -316,7 +321,7 @@ int run_chunk(gs2d_ctx *ctx, bool use_graph, const Layout &L, const FitArgs &a, 
     if (!launch) return GS2D_OK;
     return hip_status(enqueue_iterations(L, a.ws, a.target, a.xy, a.chol, a.rgb, a.m, a.v, a.step,
                                          a.trace, a.trace_len, a.cfg, a.active, k, st,
-                                         a.qat_bits_chol, a.qat_bits_rgb));
+                                         a.qat_bits_chol, a.qat_bits_rgb, a.bin_skin));
   }
   hipGraphExec_t x = nullptr;
   hipError_t e = ctx->graph_for(
@@ -324,7 +329,7 @@ int run_chunk(gs2d_ctx *ctx, bool use_graph, const Layout &L, const FitArgs &a, 
       [&](hipStream_t cs) {
         return enqueue_iterations(L, a.ws, a.target, a.xy, a.chol, a.rgb, a.m, a.v, a.step,
                                   a.trace, a.trace_len, a.cfg, a.active, k, cs, a.qat_bits_chol,
-                                  a.qat_bits_rgb);
+                                  a.qat_bits_rgb, a.bin_skin);
       },
       &x);
   if (e == hipSuccess && launch) e = hipGraphLaunch(x, st);
@@ -342,6 +347,7 @@ int check_fit_args(gs2d_ctx *ctx, const gs2d_shape *shape, const float *target, 
   if (opts->qat && (opts->qat->bits_chol < 1 || opts->qat->bits_chol > 12 ||
                     opts->qat->bits_rgb < 1 || opts->qat->bits_rgb > 12))
     return GS2D_EINVAL;
+  if (!(opts->bin_skin >= 0.f && opts->bin_skin <= 64.f)) return GS2D_EINVAL;
   return gs2d_ctx_check(ctx);
 }
 
@@ -358,9 +364,15 @@ extern "C" int gs2d_fit_prepare(gs2d_ctx *ctx, const gs2d_shape *shape, const fl
                             ws_bytes, opts, &L);
     if (rc != GS2D_OK) return rc;
     if (!opts->use_graph || opts->iters == 0) return GS2D_OK;
-    const FitArgs a{target, xy, chol, rgb, m, v, step, loss_trace, trace_len, ws, opts->adam,
-                    opts->active, opts->qat ? opts->qat->bits_chol : 0,
-                    opts->qat ? opts->qat->bits_rgb : 0};
+    const FitArgs a{target,       xy,
+                    chol,         rgb,
+                    m,            v,
+                    step,         loss_trace,
+                    trace_len,    ws,
+                    opts->adam,   opts->active,
+                    opts->qat ? opts->qat->bits_chol : 0,
+                    opts->qat ? opts->qat->bits_rgb : 0,
+                    opts->bin_skin};
     const int k0 = std::min(opts->check_every, opts->iters);
     rc = run_chunk(ctx, true, L, a, k0, nullptr, false);
     const int rem = opts->iters % opts->check_every;
@@ -385,6 +397,7 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
     stats->seconds = 0.0;
     stats->status = 0;
     stats->n_culled = 0;
+    stats->rebins = 0;
   }
   int32_t step0 = 0;
   if (hipMemcpyAsync(&step0, a.step, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -403,7 +416,7 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
 
   constexpr int TRACE_PIECE = 256;  // loss values read back per copy
   float trace_host[TRACE_PIECE];
-  int32_t misc_host[4] = {0, 0, 0, 0};
+  int32_t misc_host[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int done = 0, hit = -1;
   float last_loss = NAN;
   uint32_t sticky = 0;
@@ -439,6 +452,7 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
     stats->final_psnr = (last_loss > 0.f) ? (float)(10.0 * std::log10(1.0 / last_loss)) : INFINITY;
     stats->status = sticky;
     stats->n_culled = misc_host[MISC_N_CULLED];
+    stats->rebins = misc_host[MISC_REBINS];
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return (sticky & STATUS_OVERFLOW) ? GS2D_EOVERFLOW : GS2D_OK;
@@ -456,9 +470,15 @@ extern "C" int gs2d_fit_frame(gs2d_ctx *ctx, const gs2d_shape *shape, const floa
     const int rc = check_fit_args(ctx, shape, target, xy, chol, rgb, m, v, step, loss_trace, ws,
                                   ws_bytes, opts, &L);
     if (rc != GS2D_OK) return rc;
-    const FitArgs a{target, xy, chol, rgb, m, v, step, loss_trace, trace_len, ws, opts->adam,
-                    opts->active, opts->qat ? opts->qat->bits_chol : 0,
-                    opts->qat ? opts->qat->bits_rgb : 0};
+    const FitArgs a{target,       xy,
+                    chol,         rgb,
+                    m,            v,
+                    step,         loss_trace,
+                    trace_len,    ws,
+                    opts->adam,   opts->active,
+                    opts->qat ? opts->qat->bits_chol : 0,
+                    opts->qat ? opts->qat->bits_rgb : 0,
+                    opts->bin_skin};
     return fit_frame_run(ctx, L, a, *opts, stats, as_stream(stream));
   } catch (...) {
     return GS2D_EHIP;

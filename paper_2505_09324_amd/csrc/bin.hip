@@ -75,10 +75,29 @@ k_emit_keys(int N, int TX, int nb, int max_pairs, const int4 *__restrict__ rect,
 }
 
 // ------------------------------------------------------- single-pass path --
+// Lazy binning (skin > 0): one flag per wavefront whose Gaussians made the
+// lists stale.
+__device__ inline void flag_stale(bool stale, int *__restrict__ misc) {
+  if (__ballot(stale) && (threadIdx.x & 63) == 0) atomicOr(&misc[MISC_STALE], 1);
+}
+
 __global__ void __launch_bounds__(WIDE_PROJ)
 k_project_wide(int N, int TX, int TY, float inv_tile, const float *__restrict__ xy,
                const float *__restrict__ chol, float4 *__restrict__ geom, int4 *__restrict__ rect,
-               int *__restrict__ counts, int *__restrict__ bsum, int *__restrict__ bcull) {
+               int *__restrict__ counts, int *__restrict__ bsum, int *__restrict__ bcull,
+               float skin, const int4 *__restrict__ brect, int *__restrict__ misc) {
+  if (skin > 0.f) {
+    const int n = blockIdx.x * WIDE_PROJ + (int)threadIdx.x;
+    int v = 0;
+    bool stale = false;
+    if (n < N)
+      v = project_values<true>(n, TX, TY, inv_tile, xy[2 * n], xy[2 * n + 1], chol[3 * n],
+                               chol[3 * n + 1], chol[3 * n + 2], geom, rect, counts, skin, brect,
+                               &stale);
+    flag_stale(stale, misc);
+    block_count_sums<WIDE_PROJ>(v, bsum + blockIdx.x, bcull + blockIdx.x);
+    return;
+  }
   project_block<WIDE_PROJ>(blockIdx.x * WIDE_PROJ, N, TX, TY, inv_tile, xy, chol, geom, rect,
                            counts, bsum + blockIdx.x, bcull + blockIdx.x);
 }
@@ -93,7 +112,8 @@ k_project_wide(int N, int TX, int TY, float inv_tile, const float *__restrict__ 
 __global__ void __launch_bounds__(WIDE_PROJ)
 k_adam_project_wide(int N, int TX, int TY, float inv_tile, PendingAdam a,
                     float4 *__restrict__ geom, int4 *__restrict__ rect, int *__restrict__ counts,
-                    int *__restrict__ bsum, int *__restrict__ bcull) {
+                    int *__restrict__ bsum, int *__restrict__ bcull, float skin,
+                    const int4 *__restrict__ brect, int *__restrict__ misc) {
   __shared__ double red[WIDE_PROJ / 64];
   const int s_t = a.step[0];
   if (blockIdx.x == gridDim.x - 1) {  // the loss of the previous iteration
@@ -114,6 +134,7 @@ k_adam_project_wide(int N, int TX, int TY, float inv_tile, PendingAdam a,
   adam_bias(s_t, b1, b2, &bc1, &bc2);
   const int n = blockIdx.x * WIDE_PROJ + threadIdx.x;
   int v = 0;
+  bool stale = false;
   if (n < N) {
     const size_t N2 = 2 * (size_t)N, N5 = 5 * (size_t)N;
     // an inactive Gaussian keeps its parameters and moments (its gradient
@@ -152,16 +173,34 @@ k_adam_project_wide(int N, int TX, int TY, float inv_tile, PendingAdam a,
         a.rgb[i] = adam_update(a.rgb[i], g, a.m + N5 + i, a.v + N5 + i, a.cfg.lr[2], b1, b2, eps,
                                bc1, bc2);
     }
-    v = project_values(n, TX, TY, inv_tile, p[0], p[1], p[2], p[3], p[4], geom, rect, counts);
+    if (skin > 0.f)
+      v = project_values<true>(n, TX, TY, inv_tile, p[0], p[1], p[2], p[3], p[4], geom, rect,
+                               counts, skin, brect, &stale);
+    else
+      v = project_values(n, TX, TY, inv_tile, p[0], p[1], p[2], p[3], p[4], geom, rect, counts);
   }
+  if (skin > 0.f) flag_stale(stale, misc);
   block_count_sums<WIDE_PROJ>(v, bsum + blockIdx.x, bcull + blockIdx.x);
 }
 
+// lazy (lazy binning): with the lists still valid (misc[MISC_STALE] == 0)
+// only the step tick runs; a rebuild also records the rectangles it bins in
+// brect and counts itself in misc[MISC_REBINS].
 __global__ void __launch_bounds__(WIDE_BLOCK)
 k_emit_wide(int N, int TX, int nbp, int max_pairs, int D, const int4 *__restrict__ rect,
             const int *__restrict__ counts, const int *__restrict__ bsum,
             const int *__restrict__ bcull, int *__restrict__ offsets, uint32_t *__restrict__ keys,
-            uint32_t *__restrict__ hist, int *__restrict__ misc, int *__restrict__ tick) {
+            uint32_t *__restrict__ hist, int *__restrict__ misc, int *__restrict__ tick, int lazy,
+            int4 *__restrict__ brect) {
+  if (lazy) {
+    if (misc[MISC_STALE] == 0) {  // uniform over the grid
+      if (blockIdx.x == 0 && threadIdx.x == 0 && tick) tick[0] += 1;
+      return;
+    }
+    const int n = blockIdx.x * WIDE_BLOCK + (int)threadIdx.x;
+    if (n < N) brect[n] = rect[n];
+    if (blockIdx.x == 0 && threadIdx.x == 0) misc[MISC_REBINS] += 1;
+  }
   long long pre, end_keys, total;
   int culled;
   chunk_bounds<WIDE_BLOCK>(nbp, blockIdx.x, WIDE_GROUP, bsum, bcull, &pre, &end_keys, &total,
@@ -186,7 +225,8 @@ __global__ void __launch_bounds__(WIDE_SCATTER)
 k_scatter_wide(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
                const int *__restrict__ misc, int nb, int nbp, int D, int bits, int n_tiles,
                const int *__restrict__ bsum, const int *__restrict__ bcull,
-               const uint32_t *__restrict__ hist, int *__restrict__ tile_start) {
+               const uint32_t *__restrict__ hist, int *__restrict__ tile_start, int lazy) {
+  if (lazy && misc[MISC_STALE] == 0) return;  // the lists are still valid
   scatter_chunk_wide(in, out, nb, nbp, blockIdx.x / WIDE_SPLIT, blockIdx.x % WIDE_SPLIT, D, bits,
                      misc[MISC_N_PAIRS], n_tiles, bsum, bcull, hist, tile_start);
 }
@@ -230,8 +270,17 @@ k_tile_ranges(const uint32_t *__restrict__ keys, const int *__restrict__ misc, i
   tile_ranges(keys, misc[MISC_N_PAIRS], n_tiles, tile_start);
 }
 
+__global__ void k_mark_stale(int *__restrict__ misc) {
+  if (threadIdx.x == 0) misc[MISC_STALE] = 1;
+}
+
+hipError_t launch_mark_bins_stale(const Layout &L, void *ws, hipStream_t st) {
+  hipLaunchKernelGGL(k_mark_stale, dim3(1), dim3(64), 0, st, at<int>(ws, L.misc));
+  return hipGetLastError();
+}
+
 hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, void *ws,
-                          hipStream_t st, int *step_tick, const PendingAdam *adam) {
+                          hipStream_t st, int *step_tick, const PendingAdam *adam, float skin) {
   float4 *geom = at<float4>(ws, L.geom);
   int *counts = at<int>(ws, L.counts);
   int *offsets = at<int>(ws, L.offsets);
@@ -244,18 +293,23 @@ hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, v
   if (L.wide) {
     const int nbw = (L.N + WIDE_BLOCK - 1) / WIDE_BLOCK;  // chunks
     const int nbp = (L.N + WIDE_PROJ - 1) / WIDE_PROJ;    // projection blocks
+    const int lazy = skin > 0.f ? 1 : 0;
+    int4 *brect = at<int4>(ws, L.brect);
     if (adam)
       hipLaunchKernelGGL(k_adam_project_wide, dim3(nbp + 1), dim3(WIDE_PROJ), 0, st, L.N, L.TX, L.TY,
-                         1.0f / (float)L.T, *adam, geom, rect, counts, bsum, bcull);
+                         1.0f / (float)L.T, *adam, geom, rect, counts, bsum, bcull, skin, brect,
+                         misc);
     else
       hipLaunchKernelGGL(k_project_wide, dim3(nbp), dim3(WIDE_PROJ), 0, st, L.N, L.TX, L.TY,
-                         1.0f / (float)L.T, xy, chol, geom, rect, counts, bsum, bcull);
+                         1.0f / (float)L.T, xy, chol, geom, rect, counts, bsum, bcull, skin, brect,
+                         misc);
     hipLaunchKernelGGL(k_emit_wide, dim3(nbw), dim3(WIDE_BLOCK), 0, st, L.N, L.TX, nbp,
                        L.max_pairs, L.D, rect, counts, bsum, bcull, offsets, ka, hist, misc,
-                       step_tick);
+                       step_tick, lazy, brect);
     hipLaunchKernelGGL(k_scatter_wide, dim3(nbw * WIDE_SPLIT), dim3(WIDE_SCATTER), 0, st, ka, kb,
                        misc, nbw, nbp, L.D,
-                       L.digit_bits, L.n_tiles, bsum, bcull, hist, at<int>(ws, L.tile_start));
+                       L.digit_bits, L.n_tiles, bsum, bcull, hist, at<int>(ws, L.tile_start),
+                       lazy);
     return hipGetLastError();
   }
   if (adam) {

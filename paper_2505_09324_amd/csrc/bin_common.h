@@ -37,9 +37,39 @@ constexpr size_t HIST_BYTES =
 // rx, ry, 0}; rect[n] = {tx0, ty0, tx1, ty1}.  The box/rectangle arithmetic
 // uses the contraction-free f32_* operations (each rounded once, no fused
 // multiply-add): the tile decision must match its FP32 specification exactly.
+// Tile rectangle {tx0, ty0, tx1, ty1} of the pixel box [xlo, xhi] x [ylo,
+// yhi] clipped to the frame's TX x TY tiles; {0, 0, -1, -1} when the box
+// misses the frame.  floor of (edge / T) in FP32, division by the power of
+// two T as multiplication by its exact reciprocal.
+__device__ inline int4 tile_rect(float xlo, float xhi, float ylo, float yhi, float inv_tile, int TX,
+                                 int TY) {
+  const float fx0 = floorf(f32_mul(xlo, inv_tile)), fx1 = floorf(f32_mul(xhi, inv_tile));
+  const float fy0 = floorf(f32_mul(ylo, inv_tile)), fy1 = floorf(f32_mul(yhi, inv_tile));
+  const float lastx = (float)(TX - 1), lasty = (float)(TY - 1);
+  int4 rc = make_int4(0, 0, -1, -1);
+  if (!(fx1 < 0.f || fx0 > lastx || fy1 < 0.f || fy0 > lasty)) {
+    rc.x = (int)fmaxf(fx0, 0.f);
+    rc.z = (int)fminf(fx1, lastx);
+    rc.y = (int)fmaxf(fy0, 0.f);
+    rc.w = (int)fminf(fy1, lasty);
+  }
+  return rc;
+}
+
+__device__ inline bool rect_empty(int4 r) { return r.z < r.x || r.w < r.y; }
+
+// With LAZY (lazy binning, see launch_binning): rect[n] and counts[n] take
+// the rectangle of the box grown by `skin` pixels on every side (what a
+// rebuild bins), and *stale is set when the exact rectangle is not inside
+// brect[n] (the rectangle the current lists were built from) or when the
+// Gaussian is culled while brect[n] is not empty (its keys would render the
+// zeroed geometry).
+template <bool LAZY = false>
 __device__ inline int project_values(int n, int TX, int TY, float inv_tile, float mx, float my,
                                      float l1, float l2, float l3, float4 *__restrict__ geom,
-                                     int4 *__restrict__ rect, int *__restrict__ counts) {
+                                     int4 *__restrict__ rect, int *__restrict__ counts,
+                                     float skin = 0.f, const int4 *__restrict__ brect = nullptr,
+                                     bool *stale = nullptr) {
   const float tiny = 6.103515625e-05f;  // 2^-14
   const bool finite = isfinite(mx) && isfinite(my) && isfinite(l1) && isfinite(l2) && isfinite(l3);
   if (!finite || !(fabsf(l1) >= tiny) || !(fabsf(l3) >= tiny)) {
@@ -47,6 +77,7 @@ __device__ inline int project_values(int n, int TX, int TY, float inv_tile, floa
     rect[n] = make_int4(0, 0, -1, -1);
     geom[2 * n + 0] = make_float4(0.f, 0.f, 0.f, 0.f);
     geom[2 * n + 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (LAZY && !rect_empty(brect[n])) *stale = true;
     return -1;
   }
   const float a = f32_mul(l2, l2);
@@ -57,19 +88,16 @@ __device__ inline int project_values(int n, int TX, int TY, float inv_tile, floa
   const float rx = f32_mul(3.0f, fabsf(l1));
   const float xlo = f32_sub(mx, rx), xhi = f32_add(mx, rx);
   const float ylo = f32_sub(my, ry), yhi = f32_add(my, ry);
-  // division by a power of two == multiplication by its exact reciprocal
-  const float fx0 = floorf(f32_mul(xlo, inv_tile)), fx1 = floorf(f32_mul(xhi, inv_tile));
-  const float fy0 = floorf(f32_mul(ylo, inv_tile)), fy1 = floorf(f32_mul(yhi, inv_tile));
-  const float lastx = (float)(TX - 1), lasty = (float)(TY - 1);
-  int cnt = 0;
-  int4 rc = make_int4(0, 0, -1, -1);
-  if (!(fx1 < 0.f || fx0 > lastx || fy1 < 0.f || fy0 > lasty)) {
-    rc.x = (int)fmaxf(fx0, 0.f);
-    rc.z = (int)fminf(fx1, lastx);
-    rc.y = (int)fmaxf(fy0, 0.f);
-    rc.w = (int)fminf(fy1, lasty);
-    cnt = (rc.z - rc.x + 1) * (rc.w - rc.y + 1);
+  int4 rc = tile_rect(xlo, xhi, ylo, yhi, inv_tile, TX, TY);
+  if (LAZY) {
+    const int4 bq = brect[n];
+    if (!rect_empty(rc) &&
+        (rect_empty(bq) || rc.x < bq.x || rc.y < bq.y || rc.z > bq.z || rc.w > bq.w))
+      *stale = true;
+    rc = tile_rect(f32_sub(xlo, skin), f32_add(xhi, skin), f32_sub(ylo, skin), f32_add(yhi, skin),
+                   inv_tile, TX, TY);
   }
+  const int cnt = rect_empty(rc) ? 0 : (rc.z - rc.x + 1) * (rc.w - rc.y + 1);
   counts[n] = cnt;
   rect[n] = rc;
   geom[2 * n + 0] = make_float4(mx, my, __fdiv_rn(1.0f, l1), l2);

@@ -20,6 +20,8 @@ enum MiscSlot : int {
   MISC_STATUS = 1,    // status bits of the last binning
   MISC_N_CULLED = 2,  // culled Gaussians of the last binning
   MISC_STICKY = 3,    // OR of MISC_STATUS over a fit call
+  MISC_REBINS = 4,    // tile-list rebuilds in a fit call (lazy binning)
+  MISC_STALE = 5,     // lazy binning: the lists must be rebuilt this iteration
   MISC_COUNT = 64
 };
 
@@ -43,8 +45,8 @@ struct Layout {
   bool wide;        // single pass whose digit is the whole tile index
   int digit_bits;   // bits of that digit (8..11), D = 2^digit_bits
   int D;
-  size_t geom, rect, counts, offsets, blocks, keys_a, keys_b, hist, tile_start, loss_part, grads,
-      qparams, qws, misc, total;
+  size_t geom, rect, brect, counts, offsets, blocks, keys_a, keys_b, hist, tile_start, loss_part,
+      grads, qparams, qws, misc, total;
   // the buffer holding the sorted keys after all passes
   size_t keys_sorted() const { return (sort_passes & 1) ? keys_b : keys_a; }
 };
@@ -127,6 +129,7 @@ struct FitArgs {
   gs2d_adam_cfg cfg;
   const uint8_t *active;  // nullable: only flagged Gaussians are updated
   int qat_bits_chol, qat_bits_rgb;  // 0: plain fitting, else quantisation-aware
+  float bin_skin;  // > 0: lazy binning with this margin (px), see launch_binning
 };
 
 template <typename T>
@@ -140,9 +143,20 @@ inline T *at(void *ws, size_t off) {
 // step_tick (nullable): a device counter incremented once by the binning.
 // adam (nullable): apply that optimiser step to xy/chol/rgb first (the
 // projection then reads the updated parameters).
+// skin > 0 (single-pass path only): lazy binning.  The lists are built from
+// every Gaussian's 3-sigma box grown by `skin` pixels, and rebuilt only when
+// misc[MISC_STALE] is set: by the projection when some Gaussian's exact tile
+// rectangle has left the rectangle its keys were built from (or it is
+// culled and still has keys), or by launch_mark_bins_stale.  Otherwise
+// emission and scatter return at once and the lists of an earlier
+// iteration, a superset of the exact ones in the same (tile, index) order,
+// stay in use; the raster's exact per-pixel cutoff makes the render
+// identical.  The fused raster clears the flag (launch_render_fused).
 hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, void *ws,
                           hipStream_t st, int *step_tick = nullptr,
-                          const PendingAdam *adam = nullptr);
+                          const PendingAdam *adam = nullptr, float skin = 0.f);
+// Lazy binning: force a rebuild at the next binning.
+hipError_t launch_mark_bins_stale(const Layout &L, void *ws, hipStream_t st);
 
 // Stable LSD radix sort of keys on bits [16, 16 + 8*passes) with G sort
 // blocks; misc[0] holds the key count; hist holds RADIX * G words.
@@ -159,9 +173,10 @@ hipError_t launch_render_fwd(const Layout &L, void *ws, const float *rgb, const 
 hipError_t launch_render_bwd(const Layout &L, void *ws, const float *rgb, const float *dl_dimg,
                              float *g_xy, float *g_chol, float *g_rgb, hipStream_t st);
 // active (nullable): the backward skips Gaussians with active[n] == 0.
+// clear_stale: the launch also clears misc[MISC_STALE] (lazy binning).
 hipError_t launch_render_fused(const Layout &L, void *ws, const float *rgb, const float *target,
                                float *g_xy, float *g_chol, float *g_rgb, hipStream_t st,
-                               const uint8_t *active = nullptr);
+                               const uint8_t *active = nullptr, bool clear_stale = false);
 hipError_t launch_loss_reduce(const Layout &L, void *ws, float *loss, hipStream_t st);
 hipError_t launch_count_pairs(const Layout &L, void *ws, unsigned long long *out, hipStream_t st);
 

@@ -124,6 +124,7 @@ k_render_fused(FrameArgs f, const float *__restrict__ target, float *__restrict_
   using C = Cfg<TILE, PPL>;
   __shared__ Smem<C::NW> S;
   __shared__ float acc[CH * 8];
+  if (f.clear_stale && blockIdx.x == 0 && threadIdx.x == 0) *f.clear_stale = 0;
   fused_tile<TILE, PPL>(S, acc, f, (int)blockIdx.x, target, loss_part + blockIdx.x * C::NW,
                         grad_scale, g_xy, g_chol, g_rgb);
 }
@@ -191,6 +192,7 @@ static FrameArgs frame_args(const Layout &L, void *ws, const float *rgb) {
   f.tile_start = at<const int>(ws, L.tile_start);
   f.rgb = rgb;
   f.active = nullptr;
+  f.clear_stale = nullptr;
   return f;
 }
 
@@ -232,9 +234,10 @@ hipError_t launch_render_bwd(const Layout &L, void *ws, const float *rgb, const 
 
 hipError_t launch_render_fused(const Layout &L, void *ws, const float *rgb, const float *target,
                                float *g_xy, float *g_chol, float *g_rgb, hipStream_t st,
-                               const uint8_t *active) {
+                               const uint8_t *active, bool clear_stale) {
   FrameArgs f = frame_args(L, ws, rgb);
   f.active = active;
+  if (clear_stale) f.clear_stale = at<int>(ws, L.misc) + MISC_STALE;
   float *lp = at<float>(ws, L.loss_part);
   bool done = false;
 #define CALL(TT, PP)                                                                           \

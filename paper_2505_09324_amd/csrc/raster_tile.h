@@ -53,6 +53,9 @@ struct FrameArgs {
   // nullable [N]: the fused backward skips Gaussians with active[n] == 0
   // (they are not optimised, Sec. 3.2.C); the forward renders them all
   const uint8_t *active;
+  // nullable: the fused raster sets *clear_stale = 0 (lazy binning: the
+  // binning kernels that read the flag have finished)
+  int *clear_stale;
 };
 
 // Whether the ellipse q' <= qmax (staged units: u1 = dx a, u2 = (dy - l2s u1)

@@ -47,13 +47,15 @@ extern "C" int gs2d_fit_frame_static(const gs2d_shape *shape, const float *targe
     if (!target || !xy || !chol || !rgb || !m || !v || !step || !loss_trace || !opts)
       return GS2D_EINVAL;
     if (opts->iters < 0 || opts->check_every < 1 || opts->qat) return GS2D_EINVAL;
+    if (!(opts->bin_skin >= 0.f && opts->bin_skin <= 64.f)) return GS2D_EINVAL;
     void *ws = nullptr;
     const int rc = scratch_address(&ws);
     if (rc != GS2D_OK) return rc;
     gs2d_fit_opts eager = *opts;
     eager.use_graph = 0;  // instantiating a graph may allocate
-    const gs2d::FitArgs a{target, xy, chol, rgb, m, v, step, loss_trace, trace_len, ws,
-                          opts->adam, opts->active, 0, 0};
+    const gs2d::FitArgs a{target, xy,        chol,         rgb,         m,  v,
+                          step,   loss_trace, trace_len, ws,          opts->adam,
+                          opts->active,        0,            0,           opts->bin_skin};
     return gs2d::fit_frame_run(nullptr, L, a, eager, stats, reinterpret_cast<hipStream_t>(stream));
   } catch (...) {
     return GS2D_EHIP;
