@@ -161,19 +161,22 @@ def test_training_reduces_loss_and_decode_matches_oracle():
 
 def test_trained_initialiser_beats_plain_init_at_fixed_budget():
     """What the learned initialiser gains over the method without it, at
-    small scale: the plain fitter fits 6 synthetic 256 x 256 sequences of 8
-    frames (frame 0 from the content-aware init, then warm-started), the
-    network is trained on those fits with the project's own kernels, and on
-    later frames of the same sequences that it never saw (t = 9 and 11) the
-    fitter started from the decoded prediction reaches a higher PSNR after a
-    fixed number of iterations than the fitter started from the content-aware
-    init.  (The held-out-sequence comparison at 1080p is the learned-
-    initialiser workload.)"""
+    small scale and on scenes it never saw: the plain fitter fits 12
+    synthetic 256 x 256 sequences of 8 frames (frame 0 from the
+    content-aware init, then warm-started), the network is trained on those
+    fits with the project's own kernels, and on frames of three held-out
+    sequences (other seeds: other colours, texture and pose) the fitter
+    started from the decoded prediction reaches a higher PSNR after a fixed
+    number of iterations than the fitter started from the content-aware
+    init.  The same frames also report the learned re-initialisation of a
+    warm start (the previous frame's fit, the changed tiles replaced from
+    the network) against the warm start alone; at this scale, as at 1080p,
+    it does not beat it, so that comparison is printed, not asserted."""
     print("learned init gain", flush=True)
     from paper_2505_09324_amd import workloads
     W = H = 256
     N = 1500
-    seqs = list(range(7000, 7006))
+    seqs = list(range(7000, 7012))
     frames = {}
     samples = workloads.make_training_set(seqs, 8, W, H, N, 400, 100, DEV, log=lambda m: None,
                                           frames=frames)
@@ -185,10 +188,11 @@ def test_trained_initialiser_beats_plain_init_at_fixed_budget():
     ws = _lib.alloc_workspace(shape)
     cfg = _lib.adam_cfg(workloads.LR_DEFAULT)
     gains = {20: [], 50: [], 100: []}
-    for sd in seqs[::2]:
-        for t in (9, 11):
+    warm = {20: [], 50: [], 100: []}
+    for sd in (7100, 7101, 7102):
+        for t in (3, 5):
             f, m = synth.make_frame_torch(W, H, sd, t, DEV)
-            prev = synth.make_frame_torch(W, H, sd, t - 1, DEV)[0]
+            prev, pm = synth.make_frame_torch(W, H, sd, t - 1, DEV)
             plain = [p.contiguous() for p in workloads.plain_init_dev(f, m, N, 99 + t)]
             net.forward(f, prev)
             xy, chol, rgb, npred = net.decode(N, *plain)
@@ -197,9 +201,28 @@ def test_trained_initialiser_beats_plain_init_at_fixed_budget():
             cl = workloads.psnr_curve(shape, ws, f, [xy, chol, rgb], 101, tuple(gains), cfg)
             for k in gains:
                 gains[k].append(cl[k] - cp[k])
-    print({k: [round(x, 2) for x in v] for k, v in gains.items()}, flush=True)
-    assert np.mean(gains[50]) >= 1.5, gains
-    assert np.mean(gains[100]) >= 1.0, gains
+            # warm start: the previous frame fitted from its own plain init
+            wp = [p.contiguous() for p in workloads.plain_init_dev(prev, pm, N, 199 + t)]
+            mm = torch.zeros(8 * N, device=DEV)
+            vv = torch.zeros(8 * N, device=DEV)
+            stp = torch.zeros(1, dtype=torch.int32, device=DEV)
+            trc = torch.zeros(500, device=DEV)
+            _lib.fit_frame(shape, prev, *wp, mm, vv, stp, trc, ws, _lib.fit_opts(400, 50, cfg=cfg))
+            rp = [p.clone() for p in wp]
+            net.pframe_replace(f, prev, 1e-3, *rp)
+            cw = workloads.psnr_curve(shape, ws, f, wp, 101, tuple(warm), cfg)
+            cr = workloads.psnr_curve(shape, ws, f, rp, 101, tuple(warm), cfg)
+            for k in warm:
+                warm[k].append(cr[k] - cw[k])
+    print("learned vs plain, cold:", {k: [round(x, 2) for x in v] for k, v in gains.items()},
+          flush=True)
+    print("learned re-initialisation vs warm start:",
+          {k: [round(x, 2) for x in v] for k, v in warm.items()}, flush=True)
+    # one measurement: +0.47 dB mean after 50 iterations (4 of 6 frames
+    # ahead, both frames of one scene behind), +0.82 dB after 100; the
+    # training itself is not bit-reproducible (float atomics)
+    assert sum(g > 0 for g in gains[50]) >= 3, gains
+    assert np.mean(gains[100]) > 0.25, gains
 
 
 def _half_ulp_bf16(x):
