@@ -29,7 +29,10 @@
  *    device are reported in the workspace status word (gs2d_bins.status):
  *    bit 0 = tile-pair capacity overflow (lists truncated, no out-of-bounds
  *    write), bit 1 = at least one Gaussian culled (non-finite mean or
- *    Cholesky vector, or |l1| or |l3| < 2^-14).
+ *    Cholesky vector, or |l1| or |l3| < 2^-14), bit 2 = a lazy tile-list
+ *    rebuild (gs2d_fit_opts.bin_skin > 0) gave up its bounded device-side
+ *    wait and kept the previous lists (gs2d_fit_frame then returns
+ *    GS2D_EHIP).
  *  - Limits: 1 <= W, H; 1 <= N <= 65536; tile in {8, 16, 32};
  *    ceil(W/tile) * ceil(H/tile) <= 65536; 1 <= max_pairs <= 2^30.
  */

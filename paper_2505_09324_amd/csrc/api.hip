@@ -274,7 +274,8 @@ hipError_t enqueue_iterations(const Layout &L, void *ws, const float *target, fl
   for (int i = 0; i < k && e == hipSuccess; ++i) {
     e = launch_binning(L, xy, chol, ws, st, step, i > 0 ? &pending : nullptr, skin);
     if (e == hipSuccess)
-      e = launch_render_fused(L, ws, rgb, target, g_xy, g_chol, g_rgb, st, active, skin > 0.f);
+      e = launch_render_fused(L, ws, rgb, target, g_xy, g_chol, g_rgb, st, active, skin > 0.f,
+                              skin > 0.f ? step : nullptr);
   }
   if (e == hipSuccess && k > 0)
     e = launch_adam(L.N, xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg, active, 1,
@@ -442,7 +443,7 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
     }
     sticky = (uint32_t)misc_host[MISC_STICKY];
     done += k;
-    if (sticky & STATUS_OVERFLOW) break;
+    if (sticky & (STATUS_OVERFLOW | STATUS_STALLED)) break;
     if (hit >= 0) break;
   }
   if (stats) {
@@ -455,6 +456,7 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
     stats->rebins = misc_host[MISC_REBINS];
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
+  if (sticky & STATUS_STALLED) return GS2D_EHIP;  // a device-side wait ran out
   return (sticky & STATUS_OVERFLOW) ? GS2D_EOVERFLOW : GS2D_OK;
 }
 

@@ -281,6 +281,7 @@ k_b_render_persistent(BatchRaster a) {
     fa.rgb = a.rgb + 3 * d.g_off;
     fa.active = nullptr;
     fa.clear_stale = nullptr;
+    fa.tick = nullptr;
     const float gs = (float)(2.0 / (3.0 * (double)d.W * (double)d.H));
     fused_tile<TILE, PPL, false>(S, acc, fa, t, a.targets + d.px_off,
                           a.loss_part + (d.tile_off + t) * Cfg<TILE, PPL>::NW, gs,

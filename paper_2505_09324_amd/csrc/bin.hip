@@ -201,6 +201,7 @@ k_emit_wide(int N, int TX, int nbp, int max_pairs, int D, const int4 *__restrict
     if (n < N) brect[n] = rect[n];
     if (blockIdx.x == 0 && threadIdx.x == 0) misc[MISC_REBINS] += 1;
   }
+  __shared__ EmitLds E;
   long long pre, end_keys, total;
   int culled;
   chunk_bounds<WIDE_BLOCK>(nbp, blockIdx.x, WIDE_GROUP, bsum, bcull, &pre, &end_keys, &total,
@@ -218,7 +219,7 @@ k_emit_wide(int N, int TX, int nbp, int max_pairs, int D, const int4 *__restrict
   }
   emit_block_wide(blockIdx.x * WIDE_BLOCK, N, TX, pre, end_keys, np, D, rect, counts, offsets,
                   keys, hist + (size_t)blockIdx.x * D,
-                  hist + WIDE_PART_ROWS + (size_t)blockIdx.x * (WIDE_SPLIT - 1) * D);
+                  hist + WIDE_PART_ROWS + (size_t)blockIdx.x * (WIDE_SPLIT - 1) * D, E);
 }
 
 __global__ void __launch_bounds__(WIDE_SCATTER)
@@ -227,8 +228,97 @@ k_scatter_wide(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
                const int *__restrict__ bsum, const int *__restrict__ bcull,
                const uint32_t *__restrict__ hist, int *__restrict__ tile_start, int lazy) {
   if (lazy && misc[MISC_STALE] == 0) return;  // the lists are still valid
+  __shared__ ScatterLds L;
   scatter_chunk_wide(in, out, nb, nbp, blockIdx.x / WIDE_SPLIT, blockIdx.x % WIDE_SPLIT, D, bits,
-                     misc[MISC_N_PAIRS], n_tiles, bsum, bcull, hist, tile_start);
+                     misc[MISC_N_PAIRS], n_tiles, bsum, bcull, hist, tile_start, L);
+}
+
+// Lazy binning's emission and scatter in one launch.  While the lists stay
+// valid (misc[MISC_STALE] == 0) every block returns at once.  For a rebuild
+// the blocks take roles in the order they start, by ticket: the first nbw
+// emit one chunk each (k_emit_wide's work), the others each scatter one part
+// of a chunk (k_scatter_wide's) once every chunk is emitted; blocks have
+// the scatter's WIDE_SCATTER threads, an emission block taking two
+// Gaussians per thread (the registers of 1024-thread blocks would not hold
+// the scatter's key and histogram tiles).  A role is only
+// ever held by a running block and emission waits for nothing, so the
+// scatter's wait ends however many blocks are resident at once; it is also
+// bounded (about 0.5 s), after which the block records STATUS_STALLED and
+// skips its part, leaving the previous lists in place.  Each block's writes
+// are made visible device-wide (every thread's release fence) before its
+// chunk is counted, and read after an acquire fence.  The last block to
+// finish returns the three counters to zero.  It does not tick the step
+// (the caller's raster does, so that the early return is a single load).
+__global__ void __launch_bounds__(WIDE_SCATTER)
+k_bin_lazy_wide(int N, int TX, int nbp, int nbw, int max_pairs, int D, int bits, int n_tiles,
+                const int4 *__restrict__ rect, const int *__restrict__ counts,
+                const int *__restrict__ bsum, const int *__restrict__ bcull,
+                int *__restrict__ offsets, uint32_t *__restrict__ ka, uint32_t *__restrict__ kb,
+                uint32_t *__restrict__ hist, int *__restrict__ misc,
+                int4 *__restrict__ brect, int *__restrict__ tile_start) {
+  constexpr size_t RAW = sizeof(ScatterLds) > sizeof(EmitLds) ? sizeof(ScatterLds) : sizeof(EmitLds);
+  __shared__ __align__(16) unsigned char raw[RAW];
+  __shared__ unsigned s_ticket;
+  __shared__ int s_go;
+  const int tid = (int)threadIdx.x;
+  if (misc[MISC_STALE] == 0) return;  // uniform over the grid
+  unsigned *ctr = reinterpret_cast<unsigned *>(misc);
+  if (tid == 0) s_ticket = atomicAdd(ctr + MISC_TICKET, 1u);
+  __syncthreads();
+  const int t = (int)s_ticket;
+  if (t < nbw) {  // emission of chunk t
+    for (int n = t * WIDE_BLOCK + tid; n < min(N, (t + 1) * WIDE_BLOCK); n += WIDE_SCATTER)
+      brect[n] = rect[n];
+    long long pre, end_keys, total;
+    int culled;
+    chunk_bounds<WIDE_SCATTER>(nbp, t, WIDE_GROUP, bsum, bcull, &pre, &end_keys, &total, &culled);
+    const int np = (int)min(total, (long long)max_pairs);
+    if (t == 0 && tid == 0) {
+      offsets[N] = np;
+      const uint32_t st = (total > (long long)max_pairs ? STATUS_OVERFLOW : 0u) |
+                          (culled > 0 ? STATUS_CULLED : 0u);
+      misc[MISC_N_PAIRS] = np;
+      misc[MISC_STATUS] = (int)st;
+      misc[MISC_N_CULLED] = culled;
+      misc[MISC_STICKY] |= (int)st;
+      misc[MISC_REBINS] += 1;
+    }
+    emit_block_wide<WIDE_SCATTER>(t * WIDE_BLOCK, N, TX, pre, end_keys, np, D, rect, counts,
+                                  offsets, ka,
+                    hist + (size_t)t * D, hist + WIDE_PART_ROWS + (size_t)t * (WIDE_SPLIT - 1) * D,
+                    *reinterpret_cast<EmitLds *>(raw));
+    __threadfence();  // release this thread's writes
+    __syncthreads();
+    if (tid == 0) atomicAdd(ctr + MISC_EMITTED, 1u);
+  } else {  // scatter of part (t - nbw) % WIDE_SPLIT of chunk (t - nbw) / WIDE_SPLIT
+    if (tid == 0) {
+      int go = 1;
+      for (unsigned spin = 0;
+           __hip_atomic_load(ctr + MISC_EMITTED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+           (unsigned)nbw;) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spin == (1u << 22)) {
+          go = 0;
+          atomicOr(misc + MISC_STICKY, (int)STATUS_STALLED);
+          break;
+        }
+      }
+      s_go = go;
+    }
+    __syncthreads();
+    if (s_go) {
+      __threadfence();  // acquire the emitted keys and histograms
+      const int s = t - nbw;
+      scatter_chunk_wide(ka, kb, nbw, nbp, s / WIDE_SPLIT, s % WIDE_SPLIT, D, bits,
+                         misc[MISC_N_PAIRS], n_tiles, bsum, bcull, hist, tile_start,
+                         *reinterpret_cast<ScatterLds *>(raw));
+    }
+  }
+  if (tid == 0 && atomicAdd(ctr + MISC_FINISHED, 1u) == gridDim.x - 1) {
+    atomicExch(ctr + MISC_TICKET, 0u);
+    atomicExch(ctr + MISC_EMITTED, 0u);
+    atomicExch(ctr + MISC_FINISHED, 0u);
+  }
 }
 
 // ------------------------------------------------------------ radix sort --
@@ -303,6 +393,13 @@ hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, v
       hipLaunchKernelGGL(k_project_wide, dim3(nbp), dim3(WIDE_PROJ), 0, st, L.N, L.TX, L.TY,
                          1.0f / (float)L.T, xy, chol, geom, rect, counts, bsum, bcull, skin, brect,
                          misc);
+    if (lazy) {
+      hipLaunchKernelGGL(k_bin_lazy_wide, dim3(nbw * (1 + WIDE_SPLIT)), dim3(WIDE_SCATTER), 0, st,
+                         L.N, L.TX, nbp, nbw, L.max_pairs, L.D, L.digit_bits, L.n_tiles, rect,
+                         counts, bsum, bcull, offsets, ka, kb, hist, misc, brect,
+                         at<int>(ws, L.tile_start));
+      return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_emit_wide, dim3(nbw), dim3(WIDE_BLOCK), 0, st, L.N, L.TX, nbp,
                        L.max_pairs, L.D, rect, counts, bsum, bcull, offsets, ka, hist, misc,
                        step_tick, lazy, brect);

@@ -471,51 +471,71 @@ __device__ inline void tile_ranges(const uint32_t *__restrict__ keys, int n, int
 // index: hist_row[t] (t < D) receives how many of them fall in tile t, and
 // part_rows[r * D + t] how many of them fall in tile t within the chunk's
 // first r + 1 scatter parts (the split the scatter uses: WIDE_SPLIT parts
-// of q = ceil(keys / WIDE_SPLIT) keys), for r < WIDE_SPLIT - 1.
-__device__ inline void emit_block_wide(int base, int N, int TX, long long block_off,
+// of q = ceil(keys / WIDE_SPLIT) keys), for r < WIDE_SPLIT - 1.  NT threads
+// each take WIDE_BLOCK / NT adjacent Gaussians (the keys do not depend on
+// it).  E: the block's LDS (EmitLds).
+struct EmitLds {
+  int lds[WIDE_BLOCK / 64];
+  uint32_t hp[WIDE_SPLIT][WIDE_MAX_TILES];
+};
+
+template <int NT = WIDE_BLOCK>
+__device__ __forceinline__ void emit_block_wide(int base, int N, int TX, long long block_off,
                                        long long block_end, int n_keys, int D,
                                        const int4 *__restrict__ rect,
                                        const int *__restrict__ counts, int *__restrict__ offsets,
                                        uint32_t *__restrict__ keys,
                                        uint32_t *__restrict__ hist_row,
-                                       uint32_t *__restrict__ part_rows) {
+                                       uint32_t *__restrict__ part_rows, EmitLds &E) {
   // one LDS count per key, into its part's histogram; the chunk row is the
   // sum of the parts
-  __shared__ int lds[WIDE_BLOCK / 64];
-  __shared__ uint32_t hp[WIDE_SPLIT][WIDE_MAX_TILES];
-  for (int d = threadIdx.x; d < D; d += WIDE_BLOCK) {
+  constexpr int G = WIDE_BLOCK / NT;  // adjacent Gaussians per thread
+  static_assert(G * NT == WIDE_BLOCK && G <= 2, "one or two Gaussians per thread");
+  int *lds = E.lds;
+  uint32_t(*hp)[WIDE_MAX_TILES] = E.hp;
+  for (int d = threadIdx.x; d < D; d += NT) {
 #pragma unroll
     for (int r = 0; r < WIDE_SPLIT; ++r) hp[r][d] = 0;
   }
   const int cbeg = (int)min(block_off, (long long)n_keys);
   const int cend = (int)min(block_end, (long long)n_keys);
   const int q = (cend - cbeg + WIDE_SPLIT - 1) / WIDE_SPLIT;  // >= 1 when a key exists
-  const int n = base + (int)threadIdx.x;
-  int c = 0;
-  if (n < N) {
-    const int v = counts[n];
-    c = v > 0 ? v : 0;
+  const int n0 = base + G * (int)threadIdx.x;
+  int c[G], csum = 0;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    c[g] = 0;
+    if (n0 + g < N) {
+      const int v = counts[n0 + g];
+      c[g] = v > 0 ? v : 0;
+    }
+    csum += c[g];
   }
   int tot;
-  const int local = block_exclusive_scan_i32<WIDE_BLOCK>(c, &tot, lds);  // ends with a barrier
-  if (n < N) {
-    const long long start = block_off + local;
-    const int beg = (int)min(start, (long long)n_keys);
-    const int end = (int)min(start + c, (long long)n_keys);
-    offsets[n] = beg;
-    if (end > beg) {
-      const int4 rc = rect[n];
-      int k = beg;
-      for (int ty = rc.y; ty <= rc.w && k < end; ++ty)
-        for (int tx = rc.x; tx <= rc.z && k < end; ++tx, ++k) {
-          const uint32_t tile = (uint32_t)(ty * TX + tx);
-          keys[k] = (tile << 16) | (uint32_t)n;
-          atomicAdd(&hp[(k - cbeg) / q][tile], 1u);  // part < WIDE_SPLIT: k < cbeg + WIDE_SPLIT q
-        }
+  int local = block_exclusive_scan_i32<NT>(csum, &tot, lds);  // ends with a barrier
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int n = n0 + g;
+    if (n < N) {
+      const long long start = block_off + local;
+      const int beg = (int)min(start, (long long)n_keys);
+      const int end = (int)min(start + c[g], (long long)n_keys);
+      offsets[n] = beg;
+      if (end > beg) {
+        const int4 rc = rect[n];
+        int k = beg;
+        for (int ty = rc.y; ty <= rc.w && k < end; ++ty)
+          for (int tx = rc.x; tx <= rc.z && k < end; ++tx, ++k) {
+            const uint32_t tile = (uint32_t)(ty * TX + tx);
+            keys[k] = (tile << 16) | (uint32_t)n;
+            atomicAdd(&hp[(k - cbeg) / q][tile], 1u);  // part < WIDE_SPLIT: k < cbeg + WIDE_SPLIT q
+          }
+      }
     }
+    local += c[g];
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < D; d += WIDE_BLOCK) {
+  for (int d = threadIdx.x; d < D; d += NT) {
     uint32_t acc = 0;
 #pragma unroll
     for (int r = 0; r < WIDE_SPLIT - 1; ++r) {
@@ -542,20 +562,28 @@ __device__ inline void emit_block_wide(int base, int N, int TX, long long block_
 // earlier wavefronts; only the masks that were set are cleared.  The
 // histogram loads are issued before the chunk bounds are
 // known so that their latency overlaps the block-sum prefix.
-__device__ inline void scatter_chunk_wide(const uint32_t *__restrict__ in,
+// LDS of one scatter block (scatter_chunk_wide).
+struct ScatterLds {
+  uint32_t off[WIDE_MAX_TILES];
+  unsigned long long wmask[WIDE_SCATTER / 64][WIDE_MAX_TILES];
+  uint4 fold[2][WIDE_SCATTER];
+  int lds[WIDE_SCATTER / 64];
+};
+
+__device__ __forceinline__ void scatter_chunk_wide(const uint32_t *__restrict__ in,
                                           uint32_t *__restrict__ out, int nb, int nbp, int b,
                                           int part, int D,
                                           int bits, int n, int n_tiles,
                                           const int *__restrict__ bsum,
                                           const int *__restrict__ bcull,
                                           const uint32_t *__restrict__ hist,
-                                          int *__restrict__ tile_start) {
+                                          int *__restrict__ tile_start, ScatterLds &L) {
   constexpr int NT = WIDE_SCATTER, NW = NT / 64, RB = 16;
   static_assert(NT * 4 == WIDE_MAX_TILES, "one uint4 column of digits per thread at most");
-  __shared__ uint32_t off[WIDE_MAX_TILES];
-  __shared__ unsigned long long wmask[NW][WIDE_MAX_TILES];
-  __shared__ uint4 fold[2][NT];
-  __shared__ int lds[NW];
+  uint32_t *off = L.off;
+  unsigned long long(*wmask)[WIDE_MAX_TILES] = L.wmask;
+  uint4(*fold)[NT] = L.fold;
+  int *lds = L.lds;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   {
     uint4 *t4 = reinterpret_cast<uint4 *>(&wmask[0][0]);

@@ -22,11 +22,15 @@ enum MiscSlot : int {
   MISC_STICKY = 3,    // OR of MISC_STATUS over a fit call
   MISC_REBINS = 4,    // tile-list rebuilds in a fit call (lazy binning)
   MISC_STALE = 5,     // lazy binning: the lists must be rebuilt this iteration
+  MISC_TICKET = 6,    // lazy rebuild: roles taken (k_bin_lazy_wide), 0 between launches
+  MISC_EMITTED = 7,   // lazy rebuild: chunks emitted, 0 between launches
+  MISC_FINISHED = 8,  // lazy rebuild: blocks done, 0 between launches
   MISC_COUNT = 64
 };
 
 constexpr uint32_t STATUS_OVERFLOW = 1u;
 constexpr uint32_t STATUS_CULLED = 2u;
+constexpr uint32_t STATUS_STALLED = 4u;  // a lazy rebuild's bounded wait ran out (lists kept)
 
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
@@ -147,11 +151,12 @@ inline T *at(void *ws, size_t off) {
 // every Gaussian's 3-sigma box grown by `skin` pixels, and rebuilt only when
 // misc[MISC_STALE] is set: by the projection when some Gaussian's exact tile
 // rectangle has left the rectangle its keys were built from (or it is
-// culled and still has keys), or by launch_mark_bins_stale.  Otherwise
-// emission and scatter return at once and the lists of an earlier
-// iteration, a superset of the exact ones in the same (tile, index) order,
-// stay in use; the raster's exact per-pixel cutoff makes the render
-// identical.  The fused raster clears the flag (launch_render_fused).
+// culled and still has keys), or by launch_mark_bins_stale.  Otherwise the
+// one kernel that emits and scatters returns at once and the lists of an
+// earlier iteration, a superset of the exact ones in the same (tile, index)
+// order, stay in use; the raster's exact per-pixel cutoff makes the render
+// identical.  The fused raster clears the flag (launch_render_fused).  The
+// lazy path does not tick step_tick: its caller ticks it in the raster.
 hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, void *ws,
                           hipStream_t st, int *step_tick = nullptr,
                           const PendingAdam *adam = nullptr, float skin = 0.f);
@@ -174,9 +179,11 @@ hipError_t launch_render_bwd(const Layout &L, void *ws, const float *rgb, const 
                              float *g_xy, float *g_chol, float *g_rgb, hipStream_t st);
 // active (nullable): the backward skips Gaussians with active[n] == 0.
 // clear_stale: the launch also clears misc[MISC_STALE] (lazy binning).
+// tick (nullable): the launch also adds 1 to *tick (the step counter).
 hipError_t launch_render_fused(const Layout &L, void *ws, const float *rgb, const float *target,
                                float *g_xy, float *g_chol, float *g_rgb, hipStream_t st,
-                               const uint8_t *active = nullptr, bool clear_stale = false);
+                               const uint8_t *active = nullptr, bool clear_stale = false,
+                               int32_t *tick = nullptr);
 hipError_t launch_loss_reduce(const Layout &L, void *ws, float *loss, hipStream_t st);
 hipError_t launch_count_pairs(const Layout &L, void *ws, unsigned long long *out, hipStream_t st);
 

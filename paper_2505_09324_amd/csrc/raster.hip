@@ -124,7 +124,10 @@ k_render_fused(FrameArgs f, const float *__restrict__ target, float *__restrict_
   using C = Cfg<TILE, PPL>;
   __shared__ Smem<C::NW> S;
   __shared__ float acc[CH * 8];
-  if (f.clear_stale && blockIdx.x == 0 && threadIdx.x == 0) *f.clear_stale = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (f.clear_stale) *f.clear_stale = 0;
+    if (f.tick) *f.tick += 1;
+  }
   fused_tile<TILE, PPL>(S, acc, f, (int)blockIdx.x, target, loss_part + blockIdx.x * C::NW,
                         grad_scale, g_xy, g_chol, g_rgb);
 }
@@ -193,6 +196,7 @@ static FrameArgs frame_args(const Layout &L, void *ws, const float *rgb) {
   f.rgb = rgb;
   f.active = nullptr;
   f.clear_stale = nullptr;
+  f.tick = nullptr;
   return f;
 }
 
@@ -234,10 +238,11 @@ hipError_t launch_render_bwd(const Layout &L, void *ws, const float *rgb, const 
 
 hipError_t launch_render_fused(const Layout &L, void *ws, const float *rgb, const float *target,
                                float *g_xy, float *g_chol, float *g_rgb, hipStream_t st,
-                               const uint8_t *active, bool clear_stale) {
+                               const uint8_t *active, bool clear_stale, int32_t *tick) {
   FrameArgs f = frame_args(L, ws, rgb);
   f.active = active;
   if (clear_stale) f.clear_stale = at<int>(ws, L.misc) + MISC_STALE;
+  f.tick = tick;
   float *lp = at<float>(ws, L.loss_part);
   bool done = false;
 #define CALL(TT, PP)                                                                           \

@@ -56,6 +56,8 @@ struct FrameArgs {
   // nullable: the fused raster sets *clear_stale = 0 (lazy binning: the
   // binning kernels that read the flag have finished)
   int *clear_stale;
+  // nullable: the fused raster adds 1 to *tick (the optimiser's step)
+  int *tick;
 };
 
 // Whether the ellipse q' <= qmax (staged units: u1 = dx a, u2 = (dy - l2s u1)
