@@ -116,12 +116,12 @@ typedef struct {
    * tiles, not with qat) each Gaussian is binned into the tiles its 3-sigma
    * box grown by bin_skin pixels meets, and the lists are rebuilt only when
    * some Gaussian's exact tile rectangle has left the one it was binned with
-   * (or it became culled), and at the start of every chunk; in between the
-   * projection still runs every iteration and the lists of the last rebuild
-   * are a superset of the exact ones in the same (tile, index) order.  Every
-   * pixel's sum tests each pair against the cutoff, so the render, the loss
-   * and the gradients are those of exact binning.  gs2d_fit_batch ignores
-   * it. */
+   * (or it became culled), and at the first iteration of every call; in
+   * between the projection still runs every iteration and the lists of the
+   * last rebuild are a superset of the exact ones in the same (tile, index)
+   * order.  Every pixel's sum tests each pair against the cutoff, so the
+   * render, the loss and the gradients are those of exact binning.
+   * gs2d_fit_batch ignores it. */
   float bin_skin;
 } gs2d_fit_opts;
 

@@ -267,10 +267,11 @@ hipError_t enqueue_iterations(const Layout &L, void *ws, const float *target, fl
   const PendingAdam pending{xy,    chol, rgb,  g_xy, g_chol, g_rgb, m,         v,
                             step,  cfg,  at<const float>(ws, L.loss_part), L.loss_parts,
                             loss_scale, trace, trace_len, active};
-  // lazy binning on the single-pass path: every chunk starts with a rebuild
-  // (the parameters or the workspace may have changed between chunks)
+  // lazy binning on the single-pass path (fit_frame_run forces a rebuild at
+  // the start of each call: the parameters or the workspace may have
+  // changed since the lists were built)
   const float skin = (L.wide && bin_skin > 0.f) ? bin_skin : 0.f;
-  hipError_t e = skin > 0.f ? launch_mark_bins_stale(L, ws, st) : hipSuccess;
+  hipError_t e = hipSuccess;
   for (int i = 0; i < k && e == hipSuccess; ++i) {
     e = launch_binning(L, xy, chol, ws, st, step, i > 0 ? &pending : nullptr, skin);
     if (e == hipSuccess)
@@ -413,6 +414,8 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
   int32_t *misc = at<int32_t>(a.ws, L.misc);
   hipError_t e = launch_fill_zero_u32(reinterpret_cast<uint32_t *>(misc), MISC_COUNT, st);
   if (e == hipSuccess) e = launch_fill_zero(at<float>(a.ws, L.grads), 8 * (size_t)L.N, st);
+  if (e == hipSuccess && L.wide && a.bin_skin > 0.f && a.qat_bits_chol == 0)
+    e = launch_mark_bins_stale(L, a.ws, st);  // lazy lists: rebuilt at the call's first iteration
   if (e != hipSuccess) return GS2D_EHIP;
 
   constexpr int TRACE_PIECE = 256;  // loss values read back per copy

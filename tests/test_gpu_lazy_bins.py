@@ -81,8 +81,11 @@ def _fit(W, H, N, iters, seed, skin, lr=(2e-2, 5e-3, 5e-3), init=None, chunk=Non
 
 
 def test_lazy_lists_cover_every_pair_full_hd():
+    """Three chunks of 20 iterations: the lists of one chunk carry over to
+    the next (only the call's first iteration forces a rebuild), the Adam
+    step between chunks included."""
     print("lazy binning 1080p", flush=True)
-    shape, ws, st, tr, _ = _fit(1920, 1080, 30000, 60, 201, 1.0)
+    shape, ws, st, tr, _ = _fit(1920, 1080, 30000, 60, 201, 1.0, chunk=20)
     assert 1 <= st.rebins < 60, st.rebins
     need, have = _check_lists(shape, ws, 1920, 1080, 32)
     assert have >= need
@@ -115,7 +118,7 @@ def test_lazy_fit_follows_the_exact_fit():
     print("lazy vs exact fit", flush=True)
     a = _fit(320, 240, 1500, 200, 23, 1.0, chunk=50)
     b = _fit(320, 240, 1500, 200, 23, 0.0, chunk=50)
-    assert b[2].rebins == 0 and a[2].rebins >= 4
+    assert b[2].rebins == 0 and a[2].rebins >= 1
     # the render at the first iteration uses the same parameters: bit-equal
     assert a[3][0] == b[3][0]
     np.testing.assert_allclose(a[3], b[3], rtol=1e-4)
