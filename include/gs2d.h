@@ -297,9 +297,11 @@ int gs2d_ctx_stats(const gs2d_ctx *ctx, int32_t *cached, int64_t *captures);
  *   step[0] + opts->iters.
  * Work is enqueued on `stream` (NULL: the default stream) behind whatever the
  * caller enqueued before; the call waits for the stream at each PSNR check
+ * (with psnr_target <= 0 only once: all chunks are enqueued back to back)
  * and returns after the work is complete.  Returns GS2D_EOVERFLOW if the
- * tile-pair capacity was exceeded, GS2D_EINVAL if ctx belongs to another
- * device. */
+ * tile-pair capacity was exceeded (with psnr_target > 0 the loop stops at
+ * the check that finds it; without a target the iterations all run),
+ * GS2D_EINVAL if ctx belongs to another device. */
 int gs2d_fit_frame(gs2d_ctx *ctx, const gs2d_shape *shape, const float *target, float *xy,
                    float *chol, float *rgb, float *m, float *v, int32_t *step, float *loss_trace,
                    int32_t trace_len, void *ws, size_t ws_bytes, const gs2d_fit_opts *opts,

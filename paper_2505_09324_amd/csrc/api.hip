@@ -424,6 +424,22 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
   int done = 0, hit = -1;
   float last_loss = NAN;
   uint32_t sticky = 0;
+  if (!(opts.psnr_target > 0.f) && opts.iters > 0) {
+    // no early stop to check: every chunk back to back, one wait at the end
+    while (done < opts.iters) {
+      const int k = std::min(opts.check_every, opts.iters - done);
+      const int rc = run_chunk(cx, use_graph, L, a, k, st, true);
+      if (rc != GS2D_OK) return rc;
+      done += k;
+    }
+    if (hipMemcpyAsync(misc_host, misc, sizeof(misc_host), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(&last_loss, a.trace + step0 + done - 1, sizeof(float),
+                       hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return GS2D_EHIP;
+    sticky = (uint32_t)misc_host[MISC_STICKY];
+  }
   while (done < opts.iters) {
     const int k = std::min(opts.check_every, opts.iters - done);
     int rc = run_chunk(cx, use_graph, L, a, k, st, true);

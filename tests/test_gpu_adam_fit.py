@@ -181,6 +181,7 @@ def test_fit_frame_stops_at_psnr_and_flags_overflow():
     st2 = _lib.fit_frame(small.shape, dev(frame), P["xy"], P["chol"], P["rgb"], M, V, step, trace,
                          small.ws, _lib.fit_opts(20, 5, cfg=_lib.adam_cfg(LR)), check=False)
     assert st2.code == _lib.GS2D_EOVERFLOW and st2.status & _lib.STATUS_OVERFLOW
+    assert st2.iters_run == 20  # no target: the chunks run back to back, all of them
 
 
 def test_fit_frame_1080p_matches_separate_calls():
