@@ -294,7 +294,9 @@ int gs2d_ctx_stats(const gs2d_ctx *ctx, int32_t *cached, int64_t *captures);
  *   loss_trace [trace_len] device floats: loss_trace[k] = MSE at the
  *   parameters before update k, k = step[0] at that iteration (entries the
  *   call does not reach are left untouched); trace_len must exceed
- *   step[0] + opts->iters.
+ *   step[0] + opts->iters (with psnr_target <= 0 this is checked when the
+ *   work has run, step[0] being read only then: GS2D_EINVAL, no entry past
+ *   trace_len written).
  * Work is enqueued on `stream` (NULL: the default stream) behind whatever the
  * caller enqueued before; the call waits for the stream at each PSNR check
  * (with psnr_target <= 0 only once: all chunks are enqueued back to back)

@@ -22,7 +22,7 @@ k_adam(int N, float *__restrict__ xy, float *__restrict__ chol, float *__restric
        float *__restrict__ m, float *__restrict__ v, int32_t *__restrict__ step, float lr0,
        float lr1, float lr2, float b1, float b2, float eps, const uint8_t *__restrict__ active,
        int zero_grads, const float *__restrict__ loss_part, int n_part, float loss_scale,
-       float *__restrict__ loss_trace, int trace_len) {
+       float *__restrict__ loss_trace, int trace_len, int32_t *__restrict__ report) {
   __shared__ double red[4];
   // every thread reads the step (advanced only by a separate kernel) and
   // derives the bias corrections itself: no barrier before the loads
@@ -63,8 +63,13 @@ k_adam(int N, float *__restrict__ xy, float *__restrict__ chol, float *__restric
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0 && t - 1 < trace_len) {
-      loss_trace[t - 1] = (float)((red[0] + red[1] + red[2] + red[3]) * (double)loss_scale);
+    if (threadIdx.x == 0) {
+      const float loss = (float)((red[0] + red[1] + red[2] + red[3]) * (double)loss_scale);
+      if (t - 1 < trace_len) loss_trace[t - 1] = loss;
+      if (report) {
+        report[0] = t;
+        report[1] = __float_as_int(loss);
+      }
     }
   }
 }
@@ -90,6 +95,28 @@ __global__ void k_fill_zero_u32(uint32_t *__restrict__ p, size_t n) {
     p[i] = 0u;
 }
 
+// The start of a fitting call in one launch: misc zeroed except
+// misc[MISC_STALE] = stale (lazy binning: rebuild at the first iteration),
+// and the n_grads gradient accumulators zeroed.
+__global__ void k_fit_begin(int32_t *__restrict__ misc, float *__restrict__ grads, size_t n_grads,
+                            int stale) {
+  if (blockIdx.x == 0 && threadIdx.x < MISC_COUNT)
+    misc[threadIdx.x] = (threadIdx.x == MISC_STALE && stale) ? 1 : 0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n_grads;
+       i += (size_t)gridDim.x * blockDim.x)
+    grads[i] = 0.f;
+}
+
+hipError_t launch_fit_begin(int32_t *misc, float *grads, size_t n_grads, bool stale,
+                            hipStream_t st) {
+  static_assert(MISC_COUNT <= 256, "one block clears misc");
+  size_t nb = (n_grads + 255) / 256;
+  nb = nb < 1 ? 1 : (nb > 2048 ? 2048 : nb);
+  hipLaunchKernelGGL(k_fit_begin, dim3((unsigned)nb), dim3(256), 0, st, misc, grads, n_grads,
+                     stale ? 1 : 0);
+  return hipGetLastError();
+}
+
 static int adam_blocks(int N) {
   const int need = (8 * N + 255) / 256;
   return need < 1024 ? (need > 0 ? need : 1) : 1024;
@@ -99,11 +126,11 @@ hipError_t launch_adam(int N, float *xy, float *chol, float *rgb, float *g_xy, f
                        float *g_rgb, float *m, float *v, int32_t *step, const gs2d_adam_cfg &cfg,
                        const uint8_t *active, int zero_grads, const float *loss_part,
                        int n_loss_part, float loss_scale, float *loss_trace, int trace_len,
-                       hipStream_t st) {
+                       hipStream_t st, int32_t *report) {
   hipLaunchKernelGGL(k_adam, dim3(adam_blocks(N)), dim3(256), 0, st, N, xy, chol, rgb, g_xy, g_chol,
                      g_rgb, m, v, step, cfg.lr[0], cfg.lr[1], cfg.lr[2], cfg.beta1, cfg.beta2,
                      cfg.eps, active, zero_grads, loss_part, n_loss_part, loss_scale, loss_trace,
-                     trace_len);
+                     trace_len, report);
   return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <new>
 #include <vector>
 
@@ -260,7 +261,7 @@ hipError_t enqueue_iterations(const Layout &L, void *ws, const float *target, fl
       if (e == hipSuccess)
         e = launch_adam(L.N, xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg, active, 1,
                         at<const float>(ws, L.loss_part), L.loss_parts, loss_scale, trace,
-                        trace_len, st);
+                        trace_len, st, at<int32_t>(ws, L.misc) + MISC_STEP);
     }
     return e;
   }
@@ -281,7 +282,7 @@ hipError_t enqueue_iterations(const Layout &L, void *ws, const float *target, fl
   if (e == hipSuccess && k > 0)
     e = launch_adam(L.N, xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg, active, 1,
                     at<const float>(ws, L.loss_part), L.loss_parts, loss_scale, trace, trace_len,
-                    st);
+                    st, at<int32_t>(ws, L.misc) + MISC_STEP);
   return e;
 }
 
@@ -401,30 +402,38 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
     stats->n_culled = 0;
     stats->rebins = 0;
   }
+  // Without a PSNR target nothing is read back until the end: the step count
+  // the loop's last Adam step reports gives step[0] at the start, and the
+  // trace bound is checked then (the kernels write no entry past trace_len).
+  const bool at_end = !(opts.psnr_target > 0.f) && opts.iters > 0;
   int32_t step0 = 0;
-  if (hipMemcpyAsync(&step0, a.step, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return GS2D_EHIP;
-  if (step0 < 0 || (long long)step0 + opts.iters >= (long long)a.trace_len) return GS2D_EINVAL;
+  if (!at_end) {
+    if (hipMemcpyAsync(&step0, a.step, sizeof(int32_t), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return GS2D_EHIP;
+    if (step0 < 0 || (long long)step0 + opts.iters >= (long long)a.trace_len) return GS2D_EINVAL;
+  }
 
   // without a context the call's graphs live until it returns
   gs2d_ctx local;
   gs2d_ctx *cx = ctx ? ctx : &local;
   const bool use_graph = opts.use_graph != 0;
   int32_t *misc = at<int32_t>(a.ws, L.misc);
-  hipError_t e = launch_fill_zero_u32(reinterpret_cast<uint32_t *>(misc), MISC_COUNT, st);
-  if (e == hipSuccess) e = launch_fill_zero(at<float>(a.ws, L.grads), 8 * (size_t)L.N, st);
-  if (e == hipSuccess && L.wide && a.bin_skin > 0.f && a.qat_bits_chol == 0)
-    e = launch_mark_bins_stale(L, a.ws, st);  // lazy lists: rebuilt at the call's first iteration
+  // misc and the gradients cleared; lazy lists rebuilt at the call's first iteration
+  const hipError_t e =
+      launch_fit_begin(misc, at<float>(a.ws, L.grads), 8 * (size_t)L.N,
+                       L.wide && a.bin_skin > 0.f && a.qat_bits_chol == 0, st);
   if (e != hipSuccess) return GS2D_EHIP;
 
   constexpr int TRACE_PIECE = 256;  // loss values read back per copy
   float trace_host[TRACE_PIECE];
-  int32_t misc_host[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int32_t misc_host[16] = {};
   int done = 0, hit = -1;
   float last_loss = NAN;
   uint32_t sticky = 0;
-  if (!(opts.psnr_target > 0.f) && opts.iters > 0) {
+  bool bad_trace = false;
+  if (at_end) {
     // no early stop to check: every chunk back to back, one wait at the end
     while (done < opts.iters) {
       const int k = std::min(opts.check_every, opts.iters - done);
@@ -434,11 +443,12 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
     }
     if (hipMemcpyAsync(misc_host, misc, sizeof(misc_host), hipMemcpyDeviceToHost, st) !=
             hipSuccess ||
-        hipMemcpyAsync(&last_loss, a.trace + step0 + done - 1, sizeof(float),
-                       hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       return GS2D_EHIP;
     sticky = (uint32_t)misc_host[MISC_STICKY];
+    std::memcpy(&last_loss, &misc_host[MISC_LAST_LOSS], sizeof(float));
+    step0 = misc_host[MISC_STEP] - opts.iters;
+    bad_trace = step0 < 0 || misc_host[MISC_STEP] >= a.trace_len;
   }
   while (done < opts.iters) {
     const int k = std::min(opts.check_every, opts.iters - done);
@@ -475,6 +485,7 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
     stats->rebins = misc_host[MISC_REBINS];
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
+  if (bad_trace) return GS2D_EINVAL;
   if (sticky & STATUS_STALLED) return GS2D_EHIP;  // a device-side wait ran out
   return (sticky & STATUS_OVERFLOW) ? GS2D_EOVERFLOW : GS2D_OK;
 }

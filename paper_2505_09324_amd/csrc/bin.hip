@@ -244,9 +244,10 @@ k_scatter_wide(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
 // ever held by a running block and emission waits for nothing, so the
 // scatter's wait ends however many blocks are resident at once; it is also
 // bounded (about 0.5 s), after which the block records STATUS_STALLED and
-// skips its part, leaving the previous lists in place.  Each block's writes
-// are made visible device-wide (every thread's release fence) before its
-// chunk is counted, and read after an acquire fence.  The last block to
+// skips its part, leaving the previous lists in place.  An emission block's
+// writes are released device-wide (a barrier, then one thread's release
+// fence) before its chunk is counted, and a scatter block acquires them (one
+// thread's acquire fence, then a barrier).  The last block to
 // finish returns the three counters to zero.  It does not tick the step
 // (the caller's raster does, so that the early return is a single load).
 __global__ void __launch_bounds__(WIDE_SCATTER)
@@ -287,9 +288,11 @@ k_bin_lazy_wide(int N, int TX, int nbp, int nbw, int max_pairs, int D, int bits,
                                   offsets, ka,
                     hist + (size_t)t * D, hist + WIDE_PART_ROWS + (size_t)t * (WIDE_SPLIT - 1) * D,
                     *reinterpret_cast<EmitLds *>(raw));
-    __threadfence();  // release this thread's writes
     __syncthreads();
-    if (tid == 0) atomicAdd(ctr + MISC_EMITTED, 1u);
+    if (tid == 0) {
+      __threadfence();  // release the block's writes (after the barrier: cumulative)
+      atomicAdd(ctr + MISC_EMITTED, 1u);
+    }
   } else {  // scatter of part (t - nbw) % WIDE_SPLIT of chunk (t - nbw) / WIDE_SPLIT
     if (tid == 0) {
       int go = 1;
@@ -303,11 +306,11 @@ k_bin_lazy_wide(int N, int TX, int nbp, int nbw, int max_pairs, int D, int bits,
           break;
         }
       }
+      __threadfence();  // acquire the emitted keys and histograms (for the block: the barrier)
       s_go = go;
     }
     __syncthreads();
     if (s_go) {
-      __threadfence();  // acquire the emitted keys and histograms
       const int s = t - nbw;
       scatter_chunk_wide(ka, kb, nbw, nbp, s / WIDE_SPLIT, s % WIDE_SPLIT, D, bits,
                          misc[MISC_N_PAIRS], n_tiles, bsum, bcull, hist, tile_start,
@@ -358,15 +361,6 @@ __global__ void __launch_bounds__(256)
 k_tile_ranges(const uint32_t *__restrict__ keys, const int *__restrict__ misc, int n_tiles,
               int *__restrict__ tile_start) {
   tile_ranges(keys, misc[MISC_N_PAIRS], n_tiles, tile_start);
-}
-
-__global__ void k_mark_stale(int *__restrict__ misc) {
-  if (threadIdx.x == 0) misc[MISC_STALE] = 1;
-}
-
-hipError_t launch_mark_bins_stale(const Layout &L, void *ws, hipStream_t st) {
-  hipLaunchKernelGGL(k_mark_stale, dim3(1), dim3(64), 0, st, at<int>(ws, L.misc));
-  return hipGetLastError();
 }
 
 hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, void *ws,

@@ -25,6 +25,8 @@ enum MiscSlot : int {
   MISC_TICKET = 6,    // lazy rebuild: roles taken (k_bin_lazy_wide), 0 between launches
   MISC_EMITTED = 7,   // lazy rebuild: chunks emitted, 0 between launches
   MISC_FINISHED = 8,  // lazy rebuild: blocks done, 0 between launches
+  MISC_STEP = 9,      // the fitting loop's last Adam step: its step count ...
+  MISC_LAST_LOSS = 10,  // ... and the loss it recorded (FP32 bits)
   MISC_COUNT = 64
 };
 
@@ -151,7 +153,7 @@ inline T *at(void *ws, size_t off) {
 // every Gaussian's 3-sigma box grown by `skin` pixels, and rebuilt only when
 // misc[MISC_STALE] is set: by the projection when some Gaussian's exact tile
 // rectangle has left the rectangle its keys were built from (or it is
-// culled and still has keys), or by launch_mark_bins_stale.  Otherwise the
+// culled and still has keys), or by launch_fit_begin.  Otherwise the
 // one kernel that emits and scatters returns at once and the lists of an
 // earlier iteration, a superset of the exact ones in the same (tile, index)
 // order, stay in use; the raster's exact per-pixel cutoff makes the render
@@ -160,8 +162,6 @@ inline T *at(void *ws, size_t off) {
 hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, void *ws,
                           hipStream_t st, int *step_tick = nullptr,
                           const PendingAdam *adam = nullptr, float skin = 0.f);
-// Lazy binning: force a rebuild at the next binning.
-hipError_t launch_mark_bins_stale(const Layout &L, void *ws, hipStream_t st);
 
 // Stable LSD radix sort of keys on bits [16, 16 + 8*passes) with G sort
 // blocks; misc[0] holds the key count; hist holds RADIX * G words.
@@ -190,13 +190,14 @@ hipError_t launch_count_pairs(const Layout &L, void *ws, unsigned long long *out
 // Optimiser (adam.hip).  step[0] must already hold this step's t (>= 1):
 // either launch_step_tick or the binning's tick has run before.
 // loss_part/loss_trace may be NULL; when given, the kernel also reduces the
-// per-tile loss partials into loss_trace[t - 1].
+// per-tile loss partials into loss_trace[t - 1], and with report also
+// writes report[0] = t and report[1] = that loss (FP32 bits).
 hipError_t launch_step_tick(int32_t *step, hipStream_t st);
 hipError_t launch_adam(int N, float *xy, float *chol, float *rgb, float *g_xy, float *g_chol,
                        float *g_rgb, float *m, float *v, int32_t *step, const gs2d_adam_cfg &cfg,
                        const uint8_t *active, int zero_grads, const float *loss_part,
                        int n_loss_part, float loss_scale, float *loss_trace, int trace_len,
-                       hipStream_t st);
+                       hipStream_t st, int32_t *report = nullptr);
 
 hipError_t launch_fill_zero(float *p, size_t n, hipStream_t st);
 
@@ -209,6 +210,10 @@ hipError_t launch_quantise(int N, const float *xy, const float *chol, const floa
                            hipStream_t st);
 size_t quantise_workspace_bytes(int N);
 hipError_t launch_fill_zero_u32(uint32_t *p, size_t n, hipStream_t st);
+// Start of a fitting call: misc zeroed but misc[MISC_STALE] = stale, and
+// grads[0, n_grads) zeroed, in one launch.
+hipError_t launch_fit_begin(int32_t *misc, float *grads, size_t n_grads, bool stale,
+                            hipStream_t st);
 
 // ---- device helpers ----
 

@@ -184,6 +184,34 @@ def test_fit_frame_stops_at_psnr_and_flags_overflow():
     assert st2.iters_run == 20  # no target: the chunks run back to back, all of them
 
 
+def test_fit_frame_rejects_a_short_trace():
+    """trace_len <= step[0] + iters: with a PSNR target the call returns
+    GS2D_EINVAL before any work; without one it learns step[0] only when the
+    work has run, returns GS2D_EINVAL then, and writes no entry past
+    trace_len (the kernels bound the index)."""
+    print("fit short trace", flush=True)
+    frame, _ = synth.make_frame(96, 64, seed=101)
+    xy, chol, rgb = synth.random_gaussians(200, 96, 64, seed=102)
+    N = 200
+    f = GpuFrame(96, 64, N, 16)
+    buf = torch.full((64,), -7.0, device=DEV)
+    trace = buf[:8]
+    for target in (12.0, 0.0):
+        P = [dev(xy), dev(chol), dev(rgb)]
+        M = torch.zeros(8 * N, device=DEV)
+        V = torch.zeros(8 * N, device=DEV)
+        step = torch.full((1,), 5, dtype=torch.int32, device=DEV)
+        opts = _lib.fit_opts(10, check_every=4, psnr_target=target, cfg=_lib.adam_cfg(LR))
+        st = _lib.fit_frame(f.shape, dev(frame), *P, M, V, step, trace, f.ws, opts, check=False)
+        torch.cuda.synchronize()
+        assert st.code == _lib.GS2D_EINVAL, (target, st.code)
+        assert np.all(host(buf)[8:] == -7.0)
+        if target > 0:
+            assert int(step.item()) == 5 and np.array_equal(host(P[0]), xy)
+        else:
+            assert int(step.item()) == 15 and np.all(host(buf)[5:8] > 0)
+
+
 def test_fit_frame_1080p_matches_separate_calls():
     """1920x1080 / 30k Gaussians from the content-aware init, in the launch
     configuration the fitting benchmark times (tile 32, 2 px per lane, one
