@@ -25,7 +25,8 @@
  *    when the stream reaches them) unless their comment says that they
  *    synchronise it.
  *  - Every call returns a gs2d_status and never aborts.  Invalid arguments
- *    return GS2D_EINVAL before anything is enqueued.  Conditions found on the
+ *    return GS2D_EINVAL before anything is enqueued (except where a call's
+ *    comment says it checks one after the work).  Conditions found on the
  *    device are reported in the workspace status word (gs2d_bins.status):
  *    bit 0 = tile-pair capacity overflow (lists truncated, no out-of-bounds
  *    write), bit 1 = at least one Gaussian culled (non-finite mean or
