@@ -114,11 +114,16 @@ def test_lazy_lists_across_the_cull_threshold():
     assert np.all(np.isfinite(tr))
 
 
-def test_lazy_fit_follows_the_exact_fit():
-    print("lazy vs exact fit", flush=True)
-    a = _fit(320, 240, 1500, 200, 23, 1.0, chunk=50)
+@pytest.mark.parametrize("skin", [1.0, 0.02])
+def test_lazy_fit_follows_the_exact_fit(skin):
+    """A 0.02-px skin rebuilds the lists every few iterations (66 of 200
+    measured), running the rebuild path of the combined emission/scatter
+    launch (ticketed roles, the handoff between them) many times."""
+    print(f"lazy vs exact fit, skin {skin}", flush=True)
+    a = _fit(320, 240, 1500, 200, 23, skin, chunk=50)
     b = _fit(320, 240, 1500, 200, 23, 0.0, chunk=50)
-    assert b[2].rebins == 0 and a[2].rebins >= 1
+    print(f"rebuilds {a[2].rebins}", flush=True)
+    assert b[2].rebins == 0 and a[2].rebins >= (1 if skin >= 1.0 else 20), a[2].rebins
     # the render at the first iteration uses the same parameters: bit-equal
     assert a[3][0] == b[3][0]
     np.testing.assert_allclose(a[3], b[3], rtol=1e-4)
