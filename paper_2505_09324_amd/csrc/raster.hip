@@ -128,8 +128,9 @@ k_render_fused(FrameArgs f, const float *__restrict__ target, float *__restrict_
     if (f.clear_stale) *f.clear_stale = 0;
     if (f.tick) *f.tick += 1;
   }
-  fused_tile<TILE, PPL>(S, acc, f, (int)blockIdx.x, target, loss_part + blockIdx.x * C::NW,
-                        grad_scale, g_xy, g_chol, g_rgb);
+  fused_tile<TILE, PPL, true, true>(S, acc, f, (int)blockIdx.x, target,
+                                    loss_part + blockIdx.x * C::NW, grad_scale, g_xy, g_chol,
+                                    g_rgb);
 }
 
 // ------------------------------------------------- in-cutoff pair counting --

@@ -393,7 +393,9 @@ __device__ inline void residuals(const float (&a)[PPL][3], const float (&tg)[PPL
   *l = s;
 }
 
-template <int TILE, int PPL, bool EXACT = true>
+// ONE: the caller runs one tile per workgroup (no LDS of an earlier tile to
+// wait for before staging).
+template <int TILE, int PPL, bool EXACT = true, bool ONE = false>
 __device__ inline void fused_tile(Smem<Cfg<TILE, PPL>::NW> &S, float *acc, const FrameArgs &f,
                                   int tile, const float *__restrict__ target,
                                   float *__restrict__ loss_slots, float grad_scale,
@@ -422,7 +424,7 @@ __device__ inline void fused_tile(Smem<Cfg<TILE, PPL>::NW> &S, float *acc, const
   float l;
   if (end - beg <= CH) {
     const int cnt = end - beg;
-    __syncthreads();  // LDS of a previous tile (persistent callers) is free
+    if constexpr (!ONE) __syncthreads();  // LDS of a previous tile (persistent callers) is free
     stage_chunk<TILE, PPL, EXACT>(S, f.keys, beg, cnt, tx, ty, f.W, f.H, f.geom, f.rgb, f.active);
     for (int i = threadIdx.x; i < cnt * 8; i += C::NT) acc[i] = 0.f;
     __syncthreads();
