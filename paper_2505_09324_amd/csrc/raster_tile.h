@@ -323,22 +323,40 @@ __device__ inline void bwd_chunk(const Smem<NW> &S, float *acc, int len, float p
   }
 }
 
-// Flush the LDS accumulators of a chunk to the global gradients.
-template <int NT, int NW>
+// Flush the LDS accumulators of a chunk to the global gradients: thread t
+// adds parameter t % 8 of the chunk's Gaussians t / 8, t / 8 + NT / 8, ...,
+// so the eight parameters of a Gaussian leave from adjacent lanes of one
+// instruction and every wavefront of the tile takes a share.  PIN forms the
+// lane's pointer, stride and scale at the flush rather than letting the
+// compiler hoist them out of a caller's chunk loop, where they would hold
+// registers through the passes (which of the two spills less depends on the
+// caller).
+template <int NT, int NW, bool PIN = false>
 __device__ inline void flush_grads(const Smem<NW> &S, const float *acc, int cnt,
                                    float *__restrict__ g_xy, float *__restrict__ g_chol,
                                    float *__restrict__ g_rgb) {
-  for (int j = threadIdx.x; j < cnt; j += NT) {
-    const int id = S.id[j];
-    const float *a = acc + j * 8;
-    if (a[0] != 0.f) atomicAdd(&g_xy[2 * id + 0], a[0] * INV_H);
-    if (a[1] != 0.f) atomicAdd(&g_xy[2 * id + 1], a[1] * INV_H);
-    if (a[2] != 0.f) atomicAdd(&g_chol[3 * id + 0], a[2] * INV_H15);
-    if (a[3] != 0.f) atomicAdd(&g_chol[3 * id + 1], a[3] * INV_H15);
-    if (a[4] != 0.f) atomicAdd(&g_chol[3 * id + 2], a[4] * INV_H15);
-    if (a[5] != 0.f) atomicAdd(&g_rgb[3 * id + 0], a[5]);
-    if (a[6] != 0.f) atomicAdd(&g_rgb[3 * id + 1], a[6]);
-    if (a[7] != 0.f) atomicAdd(&g_rgb[3 * id + 2], a[7]);
+  static_assert(NT % 8 == 0, "a thread keeps one parameter");
+  int k = threadIdx.x & 7;
+  if constexpr (PIN) asm volatile("" : "+v"(k));
+  float *base;
+  int stride;
+  float scale;
+  if (k < 2) {
+    base = g_xy + k;
+    stride = 2;
+    scale = INV_H;
+  } else if (k < 5) {
+    base = g_chol + (k - 2);
+    stride = 3;
+    scale = INV_H15;
+  } else {
+    base = g_rgb + (k - 5);
+    stride = 3;
+    scale = 1.f;
+  }
+  for (int e = threadIdx.x; e < cnt * 8; e += NT) {
+    const float v = acc[e];
+    if (v != 0.f) atomicAdd(base + stride * S.id[e >> 3], v * scale);
   }
 }
 
@@ -435,7 +453,7 @@ __device__ inline void fused_tile(Smem<Cfg<TILE, PPL>::NW> &S, float *acc, const
     if (f.active) len = keep_active<C::NW>(S, len);
     bwd_chunk<C::NW, PPL, false>(S, acc, len, pxc, pyc0, g);
     __syncthreads();
-    flush_grads<C::NT, C::NW>(S, acc, cnt, g_xy, g_chol, g_rgb);
+    flush_grads<C::NT, C::NW, ONE>(S, acc, cnt, g_xy, g_chol, g_rgb);
     return;
   }
   for (int c = beg; c < end; c += CH) {
@@ -458,7 +476,7 @@ __device__ inline void fused_tile(Smem<Cfg<TILE, PPL>::NW> &S, float *acc, const
     if (f.active) len = keep_active<C::NW>(S, len);
     bwd_chunk<C::NW, PPL, !EXACT>(S, acc, len, pxc, pyc0, g);
     __syncthreads();
-    flush_grads<C::NT, C::NW>(S, acc, cnt, g_xy, g_chol, g_rgb);
+    flush_grads<C::NT, C::NW, ONE>(S, acc, cnt, g_xy, g_chol, g_rgb);
   }
 }
 
