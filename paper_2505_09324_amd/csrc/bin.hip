@@ -245,8 +245,8 @@ k_scatter_wide(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
 // scatter's wait ends however many blocks are resident at once; it is also
 // bounded (about 0.5 s), after which the block records STATUS_STALLED and
 // skips its part, leaving the previous lists in place.  An emission block's
-// writes are released device-wide (a barrier, then one thread's release
-// fence) before its chunk is counted, and a scatter block acquires them (one
+// writes are released device-wide (every wavefront's stores completed, a
+// barrier, then one thread's release fence) before its chunk is counted, and a scatter block acquires them (one
 // thread's acquire fence, then a barrier).  The last block to
 // finish returns the three counters to zero.  It does not tick the step
 // (the caller's raster does, so that the early return is a single load).
@@ -288,6 +288,10 @@ k_bin_lazy_wide(int N, int TX, int nbp, int nbw, int max_pairs, int D, int bits,
                                   offsets, ka,
                     hist + (size_t)t * D, hist + WIDE_PART_ROWS + (size_t)t * (WIDE_SPLIT - 1) * D,
                     *reinterpret_cast<EmitLds *>(raw));
+    // every wavefront's stores have completed before the barrier, so the
+    // one-thread release after it covers them without relying on the order
+    // in which the compute unit issues different wavefronts' requests
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (tid == 0) {
       __threadfence();  // release the block's writes (after the barrier: cumulative)
