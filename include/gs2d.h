@@ -16,7 +16,9 @@
  *    the caller; the library never allocates device memory for them and keeps
  *    no pointer after a call returns (except inside a gs2d_ctx's cached
  *    graphs, below).  Scratch space is one caller-provided workspace of
- *    gs2d_workspace_bytes() bytes (256-byte aligned).
+ *    gs2d_workspace_bytes() bytes (256-byte aligned).  Its contents (tile
+ *    lists, status words) carry over from call to call: a caller may zero
+ *    or reallocate it between calls, but writes nothing else into it.
  *  - Parameter layout (structure of arrays, FP32): xy [N][2] (x, y in pixel
  *    units, origin at the top-left corner of the frame), chol [N][3]
  *    (l1, l2, l3), rgb [N][3].  Images are planar FP32 [3][H][W].
@@ -117,10 +119,12 @@ typedef struct {
    * tiles, not with qat) each Gaussian is binned into the tiles its 3-sigma
    * box grown by bin_skin pixels meets, and the lists are rebuilt only when
    * some Gaussian's exact tile rectangle has left the one it was binned with
-   * (or it became culled), and at the first iteration of every call; in
-   * between the projection still runs every iteration and the lists of the
-   * last rebuild are a superset of the exact ones in the same (tile, index)
-   * order.  Every pixel's sum tests each pair against the cutoff, so the
+   * (or it became culled), and at the first iteration of a call unless the
+   * workspace still holds the complete lists of an earlier lazy fit of the
+   * same shape (no other binning into it since; the call's parameters may
+   * differ, since the test above covers them); in between the projection
+   * still runs every iteration and the lists of the last rebuild are a
+   * superset of the exact ones in the same (tile, index) order.  Every pixel's sum tests each pair against the cutoff, so the
    * render, the loss and the gradients are those of exact binning.
    * gs2d_fit_batch ignores it. */
   float bin_skin;
@@ -132,9 +136,11 @@ typedef struct {
   float final_loss;         /* MSE of the last evaluated iteration          */
   float final_psnr;
   double seconds;           /* host wall time of the call                   */
-  uint32_t status;          /* workspace status word at return              */
-  int32_t n_culled;
-  int32_t rebins;           /* tile-list rebuilds (lazy binning; else 0)    */
+  uint32_t status;          /* OR of the status words of the tile lists used */
+  int32_t n_culled;         /* culled Gaussians when the lists were built   */
+  int32_t rebins;           /* lazy binning: tile-list rebuilds in the call
+                               (0 if it kept the workspace's earlier lists
+                               throughout); 0 without lazy binning          */
 } gs2d_fit_stats;
 
 /* Human-readable name of a status code (static string). */
@@ -271,7 +277,9 @@ int gs2d_ptq(int32_t N, const float *xy, const float *chol, const float *rgb,
  * pointers until it is destroyed or the entry is dropped, so buffers freed
  * and reallocated at the same address are re-used by a cached graph.
  *   gs2d_ctx_create: *out = new context for `device` (GS2D_EINVAL for an
- *   invalid device; the current device is left unchanged).
+ *   invalid device; the current device is left unchanged).  It holds a
+ *   capture stream and 64 bytes of pinned host memory for the status words a
+ *   fitting call reads back.
  *   gs2d_ctx_destroy: frees it (NULL is ignored); no fitting call may be in
  *   flight.
  *   gs2d_ctx_stats: graphs cached now and graphs instantiated so far (each

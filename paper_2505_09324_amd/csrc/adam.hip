@@ -95,25 +95,37 @@ __global__ void k_fill_zero_u32(uint32_t *__restrict__ p, size_t n) {
     p[i] = 0u;
 }
 
-// The start of a fitting call in one launch: misc zeroed except
-// misc[MISC_STALE] = stale (lazy binning: rebuild at the first iteration),
-// and the n_grads gradient accumulators zeroed.
+// The start of a fitting call in one launch, and the n_grads gradient
+// accumulators zeroed.  With lazy binning the lists in the workspace are
+// kept when the stamp shows complete lists of this layout: then the words
+// that describe them (pair count, status, culled count) and the stamp stay,
+// and the call's sticky status starts from their status; otherwise
+// misc[MISC_STALE] = 1 (rebuild at the first iteration).  Every other word
+// is zeroed.
 __global__ void k_fit_begin(int32_t *__restrict__ misc, float *__restrict__ grads, size_t n_grads,
-                            int stale) {
-  if (blockIdx.x == 0 && threadIdx.x < MISC_COUNT)
-    misc[threadIdx.x] = (threadIdx.x == MISC_STALE && stale) ? 1 : 0;
+                            int lazy, uint32_t sig_lo, uint32_t sig_hi) {
+  const int i = (int)threadIdx.x;
+  const bool keep_lists = lazy && (uint32_t)misc[MISC_LISTS_LO] == sig_lo &&
+                          (uint32_t)misc[MISC_LISTS_HI] == sig_hi;
+  if (blockIdx.x == 0 && i < MISC_COUNT && i != MISC_LISTS_LO && i != MISC_LISTS_HI &&
+      i != MISC_N_PAIRS && i != MISC_STATUS && i != MISC_N_CULLED) {
+    int v = 0;
+    if (i == MISC_STALE) v = (lazy && !keep_lists) ? 1 : 0;
+    if (i == MISC_STICKY) v = keep_lists ? misc[MISC_STATUS] : 0;
+    misc[i] = v;
+  }
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n_grads;
        i += (size_t)gridDim.x * blockDim.x)
     grads[i] = 0.f;
 }
 
-hipError_t launch_fit_begin(int32_t *misc, float *grads, size_t n_grads, bool stale,
-                            hipStream_t st) {
+hipError_t launch_fit_begin(int32_t *misc, float *grads, size_t n_grads, bool lazy,
+                            uint32_t sig_lo, uint32_t sig_hi, hipStream_t st) {
   static_assert(MISC_COUNT <= 256, "one block clears misc");
   size_t nb = (n_grads + 255) / 256;
   nb = nb < 1 ? 1 : (nb > 2048 ? 2048 : nb);
   hipLaunchKernelGGL(k_fit_begin, dim3((unsigned)nb), dim3(256), 0, st, misc, grads, n_grads,
-                     stale ? 1 : 0);
+                     lazy ? 1 : 0, sig_lo, sig_hi);
   return hipGetLastError();
 }
 

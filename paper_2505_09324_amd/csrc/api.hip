@@ -71,6 +71,21 @@ bool make_layout(const gs2d_shape &s, Layout *L) {
   L->qws = take(quantise_workspace_bytes(s.N));
   L->misc = take(MISC_COUNT * 4);
   L->total = o;
+  // FNV-1a over the shape and the buffer offsets: the lazy lists' stamp
+  uint64_t h = 1469598103934665603ull;
+  const uint64_t words[] = {(uint64_t)L->W,        (uint64_t)L->H,         (uint64_t)L->N,
+                            (uint64_t)L->T,        (uint64_t)L->max_pairs, (uint64_t)L->ppl,
+                            (uint64_t)L->geom,     (uint64_t)L->brect,     (uint64_t)L->keys_a,
+                            (uint64_t)L->keys_b,   (uint64_t)L->tile_start, (uint64_t)L->misc,
+                            (uint64_t)L->total};
+  for (uint64_t w : words)
+    for (int b = 0; b < 8; ++b) {
+      h ^= (w >> (8 * b)) & 0xFF;
+      h *= 1099511628211ull;
+    }
+  L->sig_lo = (uint32_t)h;
+  L->sig_hi = (uint32_t)(h >> 32);
+  if (L->sig_lo == 0 && L->sig_hi == 0) L->sig_lo = 1;
   return true;
 }
 
@@ -420,15 +435,20 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
   gs2d_ctx *cx = ctx ? ctx : &local;
   const bool use_graph = opts.use_graph != 0;
   int32_t *misc = at<int32_t>(a.ws, L.misc);
-  // misc and the gradients cleared; lazy lists rebuilt at the call's first iteration
+  // misc and the gradients cleared; lazy lists rebuilt at the call's first
+  // iteration unless the workspace holds complete lists of this layout
   const hipError_t e =
       launch_fit_begin(misc, at<float>(a.ws, L.grads), 8 * (size_t)L.N,
-                       L.wide && a.bin_skin > 0.f && a.qat_bits_chol == 0, st);
+                       L.wide && a.bin_skin > 0.f && a.qat_bits_chol == 0, L.sig_lo, L.sig_hi, st);
   if (e != hipSuccess) return GS2D_EHIP;
 
   constexpr int TRACE_PIECE = 256;  // loss values read back per copy
   float trace_host[TRACE_PIECE];
-  int32_t misc_host[16] = {};
+  int32_t misc_local[gs2d_ctx::HOST_MISC_WORDS] = {};
+  // the context's pinned copy when there is one (an asynchronous read-back)
+  int32_t *misc_host = (ctx && ctx->host_misc) ? ctx->host_misc : misc_local;
+  constexpr size_t MISC_BYTES = gs2d_ctx::HOST_MISC_WORDS * sizeof(int32_t);
+  std::memset(misc_host, 0, MISC_BYTES);  // no copy in flight: every call waits for its own
   int done = 0, hit = -1;
   float last_loss = NAN;
   uint32_t sticky = 0;
@@ -441,7 +461,7 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
       if (rc != GS2D_OK) return rc;
       done += k;
     }
-    if (hipMemcpyAsync(misc_host, misc, sizeof(misc_host), hipMemcpyDeviceToHost, st) !=
+    if (hipMemcpyAsync(misc_host, misc, MISC_BYTES, hipMemcpyDeviceToHost, st) !=
             hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       return GS2D_EHIP;
@@ -454,7 +474,7 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
     const int k = std::min(opts.check_every, opts.iters - done);
     int rc = run_chunk(cx, use_graph, L, a, k, st, true);
     if (rc != GS2D_OK) return rc;
-    if (hipMemcpyAsync(misc_host, misc, sizeof(misc_host), hipMemcpyDeviceToHost, st) !=
+    if (hipMemcpyAsync(misc_host, misc, MISC_BYTES, hipMemcpyDeviceToHost, st) !=
         hipSuccess)
       return GS2D_EHIP;
     for (int i0 = 0; i0 < k; i0 += TRACE_PIECE) {

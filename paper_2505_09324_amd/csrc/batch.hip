@@ -280,7 +280,8 @@ k_b_render_persistent(BatchRaster a) {
     fa.tile_start = a.tile_start + d.tile_off + f;
     fa.rgb = a.rgb + 3 * d.g_off;
     fa.active = nullptr;
-    fa.clear_stale = nullptr;
+    fa.lazy_misc = nullptr;
+    fa.sig_lo = fa.sig_hi = 0;
     fa.tick = nullptr;
     const float gs = (float)(2.0 / (3.0 * (double)d.W * (double)d.H));
     fused_tile<TILE, PPL, false>(S, acc, fa, t, a.targets + d.px_off,

@@ -68,6 +68,7 @@ k_emit_keys(int N, int TX, int nb, int max_pairs, const int4 *__restrict__ rect,
     misc[MISC_STATUS] = (int)st;
     misc[MISC_N_CULLED] = culled;
     misc[MISC_STICKY] |= (int)st;
+    misc[MISC_LISTS_LO] = misc[MISC_LISTS_HI] = 0;  // no longer lazy lists
     if (tick) tick[0] += 1;
   }
   emit_block(blockIdx.x * BIN_BLOCK, N, TX, pre, np, rect, counts, offsets, keys,
@@ -183,24 +184,13 @@ k_adam_project_wide(int N, int TX, int TY, float inv_tile, PendingAdam a,
   block_count_sums<WIDE_PROJ>(v, bsum + blockIdx.x, bcull + blockIdx.x);
 }
 
-// lazy (lazy binning): with the lists still valid (misc[MISC_STALE] == 0)
-// only the step tick runs; a rebuild also records the rectangles it bins in
-// brect and counts itself in misc[MISC_REBINS].
+// Exact (non-lazy) emission of the single-pass path: block 0 also clears
+// the lazy lists' stamp, since these lists replace them.
 __global__ void __launch_bounds__(WIDE_BLOCK)
 k_emit_wide(int N, int TX, int nbp, int max_pairs, int D, const int4 *__restrict__ rect,
             const int *__restrict__ counts, const int *__restrict__ bsum,
             const int *__restrict__ bcull, int *__restrict__ offsets, uint32_t *__restrict__ keys,
-            uint32_t *__restrict__ hist, int *__restrict__ misc, int *__restrict__ tick, int lazy,
-            int4 *__restrict__ brect) {
-  if (lazy) {
-    if (misc[MISC_STALE] == 0) {  // uniform over the grid
-      if (blockIdx.x == 0 && threadIdx.x == 0 && tick) tick[0] += 1;
-      return;
-    }
-    const int n = blockIdx.x * WIDE_BLOCK + (int)threadIdx.x;
-    if (n < N) brect[n] = rect[n];
-    if (blockIdx.x == 0 && threadIdx.x == 0) misc[MISC_REBINS] += 1;
-  }
+            uint32_t *__restrict__ hist, int *__restrict__ misc, int *__restrict__ tick) {
   __shared__ EmitLds E;
   long long pre, end_keys, total;
   int culled;
@@ -215,6 +205,7 @@ k_emit_wide(int N, int TX, int nbp, int max_pairs, int D, const int4 *__restrict
     misc[MISC_STATUS] = (int)st;
     misc[MISC_N_CULLED] = culled;
     misc[MISC_STICKY] |= (int)st;
+    misc[MISC_LISTS_LO] = misc[MISC_LISTS_HI] = 0;  // no longer lazy lists
     if (tick) tick[0] += 1;
   }
   emit_block_wide(blockIdx.x * WIDE_BLOCK, N, TX, pre, end_keys, np, D, rect, counts, offsets,
@@ -226,8 +217,7 @@ __global__ void __launch_bounds__(WIDE_SCATTER)
 k_scatter_wide(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
                const int *__restrict__ misc, int nb, int nbp, int D, int bits, int n_tiles,
                const int *__restrict__ bsum, const int *__restrict__ bcull,
-               const uint32_t *__restrict__ hist, int *__restrict__ tile_start, int lazy) {
-  if (lazy && misc[MISC_STALE] == 0) return;  // the lists are still valid
+               const uint32_t *__restrict__ hist, int *__restrict__ tile_start) {
   __shared__ ScatterLds L;
   scatter_chunk_wide(in, out, nb, nbp, blockIdx.x / WIDE_SPLIT, blockIdx.x % WIDE_SPLIT, D, bits,
                      misc[MISC_N_PAIRS], n_tiles, bsum, bcull, hist, tile_start, L);
@@ -249,7 +239,9 @@ k_scatter_wide(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
 // barrier, then one thread's release fence) before its chunk is counted, and a scatter block acquires them (one
 // thread's acquire fence, then a barrier).  The last block to
 // finish returns the three counters to zero.  It does not tick the step
-// (the caller's raster does, so that the early return is a single load).
+// (the caller's raster does, so that the early return is a single load);
+// the raster also stamps the rebuilt lists as complete (MISC_LISTS_LO/HI)
+// unless a wait ran out.
 __global__ void __launch_bounds__(WIDE_SCATTER)
 k_bin_lazy_wide(int N, int TX, int nbp, int nbw, int max_pairs, int D, int bits, int n_tiles,
                 const int4 *__restrict__ rect, const int *__restrict__ counts,
@@ -400,11 +392,10 @@ hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, v
     }
     hipLaunchKernelGGL(k_emit_wide, dim3(nbw), dim3(WIDE_BLOCK), 0, st, L.N, L.TX, nbp,
                        L.max_pairs, L.D, rect, counts, bsum, bcull, offsets, ka, hist, misc,
-                       step_tick, lazy, brect);
+                       step_tick);
     hipLaunchKernelGGL(k_scatter_wide, dim3(nbw * WIDE_SPLIT), dim3(WIDE_SCATTER), 0, st, ka, kb,
-                       misc, nbw, nbp, L.D,
-                       L.digit_bits, L.n_tiles, bsum, bcull, hist, at<int>(ws, L.tile_start),
-                       lazy);
+                       misc, nbw, nbp, L.D, L.digit_bits, L.n_tiles, bsum, bcull, hist,
+                       at<int>(ws, L.tile_start));
     return hipGetLastError();
   }
   if (adam) {

@@ -13,6 +13,7 @@ gs2d_ctx::~gs2d_ctx() {
   for (Entry &e : graphs)
     if (e.exec) (void)hipGraphExecDestroy(e.exec);
   if (capture) (void)hipStreamDestroy(capture);
+  if (host_misc) (void)hipHostFree(host_misc);
 }
 
 hipError_t gs2d_ctx::graph_for(const gs2d::GraphKey &key,
@@ -74,6 +75,9 @@ extern "C" int gs2d_ctx_create(gs2d_ctx **out, int32_t device) {
     gs2d_ctx *c = new (std::nothrow) gs2d_ctx;
     hipError_t e = c ? hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking)
                      : hipErrorOutOfMemory;
+    if (e == hipSuccess)
+      e = hipHostMalloc(reinterpret_cast<void **>(&c->host_misc),
+                        gs2d_ctx::HOST_MISC_WORDS * sizeof(int32_t), hipHostMallocDefault);
     if (cur != device) (void)hipSetDevice(cur);
     if (e != hipSuccess) {
       delete c;

@@ -27,6 +27,13 @@ enum MiscSlot : int {
   MISC_FINISHED = 8,  // lazy rebuild: blocks done, 0 between launches
   MISC_STEP = 9,      // the fitting loop's last Adam step: its step count ...
   MISC_LAST_LOSS = 10,  // ... and the loss it recorded (FP32 bits)
+  // lazy binning: the layout's signature (Layout::sig_lo, sig_hi) while the
+  // workspace holds complete lazy lists of that layout, built from the
+  // rectangles in brect; 0 once any other binning or a stalled rebuild has
+  // written the lists.  A fitting call then starts from these lists instead
+  // of rebuilding them.
+  MISC_LISTS_LO = 12,
+  MISC_LISTS_HI = 13,
   MISC_COUNT = 64
 };
 
@@ -53,6 +60,7 @@ struct Layout {
   int D;
   size_t geom, rect, brect, counts, offsets, blocks, keys_a, keys_b, hist, tile_start, loss_part,
       grads, qparams, qws, misc, total;
+  uint32_t sig_lo, sig_hi;  // non-zero 64-bit signature of the shape and the offsets above
   // the buffer holding the sorted keys after all passes
   size_t keys_sorted() const { return (sort_passes & 1) ? keys_b : keys_a; }
 };
@@ -153,12 +161,14 @@ inline T *at(void *ws, size_t off) {
 // every Gaussian's 3-sigma box grown by `skin` pixels, and rebuilt only when
 // misc[MISC_STALE] is set: by the projection when some Gaussian's exact tile
 // rectangle has left the rectangle its keys were built from (or it is
-// culled and still has keys), or by launch_fit_begin.  Otherwise the
+// culled and still has keys), or by launch_fit_begin when the workspace
+// holds no complete lists of this layout (MISC_LISTS_LO/HI).  Otherwise the
 // one kernel that emits and scatters returns at once and the lists of an
 // earlier iteration, a superset of the exact ones in the same (tile, index)
 // order, stay in use; the raster's exact per-pixel cutoff makes the render
-// identical.  The fused raster clears the flag (launch_render_fused).  The
-// lazy path does not tick step_tick: its caller ticks it in the raster.
+// identical.  The fused raster clears the flag and stamps a rebuild's lists
+// (launch_render_fused); exact binning clears the stamp.  The lazy path
+// does not tick step_tick: its caller ticks it in the raster.
 hipError_t launch_binning(const Layout &L, const float *xy, const float *chol, void *ws,
                           hipStream_t st, int *step_tick = nullptr,
                           const PendingAdam *adam = nullptr, float skin = 0.f);
@@ -178,11 +188,12 @@ hipError_t launch_render_fwd(const Layout &L, void *ws, const float *rgb, const 
 hipError_t launch_render_bwd(const Layout &L, void *ws, const float *rgb, const float *dl_dimg,
                              float *g_xy, float *g_chol, float *g_rgb, hipStream_t st);
 // active (nullable): the backward skips Gaussians with active[n] == 0.
-// clear_stale: the launch also clears misc[MISC_STALE] (lazy binning).
+// lazy: the launch also clears misc[MISC_STALE] and, when it was set,
+// stamps the rebuilt lists (FrameArgs::lazy_misc).
 // tick (nullable): the launch also adds 1 to *tick (the step counter).
 hipError_t launch_render_fused(const Layout &L, void *ws, const float *rgb, const float *target,
                                float *g_xy, float *g_chol, float *g_rgb, hipStream_t st,
-                               const uint8_t *active = nullptr, bool clear_stale = false,
+                               const uint8_t *active = nullptr, bool lazy = false,
                                int32_t *tick = nullptr);
 hipError_t launch_loss_reduce(const Layout &L, void *ws, float *loss, hipStream_t st);
 hipError_t launch_count_pairs(const Layout &L, void *ws, unsigned long long *out, hipStream_t st);
@@ -210,10 +221,13 @@ hipError_t launch_quantise(int N, const float *xy, const float *chol, const floa
                            hipStream_t st);
 size_t quantise_workspace_bytes(int N);
 hipError_t launch_fill_zero_u32(uint32_t *p, size_t n, hipStream_t st);
-// Start of a fitting call: misc zeroed but misc[MISC_STALE] = stale, and
-// grads[0, n_grads) zeroed, in one launch.
-hipError_t launch_fit_begin(int32_t *misc, float *grads, size_t n_grads, bool stale,
-                            hipStream_t st);
+// Start of a fitting call, in one launch: grads[0, n_grads) zeroed and misc
+// reset for the call.  With lazy binning, if the stamp (MISC_LISTS_LO/HI)
+// equals (sig_lo, sig_hi) the workspace's lists are complete lists of this
+// layout and are kept (with their pair count, status and culled count; the
+// call's sticky status starts from that status); else misc[MISC_STALE] = 1.
+hipError_t launch_fit_begin(int32_t *misc, float *grads, size_t n_grads, bool lazy,
+                            uint32_t sig_lo, uint32_t sig_hi, hipStream_t st);
 
 // ---- device helpers ----
 
@@ -276,6 +290,11 @@ struct gs2d_ctx {
   std::vector<Entry> graphs;
   uint64_t clock = 0;
   uint64_t captures = 0;  // graphs instantiated over the context's life
+  // pinned host copy of a fitting call's status words (misc), so that the
+  // read-back at the end of a call is an asynchronous copy; allocated with
+  // the context (a call without a context copies to pageable memory)
+  int32_t *host_misc = nullptr;
+  static constexpr int HOST_MISC_WORDS = 16;
 
   // The executable for `key`: cached, or captured now by running `enqueue`
   // on the capture stream (the least recently used entry is dropped when

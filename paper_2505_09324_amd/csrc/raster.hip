@@ -125,7 +125,12 @@ k_render_fused(FrameArgs f, const float *__restrict__ target, float *__restrict_
   __shared__ Smem<C::NW> S;
   __shared__ float acc[CH * 8];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (f.clear_stale) *f.clear_stale = 0;
+    if (f.lazy_misc && f.lazy_misc[MISC_STALE]) {
+      const bool ok = !(f.lazy_misc[MISC_STICKY] & (int)STATUS_STALLED);
+      f.lazy_misc[MISC_LISTS_LO] = ok ? (int)f.sig_lo : 0;
+      f.lazy_misc[MISC_LISTS_HI] = ok ? (int)f.sig_hi : 0;
+      f.lazy_misc[MISC_STALE] = 0;
+    }
     if (f.tick) *f.tick += 1;
   }
   fused_tile<TILE, PPL, true, true>(S, acc, f, (int)blockIdx.x, target,
@@ -196,7 +201,8 @@ static FrameArgs frame_args(const Layout &L, void *ws, const float *rgb) {
   f.tile_start = at<const int>(ws, L.tile_start);
   f.rgb = rgb;
   f.active = nullptr;
-  f.clear_stale = nullptr;
+  f.lazy_misc = nullptr;
+  f.sig_lo = f.sig_hi = 0;
   f.tick = nullptr;
   return f;
 }
@@ -239,10 +245,14 @@ hipError_t launch_render_bwd(const Layout &L, void *ws, const float *rgb, const 
 
 hipError_t launch_render_fused(const Layout &L, void *ws, const float *rgb, const float *target,
                                float *g_xy, float *g_chol, float *g_rgb, hipStream_t st,
-                               const uint8_t *active, bool clear_stale, int32_t *tick) {
+                               const uint8_t *active, bool lazy, int32_t *tick) {
   FrameArgs f = frame_args(L, ws, rgb);
   f.active = active;
-  if (clear_stale) f.clear_stale = at<int>(ws, L.misc) + MISC_STALE;
+  if (lazy) {
+    f.lazy_misc = at<int>(ws, L.misc);
+    f.sig_lo = L.sig_lo;
+    f.sig_hi = L.sig_hi;
+  }
   f.tick = tick;
   float *lp = at<float>(ws, L.loss_part);
   bool done = false;

@@ -53,9 +53,13 @@ struct FrameArgs {
   // nullable [N]: the fused backward skips Gaussians with active[n] == 0
   // (they are not optimised, Sec. 3.2.C); the forward renders them all
   const uint8_t *active;
-  // nullable: the fused raster sets *clear_stale = 0 (lazy binning: the
-  // binning kernels that read the flag have finished)
-  int *clear_stale;
+  // nullable, lazy binning: the workspace's misc array.  The binning
+  // kernels that read misc[MISC_STALE] have finished when the fused raster
+  // runs; if the flag is set (this iteration rebuilt the lists) the raster
+  // stamps the lists with (sig_lo, sig_hi), or clears the stamp if a
+  // rebuild's wait ran out, then clears the flag.
+  int *lazy_misc;
+  uint32_t sig_lo, sig_hi;
   // nullable: the fused raster adds 1 to *tick (the optimiser's step)
   int *tick;
 };

@@ -137,3 +137,80 @@ def test_bin_skin_is_validated():
     for skin in (-1.0, 65.0, float("nan")):
         with pytest.raises(_lib.GS2DError):
             _fit(W, H, N, 2, 3, skin)
+
+
+def _state(W, H, N, seed):
+    frame, mask = synth.make_frame(W, H, seed=seed)
+    d = synth.init_draws(N, seed=seed + 1)
+    T = torch.from_numpy(frame).to(DEV)
+    xy, chol, rgb = _lib.init_plain(T, dev(mask.astype(np.uint8)), dev(d.pick_roi),
+                                    dev(d.jit_roi), dev(d.pick_out), dev(d.jit_out))
+    m = torch.zeros(8 * N, device=DEV)
+    v = torch.zeros(8 * N, device=DEV)
+    step = torch.zeros(1, dtype=torch.int32, device=DEV)
+    return T, xy, chol, rgb, m, v, step
+
+
+def _call(shape, ws, T, xy, chol, rgb, m, v, step, trace, iters, lr, chunk=None):
+    st = _lib.fit_frame(shape, T, xy, chol, rgb, m, v, step, trace, ws,
+                        _lib.fit_opts(iters, chunk or iters, cfg=_lib.adam_cfg(lr), bin_skin=1.0))
+    torch.cuda.synchronize()
+    return st
+
+
+def test_lazy_lists_carry_over_between_calls():
+    """A call on a workspace that holds complete lazy lists of the same shape
+    starts from them: with the Gaussians all but still, the first call
+    rebuilds once and the second not at all.  Exact binning into the
+    workspace, or another shape over the same memory, makes the next call
+    rebuild.  The lists cover every exact pair after each call."""
+    print("lazy lists across calls", flush=True)
+    W, H, N = 320, 240, 1500
+    T, xy, chol, rgb, m, v, step = _state(W, H, N, 61)
+    shape = _lib.make_shape(W, H, N, 32, px_per_lane=2)
+    ws = _lib.alloc_workspace(shape)
+    ws.zero_()  # no stamp left by an earlier user of this memory
+    trace = torch.zeros(200, device=DEV)
+    still = (1e-7, 1e-7, 1e-7)
+    args = (T, xy, chol, rgb, m, v, step, trace)
+    assert _call(shape, ws, *args, 10, still).rebins == 1
+    assert _call(shape, ws, *args, 10, still).rebins == 0
+    _check_lists(shape, ws, W, H, 32)
+    _lib.project_bin(shape, xy, chol, ws)  # exact lists replace the lazy ones
+    assert _call(shape, ws, *args, 10, still).rebins == 1
+    _check_lists(shape, ws, W, H, 32)
+    n2 = N - 100  # a smaller shape over the same memory
+    shape2 = _lib.make_shape(W, H, n2, 32, px_per_lane=2)
+    a2 = (T, xy[:n2], chol[:n2], rgb[:n2], m[:8 * n2], v[:8 * n2], step, trace)
+    assert _call(shape2, ws, *a2, 10, still).rebins == 1
+    assert _call(shape2, ws, *a2, 10, still).rebins == 0
+    _check_lists(shape2, ws, W, H, 32)
+    assert _call(shape, ws, *args, 10, still).rebins == 1
+    _check_lists(shape, ws, W, H, 32)
+
+
+def test_two_calls_follow_one_call():
+    """40 iterations as two calls on one workspace (the second starting from
+    the first's lists) against one call of 40 on a fresh workspace: the
+    same lists in use at every iteration, so the same loss trace up to the
+    order of the gradients' float atomics."""
+    print("two calls vs one", flush=True)
+    W, H, N = 320, 240, 1500
+    lr = (2e-2, 5e-3, 5e-3)
+    runs = []
+    for split in (True, False):
+        T, xy, chol, rgb, m, v, step = _state(W, H, N, 67)
+        shape = _lib.make_shape(W, H, N, 32, px_per_lane=2)
+        ws = _lib.alloc_workspace(shape)
+        ws.zero_()
+        trace = torch.zeros(48, device=DEV)
+        args = (T, xy, chol, rgb, m, v, step, trace)
+        if split:
+            r = _call(shape, ws, *args, 20, lr).rebins + _call(shape, ws, *args, 20, lr).rebins
+        else:
+            r = _call(shape, ws, *args, 40, lr, chunk=20).rebins
+        _check_lists(shape, ws, W, H, 32)
+        runs.append((host(trace[:40]), r))
+    print(f"rebuilds {runs[0][1]} (two calls), {runs[1][1]} (one call)", flush=True)
+    assert runs[0][0][0] == runs[1][0][0]
+    np.testing.assert_allclose(runs[0][0], runs[1][0], rtol=1e-4)
