@@ -126,7 +126,9 @@ typedef struct {
    * still runs every iteration and the lists of the last rebuild are a
    * superset of the exact ones in the same (tile, index) order.  Every pixel's sum tests each pair against the cutoff, so the
    * render, the loss and the gradients are those of exact binning.
-   * gs2d_fit_batch ignores it. */
+   * gs2d_fit_batch applies it frame by frame (a frame rebuilds its lists
+   * when one of its Gaussians has left its rectangle, and at the first
+   * iteration of every call). */
   float bin_skin;
 } gs2d_fit_opts;
 

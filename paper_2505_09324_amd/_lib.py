@@ -611,6 +611,7 @@ def read_batch_bins(sizes, tile, px_per_lane, f, ws) -> dict:
     return {"n_pairs": n_pairs, "keys": keys,
             "tile_start": _slice(ws, b.tile_start, b.n_tiles + 1, torch.int32).cpu().numpy().astype("int64"),
             "counts": _slice(ws, b.counts, N, torch.int32).cpu().numpy().astype("int64"),
+            "geom": _slice(ws, b.geom, 8 * N, torch.float32).cpu().numpy().reshape(N, 8),
             "status": int(_slice(ws, b.status, 1, torch.int32).item())}
 
 

@@ -40,14 +40,27 @@ struct BFrame {
   long long tile_off;  // first tile of the frame among all tiles of the batch
 };
 
-enum BMisc : int { BM_N_PAIRS = 0, BM_STATUS = 1, BM_N_CULLED = 2, BM_STICKY = 3, BM_STRIDE = 8 };
+// Per-frame status words.  Lazy binning (gs2d_fit_opts.bin_skin > 0):
+// BM_VALID = 1 while the frame's lists hold every pair of the rectangles in
+// brect (set after each iteration by k_b_loss, cleared by the projection
+// when a Gaussian leaves its rectangle; 0 at the start of a call), and
+// BM_REBINS counts the frame's rebuilds.
+enum BMisc : int {
+  BM_N_PAIRS = 0,
+  BM_STATUS = 1,
+  BM_N_CULLED = 2,
+  BM_STICKY = 3,
+  BM_VALID = 4,
+  BM_REBINS = 5,
+  BM_STRIDE = 8
+};
 
 struct BatchLayout {
   int F, T, ppl, passes, sort_blocks, proj_blocks;
   int nw;  // raster wavefronts per tile: loss partials per tile
   long long Ntot, keys_tot, hist_tot, tiles_tot;
-  size_t desc, blk_frame, blk_chunk, pblk_frame, queue, geom, rect, counts, offsets, bsum, bcull,
-      keys_a, keys_b, hist, hist2, tile_start, loss_part, grads, misc, counter, total;
+  size_t desc, blk_frame, blk_chunk, pblk_frame, queue, geom, rect, brect, counts, offsets, bsum,
+      bcull, keys_a, keys_b, hist, hist2, tile_start, loss_part, grads, misc, counter, total;
   std::vector<BFrame> frames;
 };
 
@@ -118,6 +131,7 @@ bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout
   B->queue = take(4 * (size_t)tiles);
   B->geom = take(32 * (size_t)g);
   B->rect = take(16 * (size_t)g);
+  B->brect = take(16 * (size_t)g);  // lazy binning: the rectangles the lists were built from
   B->counts = take(4 * (size_t)g);
   B->offsets = take(4 * ((size_t)g + F));
   B->bsum = take(4 * (size_t)pblocks);
@@ -137,15 +151,34 @@ bool batch_layout(int F, const gs2d_frame *fr, int tile, int ppl_in, BatchLayout
 
 // ------------------------------------------------------------ binning ----
 // Projection blocks never straddle frames: block b covers Gaussians
-// [b - blk_off, ...) * BIN_BLOCK of frame pblk_frame[b].
+// [b - blk_off, ...) * BIN_BLOCK of frame pblk_frame[b].  With skin > 0
+// (lazy binning) the rectangles are grown by the skin and a Gaussian whose
+// exact rectangle has left brect (or that is culled with keys) marks its
+// frame's lists invalid.
 __global__ void __launch_bounds__(BIN_BLOCK)
 k_b_project(const BFrame *__restrict__ D, const int *__restrict__ pblk_frame, int tile,
             const float *__restrict__ xy, const float *__restrict__ chol, float4 *__restrict__ geom,
             int4 *__restrict__ rect, int *__restrict__ counts, int *__restrict__ bsum,
-            int *__restrict__ bcull) {
-  const BFrame d = D[pblk_frame[blockIdx.x]];
+            int *__restrict__ bcull, float skin, const int4 *__restrict__ brect,
+            int *__restrict__ misc) {
+  const int f = pblk_frame[blockIdx.x];
+  const BFrame d = D[f];
   const int c = blockIdx.x - d.blk_off;
   const long long g = d.g_off;
+  if (skin > 0.f) {
+    const int n = c * BIN_BLOCK + (int)threadIdx.x;
+    int v = 0;
+    bool stale = false;
+    if (n < d.N) {
+      const long long i = g + n;
+      v = project_values<true>(n, d.TX, d.TY, 1.0f / (float)tile, xy[2 * i], xy[2 * i + 1],
+                               chol[3 * i], chol[3 * i + 1], chol[3 * i + 2], geom + 2 * g,
+                               rect + g, counts + g, skin, brect + g, &stale);
+    }
+    if (__ballot(stale) && (threadIdx.x & 63) == 0) misc[BM_STRIDE * f + BM_VALID] = 0;
+    block_count_sums<BIN_BLOCK>(v, bsum + blockIdx.x, bcull + blockIdx.x);
+    return;
+  }
   project_block(c * BIN_BLOCK, d.N, d.TX, d.TY, 1.0f / (float)tile, xy + 2 * g, chol + 3 * g,
                 geom + 2 * g, rect + g, counts + g, bsum + blockIdx.x, bcull + blockIdx.x);
 }
@@ -154,16 +187,31 @@ k_b_project(const BFrame *__restrict__ D, const int *__restrict__ pblk_frame, in
 // among the frame's blocks, then the keys and histogram row b of the first
 // radix pass.  The frame's first block publishes its pair
 // count and status; block 0 also advances the step counter (when given) and
-// clears the persistent raster's work counter for this iteration.
+// clears the persistent raster's work counter for this iteration.  lazy:
+// a frame whose lists are still valid keeps them (its blocks return), a
+// rebuild records the rectangles it bins in brect and counts itself.
 __global__ void __launch_bounds__(BIN_BLOCK)
 k_b_emit_keys(const BFrame *__restrict__ D, const int *__restrict__ pblk_frame,
               const int4 *__restrict__ rect, const int *__restrict__ counts,
               const int *__restrict__ bsum, const int *__restrict__ bcull,
               int *__restrict__ offsets, uint32_t *__restrict__ keys, uint32_t *__restrict__ hist,
-              int *__restrict__ misc, int *__restrict__ tick, unsigned *__restrict__ work_counter) {
+              int *__restrict__ misc, int *__restrict__ tick, unsigned *__restrict__ work_counter,
+              int lazy, int4 *__restrict__ brect) {
   const int f = pblk_frame[blockIdx.x];
   const BFrame d = D[f];
   const int c = blockIdx.x - d.blk_off;
+  if (lazy) {
+    if (misc[BM_STRIDE * f + BM_VALID]) {  // uniform over the frame's blocks
+      if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (tick) tick[0] += 1;
+        work_counter[0] = 0u;
+      }
+      return;
+    }
+    const int n = c * BIN_BLOCK + (int)threadIdx.x;
+    if (n < d.N) brect[d.g_off + n] = rect[d.g_off + n];
+    if (c == 0 && threadIdx.x == 0) misc[BM_STRIDE * f + BM_REBINS] += 1;
+  }
   long long pre, total;
   int culled;
   block_sum_prefix(d.nb, c, bsum + d.blk_off, bcull + d.blk_off, &pre, &total, &culled);
@@ -191,8 +239,9 @@ __global__ void __launch_bounds__(SORT_BLOCK)
 k_b_scatter_first(const BFrame *__restrict__ D, const int *__restrict__ pblk_frame,
                   const int *__restrict__ misc, const int *__restrict__ bsum,
                   const int *__restrict__ bcull, const uint32_t *__restrict__ in_all,
-                  uint32_t *__restrict__ out_all, const uint32_t *__restrict__ hist) {
+                  uint32_t *__restrict__ out_all, const uint32_t *__restrict__ hist, int lazy) {
   const int f = pblk_frame[blockIdx.x];
+  if (lazy && misc[BM_STRIDE * f + BM_VALID]) return;  // the frame keeps its lists
   const BFrame d = D[f];
   const int c = blockIdx.x - d.blk_off;
   long long pre, total;
@@ -208,8 +257,9 @@ k_b_scatter_first(const BFrame *__restrict__ D, const int *__restrict__ pblk_fra
 __global__ void __launch_bounds__(SORT_BLOCK)
 k_b_radix_hist(const BFrame *__restrict__ D, const int *__restrict__ blk_frame,
                const int *__restrict__ blk_chunk, const int *__restrict__ misc,
-               const uint32_t *__restrict__ keys, int shift, uint32_t *__restrict__ hist) {
+               const uint32_t *__restrict__ keys, int shift, uint32_t *__restrict__ hist, int lazy) {
   const int f = blk_frame[blockIdx.x], c = blk_chunk[blockIdx.x];
+  if (lazy && misc[BM_STRIDE * f + BM_VALID]) return;
   const BFrame d = D[f];
   chunk_histogram(keys + d.key_off, misc[BM_STRIDE * f + BM_N_PAIRS], d.G, c, shift,
                   hist + d.hist_off);
@@ -219,8 +269,9 @@ __global__ void __launch_bounds__(SORT_BLOCK)
 k_b_radix_scatter(const BFrame *__restrict__ D, const int *__restrict__ blk_frame,
                   const int *__restrict__ blk_chunk, const int *__restrict__ misc,
                   const uint32_t *__restrict__ in_all, uint32_t *__restrict__ out_all, int shift,
-                  const uint32_t *__restrict__ hist) {
+                  const uint32_t *__restrict__ hist, int lazy) {
   const int f = blk_frame[blockIdx.x], c = blk_chunk[blockIdx.x];
+  if (lazy && misc[BM_STRIDE * f + BM_VALID]) return;
   const BFrame d = D[f];
   const int n = misc[BM_STRIDE * f + BM_N_PAIRS];
   const int chunk = chunk_len(n, d.G);
@@ -233,8 +284,9 @@ k_b_radix_scatter(const BFrame *__restrict__ D, const int *__restrict__ blk_fram
 // Grid (RB, F): tile ranges of frame blockIdx.y.
 __global__ void __launch_bounds__(256)
 k_b_tile_ranges(const BFrame *__restrict__ D, const int *__restrict__ misc,
-                const uint32_t *__restrict__ keys_all, int *__restrict__ tile_start_all) {
+                const uint32_t *__restrict__ keys_all, int *__restrict__ tile_start_all, int lazy) {
   const int f = blockIdx.y;
+  if (lazy && misc[BM_STRIDE * f + BM_VALID]) return;
   const BFrame d = D[f];
   tile_ranges(keys_all + d.key_off, misc[BM_STRIDE * f + BM_N_PAIRS], d.n_tiles,
               tile_start_all + d.tile_off + f);
@@ -293,7 +345,8 @@ k_b_render_persistent(BatchRaster a) {
 // One block per frame: loss of this iteration into trace[(t-1) * F + f].
 __global__ void __launch_bounds__(256)
 k_b_loss(const BFrame *__restrict__ D, int F, int nw, const float *__restrict__ loss_part,
-         const int *__restrict__ step, float *__restrict__ trace, int trace_rows) {
+         const int *__restrict__ step, float *__restrict__ trace, int trace_rows,
+         int *__restrict__ lazy_misc) {
   __shared__ double red[4];
   const int f = blockIdx.x;
   const BFrame d = D[f];
@@ -304,6 +357,9 @@ k_b_loss(const BFrame *__restrict__ D, int F, int nw, const float *__restrict__ 
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
+    // lazy binning: the binning kernels are done, so frame f's lists now
+    // hold every pair of the rectangles in brect
+    if (lazy_misc) lazy_misc[BM_STRIDE * f + BM_VALID] = 1;
     const int row = step[0] - 1;
     if (row >= 0 && row < trace_rows)
       trace[(size_t)row * F + f] =
@@ -376,9 +432,13 @@ int batch_grid(const BatchLayout &B) {
   return 0;
 }
 
-// Binning of every frame of the batch.
+// Binning of every frame of the batch; skin > 0: lazy binning (each frame
+// rebuilds its lists only when a Gaussian has left its recorded rectangle,
+// or at the first iteration of a call).
 hipError_t enqueue_batch_binning(const BatchLayout &B, void *ws, const float *xy, const float *chol,
-                                 int *tick, hipStream_t st) {
+                                 int *tick, hipStream_t st, float skin = 0.f) {
+  const int lazy = skin > 0.f ? 1 : 0;
+  int4 *brect = at<int4>(ws, B.brect);
   const BFrame *D = at<const BFrame>(ws, B.desc);
   const int *bf = at<const int>(ws, B.blk_frame), *bc = at<const int>(ws, B.blk_chunk);
   float4 *geom = at<float4>(ws, B.geom);
@@ -391,21 +451,21 @@ hipError_t enqueue_batch_binning(const BatchLayout &B, void *ws, const float *xy
   const int *pf = at<const int>(ws, B.pblk_frame);
   int *bsum = at<int>(ws, B.bsum), *bcull = at<int>(ws, B.bcull);
   hipLaunchKernelGGL(k_b_project, dim3(B.proj_blocks), dim3(BIN_BLOCK), 0, st, D, pf, B.T, xy, chol,
-                     geom, rect, counts, bsum, bcull);
+                     geom, rect, counts, bsum, bcull, skin, brect, misc);
   hipLaunchKernelGGL(k_b_emit_keys, dim3(B.proj_blocks), dim3(BIN_BLOCK), 0, st, D, pf, rect, counts,
-                     bsum, bcull, offsets, ka, hist, misc, tick, counter);
+                     bsum, bcull, offsets, ka, hist, misc, tick, counter, lazy, brect);
   hipLaunchKernelGGL(k_b_scatter_first, dim3(B.proj_blocks), dim3(SORT_BLOCK), 0, st, D, pf, misc,
-                     bsum, bcull, ka, kb, hist);
+                     bsum, bcull, ka, kb, hist, lazy);
   const uint32_t *sorted = kb;
   if (B.passes == 2) {
     hipLaunchKernelGGL(k_b_radix_hist, dim3(B.sort_blocks), dim3(SORT_BLOCK), 0, st, D, bf, bc,
-                       misc, kb, 16 + RADIX_BITS, hist2);
+                       misc, kb, 16 + RADIX_BITS, hist2, lazy);
     hipLaunchKernelGGL(k_b_radix_scatter, dim3(B.sort_blocks), dim3(SORT_BLOCK), 0, st, D, bf, bc,
-                       misc, kb, ka, 16 + RADIX_BITS, hist2);
+                       misc, kb, ka, 16 + RADIX_BITS, hist2, lazy);
     sorted = ka;
   }
   hipLaunchKernelGGL(k_b_tile_ranges, dim3(32, B.F), dim3(256), 0, st, D, misc, sorted,
-                     at<int>(ws, B.tile_start));
+                     at<int>(ws, B.tile_start), lazy);
   return hipGetLastError();
 }
 
@@ -445,14 +505,15 @@ hipError_t enqueue_batch_raster(const BatchLayout &B, void *ws, int grid, const 
 hipError_t enqueue_batch_iteration(const BatchLayout &B, void *ws, int grid, const float *targets,
                                    float *xy, float *chol, float *rgb, float *m, float *v,
                                    int32_t *step, float *trace, int trace_rows,
-                                   const gs2d_adam_cfg &cfg, hipStream_t st) {
+                                   const gs2d_adam_cfg &cfg, hipStream_t st, float skin) {
   float *g = at<float>(ws, B.grads);
   float *g_xy = g, *g_chol = g + 2 * B.Ntot, *g_rgb = g + 5 * B.Ntot;
-  hipError_t e = enqueue_batch_binning(B, ws, xy, chol, step, st);
+  hipError_t e = enqueue_batch_binning(B, ws, xy, chol, step, st, skin);
   if (e == hipSuccess) e = enqueue_batch_raster(B, ws, grid, rgb, targets, g_xy, g_chol, g_rgb, st);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_b_loss, dim3(B.F), dim3(256), 0, st, at<const BFrame>(ws, B.desc), B.F,
-                       B.nw, at<const float>(ws, B.loss_part), step, trace, trace_rows);
+                       B.nw, at<const float>(ws, B.loss_part), step, trace, trace_rows,
+                       skin > 0.f ? at<int>(ws, B.misc) : nullptr);
     e = hipGetLastError();
   }
   if (e == hipSuccess)
@@ -507,6 +568,7 @@ extern "C" int gs2d_fit_batch(gs2d_ctx *ctx, int32_t n_frames, const gs2d_frame 
     if (!targets || !xy || !chol || !rgb || !m || !v || !step || !loss_trace || !opts)
       return GS2D_EINVAL;
     if (opts->iters < 0 || opts->check_every < 1 || opts->active || opts->qat) return GS2D_EINVAL;
+    if (!(opts->bin_skin >= 0.f && opts->bin_skin <= 64.f)) return GS2D_EINVAL;
     rc = gs2d_ctx_check(ctx);
     if (rc != GS2D_OK) return rc;
     if (stats) {
@@ -517,6 +579,7 @@ extern "C" int gs2d_fit_batch(gs2d_ctx *ctx, int32_t n_frames, const gs2d_frame 
       stats->seconds = 0.0;
       stats->status = 0;
       stats->n_culled = 0;
+      stats->rebins = 0;
     }
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     int32_t step0 = 0;
@@ -545,7 +608,7 @@ extern "C" int gs2d_fit_batch(gs2d_ctx *ctx, int32_t n_frames, const gs2d_frame 
         hipError_t ce = hipSuccess;
         for (int i = 0; i < k && ce == hipSuccess; ++i)
           ce = enqueue_batch_iteration(B, ws, grid, targets, xy, chol, rgb, m, v, step,
-                                       loss_trace, trace_rows, opts->adam, s);
+                                       loss_trace, trace_rows, opts->adam, s, opts->bin_skin);
         return ce;
       };
       if (opts->use_graph) {
@@ -560,6 +623,7 @@ extern "C" int gs2d_fit_batch(gs2d_ctx *ctx, int32_t n_frames, const gs2d_frame 
         key.push_back(key_word(opts->adam.beta1));
         key.push_back(key_word(opts->adam.beta2));
         key.push_back(key_word(opts->adam.eps));
+        key.push_back(key_word(opts->bin_skin));
         hipGraphExec_t x = nullptr;
         if (cx->graph_for(key, enqueue, &x) != hipSuccess || hipGraphLaunch(x, st) != hipSuccess)
           return GS2D_EHIP;
@@ -588,8 +652,12 @@ extern "C" int gs2d_fit_batch(gs2d_ctx *ctx, int32_t n_frames, const gs2d_frame 
       if ((sticky & STATUS_OVERFLOW) || hit >= 0) break;
     }
     if (stats) {
-      int culled = 0;
-      for (int f = 0; f < F; ++f) culled += misc_host[(size_t)BM_STRIDE * f + BM_N_CULLED];
+      int culled = 0, rebins = 0;
+      for (int f = 0; f < F; ++f) {
+        culled += misc_host[(size_t)BM_STRIDE * f + BM_N_CULLED];
+        rebins += misc_host[(size_t)BM_STRIDE * f + BM_REBINS];
+      }
+      stats->rebins = rebins;
       stats->iters_run = done;
       stats->iter_hit_target = hit;
       stats->final_loss = (float)last_mean;
@@ -634,7 +702,8 @@ extern "C" int gs2d_batch_render_grads(int32_t n_frames, const gs2d_frame *frame
       e = hipMemcpyAsync(one, &h_one, sizeof(int32_t), hipMemcpyHostToDevice, st);
       if (e == hipSuccess) {
         hipLaunchKernelGGL(k_b_loss, dim3(B.F), dim3(256), 0, st, at<const BFrame>(ws, B.desc), B.F,
-                           B.nw, at<const float>(ws, B.loss_part), one, loss_per_frame, 1);
+                           B.nw, at<const float>(ws, B.loss_part), one, loss_per_frame, 1,
+                           nullptr);
         e = hipGetLastError();
       }
       if (e == hipSuccess) e = hipStreamSynchronize(st);  // h_one leaves scope

@@ -123,6 +123,7 @@ def run_batch(n_frames=48, iters=300, seed=400, check_every=50, device="cuda", l
         "batched_seconds": round(t_batch, 3), "sequential_seconds": round(t_seq, 3),
         "mean_final_psnr_batched": round(float(np.mean([psnr(x) for x in final_b])), 3),
         "mean_final_psnr_sequential": round(float(np.mean([psnr(x) for x in final_s])), 3),
+        "batched_tile_list_rebuilds": int(st.rebins),
         "status": int(st.status),
     }
 

@@ -211,3 +211,47 @@ def test_batch_long_lists_every_variant():
             r, want = refs[fi]
             assert abs(float(loss[fi]) - mse(r["img"], fr)) <= loss_bound(r, fr)
             assert_grads_close({"xy": gx[fi], "chol": gc[fi], "rgb": gr[fi]}, want)
+
+
+def test_lazy_batch_fit_follows_the_exact_fit():
+    """Lazy binning frame by frame (a 1-px skin): each frame keeps its tile
+    lists until one of its Gaussians leaves its recorded rectangle.  Against
+    the same fit with the lists rebuilt every iteration the loss traces
+    agree (the first bit for bit), some rebuilds are skipped, and after the
+    fit every frame's lists still hold every exact (tile, Gaussian) pair of
+    its last projection, in (tile, index) order."""
+    print("lazy batch fit", flush=True)
+    from test_gpu_lazy_bins import _exact_rects
+    sizes = SMALL
+    frames, params, targets, cat = _batch_inputs(sizes, 650)
+    Nt = sum(n for _, _, n in sizes)
+    T, ppl, iters = 16, 1, 40
+    runs = []
+    for skin in (1.0, 0.0):
+        ws = torch.empty(_lib.batch_workspace_bytes(sizes, T, ppl), dtype=torch.uint8, device=DEV)
+        P = [dev(c) for c in cat]
+        m = torch.zeros(8 * Nt, device=DEV)
+        v = torch.zeros(8 * Nt, device=DEV)
+        step = torch.zeros(1, dtype=torch.int32, device=DEV)
+        trace = torch.zeros((iters + 4, len(sizes)), device=DEV)
+        st = _lib.fit_batch(sizes, T, ppl, dev(targets), *P, m, v, step, trace, ws,
+                            _lib.fit_opts(iters, 20, cfg=_lib.adam_cfg((2e-2, 5e-3, 5e-3)),
+                                          bin_skin=skin))
+        assert st.code == 0 and st.iters_run == iters
+        runs.append((host(trace[:iters]), st.rebins, ws))
+    (ta, ra, ws), (tb, rb, _) = runs
+    print(f"rebuilds {ra} of {iters * len(sizes)} frame-iterations", flush=True)
+    assert rb == 0 and len(sizes) <= ra < iters * len(sizes)
+    np.testing.assert_array_equal(ta[0], tb[0])
+    np.testing.assert_allclose(ta, tb, rtol=1e-4)
+    for f, (w, h, n) in enumerate(sizes):
+        b = _lib.read_batch_bins(sizes, T, ppl, f, ws)
+        keys = b["keys"].astype(np.int64)
+        assert np.all(np.diff(keys) > 0)
+        np.testing.assert_array_equal(
+            b["tile_start"], np.searchsorted(keys >> 16, np.arange(len(b["tile_start"]))))
+        rc, off = _exact_rects(b["geom"], w, h, T)
+        TX = (w + T - 1) // T
+        need = [((ty * TX + tx) << 16) | i for i in np.nonzero(~off)[0]
+                for ty in range(rc[i, 1], rc[i, 3] + 1) for tx in range(rc[i, 0], rc[i, 2] + 1)]
+        assert np.setdiff1d(np.array(need, np.int64), keys).size == 0, f"frame {f}"
