@@ -130,6 +130,13 @@ typedef struct {
    * when one of its Gaussians has left its rectangle, and at the first
    * iteration of every call). */
   float bin_skin;
+  /* gs2d_fit_batch's raster launch: 0 = one workgroup per (frame, tile)
+   * item of the frame-area-ordered queue, with exact block masks (the
+   * faster, default); 1 = one persistent launch of the device's resident
+   * capacity whose workgroups pop the items from that queue with one
+   * atomic each (box masks: the exact ones do not fit its registers).
+   * Ignored by gs2d_fit_frame. */
+  int32_t batch_persistent;
 } gs2d_fit_opts;
 
 typedef struct {
@@ -440,9 +447,10 @@ int gs2d_init_superpixel(int32_t W, int32_t H, const float *target, const uint8_
  * f-th slices of the concatenated xy [sum N][2], chol [sum N][3],
  * rgb [sum N][3], and its Adam moments the matching slices of m, v laid out
  * as [xy 2*sum N | chol 3*sum N | rgb 3*sum N].  Each iteration runs the
- * per-frame binning for all frames, ONE persistent raster launch that pulls
- * (frame, tile) work items (largest frames first) through an atomic
- * counter, and one Adam launch over all parameters.  Every frame's tile
+ * per-frame binning for all frames, ONE raster launch over the (frame,
+ * tile) work items, largest frames first (one workgroup per item, or with
+ * gs2d_fit_opts.batch_persistent a resident grid that pulls the items
+ * through an atomic counter), and one Adam launch over all parameters.  Every frame's tile
  * lists and image are those of the one-frame path.  `tile` and
  * `px_per_lane` are as in gs2d_shape and apply to all frames; each frame's
  * pair capacity is max(65536, 16 N + 4 tiles). */
@@ -466,7 +474,7 @@ int gs2d_fit_batch(gs2d_ctx *ctx, int32_t n_frames, const gs2d_frame *frames, in
                    void *ws, size_t ws_bytes, const gs2d_fit_opts *opts, gs2d_fit_stats *stats,
                    void *stream);
 
-/* Binning and one persistent fused raster pass of a batch without an
+/* Binning and one fused raster pass (one workgroup per item) of a batch without an
  * optimiser step: gradients of every frame's MSE are ADDED to g_* (same
  * layout as the parameters), loss_per_frame [n_frames] (nullable) receives
  * each frame's MSE.  Synchronises `stream`. */
@@ -482,8 +490,8 @@ int gs2d_batch_bins_view(int32_t n_frames, const gs2d_frame *frames, int32_t til
                          int32_t px_per_lane, int32_t f, void *ws, size_t ws_bytes,
                          gs2d_bins *out);
 
-/* Autotuner for a batch: times `reps` rounds of batched binning + persistent
- * raster for each candidate (cand_tile[i], cand_ppl[i]) with HIP events,
+/* Autotuner for a batch: times `reps` rounds of batched binning + fused
+ * raster (one workgroup per item) for each candidate (cand_tile[i], cand_ppl[i]) with HIP events,
  * writes the mean ms per round to out_ms[i] and the fastest index to *best.
  * ws must be large enough for every candidate; grad_scratch holds
  * 8 * sum(N) floats (overwritten with accumulated garbage gradients). */

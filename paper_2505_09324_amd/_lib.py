@@ -45,7 +45,7 @@ class QuantCfg(ctypes.Structure):
 class FitOpts(ctypes.Structure):
     _fields_ = [("iters", c_int32), ("check_every", c_int32), ("psnr_target", c_float),
                 ("use_graph", c_int32), ("adam", AdamCfg), ("active", c_void_p),
-                ("qat", POINTER(QuantCfg)), ("bin_skin", c_float)]
+                ("qat", POINTER(QuantCfg)), ("bin_skin", c_float), ("batch_persistent", c_int32)]
 
 
 class FitStats(ctypes.Structure):
@@ -323,13 +323,16 @@ def adam_step(xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg: AdamCfg, acti
 
 
 def fit_opts(iters, check_every=50, psnr_target=0.0, use_graph=True, cfg=None,
-             active=None, qat=None, bin_skin=1.0) -> FitOpts:
+             active=None, qat=None, bin_skin=1.0, batch_persistent=False) -> FitOpts:
     """Fitting options; active: [N] uint8 device tensor (only Gaussians with
     a non-zero flag are optimised) or None; qat: (bits_chol, bits_rgb) for
     quantisation-aware fitting, or None; bin_skin: lazy tile binning margin
-    in pixels (0: rebuild the lists every iteration)."""
+    in pixels (0: rebuild the lists every iteration); batch_persistent: the
+    batched fit's raster as one persistent work-queue launch instead of one
+    workgroup per (frame, tile)."""
     o = FitOpts(int(iters), int(check_every), float(psnr_target), int(bool(use_graph)),
-                cfg if cfg is not None else adam_cfg(), None, None, float(bin_skin))
+                cfg if cfg is not None else adam_cfg(), None, None, float(bin_skin),
+                int(bool(batch_persistent)))
     if active is not None:
         o.active = _ptr(active, "active", torch.uint8)
         o._active_ref = active  # keep the tensor alive with the options

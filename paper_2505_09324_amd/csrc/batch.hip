@@ -6,10 +6,13 @@
 //    emission, the first radix pass over each emission block's keys, a
 //    block table mapping the second pass's blocks to (frame, key chunk),
 //    and a (block, frame) grid for the tile ranges;
-//  - the raster is ONE persistent launch per iteration: a grid sized to the
-//    device's resident capacity pulls (frame, tile) work items from a queue
-//    through an atomic counter, largest frames first, and runs the same
-//    fused forward + loss + backward tile code as the one-frame kernel;
+//  - the raster is ONE launch per iteration over a queue of (frame, tile)
+//    work items, largest frames first, running the same fused forward +
+//    loss + backward tile code as the one-frame kernel: by default one
+//    workgroup per item in queue order (the one-frame kernel's single-tile
+//    path with exact block masks), or (gs2d_fit_opts.batch_persistent) a
+//    grid sized to the device's resident capacity that pulls the items
+//    through an atomic counter;
 //  - Adam runs over the concatenated parameters of all frames; a per-frame
 //    reduction writes each frame's loss into its column of the trace.
 // Keys, geometry and tile lists stay frame-local (16-bit Gaussian index,
@@ -342,6 +345,36 @@ k_b_render_persistent(BatchRaster a) {
   }
 }
 
+// One workgroup per queue item (the queue's order is the dispatch order):
+// the one-frame kernel's single-tile path, exact block masks included.
+template <int TILE, int PPL>
+__global__ void __launch_bounds__((Cfg<TILE, PPL>::NT)) GS2D_RASTER_OCCUPANCY
+k_b_render_grid(BatchRaster a) {
+  using C = Cfg<TILE, PPL>;
+  __shared__ Smem<C::NW> S;
+  __shared__ float acc[CH * 8];
+  const uint32_t q = a.queue[blockIdx.x];
+  const int f = (int)(q >> 16), t = (int)(q & 0xFFFFu);
+  const BFrame d = a.D[f];
+  FrameArgs fa;
+  fa.W = d.W;
+  fa.H = d.H;
+  fa.TX = d.TX;
+  fa.geom = a.geom + 2 * d.g_off;
+  fa.keys = a.keys + d.key_off;
+  fa.tile_start = a.tile_start + d.tile_off + f;
+  fa.rgb = a.rgb + 3 * d.g_off;
+  fa.active = nullptr;
+  fa.lazy_misc = nullptr;
+  fa.sig_lo = fa.sig_hi = 0;
+  fa.tick = nullptr;
+  const float gs = (float)(2.0 / (3.0 * (double)d.W * (double)d.H));
+  fused_tile<TILE, PPL, true, true>(S, acc, fa, t, a.targets + d.px_off,
+                                    a.loss_part + (d.tile_off + t) * C::NW, gs,
+                                    a.g_xy + 2 * d.g_off, a.g_chol + 3 * d.g_off,
+                                    a.g_rgb + 3 * d.g_off);
+}
+
 // One block per frame: loss of this iteration into trace[(t-1) * F + f].
 __global__ void __launch_bounds__(256)
 k_b_loss(const BFrame *__restrict__ D, int F, int nw, const float *__restrict__ loss_part,
@@ -473,9 +506,11 @@ const uint32_t *batch_sorted_keys(const BatchLayout &B, void *ws) {
   return at<const uint32_t>(ws, (B.passes & 1) ? B.keys_b : B.keys_a);
 }
 
+// The fused raster of every (frame, tile) item: one workgroup per item, or
+// with `persistent` a grid of `grid` workgroups popping the items.
 hipError_t enqueue_batch_raster(const BatchLayout &B, void *ws, int grid, const float *rgb,
                                 const float *targets, float *g_xy, float *g_chol, float *g_rgb,
-                                hipStream_t st) {
+                                hipStream_t st, bool persistent = false) {
   BatchRaster a;
   a.D = at<const BFrame>(ws, B.desc);
   a.queue = at<const uint32_t>(ws, B.queue);
@@ -493,8 +528,12 @@ hipError_t enqueue_batch_raster(const BatchLayout &B, void *ws, int grid, const 
   bool done = false;
 #define CASE(TT, PP)                                                                          \
   if (!done && B.T == TT && B.ppl == PP) {                                                    \
-    hipLaunchKernelGGL((k_b_render_persistent<TT, PP>), dim3(grid), dim3(Cfg<TT, PP>::NT), 0, \
-                       st, a);                                                                \
+    if (persistent)                                                                          \
+      hipLaunchKernelGGL((k_b_render_persistent<TT, PP>), dim3(grid), dim3(Cfg<TT, PP>::NT),   \
+                         0, st, a);                                                           \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_b_render_grid<TT, PP>), dim3(a.n_items), dim3(Cfg<TT, PP>::NT), 0, \
+                         st, a);                                                              \
     done = true;                                                                              \
   }
   CASE(8, 1) CASE(16, 1) CASE(16, 2) CASE(32, 1) CASE(32, 2) CASE(32, 4)
@@ -505,11 +544,13 @@ hipError_t enqueue_batch_raster(const BatchLayout &B, void *ws, int grid, const 
 hipError_t enqueue_batch_iteration(const BatchLayout &B, void *ws, int grid, const float *targets,
                                    float *xy, float *chol, float *rgb, float *m, float *v,
                                    int32_t *step, float *trace, int trace_rows,
-                                   const gs2d_adam_cfg &cfg, hipStream_t st, float skin) {
+                                   const gs2d_adam_cfg &cfg, hipStream_t st, float skin,
+                                   bool persistent) {
   float *g = at<float>(ws, B.grads);
   float *g_xy = g, *g_chol = g + 2 * B.Ntot, *g_rgb = g + 5 * B.Ntot;
   hipError_t e = enqueue_batch_binning(B, ws, xy, chol, step, st, skin);
-  if (e == hipSuccess) e = enqueue_batch_raster(B, ws, grid, rgb, targets, g_xy, g_chol, g_rgb, st);
+  if (e == hipSuccess)
+    e = enqueue_batch_raster(B, ws, grid, rgb, targets, g_xy, g_chol, g_rgb, st, persistent);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_b_loss, dim3(B.F), dim3(256), 0, st, at<const BFrame>(ws, B.desc), B.F,
                        B.nw, at<const float>(ws, B.loss_part), step, trace, trace_rows,
@@ -608,7 +649,8 @@ extern "C" int gs2d_fit_batch(gs2d_ctx *ctx, int32_t n_frames, const gs2d_frame 
         hipError_t ce = hipSuccess;
         for (int i = 0; i < k && ce == hipSuccess; ++i)
           ce = enqueue_batch_iteration(B, ws, grid, targets, xy, chol, rgb, m, v, step,
-                                       loss_trace, trace_rows, opts->adam, s, opts->bin_skin);
+                                       loss_trace, trace_rows, opts->adam, s, opts->bin_skin,
+                                       opts->batch_persistent != 0);
         return ce;
       };
       if (opts->use_graph) {
@@ -624,6 +666,7 @@ extern "C" int gs2d_fit_batch(gs2d_ctx *ctx, int32_t n_frames, const gs2d_frame 
         key.push_back(key_word(opts->adam.beta2));
         key.push_back(key_word(opts->adam.eps));
         key.push_back(key_word(opts->bin_skin));
+        key.push_back((uint64_t)(opts->batch_persistent != 0));
         hipGraphExec_t x = nullptr;
         if (cx->graph_for(key, enqueue, &x) != hipSuccess || hipGraphLaunch(x, st) != hipSuccess)
           return GS2D_EHIP;
@@ -672,7 +715,7 @@ extern "C" int gs2d_fit_batch(gs2d_ctx *ctx, int32_t n_frames, const gs2d_frame 
   }
 }
 
-// Binning + persistent raster of a batch (no optimiser step), for
+// Binning + raster (one workgroup per item) of a batch (no optimiser step), for
 // inspection and timing: builds every frame's tile lists and accumulates the
 // gradients of the summed per-frame MSE into g_* (not cleared).
 extern "C" int gs2d_batch_render_grads(int32_t n_frames, const gs2d_frame *frames, int32_t tile,
@@ -743,8 +786,8 @@ extern "C" int gs2d_batch_bins_view(int32_t n_frames, const gs2d_frame *frames, 
   }
 }
 
-// Autotuner: times `reps` rounds of (batched binning + persistent fused
-// raster) for each candidate (tile, px_per_lane) with HIP events and
+// Autotuner: times `reps` rounds of (batched binning + fused raster, one
+// workgroup per item) for each candidate (tile, px_per_lane) with HIP events and
 // returns the mean milliseconds per round in out_ms[i] and the fastest
 // candidate's index in *best.  ws must hold gs2d_batch_workspace_bytes for
 // every candidate; grad_scratch must hold 8 * sum(N) floats.

@@ -255,3 +255,34 @@ def test_lazy_batch_fit_follows_the_exact_fit():
         need = [((ty * TX + tx) << 16) | i for i in np.nonzero(~off)[0]
                 for ty in range(rc[i, 1], rc[i, 3] + 1) for tx in range(rc[i, 0], rc[i, 2] + 1)]
         assert np.setdiff1d(np.array(need, np.int64), keys).size == 0, f"frame {f}"
+
+
+def test_persistent_and_grid_batch_rasters_agree():
+    """The batched fit's two raster launches, one workgroup per (frame, tile)
+    item (exact block masks) and the persistent work-queue grid (box
+    masks): the same loss traces (the first row bit for bit, both summing
+    the same pairs in the same order) and the oracle's first loss."""
+    print("persistent vs grid batch raster", flush=True)
+    sizes = SMALL
+    frames, params, targets, cat = _batch_inputs(sizes, 700)
+    Nt = sum(n for _, _, n in sizes)
+    T, ppl, iters = 32, 2, 12
+    traces = []
+    for persistent in (False, True):
+        ws = torch.empty(_lib.batch_workspace_bytes(sizes, T, ppl), dtype=torch.uint8, device=DEV)
+        P = [dev(c) for c in cat]
+        m = torch.zeros(8 * Nt, device=DEV)
+        v = torch.zeros(8 * Nt, device=DEV)
+        step = torch.zeros(1, dtype=torch.int32, device=DEV)
+        trace = torch.zeros((iters + 4, len(sizes)), device=DEV)
+        st = _lib.fit_batch(sizes, T, ppl, dev(targets), *P, m, v, step, trace, ws,
+                            _lib.fit_opts(iters, 6, cfg=_lib.adam_cfg((2e-2, 5e-3, 5e-3)),
+                                          batch_persistent=persistent))
+        assert st.code == 0 and st.iters_run == iters
+        traces.append(host(trace[:iters]))
+    np.testing.assert_array_equal(traces[0][0], traces[1][0])
+    np.testing.assert_allclose(traces[0], traces[1], rtol=1e-4)
+    for f, (frame, (xy, chol, rgb)) in enumerate(zip(frames, params)):
+        h, w = frame.shape[1:]
+        img = render_box(xy, chol, rgb, h, w, want_bounds=False)["img"]
+        assert float(traces[0][0, f]) == pytest.approx(mse(img, frame), rel=1e-4)
