@@ -121,7 +121,8 @@ typedef struct {
    * some Gaussian's exact tile rectangle has left the one it was binned with
    * (or it became culled), and at the first iteration of a call unless the
    * workspace still holds the complete lists of an earlier lazy fit of the
-   * same shape (no other binning into it since; the call's parameters may
+   * same shape (not truncated at max_pairs, and no other binning into it
+   * since; the call's parameters may
    * differ, since the test above covers them); in between the projection
    * still runs every iteration and the lists of the last rebuild are a
    * superset of the exact ones in the same (tile, index) order.  Every pixel's sum tests each pair against the cutoff, so the

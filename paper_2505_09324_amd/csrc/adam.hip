@@ -97,7 +97,8 @@ __global__ void k_fill_zero_u32(uint32_t *__restrict__ p, size_t n) {
 
 // The start of a fitting call in one launch, and the n_grads gradient
 // accumulators zeroed.  With lazy binning the lists in the workspace are
-// kept when the stamp shows complete lists of this layout: then the words
+// kept when the stamp shows complete lists of this layout that did not
+// overflow the pair capacity: then the words
 // that describe them (pair count, status, culled count) and the stamp stay,
 // and the call's sticky status starts from their status; otherwise
 // misc[MISC_STALE] = 1 (rebuild at the first iteration).  Every other word
@@ -105,8 +106,10 @@ __global__ void k_fill_zero_u32(uint32_t *__restrict__ p, size_t n) {
 __global__ void k_fit_begin(int32_t *__restrict__ misc, float *__restrict__ grads, size_t n_grads,
                             int lazy, uint32_t sig_lo, uint32_t sig_hi) {
   const int i = (int)threadIdx.x;
+  // lists truncated at the pair capacity are never kept
   const bool keep_lists = lazy && (uint32_t)misc[MISC_LISTS_LO] == sig_lo &&
-                          (uint32_t)misc[MISC_LISTS_HI] == sig_hi;
+                          (uint32_t)misc[MISC_LISTS_HI] == sig_hi &&
+                          !(misc[MISC_STATUS] & (int)STATUS_OVERFLOW);
   if (blockIdx.x == 0 && i < MISC_COUNT && i != MISC_LISTS_LO && i != MISC_LISTS_HI &&
       i != MISC_N_PAIRS && i != MISC_STATUS && i != MISC_N_CULLED) {
     int v = 0;

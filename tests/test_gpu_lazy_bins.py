@@ -214,3 +214,22 @@ def test_two_calls_follow_one_call():
     print(f"rebuilds {runs[0][1]} (two calls), {runs[1][1]} (one call)", flush=True)
     assert runs[0][0][0] == runs[1][0][0]
     np.testing.assert_allclose(runs[0][0], runs[1][0], rtol=1e-4)
+
+
+def test_overflowed_lists_are_not_kept():
+    """Lists truncated at the pair capacity are never carried into the next
+    call: with the Gaussians all but still, each call rebuilds exactly once
+    (at its first iteration) and reports the overflow."""
+    print("overflowed lists across calls", flush=True)
+    W, H, N = 128, 128, 500
+    T, xy, chol, rgb, m, v, step = _state(W, H, N, 71)
+    shape = _lib.make_shape(W, H, N, 32, max_pairs=100, px_per_lane=2)
+    ws = _lib.alloc_workspace(shape)
+    ws.zero_()
+    trace = torch.zeros(64, device=DEV)
+    opts = _lib.fit_opts(5, 5, cfg=_lib.adam_cfg((1e-7, 1e-7, 1e-7)), bin_skin=1.0)
+    for _ in range(2):
+        st = _lib.fit_frame(shape, T, xy, chol, rgb, m, v, step, trace, ws, opts, check=False)
+        torch.cuda.synchronize()
+        assert st.code == _lib.GS2D_EOVERFLOW and st.status & _lib.STATUS_OVERFLOW
+        assert st.rebins == 1, st.rebins
