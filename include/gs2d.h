@@ -116,20 +116,20 @@ typedef struct {
   const gs2d_quant_cfg *qat;
   /* Lazy tile binning, 0 <= bin_skin <= 64 pixels; 0: the tile lists are
    * rebuilt every iteration.  With bin_skin > 0 (frames of at most 2048
-   * tiles, not with qat) each Gaussian is binned into the tiles its 3-sigma
-   * box grown by bin_skin pixels meets, and the lists are rebuilt only when
-   * some Gaussian's exact tile rectangle has left the one it was binned with
-   * (or it became culled), and at the first iteration of a call unless the
-   * workspace still holds the complete lists of an earlier lazy fit of the
-   * same shape (not truncated at max_pairs, and no other binning into it
-   * since; the call's parameters may
-   * differ, since the test above covers them); in between the projection
-   * still runs every iteration and the lists of the last rebuild are a
-   * superset of the exact ones in the same (tile, index) order.  Every pixel's sum tests each pair against the cutoff, so the
-   * render, the loss and the gradients are those of exact binning.
-   * gs2d_fit_batch applies it frame by frame (a frame rebuilds its lists
-   * when one of its Gaussians has left its rectangle, and at the first
-   * iteration of every call). */
+   * tiles; with qat, the quantised Gaussians) each Gaussian is binned into
+   * the tiles its 3-sigma box grown by bin_skin pixels meets, and the lists
+   * are rebuilt only when some Gaussian's exact tile rectangle has left the
+   * one it was binned with (or it became culled), and at the first
+   * iteration of a call unless the workspace still holds the complete lists
+   * of an earlier lazy fit of the same shape (not truncated at max_pairs,
+   * and no other binning into it since; the call's parameters may differ,
+   * since the test above covers them).  In between, the projection still
+   * runs every iteration and the lists of the last rebuild are a superset
+   * of the exact ones in the same (tile, index) order.  Every pixel's sum
+   * tests each pair against the cutoff, so the render, the loss and the
+   * gradients are those of exact binning.  gs2d_fit_batch applies it frame
+   * by frame (a frame rebuilds its lists when one of its Gaussians has left
+   * its rectangle, and at the first iteration of every call). */
   float bin_skin;
   /* gs2d_fit_batch's raster launch: 0 = one workgroup per (frame, tile)
    * item of the frame-area-ordered queue, with exact block masks (the

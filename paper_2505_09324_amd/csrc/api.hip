@@ -261,18 +261,24 @@ hipError_t enqueue_iterations(const Layout &L, void *ws, const float *target, fl
   float *g = at<float>(ws, L.grads);
   float *g_xy = g, *g_chol = g + 2 * (size_t)L.N, *g_rgb = g + 5 * (size_t)L.N;
   const float loss_scale = (float)(1.0 / (3.0 * L.W * (double)L.H));
+  // lazy binning on the single-pass path (fit_frame_run forces a rebuild at
+  // the start of a call unless the workspace holds complete lists of this
+  // layout)
+  const float skin = (L.wide && bin_skin > 0.f) ? bin_skin : 0.f;
   if (qat_bits_chol > 0) {
     // quantisation-aware: quantise, bin and render the quantised copy, then
-    // Adam on the FP32 parameters with its gradients (straight through)
+    // Adam on the FP32 parameters with its gradients (straight through); the
+    // lazy lists follow the quantised Gaussians (the raster ticks the step)
     float *q = at<float>(ws, L.qparams);
     float *q_xy = q, *q_chol = q + 2 * (size_t)L.N, *q_rgb = q + 5 * (size_t)L.N;
     hipError_t e = hipSuccess;
     for (int i = 0; i < k && e == hipSuccess; ++i) {
       e = launch_quantise(L.N, xy, chol, rgb, qat_bits_chol, qat_bits_rgb, q_xy, q_chol, q_rgb,
                           nullptr, nullptr, nullptr, at<void>(ws, L.qws), st);
-      if (e == hipSuccess) e = launch_binning(L, q_xy, q_chol, ws, st, step, nullptr);
+      if (e == hipSuccess) e = launch_binning(L, q_xy, q_chol, ws, st, step, nullptr, skin);
       if (e == hipSuccess)
-        e = launch_render_fused(L, ws, q_rgb, target, g_xy, g_chol, g_rgb, st, active);
+        e = launch_render_fused(L, ws, q_rgb, target, g_xy, g_chol, g_rgb, st, active, skin > 0.f,
+                                skin > 0.f ? step : nullptr);
       if (e == hipSuccess)
         e = launch_adam(L.N, xy, chol, rgb, g_xy, g_chol, g_rgb, m, v, step, cfg, active, 1,
                         at<const float>(ws, L.loss_part), L.loss_parts, loss_scale, trace,
@@ -283,10 +289,6 @@ hipError_t enqueue_iterations(const Layout &L, void *ws, const float *target, fl
   const PendingAdam pending{xy,    chol, rgb,  g_xy, g_chol, g_rgb, m,         v,
                             step,  cfg,  at<const float>(ws, L.loss_part), L.loss_parts,
                             loss_scale, trace, trace_len, active};
-  // lazy binning on the single-pass path (fit_frame_run forces a rebuild at
-  // the start of each call: the parameters or the workspace may have
-  // changed since the lists were built)
-  const float skin = (L.wide && bin_skin > 0.f) ? bin_skin : 0.f;
   hipError_t e = hipSuccess;
   for (int i = 0; i < k && e == hipSuccess; ++i) {
     e = launch_binning(L, xy, chol, ws, st, step, i > 0 ? &pending : nullptr, skin);
@@ -439,7 +441,7 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
   // iteration unless the workspace holds complete lists of this layout
   const hipError_t e =
       launch_fit_begin(misc, at<float>(a.ws, L.grads), 8 * (size_t)L.N,
-                       L.wide && a.bin_skin > 0.f && a.qat_bits_chol == 0, L.sig_lo, L.sig_hi, st);
+                       L.wide && a.bin_skin > 0.f, L.sig_lo, L.sig_hi, st);
   if (e != hipSuccess) return GS2D_EHIP;
 
   constexpr int TRACE_PIECE = 256;  // loss values read back per copy

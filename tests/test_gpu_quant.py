@@ -63,14 +63,15 @@ def test_ptq_constant_component_and_fitted_frame():
     np.testing.assert_array_equal(host(got["rgb"]), ref["rgb"])
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_quantisation_aware_fit_follows_the_oracle(use_graph):
+@pytest.mark.parametrize("use_graph,skin", [(True, 1.0), (False, 1.0), (True, 0.0)])
+def test_quantisation_aware_fit_follows_the_oracle(use_graph, skin):
     """128x128 / 500 Gaussians, 5-bit Cholesky and colour: the first
     iteration's loss is the oracle's loss at the quantised point (1e-5
     relative), and 10 steps follow the oracle's quantisation-aware loop
     (1e-3 relative; codes of the two trajectories may part at rounding
-    boundaries)."""
-    print(f"qat graph={use_graph}", flush=True)
+    boundaries); with lazy tile lists of the quantised Gaussians (skin 1)
+    and with the lists rebuilt every iteration (skin 0)."""
+    print(f"qat graph={use_graph} skin={skin}", flush=True)
     frame, _ = synth.make_frame(128, 128, seed=101)
     xy, chol, rgb = synth.random_gaussians(500, 128, 128, seed=102)
     N = 500
@@ -81,7 +82,7 @@ def test_quantisation_aware_fit_follows_the_oracle(use_graph):
     trace = torch.zeros(32, device=DEV)
     st = _lib.fit_frame(f.shape, dev(frame), *P, M, V, step, trace, f.ws,
                         _lib.fit_opts(10, 4, use_graph=use_graph, cfg=_lib.adam_cfg(1e-2),
-                                      qat=(5, 5)))
+                                      qat=(5, 5), bin_skin=skin))
     assert st.iters_run == 10
     _, ref = oracle_fit(xy, chol, rgb, frame, 10, lr=1e-2, quant_bits=(5, 5))
     tr = host(trace)[:10]
