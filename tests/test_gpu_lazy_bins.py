@@ -70,6 +70,10 @@ def _fit(W, H, N, iters, seed, skin, lr=(2e-2, 5e-3, 5e-3), init=None, chunk=Non
         xy, chol, rgb = (dev(a) for a in init)
     shape = _lib.make_shape(W, H, N, 32, px_per_lane=2)
     ws = _lib.alloc_workspace(shape)
+    # a recycled block could hold complete lists of this shape from an
+    # earlier test, which the first call would keep (valid, but the rebuild
+    # counts asserted below assume a fresh workspace)
+    ws.zero_()
     m = torch.zeros(8 * N, device=DEV)
     v = torch.zeros(8 * N, device=DEV)
     step = torch.zeros(1, dtype=torch.int32, device=DEV)
