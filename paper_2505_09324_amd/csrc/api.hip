@@ -303,7 +303,13 @@ hipError_t enqueue_iterations(const Layout &L, void *ws, const float *target, fl
   return e;
 }
 
-GraphKey frame_chunk_key(const Layout &L, const FitArgs &a, int k) {
+// The start of a fitting call (launch_fit_begin) on the call's workspace.
+hipError_t enqueue_fit_begin(const Layout &L, const FitArgs &a, hipStream_t st) {
+  return launch_fit_begin(at<int32_t>(a.ws, L.misc), at<float>(a.ws, L.grads), 8 * (size_t)L.N,
+                          L.wide && a.bin_skin > 0.f, L.sig_lo, L.sig_hi, st);
+}
+
+GraphKey frame_chunk_key(const Layout &L, const FitArgs &a, int k, bool first) {
   GraphKey key{1,
                (uint64_t)L.W,
                (uint64_t)L.H,
@@ -330,28 +336,27 @@ GraphKey frame_chunk_key(const Layout &L, const FitArgs &a, int k) {
   key.push_back(key_word(a.cfg.beta1));
   key.push_back(key_word(a.cfg.beta2));
   key.push_back(key_word(a.cfg.eps));
+  key.push_back(first ? 1 : 0);
   return key;
 }
 
 // Enqueue a chunk of k iterations on `st`: the context's cached graph when
 // graphs are used, else direct launches.
 int run_chunk(gs2d_ctx *ctx, bool use_graph, const Layout &L, const FitArgs &a, int k,
-              hipStream_t st, bool launch) {
-  if (!use_graph) {
-    if (!launch) return GS2D_OK;
-    return hip_status(enqueue_iterations(L, a.ws, a.target, a.xy, a.chol, a.rgb, a.m, a.v, a.step,
-                                         a.trace, a.trace_len, a.cfg, a.active, k, st,
-                                         a.qat_bits_chol, a.qat_bits_rgb, a.bin_skin));
-  }
+              hipStream_t st, bool launch, bool first) {
+  // the call's first chunk starts with launch_fit_begin (in its graph: the
+  // call's first submission is then the graph launch alone)
+  auto enqueue = [&](hipStream_t s) {
+    hipError_t e = first ? enqueue_fit_begin(L, a, s) : hipSuccess;
+    if (e == hipSuccess)
+      e = enqueue_iterations(L, a.ws, a.target, a.xy, a.chol, a.rgb, a.m, a.v, a.step, a.trace,
+                             a.trace_len, a.cfg, a.active, k, s, a.qat_bits_chol, a.qat_bits_rgb,
+                             a.bin_skin);
+    return e;
+  };
+  if (!use_graph) return launch ? hip_status(enqueue(st)) : GS2D_OK;
   hipGraphExec_t x = nullptr;
-  hipError_t e = ctx->graph_for(
-      frame_chunk_key(L, a, k),
-      [&](hipStream_t cs) {
-        return enqueue_iterations(L, a.ws, a.target, a.xy, a.chol, a.rgb, a.m, a.v, a.step,
-                                  a.trace, a.trace_len, a.cfg, a.active, k, cs, a.qat_bits_chol,
-                                  a.qat_bits_rgb, a.bin_skin);
-      },
-      &x);
+  hipError_t e = ctx->graph_for(frame_chunk_key(L, a, k, first), enqueue, &x);
   if (e == hipSuccess && launch) e = hipGraphLaunch(x, st);
   return hip_status(e);
 }
@@ -393,11 +398,15 @@ extern "C" int gs2d_fit_prepare(gs2d_ctx *ctx, const gs2d_shape *shape, const fl
                     opts->qat ? opts->qat->bits_chol : 0,
                     opts->qat ? opts->qat->bits_rgb : 0,
                     opts->bin_skin};
+    // the first chunk (with the call's start), the full chunks after it
+    // and the last, shorter one
     const int k0 = std::min(opts->check_every, opts->iters);
-    rc = run_chunk(ctx, true, L, a, k0, nullptr, false);
+    rc = run_chunk(ctx, true, L, a, k0, nullptr, false, true);
+    if (rc == GS2D_OK && opts->iters >= 2 * opts->check_every)
+      rc = run_chunk(ctx, true, L, a, k0, nullptr, false, false);
     const int rem = opts->iters % opts->check_every;
     if (rc == GS2D_OK && opts->iters > opts->check_every && rem != 0)
-      rc = run_chunk(ctx, true, L, a, rem, nullptr, false);
+      rc = run_chunk(ctx, true, L, a, rem, nullptr, false, false);
     return rc;
   } catch (...) {
     return GS2D_EHIP;
@@ -437,12 +446,10 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
   gs2d_ctx *cx = ctx ? ctx : &local;
   const bool use_graph = opts.use_graph != 0;
   int32_t *misc = at<int32_t>(a.ws, L.misc);
-  // misc and the gradients cleared; lazy lists rebuilt at the call's first
-  // iteration unless the workspace holds complete lists of this layout
-  const hipError_t e =
-      launch_fit_begin(misc, at<float>(a.ws, L.grads), 8 * (size_t)L.N,
-                       L.wide && a.bin_skin > 0.f, L.sig_lo, L.sig_hi, st);
-  if (e != hipSuccess) return GS2D_EHIP;
+  // misc and the gradients cleared, lazy lists rebuilt at the call's first
+  // iteration unless the workspace holds complete lists of this layout:
+  // at the head of the first chunk (a call without iterations runs it alone)
+  if (opts.iters == 0 && enqueue_fit_begin(L, a, st) != hipSuccess) return GS2D_EHIP;
 
   constexpr int TRACE_PIECE = 256;  // loss values read back per copy
   float trace_host[TRACE_PIECE];
@@ -459,7 +466,7 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
     // no early stop to check: every chunk back to back, one wait at the end
     while (done < opts.iters) {
       const int k = std::min(opts.check_every, opts.iters - done);
-      const int rc = run_chunk(cx, use_graph, L, a, k, st, true);
+      const int rc = run_chunk(cx, use_graph, L, a, k, st, true, done == 0);
       if (rc != GS2D_OK) return rc;
       done += k;
     }
@@ -474,7 +481,7 @@ int fit_frame_run(gs2d_ctx *ctx, const Layout &L, const FitArgs &a, const gs2d_f
   }
   while (done < opts.iters) {
     const int k = std::min(opts.check_every, opts.iters - done);
-    int rc = run_chunk(cx, use_graph, L, a, k, st, true);
+    int rc = run_chunk(cx, use_graph, L, a, k, st, true, done == 0);
     if (rc != GS2D_OK) return rc;
     if (hipMemcpyAsync(misc_host, misc, MISC_BYTES, hipMemcpyDeviceToHost, st) !=
         hipSuccess)

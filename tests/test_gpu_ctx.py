@@ -55,8 +55,9 @@ def test_context_caches_chunk_graphs_and_uses_the_callers_stream():
                                 trace, f.ws, opts, ctx=ctx)
         assert st.iters_run == 10 and int(step.item()) == 10
         traces.append(host(trace)[:10].copy())
-        # chunks of 4, 4 and 2 iterations: two graphs, captured by the first fit only
-        assert ctx.stats() == (2, 2), ctx.stats()
+        # chunks of 4 (with the call's start), 4 and 2 iterations: three
+        # graphs, captured by the first fit only
+        assert ctx.stats() == (3, 3), ctx.stats()
     for tr in traces:
         np.testing.assert_allclose(tr, ref, rtol=1e-3)
     np.testing.assert_allclose(traces[1], traces[0], rtol=1e-5)
@@ -79,17 +80,18 @@ def test_prepare_instantiates_what_the_fit_replays():
     args = (f.shape, dev(frame), P["xy"], P["chol"], P["rgb"], M, V, step, trace, f.ws)
     opts = _lib.fit_opts(23, check_every=10, cfg=_lib.adam_cfg(LR))
     _lib.fit_prepare(*args, opts, ctx=ctx)
-    assert ctx.stats() == (2, 2)  # chunks of 10 and of the remainder 3
+    # the first chunk of 10 (with the call's start), the next 10 and the remainder 3
+    assert ctx.stats() == (3, 3)
     torch.cuda.synchronize()
     assert int(step.item()) == 0  # nothing ran
     st = _lib.fit_frame(*args, opts, ctx=ctx)
-    assert st.iters_run == 23 and ctx.stats() == (2, 2)
+    assert st.iters_run == 23 and ctx.stats() == (3, 3)
     # another chunk length is another graph
     _lib.fit_frame(*args, _lib.fit_opts(5, check_every=5, cfg=_lib.adam_cfg(LR)), ctx=ctx)
-    assert ctx.stats() == (3, 3)
+    assert ctx.stats() == (4, 4)
     # a different learning rate is baked into the kernels: another graph
     _lib.fit_frame(*args, _lib.fit_opts(5, check_every=5, cfg=_lib.adam_cfg(2e-2)), ctx=ctx)
-    assert ctx.stats() == (4, 4)
+    assert ctx.stats() == (5, 5)
     assert int(step.item()) == 33
 
 
