@@ -448,6 +448,31 @@ def select_changed(shape: Shape, ws, xy, chol, frame, prev, tau, active=None, co
     return active
 
 
+class FitCall:
+    """gs2d_fit_frame with its arguments checked and marshalled once: a
+    fitting loop called again and again with the same buffers (a video
+    encoder, once per frame) pays only the library call each time.  The
+    tensors must stay allocated and unresized, and keep the options, while
+    the object is used; the call runs on the stream current at each call."""
+
+    def __init__(self, shape: Shape, target, xy, chol, rgb, m, v, step, loss_trace, ws,
+                 opts: FitOpts, ctx: Context | None = None):
+        if ctx is None:
+            ctx = default_context()
+        self._keep = (shape, target, xy, chol, rgb, m, v, step, loss_trace, ws, opts, ctx)
+        self._args = ((ctx.handle if ctx else None,)
+                      + _fit_args(shape, target, xy, chol, rgb, m, v, step, loss_trace, ws)
+                      + (ctypes.byref(opts),))
+
+    def __call__(self, check=True) -> FitStats:
+        stats = FitStats()
+        code = lib().gs2d_fit_frame(*self._args, ctypes.byref(stats), _stream())
+        if check:
+            _check("gs2d_fit_frame", code)
+        stats.code = code
+        return stats
+
+
 def fit_frame_static(shape: Shape, target, xy, chol, rgb, m, v, step, loss_trace, opts: FitOpts,
                      check=True) -> FitStats:
     """gs2d_fit_frame_static: the fitting loop with the library's own

@@ -140,3 +140,28 @@ def test_one_frame_autotuner_times_every_candidate():
                                    reps=3)
     assert len(ms) == len(cands) and all(x > 0 for x in ms)
     assert best == int(np.argmin(ms))
+
+
+def test_prepared_call_follows_fit_frame():
+    """A FitCall (arguments checked and marshalled once) called twice gives
+    the trajectory of two gs2d_fit_frame calls on the same state."""
+    print("prepared call", flush=True)
+    frame, _ = synth.make_frame(96, 64, seed=7)
+    xy, chol, rgb = synth.random_gaussians(200, 96, 64, seed=8)
+    f = GpuFrame(96, 64, 200, 16)
+    opts = _lib.fit_opts(12, check_every=5, cfg=_lib.adam_cfg(LR))
+    ctx = _lib.Context()
+    traces = []
+    for prepared in (False, True):
+        P, M, V, step = _state(xy, chol, rgb)
+        trace = torch.zeros(64, device=DEV)
+        args = (f.shape, dev(frame), P["xy"], P["chol"], P["rgb"], M, V, step, trace, f.ws, opts)
+        call = _lib.FitCall(*args, ctx=ctx) if prepared else None
+        for _ in range(2):
+            st = call() if prepared else _lib.fit_frame(*args, ctx=ctx)
+            assert st.code == 0 and st.iters_run == 12
+        torch.cuda.synchronize()
+        assert int(step.item()) == 24
+        traces.append(host(trace)[:24].copy())
+    np.testing.assert_allclose(traces[1], traces[0], rtol=1e-5)
+    ctx.close()
